@@ -1,0 +1,252 @@
+"""Pins for the CPU oracle: each test ties it to something other than itself.
+
+* closed forms (tests/golden/closed_forms.tsv),
+* exhaustive enumeration of all alignments (pins the Gotoh DP),
+* the textbook Gotoh DP on every pair of short strings and on random
+  longer pairs,
+* the Levenshtein special case (x, o, e) = (1, 0, 1),
+* CIGAR invariants (spells both sequences, M/X are true matches and
+  mismatches, re-scores to the reported optimum),
+* equality with the Gotoh traceback where the optimum is unique,
+* symmetry and the planted-edit upper bound on generated read pairs,
+* planted mistakes: mutants of the oracle built on the CPU must fail the
+  pins above.
+"""
+import itertools
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import brute
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PENALTIES = [(4, 6, 2), (1, 0, 1), (2, 3, 1), (3, 1, 4), (5, 7, 1), (1, 5, 1), (7, 2, 3)]
+
+
+def strings(alphabet: bytes, max_len: int):
+    for L in range(max_len + 1):
+        for t in itertools.product(alphabet, repeat=L):
+            yield bytes(t)
+
+
+def load_golden():
+    rows = []
+    with open(os.path.join(HERE, "golden", "closed_forms.tsv")) as f:
+        for line in f:
+            if line.startswith("#") or line.startswith("pattern\t") or not line.strip():
+                continue
+            p, t, x, o, e, score, cigar, why = line.rstrip("\n").split("\t")
+            p = b"" if p == "-" else p.encode()
+            t = b"" if t == "-" else t.encode()
+            rows.append((p, t, (int(x), int(o), int(e)), int(score), cigar, why))
+    return rows
+
+
+@pytest.mark.parametrize("row", load_golden(), ids=lambda r: r[5][:40])
+def test_golden_closed_forms(oracle_lib, row):
+    p, t, pen, score, cigar, _ = row
+    s, runs = oracle_lib.align(p, t, pen)
+    assert s == score
+    if cigar != "*":
+        assert oracle_lib.cigar_string(runs) == ("" if cigar == "-" else cigar)
+    assert brute.check_cigar(p, t, runs, *pen) == score
+    # the closed form also holds for the independent DP
+    assert brute.gotoh(p, t, *pen)[0] == score
+
+
+def test_enumeration_pins_gotoh():
+    """Gotoh's score and co-optimal count equal exhaustive enumeration."""
+    pairs = list(itertools.product(list(strings(b"ACGT", 3)), repeat=2))
+    pairs += list(itertools.product([s for s in strings(b"AC", 4) if len(s) == 4], repeat=2))
+    for pen in [(4, 6, 2), (1, 0, 1), (3, 1, 4), (20, 1, 1)]:
+        for p, t in pairs:
+            assert brute.gotoh(p, t, *pen) == brute.enumerate_costs(p, t, *pen), (p, t, pen)
+
+
+def test_gotoh_np_matches_plain_gotoh():
+    rng = np.random.default_rng(11)
+    for pen in PENALTIES:
+        for p, t in [(b"", b""), (b"", b"AC"), (b"GT", b"")] + [
+                (bytes(rng.choice(list(b"ACGT"), int(rng.integers(0, 25))).astype(np.uint8)),
+                 bytes(rng.choice(list(b"ACGT"), int(rng.integers(0, 25))).astype(np.uint8)))
+                for _ in range(40)]:
+            assert brute.gotoh_np(p, t, *pen) == brute.gotoh(p, t, *pen)[0]
+
+
+@pytest.mark.parametrize("pen", PENALTIES)
+def test_oracle_exhaustive_short(oracle_lib, pen):
+    """Every pair over ACGT up to length 3 and over AC up to length 5."""
+    seqs = list(strings(b"ACGT", 3)) + [s for s in strings(b"AC", 5) if len(s) >= 4]
+    for p, t in itertools.product(seqs, repeat=2):
+        s, runs = oracle_lib.align(p, t, pen)
+        g, count, ops = brute.gotoh(p, t, *pen, traceback=True)
+        assert s == g, (p, t, pen)
+        assert brute.check_cigar(p, t, runs, *pen) == s
+        if count == 1:
+            assert brute.runs_to_ops(runs) == ops, (p, t, pen)
+
+
+@pytest.mark.parametrize("pen", PENALTIES)
+def test_oracle_random_vs_gotoh(oracle_lib, synth_lib, pen):
+    rng = np.random.default_rng(1234 + sum(pen))
+    pairs = synth_lib.random_pairs(rng, 60, 120) + synth_lib.random_pairs(rng, 10, 300)
+    pairs += synth_lib.random_pairs(rng, 10, 60, related=False)
+    for p, t in pairs:
+        s, runs = oracle_lib.align(p, t, pen)
+        assert s == brute.gotoh_np(p, t, *pen), (p, t, pen)
+        assert brute.check_cigar(p, t, runs, *pen) == s
+        s2, _ = oracle_lib.align(t, p, pen, cigar=False)
+        assert s2 == s  # symmetry of the affine score
+
+
+def test_oracle_unique_optimum_cigar(oracle_lib, synth_lib):
+    """Where Gotoh finds exactly one optimal alignment the CIGAR is fixed."""
+    rng = np.random.default_rng(77)
+    checked = 0
+    for p, t in synth_lib.random_pairs(rng, 300, 40):
+        for pen in [(4, 6, 2), (5, 7, 1)]:
+            g, count, ops = brute.gotoh(p, t, *pen, traceback=True)
+            if count != 1:
+                continue
+            s, runs = oracle_lib.align(p, t, pen)
+            assert s == g
+            assert brute.runs_to_ops(runs) == ops, (p, t, pen)
+            checked += 1
+    assert checked > 100
+
+
+def test_levenshtein_special_case(oracle_lib, synth_lib):
+    rng = np.random.default_rng(5)
+    for p, t in synth_lib.random_pairs(rng, 80, 80) + synth_lib.random_pairs(rng, 20, 40, related=False):
+        s, runs = oracle_lib.align(p, t, (1, 0, 1))
+        assert s == brute.levenshtein(p, t)
+        assert brute.check_cigar(p, t, runs, 1, 0, 1) == s
+
+
+def test_score_only_equals_cigar_mode(oracle_lib, synth_lib):
+    b = synth_lib.workload("uneven50_300_2m", 300)
+    for pen in [(4, 6, 2), (2, 3, 1)]:
+        full = oracle_lib.align_batch(b, pen, cigar=True, threads=4)
+        sc = oracle_lib.align_batch(b, pen, cigar=False, threads=4)
+        assert np.array_equal(full.scores, sc.scores)
+
+
+def test_generated_pairs_properties(oracle_lib, synth_lib):
+    """Planted-edit bound and CIGAR invariants on the 100 bp workloads."""
+    x, o, e = 4, 6, 2
+    for name, edits in [("pairs100_e2_10k", 2), ("pairs100_e4_5m", 4)]:
+        b = synth_lib.workload(name, 400)
+        r = oracle_lib.align_batch(b, (x, o, e), threads=4)
+        # every planted event costs at most o + e (indel) or x (substitution)
+        assert int(r.scores.max()) <= edits * max(x, o + e)
+        assert int(r.scores.min()) >= 0
+        for i in range(len(b)):
+            p, t = b.pair(i)
+            runs = r.runs[int(r.offsets[i]):int(r.offsets[i + 1])]
+            assert brute.check_cigar(p, t, runs, x, o, e) == int(r.scores[i])
+        for i in range(0, len(b), 37):
+            p, t = b.pair(i)
+            assert brute.gotoh_np(p, t, x, o, e) == int(r.scores[i])
+
+
+def test_batch_equals_single(oracle_lib, synth_lib):
+    b = synth_lib.workload("uneven50_300_2m", 64)
+    r = oracle_lib.align_batch(b, (4, 6, 2), threads=3)
+    for i in range(len(b)):
+        s, runs = oracle_lib.align(*b.pair(i), (4, 6, 2))
+        assert s == int(r.scores[i])
+        assert list(r.runs[int(r.offsets[i]):int(r.offsets[i + 1])]) == runs
+
+
+def test_pack2bit_definition(oracle_lib):
+    # A=0 C=1 G=2 T=3, base i at bits 2*(i%32) of word i//32
+    w = oracle_lib.pack2bit(b"ACGT")
+    assert w.tolist() == [0 | 1 << 2 | 2 << 4 | 3 << 6]
+    w = oracle_lib.pack2bit(b"T" * 33)
+    assert w.tolist() == [(1 << 64) - 1, 3]
+    assert oracle_lib.pack2bit(b"acgt").tolist() == oracle_lib.pack2bit(b"ACGT").tolist()
+    with pytest.raises(ValueError):
+        oracle_lib.pack2bit(b"ACNT")
+
+
+# ---- planted mistakes ------------------------------------------------------
+# Each mutant changes one line of the oracle's arithmetic the way a plausible
+# slip would; the pins must reject every one of them.
+MUTANTS = {
+    "I_from_k_plus_1": ("int a = wf_get(&t, so, 'M', k - 1);", "int a = wf_get(&t, so, 'M', k + 1);"),
+    "no_open_cost": ("int sx = s - x, so = s - o - e, se = s - e;", "int sx = s - x, so = s - e, se = s - e;"),
+    "D_extends_from_I": ("int d = wf_get(&t, se, 'D', k + 1);", "int d = wf_get(&t, se, 'I', k + 1);"),
+    "extend_skips_first": ("int v = h - k;\n    int run = 0;", "int v = h - k + 1;\n    int run = 0;"),
+    "target_transposed": ("int target_k = m - n;", "int target_k = n - m;"),
+    "mismatch_no_advance": ("xx = xx == OFF_NULL ? OFF_NULL : xx + 1;\n            int Mv",
+                            "xx = xx == OFF_NULL ? OFF_NULL : xx;\n            int Mv"),
+    "backtrace_D_moves_h": ("                k += 1;\n            }\n        }", "                k += 1;\n                h -= 1;\n            }\n        }"),
+}
+
+
+def _build_mutant(tmp_path, name):
+    src = open(os.path.join(HERE, "..", "oracle", "wfa_oracle.c")).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, f"mutant {name} no longer applies"
+    src = src.replace(old, new, 1)
+    d = tmp_path / name
+    d.mkdir()
+    (d / "wfa_oracle.c").write_text(src)
+    hdr = open(os.path.join(HERE, "..", "oracle", "wfa_oracle.h")).read()
+    (d / "wfa_oracle.h").write_text(hdr)
+    so = d / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-pthread", "-o", str(so),
+                           str(d / "wfa_oracle.c")])
+    return str(so)
+
+
+def _mutant_caught(so_path) -> bool:
+    import ctypes
+
+    lib = ctypes.CDLL(so_path)
+    p, i, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    lib.oracle_align.argtypes = [p, i, p, i, i, i, i, i, p, p, i64, p, p]
+    rng = np.random.default_rng(3)
+    cases = [(a, b) for a in strings(b"ACG", 3) for b in strings(b"ACG", 3)]
+    cases += [(bytes(rng.choice(list(b"ACGT"), 30).astype(np.uint8)),
+               bytes(rng.choice(list(b"ACGT"), 27).astype(np.uint8))) for _ in range(20)]
+    for pen in [(4, 6, 2), (1, 0, 1)]:
+        for P, T in cases:
+            n, m = len(P), len(T)
+            runs = (ctypes.c_uint32 * (n + m + 1))()
+            sc = ctypes.c_int32()
+            nr = ctypes.c_int64()
+            # run the mutant in a child-safe way: bound the work by a step cap
+            rc = lib.oracle_align(ctypes.create_string_buffer(P, n + 1), n,
+                                  ctypes.create_string_buffer(T, m + 1), m, *pen, 1,
+                                  ctypes.byref(sc), runs, n + m + 1, ctypes.byref(nr), None)
+            if rc != 0 or sc.value != brute.gotoh(P, T, *pen)[0]:
+                return True
+            try:
+                if brute.check_cigar(P, T, list(runs)[:nr.value], *pen) != sc.value:
+                    return True
+            except AssertionError:
+                return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    so = _build_mutant(tmp_path, name)
+    # mutants can loop forever (never reaching the end cell): run in a child
+    import multiprocessing as mp
+
+    ctx = mp.get_context("fork")
+    q = ctx.Queue()
+    proc = ctx.Process(target=lambda: q.put(_mutant_caught(so)))
+    proc.start()
+    proc.join(5)
+    if proc.is_alive():
+        proc.kill()
+        proc.join()
+        return  # non-termination is itself a caught mistake
+    if proc.exitcode != 0:
+        return  # crash: caught
+    assert q.get(timeout=5), f"mutant {name} passed the pins"
