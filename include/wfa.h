@@ -1,0 +1,273 @@
+/*
+ * wfa.h - batched gap-affine global pair alignment with the wavefront
+ * algorithm on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed.  The paper aligns many independent read pairs with the
+ * wavefront algorithm (Introduction and Methods: each pair is aligned
+ * independently and one result per pair is written back).  The algorithm
+ * is WFA (Marco-Sola, Moure, Moreto, Espinosa, Bioinformatics 37(4), 2021):
+ * for a pattern P of n bases and a text T of m bases it returns the optimal
+ * gap-affine score
+ *
+ *     score = min over global alignments of
+ *             x * #mismatches + sum over maximal gap runs (o + e * length)
+ *
+ * (matches cost 0) and, in CIGAR mode, one optimal alignment.  Where
+ * several alignments are optimal a fixed tie-break picks one: in a match
+ * state, a mismatch on the same diagonal is preferred to the end of an
+ * insertion, which is preferred to the end of a deletion; inside a gap,
+ * opening from a match state is preferred to extending the gap.  Scores
+ * and CIGARs are bit-identical across every schedule and launch shape the
+ * library offers.
+ *
+ * Conventions.
+ *   - Diagonal k = h - v, offset = h, where (v, h) aligns P[0..v) with
+ *     T[0..h).
+ *   - CIGAR runs are 32-bit words  len << 4 | op  with op
+ *       WFA_OP_MATCH    (0, 'M'): P[v] == T[h], consumes one base of each;
+ *       WFA_OP_MISMATCH (1, 'X'): P[v] != T[h], consumes one base of each;
+ *       WFA_OP_INS      (2, 'I'): consumes one base of the TEXT only;
+ *       WFA_OP_DEL      (3, 'D'): consumes one base of the PATTERN only.
+ *     Neighbouring runs always have different ops.
+ *   - Penalties: x = mismatch > 0, o = gap_open >= 0, e = gap_extend > 0.
+ *
+ * Sequence encodings.
+ *   - WFA_ASCII:   bytes A, C, G, T (either case).  p_start / t_start are
+ *                  byte offsets into `patterns` / `texts`.  Any other byte
+ *                  makes the call fail with WFA_E_ALPHABET.
+ *   - WFA_PACKED2: 2 bits per base in little-endian 64-bit words, A=0, C=1,
+ *                  G=2, T=3; base i of a sequence sits in bits 2*(i%32) and
+ *                  2*(i%32)+1 of word start + i/32.  p_start / t_start are
+ *                  64-bit word indices.  Only the ceil(len/32) words of a
+ *                  sequence are read; bits past its end are ignored.
+ *
+ * Memory spaces.  All buffer arguments of one call live in the space named
+ * by `mem`: host memory (WFA_HOST; the library stages to and from the
+ * device) or device memory of the context's GPU (WFA_DEVICE, e.g. torch
+ * tensors' data pointers).  Scalar out-parameters (cigar_needed, bad_pair,
+ * stats, tickets) are always host pointers.
+ *
+ * Ownership.  The caller owns every input and output buffer; the library
+ * keeps no caller pointer after a call returns.  The library owns its
+ * device workspace, which grows on demand within the context's HBM budget.
+ *
+ * Synchronisation.  wfa_align_batch enqueues its work on `stream` (a
+ * hipStream_t; NULL selects the context's own stream) and returns after that
+ * work has completed.
+ *
+ * Threading.  A wfa_ctx is used by one host thread at a time.  The server
+ * functions are thread-safe.
+ *
+ * Errors.  Every int-returning function returns WFA_OK (0) or a negative
+ * WFA_E_* code; wfa_strerror gives its text.  On a validation error nothing
+ * is written except *bad_pair.
+ */
+#ifndef WFA_H
+#define WFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wfa_ctx wfa_ctx;
+
+typedef struct {
+    int32_t mismatch;   /* x > 0  */
+    int32_t gap_open;   /* o >= 0 */
+    int32_t gap_extend; /* e > 0  */
+} wfa_penalties;
+
+/* One pair: start offsets (bytes for ASCII, 64-bit words for PACKED2) and
+ * lengths.  24 bytes, naturally aligned. */
+typedef struct {
+    uint64_t p_start;
+    uint64_t t_start;
+    uint32_t p_len;
+    uint32_t t_len;
+} wfa_pair;
+
+typedef enum { WFA_SCORE = 0, WFA_CIGAR = 1 } wfa_mode;
+typedef enum { WFA_ASCII = 0, WFA_PACKED2 = 1 } wfa_encoding;
+typedef enum { WFA_HOST = 0, WFA_DEVICE = 1 } wfa_memspace;
+
+/* Schedules (all give identical results):
+ *   AUTO:       persistent, bucketed, graph-replayed short-pair kernel, with
+ *               the general kernel for pairs it cannot hold;
+ *   PLAIN:      one launch, pair i on lane group i, no bucketing;
+ *   PERSISTENT: grid sized to the GPU, lane groups pull pairs from a device
+ *               queue in bucketed order;
+ *   GENERAL:    every pair on the workgroup-per-pair kernel whose
+ *               wavefronts live in the HBM arena (any length, any score). */
+typedef enum {
+    WFA_SCHED_AUTO = 0,
+    WFA_SCHED_PLAIN = 1,
+    WFA_SCHED_PERSISTENT = 2,
+    WFA_SCHED_GENERAL = 3
+} wfa_schedule;
+
+/* Tuning knobs.  Zero means "choose automatically".  None of them changes
+ * any result. */
+typedef struct {
+    int32_t schedule;       /* wfa_schedule                                      */
+    int32_t window;         /* diagonals held per pair by the short kernel: 16, 32, 64, 128, 256 */
+    int32_t step_cap;       /* score steps (in units of gcd(x,o,e)) held in LDS  */
+    int32_t use_graph;      /* 1: replay a captured hipGraph; -1: never; 0: auto */
+    int32_t bucket;         /* 1: sort pairs by (length, length difference); -1: off */
+    int32_t general_pairs;  /* concurrent pairs of the general kernel; 0: by budget */
+    int32_t block_threads;  /* threads per workgroup of the short kernel: 64..1024 */
+    int32_t reserved;
+} wfa_options;
+
+/* Counters of the last wfa_align_batch call on a context. */
+typedef struct {
+    uint64_t pairs;              /* pairs aligned                                    */
+    uint64_t short_pairs;        /* pairs finished by the short-pair kernel          */
+    uint64_t general_pairs;      /* pairs finished by the general kernel             */
+    uint64_t requeued;           /* pairs re-run after exceeding a window, step or
+                                    memory limit (results are unaffected)            */
+    uint64_t cigar_runs;         /* total runs written                               */
+    int32_t window;              /* short-kernel window used                         */
+    int32_t step_cap;            /* short-kernel step cap used                       */
+    int32_t schedule;            /* schedule used                                    */
+    int32_t graph_replayed;      /* 1 if a captured graph was replayed               */
+    double ms_pack;              /* device time of each phase, milliseconds          */
+    double ms_align;
+    double ms_general;
+    double ms_compact;
+    double ms_total;             /* host wall time of the call                       */
+} wfa_stats;
+
+enum {
+    WFA_OK = 0,
+    WFA_E_INVAL = -1,    /* bad argument: penalties, NULL pointer, enum value */
+    WFA_E_ALPHABET = -2, /* a byte outside ACGTacgt (ASCII input)             */
+    WFA_E_NOMEM = -3,    /* the HBM budget cannot hold the work               */
+    WFA_E_CAPACITY = -4, /* cigar_capacity is smaller than *cigar_needed      */
+    WFA_E_DEVICE = -5,   /* a HIP call failed                                 */
+    WFA_E_TOO_LONG = -6, /* a sequence longer than WFA_MAX_LENGTH             */
+    WFA_E_BUSY = -7,     /* server queue full / ticket not finished          */
+    WFA_E_NOTFOUND = -8  /* unknown server ticket                             */
+};
+
+enum { WFA_OP_MATCH = 0, WFA_OP_MISMATCH = 1, WFA_OP_INS = 2, WFA_OP_DEL = 3 };
+
+#define WFA_MAX_LENGTH ((uint32_t)1 << 26) /* bases per sequence */
+
+/* Create a context on HIP device `device` whose device workspace may grow to
+ * `hbm_budget_bytes` (0: 64 GiB).  *out receives the context. */
+int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx **out);
+
+/* Free the context and all device memory it owns.  NULL is ignored. */
+void wfa_ctx_destroy(wfa_ctx *ctx);
+
+/* Set tuning knobs for later calls (NULL restores the defaults). */
+int wfa_set_options(wfa_ctx *ctx, const wfa_options *opt);
+
+/* Align num_pairs pairs.
+ *   patterns, texts   sequence buffers in `enc` and `mem`
+ *   pairs             [num_pairs] descriptors, in `mem`
+ *   pen, mode         penalties and result mode
+ *   scores            [num_pairs] int32 out, in `mem`
+ *   cigar_runs        runs out (CIGAR mode; NULL allowed with capacity 0)
+ *   cigar_capacity    number of uint32 words cigar_runs can hold
+ *   cigar_offsets     [num_pairs + 1] uint64 out (CIGAR mode): pair i's runs
+ *                     are cigar_runs[cigar_offsets[i] .. cigar_offsets[i+1])
+ *   cigar_needed      host out: total runs of all pairs (may be NULL)
+ *   bad_pair          host out: first pair that failed validation, else -1
+ *   stream            hipStream_t or NULL
+ * In WFA_SCORE mode the CIGAR arguments are ignored.  If cigar_capacity is
+ * too small the call returns WFA_E_CAPACITY after writing scores, offsets
+ * and *cigar_needed; the runs can then be fetched with wfa_copy_last_cigars.
+ */
+int wfa_align_batch(wfa_ctx *ctx, const void *patterns, const void *texts,
+                    const wfa_pair *pairs, size_t num_pairs, wfa_encoding enc,
+                    wfa_memspace mem, wfa_penalties pen, wfa_mode mode, int32_t *scores,
+                    uint32_t *cigar_runs, size_t cigar_capacity, uint64_t *cigar_offsets,
+                    size_t *cigar_needed, int64_t *bad_pair, void *stream);
+
+/* After WFA_E_CAPACITY: copy the runs of the last call into `runs` (in the
+ * last call's memory space) if `capacity` suffices; offsets are those the
+ * last call wrote and may be passed again (NULL: not rewritten). */
+int wfa_copy_last_cigars(wfa_ctx *ctx, uint32_t *runs, size_t capacity, uint64_t *offsets);
+
+/* Encode ASCII sequences to the PACKED2 layout on the device.
+ *   ascii        device bytes
+ *   starts/lens  [count] device arrays: byte offset and length per sequence
+ *   words        device output; sequence i starts at word word_starts[i]
+ *   word_starts  [count + 1] device out: exclusive scan of ceil(len/32),
+ *                the last entry being the total
+ *   total_words  host out: words written
+ *   bad_index    host out: sequence index of the first non-ACGT byte, or -1
+ * Fails with WFA_E_ALPHABET if any byte is outside ACGTacgt; WFA_E_CAPACITY
+ * if `words_capacity` is smaller than the words needed. */
+int wfa_pack2bit(wfa_ctx *ctx, const uint8_t *ascii, const uint64_t *starts,
+                 const uint32_t *lens, size_t count, uint64_t *words, size_t words_capacity,
+                 uint64_t *word_starts, size_t *total_words, int64_t *bad_index, void *stream);
+
+/* Counters of the last wfa_align_batch call. */
+int wfa_last_stats(const wfa_ctx *ctx, wfa_stats *out);
+
+/* Text of a status code (static storage). */
+const char *wfa_strerror(int status);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of alignment requests.
+ *
+ * Requests (each a set of pairs) are submitted from any thread and get a
+ * ticket.  A scheduler thread admits requests in arrival order while their
+ * estimated device memory fits the budget (large requests are admitted in
+ * chunks), launches admitted work as it arrives on several streams so that
+ * requests overlap on the device, and completes each request when all its
+ * chunks are done.  Results equal those of wfa_align_batch on the same pairs
+ * alone.
+ * ------------------------------------------------------------------------- */
+typedef struct wfa_server wfa_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* admission budget (0: 64 GiB)                   */
+    int32_t streams;          /* concurrent device streams (0: 4)               */
+    int32_t max_chunk_pairs;  /* pairs per launched chunk (0: 65536)            */
+    int32_t queue_limit;      /* requests waiting for admission (0: 1 << 20)     */
+    int32_t mode;             /* wfa_mode for every request                     */
+    wfa_penalties pen;
+} wfa_server_cfg;
+
+/* A request: host ASCII sequences, copied by wfa_server_submit. */
+typedef struct {
+    const uint8_t *patterns;
+    const uint8_t *texts;
+    const wfa_pair *pairs;
+    size_t num_pairs;
+} wfa_request;
+
+/* A finished request: host arrays owned by the server until the ticket is
+ * released (wfa_server_release) or the server closes. */
+typedef struct {
+    size_t num_pairs;
+    const int32_t *scores;
+    const uint32_t *cigar_runs;
+    const uint64_t *cigar_offsets; /* [num_pairs + 1]                           */
+    double submit_time_s;          /* seconds since the server opened           */
+    double admit_time_s;
+    double done_time_s;
+    int32_t status;
+} wfa_result;
+
+int wfa_server_open(wfa_ctx *ctx, const wfa_server_cfg *cfg, wfa_server **out);
+int wfa_server_submit(wfa_server *srv, const wfa_request *req, uint64_t *ticket);
+/* Wait up to timeout_us (negative: forever) for a ticket.  Returns WFA_OK and
+ * fills *out, or WFA_E_BUSY on time-out. */
+int wfa_server_poll(wfa_server *srv, uint64_t ticket, int64_t timeout_us, wfa_result *out);
+int wfa_server_release(wfa_server *srv, uint64_t ticket);
+/* Bytes of device memory the admission controller reserves for a request. */
+size_t wfa_server_estimate_bytes(const wfa_server *srv, const wfa_request *req);
+/* Finish all submitted work, stop the scheduler and free the server. */
+int wfa_server_close(wfa_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WFA_H */

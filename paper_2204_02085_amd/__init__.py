@@ -1,0 +1,287 @@
+"""Python binding of libwfa (batched gap-affine WFA on MI355X / gfx950).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+kernels behind the C ABI declared in ``include/wfa.h``.  The functions below
+carry the C names; ``Aligner`` adds a convenience layer that moves numpy
+arrays into torch device tensors (PyTorch provides device memory and
+streams, nothing else).
+
+The library must be built (``python -m paper_2204_02085_amd.build``); if it
+is missing, importing the binding raises ``ImportError`` -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwfa.so")
+
+# ---- C types (mirror include/wfa.h) -----------------------------------------
+WFA_SCORE, WFA_CIGAR = 0, 1
+WFA_ASCII, WFA_PACKED2 = 0, 1
+WFA_HOST, WFA_DEVICE = 0, 1
+WFA_SCHED_AUTO, WFA_SCHED_PLAIN, WFA_SCHED_PERSISTENT, WFA_SCHED_GENERAL = 0, 1, 2, 3
+WFA_OK, WFA_E_INVAL, WFA_E_ALPHABET, WFA_E_NOMEM = 0, -1, -2, -3
+WFA_E_CAPACITY, WFA_E_DEVICE, WFA_E_TOO_LONG, WFA_E_BUSY, WFA_E_NOTFOUND = -4, -5, -6, -7, -8
+WFA_OP_MATCH, WFA_OP_MISMATCH, WFA_OP_INS, WFA_OP_DEL = 0, 1, 2, 3
+WFA_MAX_LENGTH = 1 << 26
+
+EXPORTED = [
+    "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_align_batch",
+    "wfa_copy_last_cigars", "wfa_pack2bit", "wfa_last_stats", "wfa_strerror",
+    "wfa_server_open", "wfa_server_submit", "wfa_server_poll", "wfa_server_release",
+    "wfa_server_estimate_bytes", "wfa_server_close",
+]
+
+PAIR_DTYPE = np.dtype([("p_start", "<u8"), ("t_start", "<u8"), ("p_len", "<u4"),
+                       ("t_len", "<u4")])
+
+
+class wfa_penalties(ctypes.Structure):
+    _fields_ = [("mismatch", ctypes.c_int32), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32)]
+
+
+class wfa_options(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("step_cap", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("bucket", ctypes.c_int32), ("general_pairs", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class wfa_stats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_uint64), ("short_pairs", ctypes.c_uint64),
+                ("general_pairs", ctypes.c_uint64), ("requeued", ctypes.c_uint64),
+                ("cigar_runs", ctypes.c_uint64), ("window", ctypes.c_int32),
+                ("step_cap", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("graph_replayed", ctypes.c_int32), ("ms_pack", ctypes.c_double),
+                ("ms_align", ctypes.c_double), ("ms_general", ctypes.c_double),
+                ("ms_compact", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class wfa_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int32),
+                ("max_chunk_pairs", ctypes.c_int32), ("queue_limit", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("pen", wfa_penalties)]
+
+
+class wfa_request(ctypes.Structure):
+    _fields_ = [("patterns", ctypes.c_void_p), ("texts", ctypes.c_void_p),
+                ("pairs", ctypes.c_void_p), ("num_pairs", ctypes.c_size_t)]
+
+
+class wfa_result(ctypes.Structure):
+    _fields_ = [("num_pairs", ctypes.c_size_t), ("scores", ctypes.POINTER(ctypes.c_int32)),
+                ("cigar_runs", ctypes.POINTER(ctypes.c_uint32)),
+                ("cigar_offsets", ctypes.POINTER(ctypes.c_uint64)),
+                ("submit_time_s", ctypes.c_double), ("admit_time_s", ctypes.c_double),
+                ("done_time_s", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2204_02085_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, u64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                            ctypes.c_size_t)
+    sig = {
+        "wfa_ctx_create": ([ctypes.c_int, sz, ctypes.POINTER(p)], ctypes.c_int),
+        "wfa_ctx_destroy": ([p], None),
+        "wfa_set_options": ([p, ctypes.POINTER(wfa_options)], ctypes.c_int),
+        "wfa_align_batch": ([p, p, p, p, sz, ctypes.c_int, ctypes.c_int, wfa_penalties,
+                             ctypes.c_int, p, p, sz, p, ctypes.POINTER(sz),
+                             ctypes.POINTER(i64), p], ctypes.c_int),
+        "wfa_copy_last_cigars": ([p, p, sz, p], ctypes.c_int),
+        "wfa_pack2bit": ([p, p, p, p, sz, p, sz, p, ctypes.POINTER(sz), ctypes.POINTER(i64), p],
+                         ctypes.c_int),
+        "wfa_last_stats": ([p, ctypes.POINTER(wfa_stats)], ctypes.c_int),
+        "wfa_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "wfa_server_open": ([p, ctypes.POINTER(wfa_server_cfg), ctypes.POINTER(p)], ctypes.c_int),
+        "wfa_server_submit": ([p, ctypes.POINTER(wfa_request), ctypes.POINTER(u64)],
+                              ctypes.c_int),
+        "wfa_server_poll": ([p, u64, i64, ctypes.POINTER(wfa_result)], ctypes.c_int),
+        "wfa_server_release": ([p, u64], ctypes.c_int),
+        "wfa_server_estimate_bytes": ([p, ctypes.POINTER(wfa_request)], sz),
+        "wfa_server_close": ([p], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    del i32, u64
+    return lib
+
+
+lib = _load()
+
+# C entry points under their own names
+wfa_ctx_create = lib.wfa_ctx_create
+wfa_ctx_destroy = lib.wfa_ctx_destroy
+wfa_set_options = lib.wfa_set_options
+wfa_align_batch = lib.wfa_align_batch
+wfa_copy_last_cigars = lib.wfa_copy_last_cigars
+wfa_pack2bit = lib.wfa_pack2bit
+wfa_last_stats = lib.wfa_last_stats
+wfa_strerror = lib.wfa_strerror
+wfa_server_open = lib.wfa_server_open
+wfa_server_submit = lib.wfa_server_submit
+wfa_server_poll = lib.wfa_server_poll
+wfa_server_release = lib.wfa_server_release
+wfa_server_estimate_bytes = lib.wfa_server_estimate_bytes
+wfa_server_close = lib.wfa_server_close
+
+
+class WFAError(RuntimeError):
+    def __init__(self, status: int, what: str = "", bad: int = -1):
+        msg = wfa_strerror(status).decode()
+        super().__init__(f"{what}: {msg} (status {status}{', pair ' + str(bad) if bad >= 0 else ''})")
+        self.status = status
+        self.bad = bad
+
+
+def pairs_array(p_off, p_len, t_off, t_len) -> np.ndarray:
+    """Descriptor array (wfa_pair layout) from per-pair starts and lengths."""
+    a = np.zeros(len(p_len), dtype=PAIR_DTYPE)
+    a["p_start"] = p_off
+    a["t_start"] = t_off
+    a["p_len"] = p_len
+    a["t_len"] = t_len
+    return a
+
+
+class Aligner:
+    """One library context on one GPU, with device-resident batches.
+
+    ``align`` takes a batch with numpy fields (``patterns``, ``texts``,
+    ``p_off``, ``p_len``, ``t_off``, ``t_len``; e.g. ``synth.Batch``), copies
+    it to the device with torch, and returns numpy (scores, runs, offsets).
+    ``align_device`` works on torch device tensors already in HBM.
+    """
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        torch.cuda.set_device(device)
+        ctx = ctypes.c_void_p()
+        rc = wfa_ctx_create(device, hbm_budget_bytes, ctypes.byref(ctx))
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_ctx_create")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            wfa_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, **kw):
+        o = wfa_options(**kw)
+        rc = wfa_set_options(self.ctx, ctypes.byref(o))
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_set_options")
+
+    def stats(self) -> dict:
+        s = wfa_stats()
+        wfa_last_stats(self.ctx, ctypes.byref(s))
+        return s.as_dict()
+
+    def to_device(self, batch):
+        """Device tensors (patterns, texts, pairs) for a numpy batch."""
+        t = self.torch
+        dev = f"cuda:{self.device}"
+        pairs = pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len)
+        return (t.from_numpy(np.ascontiguousarray(batch.patterns)).to(dev),
+                t.from_numpy(np.ascontiguousarray(batch.texts)).to(dev),
+                t.from_numpy(pairs.view(np.uint8).copy()).to(dev))
+
+    def alloc_outputs(self, n: int, capacity: int, cigar: bool = True):
+        t = self.torch
+        dev = f"cuda:{self.device}"
+        scores = t.empty(n, dtype=t.int32, device=dev)
+        offsets = t.empty(n + 1, dtype=t.int64, device=dev) if cigar else None
+        runs = t.empty(max(capacity, 1), dtype=t.int32, device=dev) if cigar else None
+        return scores, runs, offsets
+
+    def align_device(self, patterns, texts, pairs, n, scores, runs=None, offsets=None,
+                     penalties=(4, 6, 2), cigar=True, encoding=WFA_ASCII, stream=None):
+        """Run wfa_align_batch on device tensors; returns runs needed."""
+        t = self.torch
+        needed = ctypes.c_size_t(0)
+        bad = ctypes.c_int64(-1)
+        if stream is None:
+            stream = t.cuda.current_stream(self.device).cuda_stream
+        rc = wfa_align_batch(
+            self.ctx, patterns.data_ptr(), texts.data_ptr(), pairs.data_ptr(), n, encoding,
+            WFA_DEVICE, wfa_penalties(*penalties), WFA_CIGAR if cigar else WFA_SCORE,
+            scores.data_ptr(), runs.data_ptr() if cigar else None,
+            runs.numel() if cigar else 0, offsets.data_ptr() if cigar else None,
+            ctypes.byref(needed), ctypes.byref(bad), stream)
+        self._needed = needed.value
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_align_batch", bad.value)
+        return needed.value
+
+    def align(self, batch, penalties=(4, 6, 2), cigar=True, capacity=None):
+        """Align a numpy batch on the GPU; returns numpy scores, runs, offsets."""
+        n = len(batch.p_len)
+        pat, txt, pairs = self.to_device(batch)
+        if capacity is None:
+            capacity = int(n * 24 + 1024)
+        scores, runs, offsets = self.alloc_outputs(n, capacity, cigar)
+        try:
+            needed = self.align_device(pat, txt, pairs, n, scores, runs, offsets, penalties, cigar)
+        except WFAError as e:
+            if e.status != WFA_E_CAPACITY:
+                raise
+            runs = self.torch.empty(int(self.last_needed()), dtype=self.torch.int32,
+                                    device=scores.device)
+            rc = wfa_copy_last_cigars(self.ctx, runs.data_ptr(), runs.numel(),
+                                      offsets.data_ptr())
+            if rc != WFA_OK:
+                raise WFAError(rc, "wfa_copy_last_cigars")
+            needed = runs.numel()
+        self.torch.cuda.synchronize(self.device)
+        sc = scores.cpu().numpy()
+        if not cigar:
+            return sc, None, None
+        off = offsets.cpu().numpy().astype(np.uint64)
+        rr = runs[:needed].cpu().numpy().view(np.uint32).copy()
+        return sc, rr, off
+
+    def last_needed(self) -> int:
+        return int(getattr(self, "_needed", 0))
+
+    def align_host(self, batch, penalties=(4, 6, 2), cigar=True, encoding=WFA_ASCII):
+        """Host-memory variant: the library stages to and from the device."""
+        n = len(batch.p_len)
+        pairs = pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len)
+        scores = np.zeros(n, dtype=np.int32)
+        offsets = np.zeros(n + 1, dtype=np.uint64)
+        cap = n * 24 + 1024
+        runs = np.zeros(cap, dtype=np.uint32)
+        needed = ctypes.c_size_t(0)
+        bad = ctypes.c_int64(-1)
+        rc = wfa_align_batch(
+            self.ctx, batch.patterns.ctypes.data, batch.texts.ctypes.data, pairs.ctypes.data, n,
+            encoding, WFA_HOST, wfa_penalties(*penalties), WFA_CIGAR if cigar else WFA_SCORE,
+            scores.ctypes.data, runs.ctypes.data if cigar else None, cap if cigar else 0,
+            offsets.ctypes.data if cigar else None, ctypes.byref(needed), ctypes.byref(bad), None)
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_align_batch", bad.value)
+        if not cigar:
+            return scores, None, None
+        return scores, runs[:needed.value].copy(), offsets

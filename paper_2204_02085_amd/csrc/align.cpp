@@ -1,0 +1,543 @@
+// One batch: stage, plan, pack, short-pair kernel (plain or persistent, with
+// optional bucketing and graph replay), general kernel for whatever the short
+// kernel hands over, CIGAR offsets and compaction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "../../include/wfa.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace wfa;
+
+namespace {
+
+constexpr uint32_t SHORT_MAX_LEN = 2400;  // longest sequence the short kernel stages in LDS
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t _e = (x);                        \
+        if (_e != hipSuccess) {                     \
+            (void)hipGetLastError();                \
+            return WFA_E_DEVICE;                    \
+        }                                           \
+    } while (0)
+
+#define RCCHK(x)                  \
+    do {                          \
+        int _r = (x);             \
+        if (_r != WFA_OK) return _r; \
+    } while (0)
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+double ev_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0;
+    }
+    return ms;
+}
+
+int auto_window(uint32_t max_len) {
+    if (max_len <= 160) return 32;
+    if (max_len <= 400) return 64;
+    if (max_len <= 1200) return 128;
+    if (max_len <= SHORT_MAX_LEN) return 256;
+    return 0;
+}
+
+// Grow `b` to `bytes`, keeping its first `keep` bytes.
+int ensure_keep(Workspace& ws, Buf& b, size_t bytes, size_t keep, hipStream_t s) {
+    if (b.bytes >= bytes) return WFA_OK;
+    Buf nb;
+    int rc = ws.ensure(nb, std::max(bytes, b.bytes * 2));
+    if (rc != WFA_OK) return rc;
+    if (keep) HIPCHK(hipMemcpyAsync(nb.ptr, b.ptr, keep, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ws.release(b);
+    b = nb;
+    return WFA_OK;
+}
+
+struct Dev {
+    const PairDesc* pairs;    // descriptors of the packed words
+    const uint64_t* pw;
+    const uint64_t* tw;
+    int32_t* scores;
+    uint32_t* runs;
+    uint64_t* offsets;
+    uint64_t capacity;
+};
+
+// Pairs in `pending` on the workgroup-per-pair kernel, chunked by the budget;
+// pairs whose slice is too small are retried with a 4x slice.
+int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const BatchStats& st,
+                std::vector<uint32_t> pending, uint64_t& gen_used, hipStream_t s,
+                uint64_t* general_done, uint64_t* requeued) {
+    Workspace& ws = e->ws;
+    const uint64_t nm1 = (uint64_t)st.max_p + st.max_t + 1;
+    const uint64_t R = (uint64_t)pen.pre + 1;
+    uint64_t slice;
+    if (cigar) {
+        const double est = 12.0 * (double)nm1 * (double)nm1 / 64.0;
+        slice = (uint64_t)std::min(std::max(est, 256.0 * 1024), 64.0 * 1024 * 1024);
+    } else {
+        slice = R * 3 * 4 * nm1;
+    }
+    slice = (slice + 255) & ~(uint64_t)255;
+    const uint32_t lds_words = (st.max_p + 31) / 32 + 1 + (st.max_t + 31) / 32 + 1;
+    const bool seq_lds = (uint64_t)lds_words * 8 <= 48 * 1024;
+    const int lds_bytes = seq_lds ? (int)(lds_words * 8) : 0;
+    const uint32_t max_len = std::max(st.max_p, st.max_t);
+    const int bt = max_len > 3000 ? 1024 : (max_len > 600 ? 256 : 64);
+
+    RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
+    DevFlags* flags = ws.flags.as<DevFlags>();
+    int attempts = 0;
+    while (!pending.empty()) {
+        if (++attempts > 40) return WFA_E_NOMEM;
+        const size_t free_bytes = ws.budget > ws.total ? ws.budget - ws.total + ws.arena.bytes : 0;
+        size_t conc = (size_t)(free_bytes * 0.9 / slice);
+        if (e->opt.general_pairs > 0) conc = std::min(conc, (size_t)e->opt.general_pairs);
+        conc = std::min(conc, pending.size());
+        conc = std::min(conc, (size_t)1 << 20);
+        if (conc == 0) {
+            if (cigar) return WFA_E_NOMEM;
+            return WFA_E_NOMEM;
+        }
+        RCCHK(ws.ensure(ws.arena, conc * slice));
+        RCCHK(ws.ensure(ws.jobs, conc * 4));
+        RCCHK(ws.ensure(ws.job_nruns, conc * 4));
+        RCCHK(ws.ensure(ws.job_offsets, (conc + 1) * 8));
+        RCCHK(ws.ensure(ws.fail_list, conc * 4));
+        RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(conc) + 64));
+        std::vector<uint32_t> failed;
+        for (size_t off = 0; off < pending.size(); off += conc) {
+            const size_t nj = std::min(conc, pending.size() - off);
+            HIPCHK(hipMemcpyAsync(ws.jobs.ptr, pending.data() + off, nj * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_fill_u32(ws.job_nruns.as<uint32_t>(), 0u, nj, s));
+            HIPCHK(launch_fill_u32(&flags->fail_count, 0u, 1, s));
+            GeneralArgs g{};
+            g.pairs = d.pairs;
+            g.pw = d.pw;
+            g.tw = d.tw;
+            g.jobs = ws.jobs.as<uint32_t>();
+            g.num_jobs = (uint32_t)nj;
+            g.pen = pen;
+            g.cigar = cigar ? 1 : 0;
+            g.arena = ws.arena.as<uint8_t>();
+            g.slice_bytes = slice;
+            g.scores = d.scores;
+            g.nruns = ws.nruns.as<uint32_t>();
+            g.run_src = ws.run_src.as<uint64_t>();
+            g.job_nruns = ws.job_nruns.as<uint32_t>();
+            g.fail_list = ws.fail_list.as<uint32_t>();
+            g.fail_count = &flags->fail_count;
+            HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, s));
+            uint32_t nfail = 0;
+            HIPCHK(hipMemcpyAsync(&nfail, &flags->fail_count, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (nfail) {
+                std::vector<uint32_t> f(nfail);
+                HIPCHK(hipMemcpy(f.data(), ws.fail_list.ptr, nfail * 4ull, hipMemcpyDeviceToHost));
+                failed.insert(failed.end(), f.begin(), f.end());
+            }
+            *general_done += nj - nfail;
+            if (cigar) {
+                // gather this chunk's runs out of the arena before it is reused
+                HIPCHK(launch_scan(SCAN_U32, ws.job_nruns.ptr, nj, ws.job_offsets.as<uint64_t>(),
+                                   ws.scan_tmp.ptr, s));
+                uint64_t chunk_runs = 0;
+                HIPCHK(hipMemcpyAsync(&chunk_runs, ws.job_offsets.as<uint64_t>() + nj, 8,
+                                      hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                RCCHK(ensure_keep(ws, ws.gen_runs, (gen_used + chunk_runs + 1) * 4, gen_used * 4, s));
+                HIPCHK(launch_gather_general(ws.jobs.as<uint32_t>(), nj, ws.job_nruns.as<uint32_t>(),
+                                             ws.run_src.as<uint64_t>(), ws.arena.as<uint8_t>(), slice,
+                                             ws.job_offsets.as<uint64_t>(), gen_used,
+                                             ws.gen_runs.as<uint32_t>(), s));
+                gen_used += chunk_runs;
+            }
+        }
+        if (!failed.empty()) {
+            *requeued += failed.size();
+            std::sort(failed.begin(), failed.end());
+            pending.swap(failed);
+            slice *= 4;
+            // the arena is regrown for the larger slices
+            ws.release(ws.arena);
+        } else {
+            pending.clear();
+        }
+    }
+    return WFA_OK;
+}
+
+}  // namespace
+
+bool GraphKey::operator==(const GraphKey& o) const {
+    for (int i = 0; i < 8; i++)
+        if (p[i] != o.p[i]) return false;
+    for (int i = 0; i < 12; i++)
+        if (ints[i] != o.ints[i]) return false;
+    return n == o.n;
+}
+
+void graph_cache_clear(Engine* e) {
+    for (auto& g : e->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    e->graphs.clear();
+}
+
+int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
+                 int64_t* bad_pair) {
+    const double t_start = now_ms();
+    if (bad_pair) *bad_pair = -1;
+    if (cigar_needed) *cigar_needed = 0;
+    Pen pen;
+    RCCHK(make_pen(io.pen, &pen));
+    if (io.enc != WFA_ASCII && io.enc != WFA_PACKED2) return WFA_E_INVAL;
+    if (io.mem != WFA_HOST && io.mem != WFA_DEVICE) return WFA_E_INVAL;
+    if (io.mode != WFA_SCORE && io.mode != WFA_CIGAR) return WFA_E_INVAL;
+    const bool cigar = io.mode == WFA_CIGAR;
+    const size_t N = io.n;
+    if (N > 0 && (!io.patterns || !io.texts || !io.pairs || !io.scores)) return WFA_E_INVAL;
+    if (cigar && !io.offsets) return WFA_E_INVAL;
+    if (cigar && io.capacity && !io.runs) return WFA_E_INVAL;
+    if (N >= ((size_t)1 << 32) - 1) return WFA_E_INVAL;
+    if (hipSetDevice(e->device) != hipSuccess) return WFA_E_DEVICE;
+    Workspace& ws = e->ws;
+    hipStream_t s = e->stream;
+    std::memset(&e->last, 0, sizeof(e->last));
+    e->last_valid = false;
+    if (user_stream) {
+        HIPCHK(hipEventRecord(e->ev[7], user_stream));
+        HIPCHK(hipStreamWaitEvent(s, e->ev[7], 0));
+    }
+    auto finish_user = [&]() -> int {
+        if (user_stream) {
+            HIPCHK(hipEventRecord(e->ev[6], s));
+            HIPCHK(hipStreamWaitEvent(user_stream, e->ev[6], 0));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        return WFA_OK;
+    };
+
+    if (N == 0) {
+        if (cigar) {
+            if (io.mem == WFA_HOST) {
+                io.offsets[0] = 0;
+            } else {
+                HIPCHK(launch_fill_u64(io.offsets, 0ull, 1, s));
+            }
+        }
+        return finish_user();
+    }
+
+    // ---- staging (host memory) -------------------------------------------
+    const PairDesc* in_pairs;
+    const void* in_p;
+    const void* in_t;
+    Dev d{};
+    if (io.mem == WFA_HOST) {
+        uint64_t endp = 0, endt = 0;
+        const bool ascii = io.enc == WFA_ASCII;
+        for (size_t i = 0; i < N; i++) {
+            const wfa_pair& q = io.pairs[i];
+            const uint64_t lp = ascii ? q.p_len : (q.p_len + 31ull) / 32;
+            const uint64_t lt = ascii ? q.t_len : (q.t_len + 31ull) / 32;
+            endp = std::max(endp, q.p_start + lp);
+            endt = std::max(endt, q.t_start + lt);
+        }
+        const size_t unit = ascii ? 1 : 8;
+        RCCHK(ws.ensure(ws.in_pairs, N * sizeof(PairDesc)));
+        RCCHK(ws.ensure(ws.in_p, endp * unit + 8));
+        RCCHK(ws.ensure(ws.in_t, endt * unit + 8));
+        HIPCHK(hipMemcpyAsync(ws.in_pairs.ptr, io.pairs, N * sizeof(PairDesc), hipMemcpyHostToDevice, s));
+        if (endp) HIPCHK(hipMemcpyAsync(ws.in_p.ptr, io.patterns, endp * unit, hipMemcpyHostToDevice, s));
+        if (endt) HIPCHK(hipMemcpyAsync(ws.in_t.ptr, io.texts, endt * unit, hipMemcpyHostToDevice, s));
+        in_pairs = ws.in_pairs.as<PairDesc>();
+        in_p = ws.in_p.ptr;
+        in_t = ws.in_t.ptr;
+        RCCHK(ws.ensure(ws.out_scores, N * 4));
+        d.scores = ws.out_scores.as<int32_t>();
+        if (cigar) {
+            RCCHK(ws.ensure(ws.out_offsets, (N + 1) * 8));
+            d.offsets = ws.out_offsets.as<uint64_t>();
+        }
+    } else {
+        in_pairs = (const PairDesc*)io.pairs;
+        in_p = io.patterns;
+        in_t = io.texts;
+        d.scores = io.scores;
+        d.offsets = io.offsets;
+        d.runs = io.runs;
+        d.capacity = io.capacity;
+    }
+
+    // ---- batch facts -------------------------------------------------------
+    RCCHK(ws.ensure(ws.stats, sizeof(BatchStats)));
+    RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
+    BatchStats st;
+    HIPCHK(launch_batch_stats(in_pairs, N, ws.stats.as<BatchStats>(), WFA_MAX_LENGTH, s));
+    HIPCHK(hipMemcpyAsync(&st, ws.stats.ptr, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st.too_long) {
+        if (bad_pair) *bad_pair = (int64_t)st.first_too_long;
+        return WFA_E_TOO_LONG;
+    }
+    const uint32_t max_len = std::max(st.max_p, st.max_t);
+
+    // ---- plan ------------------------------------------------------------
+    int schedule = e->opt.schedule ? e->opt.schedule : WFA_SCHED_AUTO;
+    int window = e->opt.window ? e->opt.window : auto_window(max_len);
+    ShortPlan sp;
+    bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN;
+    if (use_short) {
+        const int cap = e->opt.step_cap ? e->opt.step_cap : default_cap(pen, window);
+        if (short_plan(e, pen, cigar, window, cap, max_len, &sp) != WFA_OK) use_short = false;
+    }
+    const bool persistent = use_short && schedule != WFA_SCHED_PLAIN;
+    const bool bucket = persistent && e->opt.bucket >= 0;
+    const bool graph = use_short && e->opt.use_graph >= 0 && schedule != WFA_SCHED_PLAIN &&
+                       (e->opt.use_graph > 0 || schedule == WFA_SCHED_AUTO ||
+                        schedule == WFA_SCHED_PERSISTENT);
+
+    // ---- buffers -----------------------------------------------------------
+    const bool ascii = io.enc == WFA_ASCII;
+    if (ascii) {
+        RCCHK(ws.ensure(ws.ws_p, (N + 1) * 8));
+        RCCHK(ws.ensure(ws.ws_t, (N + 1) * 8));
+        RCCHK(ws.ensure(ws.words_p, st.words_p * 8 + 8));
+        RCCHK(ws.ensure(ws.words_t, st.words_t * 8 + 8));
+        RCCHK(ws.ensure(ws.packed_pairs, N * sizeof(PairDesc)));
+        d.pairs = ws.packed_pairs.as<PairDesc>();
+        d.pw = ws.words_p.as<uint64_t>();
+        d.tw = ws.words_t.as<uint64_t>();
+    } else {
+        d.pairs = in_pairs;
+        d.pw = (const uint64_t*)in_p;
+        d.tw = (const uint64_t*)in_t;
+    }
+    RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64));
+    RCCHK(ws.ensure(ws.nruns, N * 4));
+    RCCHK(ws.ensure(ws.run_src, N * 8));
+    RCCHK(ws.ensure(ws.ovf_list, N * 4));
+    if (use_short && cigar) RCCHK(ws.ensure(ws.slots, (size_t)N * sp.slot_cap * 4));
+    if (bucket) {
+        RCCHK(ws.ensure(ws.order, N * 4));
+        RCCHK(ws.ensure(ws.keys, N * 4));
+        RCCHK(ws.ensure(ws.hist, BUCKET_KEYS * 4 + (BUCKET_KEYS + 1) * 8));
+    }
+    // exclusive scan of the bucket histogram, after its BUCKET_KEYS counters
+    uint64_t* cursor = bucket ? (uint64_t*)(ws.hist.as<uint8_t>() + BUCKET_KEYS * 4) : nullptr;
+    DevFlags* flags = ws.flags.as<DevFlags>();
+
+    int grid = 1;
+    if (use_short) {
+        const int gpb = short_groups_per_block(window, sp.block_threads);
+        if (persistent) {
+            int bpc = short_max_blocks_per_cu(window, cigar, sp.block_threads, sp.lds_per_block);
+            if (bpc < 1) bpc = 1;
+            grid = e->num_cus * bpc;
+            const size_t needed = (N + gpb - 1) / gpb;
+            if ((size_t)grid > needed) grid = (int)needed;
+        } else {
+            grid = (int)((N + gpb - 1) / gpb);
+        }
+    }
+
+    // ---- device phase (graph-capturable) ----------------------------------
+    auto device_phase = [&](hipStream_t q) -> int {
+        HIPCHK(launch_fill_u32((uint32_t*)flags, 0u, sizeof(DevFlags) / 4, q));
+        HIPCHK(launch_fill_u64((uint64_t*)&flags->err_pair, ~0ull, 1, q));
+        if (ascii) {
+            HIPCHK(launch_scan(SCAN_WORDS_P, in_pairs, N, ws.ws_p.as<uint64_t>(), ws.scan_tmp.ptr, q));
+            HIPCHK(launch_scan(SCAN_WORDS_T, in_pairs, N, ws.ws_t.as<uint64_t>(), ws.scan_tmp.ptr, q));
+            HIPCHK(launch_pack_pairs(in_pairs, N, (const uint8_t*)in_p, 0, ws.ws_p.as<uint64_t>(),
+                                     (st.max_p + 31) / 32, ws.words_p.as<uint64_t>(),
+                                     ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
+            HIPCHK(launch_pack_pairs(in_pairs, N, (const uint8_t*)in_t, 1, ws.ws_t.as<uint64_t>(),
+                                     (st.max_t + 31) / 32, ws.words_t.as<uint64_t>(),
+                                     ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
+        }
+        HIPCHK(launch_fill_u32(ws.nruns.as<uint32_t>(), 0u, N, q));
+        if (use_short) {
+            if (bucket) {
+                HIPCHK(launch_bucket_keys(d.pairs, N, ws.keys.as<uint32_t>(), ws.hist.as<uint32_t>(), q));
+                HIPCHK(launch_scan(SCAN_U32, ws.hist.ptr, BUCKET_KEYS, cursor, ws.scan_tmp.ptr, q));
+            }
+            ShortArgs a{};
+            a.pairs = d.pairs;
+            a.pw = d.pw;
+            a.tw = d.tw;
+            a.order = bucket ? ws.order.as<uint32_t>() : nullptr;
+            a.num = (uint32_t)N;
+            a.queue = &flags->queue;
+            a.pen = pen;
+            a.cap = sp.cap;
+            a.ring = sp.ring;
+            a.seq_words = sp.seq_words;
+            a.group_bytes = sp.group_bytes;
+            a.slot_cap = sp.slot_cap;
+            a.scores = d.scores;
+            a.nruns = ws.nruns.as<uint32_t>();
+            a.run_src = ws.run_src.as<uint64_t>();
+            a.slots = ws.slots.as<uint32_t>();
+            a.ovf_list = ws.ovf_list.as<uint32_t>();
+            a.ovf_count = &flags->ovf_count;
+            if (bucket)
+                HIPCHK(launch_bucket_scatter(ws.keys.as<uint32_t>(), N, cursor,
+                                             ws.order.as<uint32_t>(), q));
+            HIPCHK(launch_short(a, window, cigar, persistent, sp.block_threads, grid, q));
+        }
+        if (cigar && use_short) {
+            HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, q));
+            if (io.mem == WFA_DEVICE)
+                HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+                                      ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), d.offsets,
+                                      N, d.runs, d.capacity, q));
+        }
+        return WFA_OK;
+    };
+
+    HIPCHK(hipEventRecord(e->ev[0], s));
+    bool replayed = false;
+    if (graph) {
+        GraphKey key;
+        const void* ptrs[8] = {in_pairs, in_p, in_t, d.scores, d.runs, d.offsets,
+                               (const void*)(uintptr_t)ws.generation, nullptr};
+        for (int i = 0; i < 8; i++) key.p[i] = ptrs[i];
+        key.n = N;
+        const int ints[12] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g, window, sp.cap,
+                              (int)st.max_p, (int)st.max_t, grid, (int)(bucket ? 1 : 0) | (int)(d.capacity > 0x7fffffff ? 2 : 0)};
+        for (int i = 0; i < 12; i++) key.ints[i] = ints[i];
+        GraphEntry* hit = nullptr;
+        for (auto& g : e->graphs)
+            if (g.key == key) hit = &g;
+        if (!hit) {
+            GraphEntry g;
+            g.key = key;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            int rc = device_phase(s);
+            hipGraph_t gr = nullptr;
+            hipError_t ce = hipStreamEndCapture(s, &gr);
+            if (rc != WFA_OK || ce != hipSuccess || !gr) {
+                (void)hipGetLastError();
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc != WFA_OK ? rc : WFA_E_DEVICE;
+            }
+            g.graph = gr;
+            if (hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipGraphDestroy(gr);
+                return WFA_E_DEVICE;
+            }
+            if (e->graphs.size() >= 4) {
+                (void)hipGraphExecDestroy(e->graphs.front().exec);
+                (void)hipGraphDestroy(e->graphs.front().graph);
+                e->graphs.erase(e->graphs.begin());
+            }
+            e->graphs.push_back(g);
+            hit = &e->graphs.back();
+        }
+        HIPCHK(hipGraphLaunch(hit->exec, s));
+        replayed = true;
+    } else {
+        RCCHK(device_phase(s));
+    }
+    HIPCHK(hipEventRecord(e->ev[1], s));
+    DevFlags fl;
+    HIPCHK(hipMemcpyAsync(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (fl.err_pair != ~0ull) {
+        if (bad_pair) *bad_pair = (int64_t)fl.err_pair;
+        return WFA_E_ALPHABET;
+    }
+
+    // ---- general kernel for the rest ---------------------------------------
+    uint64_t general_done = 0, requeued = 0, gen_used = 0;
+    std::vector<uint32_t> pending;
+    if (!use_short) {
+        pending.resize(N);
+        for (size_t i = 0; i < N; i++) pending[i] = (uint32_t)i;
+    } else if (fl.ovf_count) {
+        pending.resize(fl.ovf_count);
+        HIPCHK(hipMemcpy(pending.data(), ws.ovf_list.ptr, fl.ovf_count * 4ull, hipMemcpyDeviceToHost));
+        std::sort(pending.begin(), pending.end());
+        requeued += fl.ovf_count;
+    }
+    HIPCHK(hipEventRecord(e->ev[2], s));
+    if (!pending.empty()) {
+        RCCHK(run_general(e, pen, cigar, d, st, pending, gen_used, s, &general_done, &requeued));
+        flags = ws.flags.as<DevFlags>();
+    }
+    HIPCHK(hipEventRecord(e->ev[3], s));
+
+    // ---- CIGAR offsets and compaction ------------------------------------------
+    uint64_t total = 0;
+    if (cigar) {
+        const bool rescan = !use_short || !pending.empty();
+        if (rescan) {
+            RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64));
+            HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, s));
+        }
+        HIPCHK(hipMemcpyAsync(&total, d.offsets + N, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (io.mem == WFA_HOST) {
+            RCCHK(ws.ensure(ws.out_runs, total * 4 + 4));
+            d.runs = ws.out_runs.as<uint32_t>();
+            d.capacity = total;
+        }
+        if ((rescan || io.mem == WFA_HOST) && total <= d.capacity)
+            HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), d.offsets, N,
+                                  d.runs, d.capacity, s));
+        if (cigar_needed) *cigar_needed = (size_t)total;
+    }
+    HIPCHK(hipEventRecord(e->ev[4], s));
+
+    // ---- results to the host --------------------------------------------------
+    if (io.mem == WFA_HOST) {
+        HIPCHK(hipMemcpyAsync(io.scores, d.scores, N * 4, hipMemcpyDeviceToHost, s));
+        if (cigar) {
+            HIPCHK(hipMemcpyAsync(io.offsets, d.offsets, (N + 1) * 8, hipMemcpyDeviceToHost, s));
+            if (total <= io.capacity && total)
+                HIPCHK(hipMemcpyAsync(io.runs, d.runs, total * 4, hipMemcpyDeviceToHost, s));
+        }
+    }
+    RCCHK(finish_user());
+
+    wfa_stats& L = e->last;
+    L.pairs = N;
+    L.general_pairs = general_done;
+    L.short_pairs = use_short ? N - (fl.ovf_count) : 0;
+    L.requeued = requeued;
+    L.cigar_runs = total;
+    L.window = use_short ? window : 0;
+    L.step_cap = use_short ? sp.cap : 0;
+    L.schedule = !use_short ? WFA_SCHED_GENERAL : (persistent ? WFA_SCHED_PERSISTENT : WFA_SCHED_PLAIN);
+    L.graph_replayed = replayed ? 1 : 0;
+    L.ms_align = ev_ms(e->ev[0], e->ev[1]);
+    L.ms_general = ev_ms(e->ev[2], e->ev[3]);
+    L.ms_compact = ev_ms(e->ev[3], e->ev[4]);
+    L.ms_total = now_ms() - t_start;
+
+    e->last_valid = cigar;
+    e->last_n = N;
+    e->last_mem = io.mem;
+    e->last_total = total;
+    if (cigar && total > io.capacity) return WFA_E_CAPACITY;
+    return WFA_OK;
+}

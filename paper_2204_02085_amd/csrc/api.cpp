@@ -1,0 +1,313 @@
+// C-ABI of the batched WFA library: validation, planning, device workspace
+// and the launch sequence of one batch.  All alignment arithmetic runs in the
+// HIP kernels (kernels.hip); this file only moves data and decides which
+// kernel gets which pairs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/wfa.h"
+#include "kernels.h"
+#include "internal.h"
+
+using namespace wfa;
+
+namespace {
+
+int gcd3(int a, int b, int c) { return std::gcd(std::gcd(a, b), c); }
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+int Workspace::ensure(Buf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (b.bytes >= bytes) return WFA_OK;
+    if (b.ptr) {
+        (void)hipFree(b.ptr);
+        total -= b.bytes;
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    generation++;
+    if (total + bytes > budget) return WFA_E_NOMEM;
+    if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        return WFA_E_NOMEM;
+    }
+    b.bytes = bytes;
+    total += bytes;
+    return WFA_OK;
+}
+
+void Workspace::release(Buf& b) {
+    if (b.ptr) {
+        (void)hipFree(b.ptr);
+        total -= b.bytes;
+    }
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+void Workspace::release_all() {
+    for (Buf* b : all()) release(*b);
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_bytes = 0;
+}
+
+int Workspace::ensure_pinned(size_t bytes) {
+    if (pinned_bytes >= bytes) return WFA_OK;
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_bytes = 0;
+    if (hipHostMalloc(&pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        pinned = nullptr;
+        return WFA_E_NOMEM;
+    }
+    pinned_bytes = bytes;
+    return WFA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx** out) {
+    if (!out) return WFA_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return WFA_E_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return WFA_E_DEVICE;
+    wfa_ctx* c = new wfa_ctx();
+    c->device = device;
+    c->ws.budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)64 << 30);
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return WFA_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+    if (c->num_cus <= 0) c->num_cus = 256;
+    for (auto& e : c->ev) (void)hipEventCreate(&e);
+    std::memset(&c->opt, 0, sizeof(c->opt));
+    std::memset(&c->last, 0, sizeof(c->last));
+    *out = c;
+    return WFA_OK;
+}
+
+extern "C" void wfa_ctx_destroy(wfa_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    graph_cache_clear(ctx);
+    ctx->ws.release_all();
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
+    if (!ctx) return WFA_E_INVAL;
+    if (!opt) {
+        std::memset(&ctx->opt, 0, sizeof(ctx->opt));
+        return WFA_OK;
+    }
+    if (opt->schedule < 0 || opt->schedule > WFA_SCHED_GENERAL) return WFA_E_INVAL;
+    if (opt->window && opt->window != 16 && opt->window != 32 && opt->window != 64 &&
+        opt->window != 128 && opt->window != 256)
+        return WFA_E_INVAL;
+    if (opt->step_cap < 0 || opt->step_cap > 4096) return WFA_E_INVAL;
+    if (opt->block_threads && (opt->block_threads < 64 || opt->block_threads > 256 ||
+                               opt->block_threads % 64))
+        return WFA_E_INVAL;
+    if (opt->general_pairs < 0) return WFA_E_INVAL;
+    ctx->opt = *opt;
+    return WFA_OK;
+}
+
+extern "C" int wfa_last_stats(const wfa_ctx* ctx, wfa_stats* out) {
+    if (!ctx || !out) return WFA_E_INVAL;
+    *out = ctx->last;
+    return WFA_OK;
+}
+
+extern "C" const char* wfa_strerror(int status) {
+    switch (status) {
+    case WFA_OK: return "ok";
+    case WFA_E_INVAL: return "invalid argument";
+    case WFA_E_ALPHABET: return "sequence byte outside ACGTacgt";
+    case WFA_E_NOMEM: return "HBM budget or device memory exhausted";
+    case WFA_E_CAPACITY: return "CIGAR buffer too small (see cigar_needed)";
+    case WFA_E_DEVICE: return "HIP runtime error";
+    case WFA_E_TOO_LONG: return "sequence longer than WFA_MAX_LENGTH";
+    case WFA_E_BUSY: return "not finished / queue full";
+    case WFA_E_NOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+// ---------------------------------------------------------------------------
+// planning helpers
+// ---------------------------------------------------------------------------
+int make_pen(const wfa_penalties& p, Pen* out) {
+    if (p.mismatch <= 0 || p.gap_extend <= 0 || p.gap_open < 0) return WFA_E_INVAL;
+    if (p.mismatch > (1 << 20) || p.gap_open > (1 << 20) || p.gap_extend > (1 << 20))
+        return WFA_E_INVAL;
+    const int g = gcd3(p.mismatch, p.gap_open, p.gap_extend);
+    out->g = g;
+    out->x = p.mismatch / g;
+    out->oe = (p.gap_open + p.gap_extend) / g;
+    out->e = p.gap_extend / g;
+    out->pre = std::max(out->x, std::max(out->oe, out->e));
+    if (out->pre + 1 > GENERAL_MAX_RING) return WFA_E_INVAL;
+    return WFA_OK;
+}
+
+// Steps a window of W diagonals can run before the wavefront can reach its
+// edge: a gap must open (oe steps) and then spread W/2 diagonals (e steps
+// each); a mismatch step beyond that adds nothing that stays in the window.
+int default_cap(const Pen& pen, int window) { return pen.oe + (window / 2) * pen.e + pen.x; }
+
+int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int cap, uint32_t max_len,
+               ShortPlan* sp) {
+    sp->window = window;
+    sp->cap = cap;
+    sp->seq_words = (int)((max_len + 31) / 32) + 1;
+    sp->ring = cigar ? cap + 1 + pen.pre : pen.pre + 1;
+    const int RW = window + 2;
+    const int rows_bytes = ((3 * sp->ring * RW * 2) + 15) & ~15;
+    sp->group_bytes = rows_bytes + 2 * sp->seq_words * 8;
+    sp->group_bytes = (sp->group_bytes + 15) & ~15;
+    // runs: every non-match op costs at least min(x, e) (in units of g)
+    const int minc = std::min(pen.x, pen.e);
+    sp->slot_cap = 2 * ((cap / minc) + 1) + 2;
+    int bt = ctx->opt.block_threads ? ctx->opt.block_threads : 256;
+    while (bt > 64 && (size_t)short_groups_per_block(window, bt) * sp->group_bytes > 64 * 1024)
+        bt -= 64;
+    if ((size_t)short_groups_per_block(window, bt) * sp->group_bytes > 64 * 1024) return WFA_E_NOMEM;
+    sp->block_threads = bt;
+    sp->lds_per_block = short_groups_per_block(window, bt) * sp->group_bytes;
+    return WFA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch entry points
+// ---------------------------------------------------------------------------
+extern "C" int wfa_align_batch(wfa_ctx* ctx, const void* patterns, const void* texts,
+                               const wfa_pair* pairs, size_t num_pairs, wfa_encoding enc,
+                               wfa_memspace mem, wfa_penalties pen, wfa_mode mode, int32_t* scores,
+                               uint32_t* cigar_runs, size_t cigar_capacity,
+                               uint64_t* cigar_offsets, size_t* cigar_needed, int64_t* bad_pair,
+                               void* stream) {
+    if (bad_pair) *bad_pair = -1;
+    if (!ctx) return WFA_E_INVAL;
+    BatchIO io{patterns, texts, pairs, num_pairs, enc, mem, pen, mode,
+               scores, cigar_runs, cigar_capacity, cigar_offsets};
+    return engine_align(ctx, io, (hipStream_t)stream, cigar_needed, bad_pair);
+}
+
+#define API_HIPCHK(x)                \
+    do {                             \
+        if ((x) != hipSuccess) {     \
+            (void)hipGetLastError(); \
+            return WFA_E_DEVICE;     \
+        }                            \
+    } while (0)
+
+extern "C" int wfa_copy_last_cigars(wfa_ctx* ctx, uint32_t* runs, size_t capacity,
+                                    uint64_t* offsets) {
+    if (!ctx || !ctx->last_valid) return WFA_E_INVAL;
+    if (capacity < ctx->last_total) return WFA_E_CAPACITY;
+    if (ctx->last_total && !runs) return WFA_E_INVAL;
+    Workspace& ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    const size_t N = ctx->last_n;
+    API_HIPCHK(hipSetDevice(ctx->device));
+    int rc = ws.ensure(ws.out_offsets, (N + 1) * 8);
+    if (rc == WFA_OK) rc = ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64);
+    if (rc != WFA_OK) return rc;
+    uint64_t* off = ws.out_offsets.as<uint64_t>();
+    API_HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, off, ws.scan_tmp.ptr, s));
+    if (ctx->last_mem == WFA_DEVICE) {
+        API_HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), off, N, runs,
+                                  capacity, s));
+        if (offsets)
+            API_HIPCHK(hipMemcpyAsync(offsets, off, (N + 1) * 8, hipMemcpyDeviceToDevice, s));
+    } else {
+        rc = ws.ensure(ws.out_runs, ctx->last_total * 4 + 4);
+        if (rc != WFA_OK) return rc;
+        API_HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), off, N,
+                                  ws.out_runs.as<uint32_t>(), ctx->last_total, s));
+        if (ctx->last_total)
+            API_HIPCHK(hipMemcpyAsync(runs, ws.out_runs.ptr, ctx->last_total * 4,
+                                      hipMemcpyDeviceToHost, s));
+        if (offsets)
+            API_HIPCHK(hipMemcpyAsync(offsets, off, (N + 1) * 8, hipMemcpyDeviceToHost, s));
+    }
+    API_HIPCHK(hipStreamSynchronize(s));
+    return WFA_OK;
+}
+
+extern "C" int wfa_pack2bit(wfa_ctx* ctx, const uint8_t* ascii, const uint64_t* starts,
+                            const uint32_t* lens, size_t count, uint64_t* words,
+                            size_t words_capacity, uint64_t* word_starts, size_t* total_words,
+                            int64_t* bad_index, void* stream) {
+    if (bad_index) *bad_index = -1;
+    if (total_words) *total_words = 0;
+    if (!ctx || (count && (!ascii || !starts || !lens || !word_starts))) return WFA_E_INVAL;
+    if (!count) return WFA_OK;
+    Workspace& ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    API_HIPCHK(hipSetDevice(ctx->device));
+    if (stream) {
+        API_HIPCHK(hipEventRecord(ctx->ev[7], (hipStream_t)stream));
+        API_HIPCHK(hipStreamWaitEvent(s, ctx->ev[7], 0));
+    }
+    int rc = ws.ensure(ws.scan_tmp, scan_temp_bytes(count + 1) + 64);
+    if (rc == WFA_OK) rc = ws.ensure(ws.flags, sizeof(DevFlags));
+    if (rc != WFA_OK) return rc;
+    API_HIPCHK(launch_scan(SCAN_WORDS_LEN, lens, count, word_starts, ws.scan_tmp.ptr, s));
+    uint64_t total = 0;
+    API_HIPCHK(hipMemcpyAsync(&total, word_starts + count, 8, hipMemcpyDeviceToHost, s));
+    API_HIPCHK(hipStreamSynchronize(s));
+    if (total_words) *total_words = total;
+    if (total > words_capacity || (total && !words)) return WFA_E_CAPACITY;
+    DevFlags* fl = ws.flags.as<DevFlags>();
+    API_HIPCHK(launch_fill_u64((uint64_t*)&fl->err_pair, ~0ull, 1, s));
+    API_HIPCHK(launch_pack_seqs(ascii, starts, lens, count, word_starts, total, words,
+                                &fl->err_pair, s));
+    unsigned long long err = 0;
+    API_HIPCHK(hipMemcpyAsync(&err, &fl->err_pair, 8, hipMemcpyDeviceToHost, s));
+    if (stream) {
+        API_HIPCHK(hipEventRecord(ctx->ev[6], s));
+        API_HIPCHK(hipStreamWaitEvent((hipStream_t)stream, ctx->ev[6], 0));
+    }
+    API_HIPCHK(hipStreamSynchronize(s));
+    if (err != ~0ull) {
+        if (bad_index) *bad_index = (int64_t)err;
+        return WFA_E_ALPHABET;
+    }
+    return WFA_OK;
+}

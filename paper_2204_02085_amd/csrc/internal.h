@@ -1,0 +1,119 @@
+// Library-internal state: device workspace, plans, engines and contexts.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <vector>
+
+#include "../../include/wfa.h"
+#include "kernels.h"
+
+struct Buf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    template <class T>
+    T* as() const {
+        return (T*)ptr;
+    }
+};
+
+// Device buffers of one engine.  Each grows on demand; the sum stays within
+// `budget` bytes (WFA_E_NOMEM otherwise).
+struct Workspace {
+    size_t budget = 0;
+    size_t total = 0;
+    uint64_t generation = 0;  // bumped whenever a buffer moves (invalidates graphs)
+    // planning / packing
+    Buf stats, flags, scan_tmp, ws_p, ws_t, words_p, words_t, packed_pairs;
+    // host-mode staging of inputs and outputs
+    Buf in_pairs, in_p, in_t, out_scores, out_runs, out_offsets;
+    // short kernel
+    Buf nruns, run_src, slots, ovf_list, order, keys, hist;
+    // general kernel
+    Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+
+    std::array<Buf*, 28> all() {
+        return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,
+                &words_t, &packed_pairs, &in_pairs, &in_p,      &in_t,      &out_scores,
+                &out_runs, &out_offsets, &nruns,   &run_src,     &slots,     &ovf_list,
+                &order,   &keys,       &hist,     &jobs,        &job_nruns, &job_offsets,
+                &fail_list, &arena,    &gen_runs, &gen_tmp};
+    }
+    int ensure(Buf& b, size_t bytes);
+    void release(Buf& b);
+    void release_all();
+    int ensure_pinned(size_t bytes);
+};
+
+// Device-side flags read back once per batch.
+struct DevFlags {
+    unsigned long long err_pair;  // first pair with a non-ACGT byte (~0: none)
+    uint32_t ovf_count;           // pairs the short kernel handed over
+    uint32_t queue;               // persistent queue head
+    uint32_t fail_count;          // general jobs whose slice was too small
+    uint32_t pad;
+    uint64_t total_runs;          // exclusive-scan total of per-pair runs
+};
+
+struct ShortPlan {
+    int window = 0, cap = 0, seq_words = 0, ring = 0, group_bytes = 0, slot_cap = 0;
+    int block_threads = 256, lds_per_block = 0;
+};
+
+struct GraphKey {
+    const void* p[8] = {};
+    size_t n = 0;
+    int ints[12] = {};
+    bool operator==(const GraphKey& o) const;
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// Everything one batch needs: a stream, a workspace, events and options.
+struct Engine {
+    int device = 0;
+    int num_cus = 256;
+    hipStream_t stream = nullptr;
+    Workspace ws;
+    hipEvent_t ev[8] = {};
+    wfa_options opt{};
+    wfa_stats last{};
+    std::vector<GraphEntry> graphs;
+    // state kept for wfa_copy_last_cigars
+    bool last_valid = false;
+    size_t last_n = 0;
+    int last_mem = 0;
+    uint64_t last_total = 0;
+};
+
+struct wfa_ctx : Engine {};
+
+// Batch inputs/outputs as given by the caller.
+struct BatchIO {
+    const void* patterns;
+    const void* texts;
+    const wfa_pair* pairs;
+    size_t n;
+    wfa_encoding enc;
+    wfa_memspace mem;
+    wfa_penalties pen;
+    wfa_mode mode;
+    int32_t* scores;
+    uint32_t* runs;
+    size_t capacity;
+    uint64_t* offsets;
+};
+
+int make_pen(const wfa_penalties& p, wfa::Pen* out);
+int default_cap(const wfa::Pen& pen, int window);
+int short_plan(Engine* ctx, const wfa::Pen& pen, bool cigar, int window, int cap,
+               uint32_t max_len, ShortPlan* sp);
+int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
+                 int64_t* bad_pair);
+void graph_cache_clear(Engine* e);

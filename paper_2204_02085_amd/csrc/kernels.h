@@ -1,0 +1,134 @@
+// Internal launch interface between the C-ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wfa {
+
+// Same layout as the public wfa_pair.
+struct PairDesc {
+    uint64_t p_start;
+    uint64_t t_start;
+    uint32_t p_len;
+    uint32_t t_len;
+};
+
+// Batch-wide facts gathered on the device before planning.
+struct BatchStats {
+    uint32_t max_p;
+    uint32_t max_t;
+    uint32_t max_absdiff;
+    uint32_t too_long;
+    uint64_t words_p;  // sum of ceil(p_len / 32)
+    uint64_t words_t;
+    uint64_t first_too_long;  // lowest pair index over the length limit, or ~0
+};
+
+// Largest pre + 1 (rows a step reads back, plus the current one) the kernels hold.
+constexpr int GENERAL_MAX_RING = 512;
+
+// Penalties divided by their gcd g: every reachable score is a multiple of g,
+// so the kernels step s' = s / g and report g * s'.
+struct Pen {
+    int x, oe, e;  // x/g, (o+e)/g, e/g
+    int g;
+    int pre;       // max(x, oe, e): rows a step reads back
+};
+
+// Arguments of the short-pair kernel (all device pointers).
+struct ShortArgs {
+    const PairDesc* pairs;
+    const uint64_t* pw;         // packed pattern words
+    const uint64_t* tw;         // packed text words
+    const uint32_t* order;      // queue position -> pair index (NULL: identity)
+    uint32_t num;               // pairs in the queue
+    uint32_t* queue;            // persistent: next queue position (device counter)
+    Pen pen;
+    int cap;                    // last step s' held
+    int ring;                   // rows held (cap + 1 + pre in CIGAR mode, pre + 1 otherwise)
+    int seq_words;              // 64-bit words of LDS per sequence
+    int group_bytes;            // LDS bytes per lane group
+    int slot_cap;               // runs per pair slot
+    int32_t* scores;            // [pairs]
+    uint32_t* nruns;            // [pairs] runs written
+    uint64_t* run_src;          // [pairs] where the reversed runs live
+    uint32_t* slots;            // [pairs * slot_cap] reversed runs
+    uint32_t* ovf_list;         // pairs the kernel could not hold
+    uint32_t* ovf_count;
+};
+
+// Arguments of the general (workgroup-per-pair, HBM arena) kernel.
+struct GeneralArgs {
+    const PairDesc* pairs;
+    const uint64_t* pw;
+    const uint64_t* tw;
+    const uint32_t* jobs;       // pair index per workgroup
+    uint32_t num_jobs;
+    Pen pen;
+    int cigar;
+    uint8_t* arena;             // num_jobs slices of slice_bytes
+    uint64_t slice_bytes;
+    int32_t* scores;
+    uint32_t* nruns;
+    uint64_t* run_src;          // offset (in uint32 words) of the job's runs in the arena
+    uint32_t* job_nruns;        // [num_jobs] runs of each finished job (0 if it failed)
+    uint32_t* fail_list;        // jobs whose slice was too small
+    uint32_t* fail_count;
+};
+
+// Kernel entry points (host-side launchers; all asynchronous on `s`).
+hipError_t launch_batch_stats(const PairDesc* pairs, size_t n, BatchStats* out, uint32_t max_len,
+                              hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+
+// Exclusive scan: out[i] = sum_{j<i} in(j), out[n] = total.  `in` selects a
+// per-pair quantity through `kind`.
+enum ScanKind { SCAN_WORDS_P = 0, SCAN_WORDS_T = 1, SCAN_U32 = 2, SCAN_WORDS_LEN = 3 };
+size_t scan_temp_bytes(size_t n);
+hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, void* temp,
+                       hipStream_t s);
+
+// ASCII -> PACKED2 for the pattern (which = 0) or text (which = 1) side of
+// `pairs`, writing new descriptors with word starts.  Sets *err_pair to the
+// lowest pair index holding a non-ACGT byte (initialise to UINT64_MAX).
+hipError_t launch_pack_pairs(const PairDesc* pairs, size_t n, const uint8_t* ascii, int which,
+                             const uint64_t* word_starts, uint32_t max_words, uint64_t* words,
+                             PairDesc* packed_pairs, unsigned long long* err_pair, hipStream_t s);
+// ASCII -> PACKED2 for independent sequences (public wfa_pack2bit);
+// word_starts[0..n] is the exclusive scan of ceil(len/32), total_words its end.
+hipError_t launch_pack_seqs(const uint8_t* ascii, const uint64_t* starts, const uint32_t* lens,
+                            size_t n, const uint64_t* word_starts, uint64_t total_words,
+                            uint64_t* words, unsigned long long* err_index, hipStream_t s);
+
+// Short-pair kernel.  window in {16, 32, 64, 128, 256}.
+hipError_t launch_short(const ShortArgs& a, int window, bool cigar, bool persistent,
+                        int block_threads, int grid, hipStream_t s);
+int short_groups_per_block(int window, int block_threads);
+int short_max_blocks_per_cu(int window, bool cigar, int block_threads, int lds_per_block);
+
+hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds,
+                          int lds_bytes, hipStream_t s);
+
+// Copy reversed runs from their staging places into the caller's buffer.
+// Nothing is written if offsets[n] exceeds `capacity`.
+hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const uint32_t* slots,
+                          const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
+                          uint32_t* out, uint64_t capacity, hipStream_t s);
+
+// Counting sort of pairs by expected work: keys + histogram, then (after an
+// exclusive scan of the histogram into `cursor`) the scatter into `order`.
+constexpr int BUCKET_KEYS = 4096;
+hipError_t launch_bucket_keys(const PairDesc* pairs, size_t n, uint32_t* keys, uint32_t* hist,
+                              hipStream_t s);
+hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, uint64_t* cursor, uint32_t* order,
+                                 hipStream_t s);
+// Gather runs of finished general jobs from the arena into gen_runs.
+hipError_t launch_gather_general(const uint32_t* jobs, size_t njobs, const uint32_t* nruns,
+                                 uint64_t* run_src, const uint8_t* arena, uint64_t slice_bytes,
+                                 const uint64_t* job_offsets, uint64_t gen_base,
+                                 uint32_t* gen_runs, hipStream_t s);
+hipError_t launch_scatter_scores_fail(const uint32_t* list, size_t n, int32_t* scores,
+                                      hipStream_t s);
+
+}  // namespace wfa

@@ -1,0 +1,1153 @@
+// HIP kernels for batched gap-affine WFA on gfx950 (CDNA4, wave64).
+//
+// Method: the wavefront algorithm (Marco-Sola et al., Bioinformatics 2021),
+// which the paper runs per read pair (Introduction and Methods).  For a
+// pattern P (n bases) and a text T (m bases), diagonal k = h - v and offset h:
+//   I_s[k] = max{M_{s-o-e}[k-1] + 1, I_{s-e}[k-1] + 1}
+//   D_s[k] = max{M_{s-o-e}[k+1],     D_{s-e}[k+1]}
+//   M_s[k] = max{M_{s-x}[k] + 1, I_s[k], D_s[k]},  then extend M_s[k]
+// A candidate offset c on diagonal k counts only if it is a real cell,
+// c <= m and c - k <= n; the alignment ends at the first s with
+// M_s[m-n] == m.  Scores step in units of g = gcd(x, o, e).
+//
+// Kernels:
+//   k_batch_stats   lengths and word counts of a batch (planning)
+//   k_scan_*        exclusive scan (word starts, CIGAR offsets)
+//   k_pack_*        ASCII -> 2-bit little-endian words, alphabet check
+//   k_short         short pairs: a lane group owns a fixed window of
+//                   diagonals (one or more per lane); all wavefront rows of a
+//                   pair live in LDS; one lane walks the backtrace
+//   k_general       any pair: one workgroup per pair, wavefront rows in a
+//                   per-pair slice of the HBM arena
+//   k_compact       reversed per-pair runs -> caller's CIGAR buffer
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace wfa {
+
+namespace {
+
+constexpr int NUL16 = -16384;          // NULL offset in int16 rows
+constexpr int NUL32 = -(1 << 30);      // NULL offset in int32 rows
+constexpr uint64_t GEN_BIT = 1ULL << 63;
+enum { OP_M = 0, OP_X = 1, OP_I = 2, OP_D = 3 };
+
+__device__ __forceinline__ void wave_sync() {
+    // LDS traffic of one wave executes in order; this only stops the compiler
+    // from moving LDS accesses across a hand-off between lanes.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 32 bases starting at base `pos` of a 2-bit little-endian sequence held as
+// 32-bit words S[] (16 bases each); dwords S[pos/16 .. pos/16 + 2] must exist.
+__device__ __forceinline__ uint64_t window32(const uint32_t* S, int pos) {
+    const int q = pos >> 4;
+    const uint32_t b = (uint32_t)(pos & 15) << 1;
+    const uint32_t w0 = S[q], w1 = S[q + 1], w2 = S[q + 2];
+    const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, b);
+    const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, b);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Matching bases at the start of two windows (32 if all match).
+__device__ __forceinline__ int common_prefix(uint64_t a, uint64_t b) {
+    const uint64_t d = a ^ b;
+    return d ? (__builtin_ctzll(d) >> 1) : 32;
+}
+
+__device__ __forceinline__ uint32_t cdiv32(uint32_t a) { return (a + 31u) >> 5; }
+
+// ---------------------------------------------------------------------------
+// planning
+// ---------------------------------------------------------------------------
+__global__ void k_batch_stats(const PairDesc* __restrict__ pairs, size_t n, BatchStats* out,
+                              uint32_t max_len) {
+    uint32_t mp = 0, mt = 0, md = 0, tl = 0;
+    unsigned long long wp = 0, wt = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t p = pairs[i].p_len, t = pairs[i].t_len;
+        mp = max(mp, p);
+        mt = max(mt, t);
+        md = max(md, p > t ? p - t : t - p);
+        if (p > max_len || t > max_len) {
+            tl = 1u;
+            atomicMin((unsigned long long*)&out->first_too_long, (unsigned long long)i);
+        }
+        wp += cdiv32(p);
+        wt += cdiv32(t);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mp = max(mp, (uint32_t)__shfl_xor((int)mp, off));
+        mt = max(mt, (uint32_t)__shfl_xor((int)mt, off));
+        md = max(md, (uint32_t)__shfl_xor((int)md, off));
+        tl |= (uint32_t)__shfl_xor((int)tl, off);
+        wp += __shfl_xor(wp, off);
+        wt += __shfl_xor(wt, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&out->max_p, mp);
+        atomicMax(&out->max_t, mt);
+        atomicMax(&out->max_absdiff, md);
+        atomicOr(&out->too_long, tl);
+        atomicAdd((unsigned long long*)&out->words_p, wp);
+        atomicAdd((unsigned long long*)&out->words_t, wt);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan: tile of SCAN_T threads x SCAN_ITEMS items
+// ---------------------------------------------------------------------------
+constexpr int SCAN_T = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_T * SCAN_ITEMS;
+
+__device__ __forceinline__ uint64_t scan_item(ScanKind kind, const void* in, size_t i) {
+    switch (kind) {
+    case SCAN_WORDS_P: return cdiv32(((const PairDesc*)in)[i].p_len);
+    case SCAN_WORDS_T: return cdiv32(((const PairDesc*)in)[i].t_len);
+    case SCAN_WORDS_LEN: return cdiv32(((const uint32_t*)in)[i]);
+    default: return ((const uint32_t*)in)[i];
+    }
+}
+
+// inclusive scan of one value per thread over the block; returns the block total
+__device__ uint64_t block_inclusive_scan(uint64_t& v) {
+    __shared__ uint64_t wsum[SCAN_T / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (int w = 0; w < SCAN_T / 64; w++) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    v += before;
+    __syncthreads();
+    return total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_partial(ScanKind kind, const void* in, size_t n,
+                                                         uint64_t* block_sums) {
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; j++)
+        if (base + j < n) s += scan_item(kind, in, base + j);
+    uint64_t total = block_inclusive_scan(s);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(uint64_t* block_sums, size_t nb,
+                                                        uint64_t* out_total) {
+    uint64_t carry = 0;
+    for (size_t base = 0; base < nb; base += SCAN_T) {
+        const size_t i = base + threadIdx.x;
+        uint64_t v = i < nb ? block_sums[i] : 0;
+        const uint64_t mine = v;
+        uint64_t total = block_inclusive_scan(v);
+        if (i < nb) block_sums[i] = carry + v - mine;  // exclusive
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_final(ScanKind kind, const void* in, size_t n,
+                                                       const uint64_t* block_sums, uint64_t* out) {
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t vals[SCAN_ITEMS];
+    uint64_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        vals[j] = base + j < n ? scan_item(kind, in, base + j) : 0;
+        s += vals[j];
+    }
+    uint64_t incl = s;
+    block_inclusive_scan(incl);
+    uint64_t run = block_sums[blockIdx.x] + incl - s;
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        if (base + j < n) out[base + j] = run;
+        run += vals[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ASCII -> 2-bit packing.  One thread per output word (32 bases).
+// ---------------------------------------------------------------------------
+// codes of the 4 bytes of x (A/a=0, C/c=1, G/g=2, T/t=3) in 8 bits, and a
+// validity flag for the first `cnt` (0..4) bytes
+__device__ __forceinline__ uint32_t pack4(uint32_t x, int cnt, bool& ok) {
+    for (int b = 0; b < 4; b++) {
+        if (b < cnt) {
+            const uint32_t c = ((x >> (8 * b)) & 0xFFu) | 0x20u;
+            const uint32_t d = (c - 0x61u) & 0xFFu;  // 'a' -> 0, 'c' -> 2, 'g' -> 6, 't' -> 19
+            ok = ok && d < 20u && ((0x80045u >> d) & 1u);
+        }
+    }
+    uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t keep = cnt >= 4 ? 0xFFFFFFFFu : ((1u << (8 * cnt)) - 1u);
+    c &= keep;
+    c = (c | (c >> 6)) & 0x000F000Fu;
+    c = (c | (c >> 12)) & 0xFFu;
+    return c;
+}
+
+__device__ __forceinline__ uint64_t pack_word(const uint8_t* __restrict__ ascii, uint64_t b0,
+                                              int cnt, bool& ok) {
+    // aligned dwords covering [b0, b0 + cnt); only dwords holding a byte of the
+    // range are read
+    const uintptr_t first = (uintptr_t)ascii + b0;
+    const uintptr_t a0 = first & ~(uintptr_t)3;
+    const uintptr_t last = (first + cnt - 1) >> 2;
+    const uint32_t* src = (const uint32_t*)a0;
+    uint32_t raw[9];
+#pragma unroll
+    for (int d = 0; d < 9; d++) raw[d] = ((a0 >> 2) + d <= last) ? src[d] : 0u;
+    const uint32_t sh = (uint32_t)(first & 3);
+    uint64_t word = 0;
+#pragma unroll
+    for (int d = 0; d < 8; d++) {
+        const uint32_t x = __builtin_amdgcn_alignbyte(raw[d + 1], raw[d], sh);
+        int c = cnt - 4 * d;
+        c = c < 0 ? 0 : (c > 4 ? 4 : c);
+        word |= (uint64_t)pack4(x, c, ok) << (8 * d);
+    }
+    return word;
+}
+
+__global__ void k_pack_pairs(const PairDesc* __restrict__ pairs, size_t n,
+                             const uint8_t* __restrict__ ascii, int which,
+                             const uint64_t* __restrict__ word_starts, uint32_t max_words,
+                             uint64_t* __restrict__ words, PairDesc* __restrict__ packed,
+                             unsigned long long* err_pair) {
+    const size_t total = n * (size_t)max_words;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = t / max_words;
+        const uint32_t w = (uint32_t)(t - i * max_words);
+        const PairDesc d = pairs[i];
+        const uint32_t len = which ? d.t_len : d.p_len;
+        const uint64_t start = which ? d.t_start : d.p_start;
+        if (w == 0) {
+            if (which) {
+                packed[i].t_start = word_starts[i];
+                packed[i].t_len = d.t_len;
+            } else {
+                packed[i].p_start = word_starts[i];
+                packed[i].p_len = d.p_len;
+            }
+        }
+        if (w >= cdiv32(len)) continue;
+        int cnt = (int)min(32u, len - 32u * w);
+        bool ok = true;
+        words[word_starts[i] + w] = pack_word(ascii, start + 32ull * w, cnt, ok);
+        if (!ok) atomicMin(err_pair, (unsigned long long)i);
+    }
+}
+
+__global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* __restrict__ starts,
+                            const uint32_t* __restrict__ lens, size_t n,
+                            const uint64_t* __restrict__ word_starts, uint64_t total_words,
+                            uint64_t* __restrict__ words, unsigned long long* err_index) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total_words;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        // sequence holding word t: the last i with word_starts[i] <= t
+        size_t lo = 0, hi = n;  // invariant: word_starts[lo] <= t < word_starts[hi]
+        while (hi - lo > 1) {
+            const size_t mid = (lo + hi) >> 1;
+            if (word_starts[mid] <= t) lo = mid; else hi = mid;
+        }
+        const size_t i = lo;
+        const uint32_t w = (uint32_t)(t - word_starts[i]);
+        const uint32_t len = lens[i];
+        int cnt = (int)min(32u, len - 32u * w);
+        bool ok = true;
+        words[t] = pack_word(ascii, starts[i] + 32ull * w, cnt, ok);
+        if (!ok) atomicMin(err_index, (unsigned long long)i);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Short-pair kernel.
+//
+// A lane group of G lanes aligns one pair; 64/G groups share a wave and step
+// through scores together.  Lane l of a group owns diagonals
+// kmin + l + d*G (d < DPL), a window of W = G*DPL diagonals centred between
+// diagonal 0 and the target diagonal m-n.  Row r of the LDS history holds,
+// for one score step, the int16 offsets of M (after extension), I and D on
+// the W diagonals plus a NULL pad on each side, so neighbouring diagonals
+// are read without bounds checks.  Rows for steps -pre..-1 hold NULL.
+//
+// A pair leaves the kernel through the overflow list (and is finished by the
+// general kernel) when its wavefront touches a window edge before reaching
+// the end, when it needs more than `cap` steps, when a sequence does not fit
+// the LDS words, or when its runs overflow the slot.  Values are never
+// computed from an incomplete window.
+// ---------------------------------------------------------------------------
+template <int G, int DPL, bool CIGAR>
+__global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int W = G * DPL;
+    constexpr int RW = W + 2;
+    constexpr int GPW = 64 / G;
+    constexpr uint64_t GMASK = G == 64 ? ~0ULL : ((1ULL << G) - 1ULL);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int grp = lane / G;
+    const int gl = lane - grp * G;
+    const int gshift = grp * G;
+
+    unsigned char* gbase = lds + (size_t)(wave * GPW + grp) * a.group_bytes;
+    int16_t* RM = (int16_t*)gbase;
+    int16_t* RI = RM + a.ring * RW;
+    int16_t* RD = RI + a.ring * RW;
+    const int rows_bytes = ((3 * a.ring * RW * 2) + 15) & ~15;
+    uint64_t* SP64 = (uint64_t*)(gbase + rows_bytes);
+    uint64_t* ST64 = SP64 + a.seq_words;
+    const uint32_t* SP = (const uint32_t*)SP64;
+    const uint32_t* ST = (const uint32_t*)ST64;
+
+    const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
+    const int ring = a.ring;
+
+    // side pads of every row stay NULL for the life of the kernel
+    for (int r = gl; r < ring; r += G) {
+        RM[r * RW] = RM[r * RW + RW - 1] = (int16_t)NUL16;
+        RI[r * RW] = RI[r * RW + RW - 1] = (int16_t)NUL16;
+        RD[r * RW] = RD[r * RW + RW - 1] = (int16_t)NUL16;
+    }
+
+    for (uint32_t iter = 0;; iter++) {
+        uint32_t qbase;
+        if (persistent) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(a.queue, (uint32_t)GPW);
+            qbase = __builtin_amdgcn_readfirstlane(t);
+        } else {
+            if (iter) break;
+            qbase = (blockIdx.x * wpb + wave) * GPW;
+        }
+        if (qbase >= a.num) break;
+        const uint32_t q = qbase + grp;
+        const bool active = q < a.num;
+        uint32_t pair = 0;
+        int n = 0, m = 0;
+        uint64_t ps = 0, ts = 0;
+        bool active_ok = active;
+        if (active) {
+            pair = a.order ? a.order[q] : q;
+            if (pair >= a.num) {  // a corrupt permutation must not fault: skip the entry
+                active_ok = false;
+                pair = 0;
+            }
+        }
+        if (active_ok) {
+            const PairDesc d = a.pairs[pair];
+            n = (int)d.p_len;
+            m = (int)d.t_len;
+            ps = d.p_start;
+            ts = d.t_start;
+        }
+        const int kt = m - n;
+        const int kmin = (kt >> 1) - W / 2;
+        const int nwp = (n + 31) >> 5, nwt = (m + 31) >> 5;
+        // 0 running, 1 finished or idle, 2 overflow
+        int st = active_ok ? 0 : 1;
+        if (active_ok && !(kmin <= 0 && 0 < kmin + W && kmin <= kt && kt < kmin + W &&
+                        nwp + 1 <= a.seq_words && nwt + 1 <= a.seq_words))
+            st = 2;
+
+        // stage both sequences (zero past their ends)
+        for (int w = gl; w < a.seq_words; w += G) {
+            SP64[w] = (st == 0 && w < nwp) ? a.pw[ps + w] : 0ULL;
+            ST64[w] = (st == 0 && w < nwt) ? a.tw[ts + w] : 0ULL;
+        }
+        // rows of steps -pre .. -1
+        for (int idx = gl; idx < PRE * W; idx += G) {
+            const int r = idx / W, j = idx - (idx / W) * W;
+            RM[r * RW + 1 + j] = (int16_t)NUL16;
+            RI[r * RW + 1 + j] = (int16_t)NUL16;
+            RD[r * RW + 1 + j] = (int16_t)NUL16;
+        }
+        wave_sync();
+
+        int lim[DPL];
+#pragma unroll
+        for (int d = 0; d < DPL; d++) {
+            const int k = kmin + gl + d * G;
+            lim[d] = min(m, n + k);
+        }
+        const int jt = kt - kmin;  // window index of the target diagonal
+        int S = 0;
+        int cur = PRE;             // row of step 0
+        for (int s = 0;; s++) {
+            const uint64_t running = __ballot(st == 0);
+            if (running == 0) break;
+            const bool run = st == 0;
+            int Mv[DPL], Iv[DPL], Dv[DPL];
+            if (s == 0) {
+#pragma unroll
+                for (int d = 0; d < DPL; d++) {
+                    const int k = kmin + gl + d * G;
+                    Mv[d] = (run && k == 0) ? 0 : NUL16;
+                    Iv[d] = NUL16;
+                    Dv[d] = NUL16;
+                }
+            } else {
+                cur = cur + 1 == ring ? 0 : cur + 1;
+                int ix = cur - X, io = cur - OE, ie = cur - E;
+                ix += ix < 0 ? ring : 0;
+                io += io < 0 ? ring : 0;
+                ie += ie < 0 ? ring : 0;
+                const int16_t* mx = RM + ix * RW + 1;
+                const int16_t* mo = RM + io * RW + 1;
+                const int16_t* il = RI + ie * RW + 1;
+                const int16_t* dr = RD + ie * RW + 1;
+#pragma unroll
+                for (int d = 0; d < DPL; d++) {
+                    const int j = gl + d * G;
+                    const int L = lim[d];
+                    const int a1 = mo[j - 1] + 1, a2 = il[j - 1] + 1;
+                    const int iv = max(a1 <= L ? a1 : NUL16, a2 <= L ? a2 : NUL16);
+                    const int c1 = mo[j + 1], c2 = dr[j + 1];
+                    const int dv = max(c1 <= L ? c1 : NUL16, c2 <= L ? c2 : NUL16);
+                    const int xv = mx[j] + 1;
+                    Mv[d] = max(max(xv <= L ? xv : NUL16, iv), dv);
+                    Iv[d] = iv;
+                    Dv[d] = dv;
+                }
+            }
+            // extend along matches, 32 bases per compare
+            int hv[DPL];
+            bool go[DPL];
+            bool any_go = false;
+#pragma unroll
+            for (int d = 0; d < DPL; d++) {
+                const int k = kmin + gl + d * G;
+                hv[d] = Mv[d];
+                go[d] = run && hv[d] >= 0 && hv[d] - k < n && hv[d] < m;
+                any_go |= go[d];
+            }
+            while (__ballot(any_go)) {
+                any_go = false;
+#pragma unroll
+                for (int d = 0; d < DPL; d++) {
+                    if (go[d]) {
+                        const int k = kmin + gl + d * G;
+                        const int h = hv[d], v = h - k;
+                        int r = common_prefix(window32(SP, v), window32(ST, h));
+                        r = min(r, min(n - v, m - h));
+                        hv[d] = h + r;
+                        go[d] = r == 32 && v + r < n && h + r < m;
+                        any_go |= go[d];
+                    }
+                }
+            }
+            // store the step's rows
+            bool term = false, edge = false;
+#pragma unroll
+            for (int d = 0; d < DPL; d++) {
+                const int j = gl + d * G;
+                if (run) {
+                    RM[cur * RW + 1 + j] = (int16_t)hv[d];
+                    RI[cur * RW + 1 + j] = (int16_t)Iv[d];
+                    RD[cur * RW + 1 + j] = (int16_t)Dv[d];
+                }
+                term |= (j == jt) && hv[d] == m;
+                edge |= (j == 0 || j == W - 1) && (hv[d] >= 0 || Iv[d] >= 0 || Dv[d] >= 0);
+            }
+            const bool gterm = ((__ballot(run && term) >> gshift) & GMASK) != 0;
+            const bool gedge = ((__ballot(run && edge) >> gshift) & GMASK) != 0;
+            if (run) {
+                if (gterm) {
+                    st = 1;
+                    S = s;
+                } else if (gedge || s >= a.cap) {
+                    st = 2;
+                }
+            }
+            wave_sync();
+        }
+
+        // results
+        if (active_ok && gl == 0) {
+            bool overflow = st == 2;
+            if (!overflow && CIGAR) {
+                uint32_t* out = a.slots + (uint64_t)pair * a.slot_cap;
+                int nr = 0, cop = -1, clen = 0;
+                const int cap_runs = a.slot_cap;
+                auto emit = [&](int op, int len) {
+                    if (len <= 0) return;
+                    if (op == cop) {
+                        clen += len;
+                    } else {
+                        if (cop >= 0) {
+                            if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                            nr++;
+                        }
+                        cop = op;
+                        clen = len;
+                    }
+                };
+                int s = S, k = kt, h = m, comp = 0;
+                int guard = 2 * S + 4;  // every two iterations lower s by at least 1
+                // rows of step s live at index s + PRE (no wrap in CIGAR mode)
+                for (;;) {
+                    const int j = k - kmin;
+                    if (s < 0 || j < 0 || j >= W || h < 0 || --guard < 0) {
+                        overflow = true;  // inconsistent walk: leave it to the general kernel
+                        break;
+                    }
+                    if (comp == 0) {
+                        int h0, xv = NUL16, iv = NUL16, dv = NUL16;
+                        if (s == 0) {
+                            h0 = 0;
+                        } else {
+                            const int L = min(m, n + k);
+                            xv = RM[(s - X + PRE) * RW + 1 + j] + 1;
+                            if (xv < 0 || xv > L) xv = NUL16;
+                            iv = RI[(s + PRE) * RW + 1 + j];
+                            dv = RD[(s + PRE) * RW + 1 + j];
+                            h0 = max(xv, max(iv, dv));
+                        }
+                        emit(OP_M, h - h0);
+                        h = h0;
+                        if (s == 0) break;
+                        if (xv >= 0 && xv == h0) {
+                            emit(OP_X, 1);
+                            s -= X;
+                            h -= 1;
+                        } else if (iv == h0) {
+                            comp = 1;
+                        } else {
+                            comp = 2;
+                        }
+                    } else if (comp == 1) {
+                        emit(OP_I, 1);
+                        const int L = min(m, n + k);
+                        const int a1 = RM[(s - OE + PRE) * RW + j] + 1;  // diagonal k-1
+                        if (a1 >= 0 && a1 <= L && a1 == h) {
+                            s -= OE;
+                            comp = 0;
+                        } else {
+                            s -= E;
+                        }
+                        k -= 1;
+                        h -= 1;
+                    } else {
+                        emit(OP_D, 1);
+                        const int L = min(m, n + k);
+                        const int c1 = RM[(s - OE + PRE) * RW + 2 + j];  // diagonal k+1
+                        if (c1 >= 0 && c1 <= L && c1 == h) {
+                            s -= OE;
+                            comp = 0;
+                        } else {
+                            s -= E;
+                        }
+                        k += 1;
+                    }
+                }
+                if (cop >= 0) {
+                    if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    nr++;
+                }
+                if (overflow || nr > cap_runs) {
+                    overflow = true;
+                } else {
+                    a.nruns[pair] = (uint32_t)nr;
+                    a.run_src[pair] = (uint64_t)pair * a.slot_cap;
+                }
+            }
+            if (overflow) {
+                const uint32_t at = atomicAdd(a.ovf_count, 1u);
+                a.ovf_list[at] = pair;
+            } else {
+                a.scores[pair] = S * a.pen.g;
+                if (!CIGAR) a.nruns[pair] = 0;
+            }
+        }
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General kernel: one workgroup per pair, any length, any score.
+//
+// Slice layout (bytes): wavefront rows grow up from 0; in CIGAR mode the
+// step table {lo, hi, offset} grows down from the end.  In score mode the
+// rows form a ring of pre+1 full-width rows (k in [-n, m]).
+// ---------------------------------------------------------------------------
+struct RowMeta {
+    int lo, hi;
+    long long off;  // byte offset of the row in the slice; -1: no wavefront
+};
+
+template <bool SEQ_LDS>
+struct SeqView {
+    const uint32_t* p;
+    const uint32_t* t;
+    int np32, nt32;  // valid dwords (global variant bounds reads)
+    __device__ __forceinline__ uint32_t P(int q) const {
+        if (SEQ_LDS) return p[q];
+        return q < np32 ? p[q] : 0u;
+    }
+    __device__ __forceinline__ uint32_t T(int q) const {
+        if (SEQ_LDS) return t[q];
+        return q < nt32 ? t[q] : 0u;
+    }
+    __device__ __forceinline__ uint64_t winP(int pos) const {
+        const int q = pos >> 4;
+        const uint32_t b = (uint32_t)(pos & 15) << 1;
+        const uint32_t w0 = P(q), w1 = P(q + 1), w2 = P(q + 2);
+        return ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, b) << 32) |
+               __builtin_amdgcn_alignbit(w1, w0, b);
+    }
+    __device__ __forceinline__ uint64_t winT(int pos) const {
+        const int q = pos >> 4;
+        const uint32_t b = (uint32_t)(pos & 15) << 1;
+        const uint32_t w0 = T(q), w1 = T(q + 1), w2 = T(q + 2);
+        return ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, b) << 32) |
+               __builtin_amdgcn_alignbit(w1, w0, b);
+    }
+};
+
+template <bool SEQ_LDS>
+__device__ __forceinline__ int extend_general(const SeqView<SEQ_LDS>& sv, int n, int m, int k,
+                                              int h) {
+    int v = h - k;
+    while (v < n && h < m) {
+        int r = common_prefix(sv.winP(v), sv.winT(h));
+        r = min(r, min(n - v, m - h));
+        v += r;
+        h += r;
+        if (r < 32) break;
+    }
+    return h;
+}
+
+template <bool SEQ_LDS>
+__global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int MAXR = GENERAL_MAX_RING;  // metadata ring (pre + 1 <= MAXR)
+    __shared__ RowMeta meta[MAXR];
+    __shared__ int sh_flag;
+    __shared__ int sh_fail;
+
+    const uint32_t job = blockIdx.x;
+    if (job >= a.num_jobs) return;
+    const uint32_t pair = a.jobs[job];
+    const PairDesc desc = a.pairs[pair];
+    const int n = (int)desc.p_len, m = (int)desc.t_len;
+    const int tid = threadIdx.x, BT = blockDim.x;
+    const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
+    const int R = PRE + 1;
+    const int kt = m - n;
+    unsigned char* slice = a.arena + (uint64_t)job * a.slice_bytes;
+    const long long slice_bytes = (long long)a.slice_bytes;
+
+    SeqView<SEQ_LDS> sv;
+    const int nwp = (n + 31) >> 5, nwt = (m + 31) >> 5;
+    if (SEQ_LDS) {
+        uint64_t* p64 = (uint64_t*)lds;
+        uint64_t* t64 = p64 + nwp + 1;
+        for (int w = tid; w <= nwp; w += BT) p64[w] = w < nwp ? a.pw[desc.p_start + w] : 0ULL;
+        for (int w = tid; w <= nwt; w += BT) t64[w] = w < nwt ? a.tw[desc.t_start + w] : 0ULL;
+        sv.p = (const uint32_t*)p64;
+        sv.t = (const uint32_t*)t64;
+    } else {
+        sv.p = (const uint32_t*)(a.pw + desc.p_start);
+        sv.t = (const uint32_t*)(a.tw + desc.t_start);
+    }
+    sv.np32 = 2 * nwp;
+    sv.nt32 = 2 * nwt;
+    for (int r = tid; r < MAXR; r += BT) meta[r] = RowMeta{0, -1, -1};
+    if (tid == 0) {
+        sh_flag = 0;
+        sh_fail = 0;
+    }
+    __syncthreads();
+
+    // step table (CIGAR mode) lives at the end of the slice, entry s at
+    // slice_bytes - 16 * (s + 1)
+    RowMeta* table = (RowMeta*)(slice + slice_bytes) - 1;
+    const long long full_row = 3LL * 4 * (n + m + 1);
+    long long bump = 0;
+    // a hard bound on steps: deleting all of P and inserting all of T
+    const long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
+
+    int S = -1;
+    for (long long s = 0;; s++) {
+        if (s > max_score_g) {
+            if (tid == 0) sh_fail = 2;
+            break;
+        }
+        int lo, hi;
+        bool present;
+        if (s == 0) {
+            lo = hi = 0;
+            present = true;
+        } else {
+            lo = 1 << 30;
+            hi = -(1 << 30);
+            const long long src[3] = {s - X, s - OE, s - E};
+            for (int i = 0; i < 3; i++) {
+                if (src[i] < 0) continue;
+                const RowMeta& mm = meta[src[i] % R];
+                if (mm.off < 0) continue;
+                lo = min(lo, mm.lo);
+                hi = max(hi, mm.hi);
+            }
+            present = lo <= hi;
+            lo = max(lo - 1, -n);
+            hi = min(hi + 1, m);
+        }
+        long long off = -1;
+        if (present) {
+            const int w = hi - lo + 1;
+            if (a.cigar) {
+                off = bump;
+                bump += ((3LL * 4 * w) + 15) & ~15LL;
+                if (bump > slice_bytes - 16LL * (s + 2)) {
+                    if (tid == 0) sh_fail = 1;
+                    break;
+                }
+            } else {
+                off = (s % R) * full_row;
+                if (R * full_row > slice_bytes) {
+                    if (tid == 0) sh_fail = 1;
+                    break;
+                }
+            }
+            int* rowM = (int*)(slice + off);
+            int* rowI = rowM + w;
+            int* rowD = rowI + w;
+            for (int k = lo + tid; k <= hi; k += BT) {
+                int mval;
+                int ival = NUL32, dval = NUL32;
+                if (s == 0) {
+                    mval = 0;
+                } else {
+                    const int L = min(m, n + k);
+                    auto get = [&](long long ss, int comp, int kk) -> int {
+                        if (ss < 0) return NUL32;
+                        const RowMeta& mm = meta[ss % R];
+                        if (mm.off < 0 || kk < mm.lo || kk > mm.hi) return NUL32;
+                        const int ww = mm.hi - mm.lo + 1;
+                        const int* base = (const int*)(slice + mm.off) + comp * ww;
+                        return base[kk - mm.lo];
+                    };
+                    const int mo_l = get(s - OE, 0, k - 1), i_l = get(s - E, 1, k - 1);
+                    const int mo_r = get(s - OE, 0, k + 1), d_r = get(s - E, 2, k + 1);
+                    const int mx = get(s - X, 0, k);
+                    const int a1 = mo_l == NUL32 ? NUL32 : mo_l + 1;
+                    const int a2 = i_l == NUL32 ? NUL32 : i_l + 1;
+                    ival = max(a1 >= 0 && a1 <= L ? a1 : NUL32, a2 >= 0 && a2 <= L ? a2 : NUL32);
+                    dval = max(mo_r >= 0 && mo_r <= L ? mo_r : NUL32,
+                               d_r >= 0 && d_r <= L ? d_r : NUL32);
+                    const int xv = mx == NUL32 ? NUL32 : mx + 1;
+                    mval = max(max(xv >= 0 && xv <= L ? xv : NUL32, ival), dval);
+                }
+                if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
+                rowM[k - lo] = mval;
+                rowI[k - lo] = ival;
+                rowD[k - lo] = dval;
+                if (k == kt && mval == m) sh_flag = 1;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            meta[s % R] = RowMeta{lo, hi, off};
+            if (a.cigar) table[-s] = RowMeta{lo, hi, off};
+        }
+        __syncthreads();
+        if (sh_flag) {
+            S = (int)s;
+            break;
+        }
+    }
+    __syncthreads();
+    if (sh_fail == 2) {  // step bound exceeded: report an invalid score, never loop
+        if (tid == 0) {
+            a.scores[pair] = -2;
+            a.nruns[pair] = 0;
+        }
+        return;
+    }
+    if (sh_fail) {
+        if (tid == 0) {
+            const uint32_t at = atomicAdd(a.fail_count, 1u);
+            a.fail_list[at] = pair;
+        }
+        return;
+    }
+    if (!a.cigar) {
+        if (tid == 0) {
+            a.scores[pair] = S * a.pen.g;
+            a.nruns[pair] = 0;
+        }
+        return;
+    }
+    // backtrace by one thread over the step table and rows
+    if (tid != 0) return;
+    uint32_t* out = (uint32_t*)(slice + bump);
+    const long long table_bottom = slice_bytes - 16LL * (S + 1);
+    const long long cap_runs = (table_bottom - bump) / 4;
+    long long nr = 0;
+    int cop = -1;
+    long long clen = 0;
+    auto emit = [&](int op, long long len) {
+        if (len <= 0) return;
+        if (op == cop) {
+            clen += len;
+        } else {
+            if (cop >= 0) {
+                if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                nr++;
+            }
+            cop = op;
+            clen = len;
+        }
+    };
+    auto get = [&](long long ss, int comp, int kk) -> int {
+        if (ss < 0) return NUL32;
+        const RowMeta mm = table[-ss];
+        if (mm.off < 0 || kk < mm.lo || kk > mm.hi) return NUL32;
+        const int ww = mm.hi - mm.lo + 1;
+        return ((const int*)(slice + mm.off))[comp * ww + kk - mm.lo];
+    };
+    long long s = S;
+    int k = kt, h = m, comp = 0;
+    long long guard = 2LL * S + 4;
+    for (;;) {
+        if (s < 0 || h < 0 || --guard < 0) {  // inconsistent walk: invalid score, no loop
+            a.scores[pair] = -2;
+            a.nruns[pair] = 0;
+            return;
+        }
+        if (comp == 0) {
+            int h0, xv = NUL32, iv = NUL32, dv = NUL32;
+            if (s == 0) {
+                h0 = 0;
+            } else {
+                const int L = min(m, n + k);
+                const int mx = get(s - X, 0, k);
+                xv = mx == NUL32 ? NUL32 : mx + 1;
+                if (xv < 0 || xv > L) xv = NUL32;
+                iv = get(s, 1, k);
+                dv = get(s, 2, k);
+                h0 = max(xv, max(iv, dv));
+            }
+            emit(OP_M, h - h0);
+            h = h0;
+            if (s == 0) break;
+            if (xv >= 0 && xv == h0) {
+                emit(OP_X, 1);
+                s -= X;
+                h -= 1;
+            } else if (iv == h0) {
+                comp = 1;
+            } else {
+                comp = 2;
+            }
+        } else if (comp == 1) {
+            emit(OP_I, 1);
+            const int L = min(m, n + k);
+            const int mo = get(s - OE, 0, k - 1);
+            const int a1 = mo == NUL32 ? NUL32 : mo + 1;
+            if (a1 >= 0 && a1 <= L && a1 == h) {
+                s -= OE;
+                comp = 0;
+            } else {
+                s -= E;
+            }
+            k -= 1;
+            h -= 1;
+        } else {
+            emit(OP_D, 1);
+            const int L = min(m, n + k);
+            const int c1 = get(s - OE, 0, k + 1);
+            if (c1 >= 0 && c1 <= L && c1 == h) {
+                s -= OE;
+                comp = 0;
+            } else {
+                s -= E;
+            }
+            k += 1;
+        }
+    }
+    if (cop >= 0) {
+        if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+        nr++;
+    }
+    if (nr > cap_runs) {
+        const uint32_t at = atomicAdd(a.fail_count, 1u);
+        a.fail_list[at] = pair;
+        return;
+    }
+    a.scores[pair] = S * a.pen.g;
+    a.nruns[pair] = (uint32_t)nr;
+    a.job_nruns[job] = (uint32_t)nr;
+    a.run_src[pair] = ((uint64_t)job * a.slice_bytes + (uint64_t)bump) / 4;  // arena words
+}
+
+// Move the runs of finished general jobs out of the arena.
+__global__ void k_gather_general(const uint32_t* __restrict__ jobs, size_t njobs,
+                                 const uint32_t* __restrict__ nruns, uint64_t* __restrict__ run_src,
+                                 const uint32_t* __restrict__ arena32,
+                                 const uint64_t* __restrict__ job_offsets, uint64_t gen_base,
+                                 uint32_t* __restrict__ gen_runs) {
+    const size_t j = blockIdx.x;
+    if (j >= njobs) return;
+    const uint32_t pair = jobs[j];
+    const uint64_t src = run_src[pair];
+    const uint64_t dst = gen_base + job_offsets[j];
+    const uint32_t cnt = nruns[j];  // per job; 0 for jobs that failed
+    if (cnt == 0) return;
+    for (uint32_t r = threadIdx.x; r < cnt; r += blockDim.x) gen_runs[dst + r] = arena32[src + r];
+    __syncthreads();
+    if (threadIdx.x == 0) run_src[pair] = GEN_BIT | dst;
+}
+
+// reversed runs -> caller buffer in alignment order (nothing is written if
+// the total exceeds the capacity)
+__global__ void k_compact(const uint32_t* __restrict__ nruns, const uint64_t* __restrict__ run_src,
+                          const uint32_t* __restrict__ slots, const uint32_t* __restrict__ gen_runs,
+                          const uint64_t* __restrict__ offsets, size_t n,
+                          uint32_t* __restrict__ out, uint64_t capacity) {
+    if (offsets[n] > capacity) return;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t cnt = nruns[i];
+        const uint64_t src = run_src[i];
+        const uint32_t* s = (src & GEN_BIT) ? gen_runs + (src & ~GEN_BIT) : slots + src;
+        uint32_t* o = out + offsets[i];
+        for (uint32_t r = 0; r < cnt; r++) o[cnt - 1 - r] = s[r];
+    }
+}
+
+// Bucket key: longer pairs and larger length differences (more expected
+// work) first, so a persistent grid starts the long jobs early and lane
+// groups sharing a wave hold pairs of similar cost.
+__global__ void k_bucket_keys(const PairDesc* __restrict__ pairs, size_t n,
+                              uint32_t* __restrict__ keys, uint32_t* __restrict__ hist) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t p = pairs[i].p_len, t = pairs[i].t_len;
+        const uint32_t len = max(p, t), diff = p > t ? p - t : t - p;
+        const uint32_t k = min(len >> 5, 63u) * 64u + min(diff, 63u);
+        const uint32_t key = (BUCKET_KEYS - 1) - k;
+        keys[i] = key;
+        atomicAdd(&hist[key], 1u);
+    }
+}
+
+__global__ void k_bucket_scatter(const uint32_t* __restrict__ keys, size_t n,
+                                 unsigned long long* __restrict__ cursor,
+                                 uint32_t* __restrict__ order) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const unsigned long long at = atomicAdd(&cursor[keys[i]], 1ull);
+        order[at] = (uint32_t)i;
+    }
+}
+
+__global__ void k_scores_fail(const uint32_t* list, size_t n, int32_t* scores) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        scores[list[i]] = -1;
+}
+
+int grid_for(size_t n, int block, int max_blocks = 65536) {
+    size_t b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > (size_t)max_blocks) b = max_blocks;
+    return (int)b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_batch_stats(const PairDesc* pairs, size_t n, BatchStats* out, uint32_t max_len,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out,
+                       0u, sizeof(BatchStats) / 4);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &out->first_too_long, ~0ull, (size_t)1);
+    if (n) hipLaunchKernelGGL(k_batch_stats, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, pairs, n,
+                              out, max_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+size_t scan_temp_bytes(size_t n) { return ((n + SCAN_TILE - 1) / SCAN_TILE + 1) * sizeof(uint64_t); }
+
+hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, void* temp,
+                       hipStream_t s) {
+    const size_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    uint64_t* bs = (uint64_t*)temp;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, out, 0ull, (size_t)1);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_partial, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, s, bs, nb, out + n);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_pairs(const PairDesc* pairs, size_t n, const uint8_t* ascii, int which,
+                             const uint64_t* word_starts, uint32_t max_words, uint64_t* words,
+                             PairDesc* packed_pairs, unsigned long long* err_pair, hipStream_t s) {
+    const size_t total = n * (size_t)(max_words ? max_words : 1);
+    if (n)
+        hipLaunchKernelGGL(k_pack_pairs, dim3(grid_for(total, 256, 1 << 20)), dim3(256), 0, s, pairs,
+                           n, ascii, which, word_starts, max_words ? max_words : 1, words,
+                           packed_pairs, err_pair);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_seqs(const uint8_t* ascii, const uint64_t* starts, const uint32_t* lens,
+                            size_t n, const uint64_t* word_starts, uint64_t total_words,
+                            uint64_t* words, unsigned long long* err_index, hipStream_t s) {
+    if (n && total_words)
+        hipLaunchKernelGGL(k_pack_seqs, dim3(grid_for(total_words, 256, 1 << 20)), dim3(256), 0, s,
+                           ascii, starts, lens, n, word_starts, total_words, words, err_index);
+    return hipGetLastError();
+}
+
+int short_groups_per_block(int window, int block_threads) {
+    const int G = window >= 64 ? 64 : window;
+    return (block_threads / 64) * (64 / G);
+}
+
+template <int G, int DPL>
+static hipError_t launch_short_t(const ShortArgs& a, bool cigar, bool persistent, int bt, int grid,
+                                 hipStream_t s) {
+    const size_t lds = (size_t)short_groups_per_block(G * DPL, bt) * a.group_bytes;
+    if (cigar)
+        hipLaunchKernelGGL((k_short<G, DPL, true>), dim3(grid), dim3(bt), lds, s, a,
+                           persistent ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_short<G, DPL, false>), dim3(grid), dim3(bt), lds, s, a,
+                           persistent ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_short(const ShortArgs& a, int window, bool cigar, bool persistent,
+                        int block_threads, int grid, hipStream_t s) {
+    switch (window) {
+    case 16: return launch_short_t<16, 1>(a, cigar, persistent, block_threads, grid, s);
+    case 32: return launch_short_t<32, 1>(a, cigar, persistent, block_threads, grid, s);
+    case 64: return launch_short_t<64, 1>(a, cigar, persistent, block_threads, grid, s);
+    case 128: return launch_short_t<64, 2>(a, cigar, persistent, block_threads, grid, s);
+    case 256: return launch_short_t<64, 4>(a, cigar, persistent, block_threads, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int G, int DPL>
+static int occ_t(bool cigar, int bt, int lds) {
+    int blocks = 0;
+    hipError_t e = cigar ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &blocks, (const void*)k_short<G, DPL, true>, bt, lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &blocks, (const void*)k_short<G, DPL, false>, bt, lds);
+    return e == hipSuccess ? blocks : 0;
+}
+
+int short_max_blocks_per_cu(int window, bool cigar, int bt, int lds_per_block) {
+    switch (window) {
+    case 16: return occ_t<16, 1>(cigar, bt, lds_per_block);
+    case 32: return occ_t<32, 1>(cigar, bt, lds_per_block);
+    case 64: return occ_t<64, 1>(cigar, bt, lds_per_block);
+    case 128: return occ_t<64, 2>(cigar, bt, lds_per_block);
+    case 256: return occ_t<64, 4>(cigar, bt, lds_per_block);
+    default: return 0;
+    }
+}
+
+hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds, int lds_bytes,
+                          hipStream_t s) {
+    if (!a.num_jobs) return hipSuccess;
+    if (seq_in_lds)
+        hipLaunchKernelGGL(k_general<true>, dim3(a.num_jobs), dim3(block_threads), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL(k_general<false>, dim3(a.num_jobs), dim3(block_threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_general(const uint32_t* jobs, size_t njobs, const uint32_t* nruns,
+                                 uint64_t* run_src, const uint8_t* arena, uint64_t slice_bytes,
+                                 const uint64_t* job_offsets, uint64_t gen_base,
+                                 uint32_t* gen_runs, hipStream_t s) {
+    (void)slice_bytes;
+    if (njobs)
+        hipLaunchKernelGGL(k_gather_general, dim3(njobs), dim3(256), 0, s, jobs, njobs, nruns,
+                           run_src, (const uint32_t*)arena, job_offsets, gen_base, gen_runs);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const uint32_t* slots,
+                          const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
+                          uint32_t* out, uint64_t capacity, hipStream_t s) {
+    if (n)
+        hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, nruns, run_src, slots,
+                           gen_runs, offsets, n, out, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_keys(const PairDesc* pairs, size_t n, uint32_t* keys, uint32_t* hist,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, s, hist, 0u, (size_t)BUCKET_KEYS);
+    if (n)
+        hipLaunchKernelGGL(k_bucket_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, pairs, n, keys,
+                           hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, uint64_t* cursor, uint32_t* order,
+                                 hipStream_t s) {
+    if (n)
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, n,
+                           (unsigned long long*)cursor, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_scores_fail(const uint32_t* list, size_t n, int32_t* scores,
+                                      hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_scores_fail, dim3(grid_for(n, 256)), dim3(256), 0, s, list, n, scores);
+    return hipGetLastError();
+}
+
+}  // namespace wfa

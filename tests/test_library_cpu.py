@@ -1,0 +1,54 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "wfa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wfa_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["wfa_ctx_create", "wfa_ctx_destroy", "wfa_align_batch", "wfa_copy_last_cigars",
+              "wfa_strerror", "wfa_server_open", "wfa_server_submit", "wfa_server_poll",
+              "wfa_server_close"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2204_02085_amd as wfa
+
+    lib = ctypes.CDLL(wfa.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} not exported"
+    assert sorted(wfa.EXPORTED) == declared_functions()
+
+
+def test_strerror_and_null_context():
+    import paper_2204_02085_amd as wfa
+
+    assert wfa.wfa_strerror(wfa.WFA_E_CAPACITY).decode().startswith("CIGAR buffer")
+    assert wfa.wfa_strerror(12345) == b"unknown status"
+    assert wfa.wfa_set_options(None, None) == wfa.WFA_E_INVAL
+    needed = ctypes.c_size_t(7)
+    bad = ctypes.c_int64(7)
+    rc = wfa.wfa_align_batch(None, None, None, None, 0, 0, 0, wfa.wfa_penalties(4, 6, 2), 1, None,
+                             None, 0, None, ctypes.byref(needed), ctypes.byref(bad), None)
+    assert rc == wfa.WFA_E_INVAL and bad.value == -1
+    assert wfa.wfa_copy_last_cigars(None, None, 0, None) == wfa.WFA_E_INVAL
+    assert wfa.wfa_server_close(None) == wfa.WFA_E_INVAL
+
+
+def test_pair_descriptor_layout():
+    import paper_2204_02085_amd as wfa
+
+    assert wfa.PAIR_DTYPE.itemsize == 24
+    assert ctypes.sizeof(wfa.wfa_options) == 32
