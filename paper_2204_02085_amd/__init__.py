@@ -88,6 +88,9 @@ class wfa_result(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2204_02085_amd.build`")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that the process holds exactly one HIP runtime, shared with torch.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     p, i32, i64, u64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                             ctypes.c_size_t)

@@ -93,15 +93,27 @@ extern "C" int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx** out
     if (!out) return WFA_E_INVAL;
     *out = nullptr;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess || device < 0 || device >= ndev) {
+        if (std::getenv("WFA_DEBUG"))
+            std::fprintf(stderr, "wfa_ctx_create: hipGetDeviceCount -> %s, %d devices\n",
+                         hipGetErrorString(he), ndev);
         (void)hipGetLastError();
         return WFA_E_DEVICE;
     }
-    if (hipSetDevice(device) != hipSuccess) return WFA_E_DEVICE;
+    he = hipSetDevice(device);
+    if (he != hipSuccess) {
+        if (std::getenv("WFA_DEBUG"))
+            std::fprintf(stderr, "wfa_ctx_create: hipSetDevice -> %s\n", hipGetErrorString(he));
+        return WFA_E_DEVICE;
+    }
     wfa_ctx* c = new wfa_ctx();
     c->device = device;
     c->ws.budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)64 << 30);
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (he != hipSuccess) {
+        if (std::getenv("WFA_DEBUG"))
+            std::fprintf(stderr, "wfa_ctx_create: hipStreamCreate -> %s\n", hipGetErrorString(he));
         delete c;
         return WFA_E_DEVICE;
     }
