@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -18,14 +19,20 @@ namespace {
 
 constexpr uint32_t SHORT_MAX_LEN = 2400;  // longest sequence the short kernel stages in LDS
 
-#define HIPCHK(x)                                   \
-    do {                                            \
-        hipError_t _e = (x);                        \
-        if (_e != hipSuccess) {                     \
-            (void)hipGetLastError();                \
-            return WFA_E_DEVICE;                    \
-        }                                           \
+#define HIPCHK(x)                                                  \
+    do {                                                           \
+        hipError_t _e = (x);                                       \
+        if (_e != hipSuccess) {                                    \
+            report_hip_error(_e, #x, __FILE__, __LINE__);          \
+            (void)hipGetLastError();                               \
+            return WFA_E_DEVICE;                                   \
+        }                                                          \
     } while (0)
+
+void report_hip_error(hipError_t e, const char* what, const char* file, int line) {
+    std::fprintf(stderr, "libwfa: %s failed (%s:%d): %s\n", what, file, line,
+                 hipGetErrorString(e));
+}
 
 #define RCCHK(x)                  \
     do {                          \
@@ -65,6 +72,32 @@ int ensure_keep(Workspace& ws, Buf& b, size_t bytes, size_t keep, hipStream_t s)
     HIPCHK(hipStreamSynchronize(s));
     ws.release(b);
     b = nb;
+    return WFA_OK;
+}
+
+template <class F>
+int capture_graph(hipStream_t s, F&& body, hipGraph_t* graph, hipGraphExec_t* exec) {
+    *graph = nullptr;
+    *exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = body(s);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(s, &g);
+    if (rc != WFA_OK || ce != hipSuccess || !g) {
+        if (ce != hipSuccess) report_hip_error(ce, "hipStreamEndCapture", __FILE__, __LINE__);
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return rc != WFA_OK ? rc : WFA_E_DEVICE;
+    }
+    const hipError_t ie = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        report_hip_error(ie, "hipGraphInstantiate", __FILE__, __LINE__);
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        *exec = nullptr;
+        return WFA_E_DEVICE;
+    }
+    *graph = g;
     return WFA_OK;
 }
 
@@ -192,11 +225,16 @@ bool GraphKey::operator==(const GraphKey& o) const {
     return n == o.n;
 }
 
+void destroy_graph(GraphEntry& g) {
+    if (g.exec_pre) (void)hipGraphExecDestroy(g.exec_pre);
+    if (g.graph_pre) (void)hipGraphDestroy(g.graph_pre);
+    if (g.exec_post) (void)hipGraphExecDestroy(g.exec_post);
+    if (g.graph_post) (void)hipGraphDestroy(g.graph_post);
+    g = GraphEntry{};
+}
+
 void graph_cache_clear(Engine* e) {
-    for (auto& g : e->graphs) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-    }
+    for (auto& g : e->graphs) destroy_graph(g);
     e->graphs.clear();
 }
 
@@ -345,21 +383,32 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     DevFlags* flags = ws.flags.as<DevFlags>();
 
     int grid = 1;
+    int queue_chunk = 1;
     if (use_short) {
         const int gpb = short_groups_per_block(window, sp.block_threads);
         if (persistent) {
-            int bpc = short_max_blocks_per_cu(window, cigar, sp.block_threads, sp.lds_per_block);
+            int bpc = short_max_blocks_per_cu(window, cigar, sp.block_threads, sp.lds_per_block,
+                                              sp.row_bytes);
             if (bpc < 1) bpc = 1;
             grid = e->num_cus * bpc;
             const size_t needed = (N + gpb - 1) / gpb;
             if ((size_t)grid > needed) grid = (int)needed;
+            // claims of several rounds keep the queue atomic off the critical
+            // path; at most ~1/16 of a wave's share is claimed at once
+            const size_t rounds = (N + (size_t)grid * gpb - 1) / ((size_t)grid * gpb);
+            queue_chunk = (int)std::max<size_t>(1, std::min<size_t>(16, rounds / 16));
         } else {
             grid = (int)((N + gpb - 1) / gpb);
         }
     }
 
     // ---- device phase (graph-capturable) ----------------------------------
-    auto device_phase = [&](hipStream_t q) -> int {
+    // Three phases; in graph mode the first and last are captured graphs and
+    // the kernel between them is launched directly, so plain events around it
+    // time exactly the short-pair kernel (ev[0] start, ev[4]/ev[5] around the
+    // kernel, ev[1] end).
+    // pre: counters, packing, bucketing
+    auto phase_pre = [&](hipStream_t q) -> int {
         HIPCHK(launch_fill_u32((uint32_t*)flags, 0u, sizeof(DevFlags) / 4, q));
         HIPCHK(launch_fill_u64((uint64_t*)&flags->err_pair, ~0ull, 1, q));
         if (ascii) {
@@ -373,11 +422,17 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
                                      ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
         }
         HIPCHK(launch_fill_u32(ws.nruns.as<uint32_t>(), 0u, N, q));
+        if (use_short && bucket) {
+            HIPCHK(launch_bucket_keys(d.pairs, N, ws.keys.as<uint32_t>(), ws.hist.as<uint32_t>(), q));
+            HIPCHK(launch_scan(SCAN_U32, ws.hist.ptr, BUCKET_KEYS, cursor, ws.scan_tmp.ptr, q));
+            HIPCHK(launch_bucket_scatter(ws.keys.as<uint32_t>(), N, cursor, ws.order.as<uint32_t>(),
+                                         q));
+        }
+        return WFA_OK;
+    };
+    // the short-pair kernel itself
+    auto phase_kernel = [&](hipStream_t q) -> int {
         if (use_short) {
-            if (bucket) {
-                HIPCHK(launch_bucket_keys(d.pairs, N, ws.keys.as<uint32_t>(), ws.hist.as<uint32_t>(), q));
-                HIPCHK(launch_scan(SCAN_U32, ws.hist.ptr, BUCKET_KEYS, cursor, ws.scan_tmp.ptr, q));
-            }
             ShortArgs a{};
             a.pairs = d.pairs;
             a.pw = d.pw;
@@ -385,23 +440,26 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
             a.order = bucket ? ws.order.as<uint32_t>() : nullptr;
             a.num = (uint32_t)N;
             a.queue = &flags->queue;
+            a.queue_chunk = queue_chunk;
             a.pen = pen;
             a.cap = sp.cap;
             a.ring = sp.ring;
             a.seq_words = sp.seq_words;
             a.group_bytes = sp.group_bytes;
             a.slot_cap = sp.slot_cap;
+            a.row_bytes = sp.row_bytes;
             a.scores = d.scores;
             a.nruns = ws.nruns.as<uint32_t>();
             a.run_src = ws.run_src.as<uint64_t>();
             a.slots = ws.slots.as<uint32_t>();
             a.ovf_list = ws.ovf_list.as<uint32_t>();
             a.ovf_count = &flags->ovf_count;
-            if (bucket)
-                HIPCHK(launch_bucket_scatter(ws.keys.as<uint32_t>(), N, cursor,
-                                             ws.order.as<uint32_t>(), q));
             HIPCHK(launch_short(a, window, cigar, persistent, sp.block_threads, grid, q));
         }
+        return WFA_OK;
+    };
+    // post: CIGAR offsets and compaction
+    auto phase_post = [&](hipStream_t q) -> int {
         if (cigar && use_short) {
             HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, q));
             if (io.mem == WFA_DEVICE)
@@ -412,8 +470,8 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
         return WFA_OK;
     };
 
-    HIPCHK(hipEventRecord(e->ev[0], s));
     bool replayed = false;
+    GraphEntry* hit = nullptr;
     if (graph) {
         GraphKey key;
         const void* ptrs[8] = {in_pairs, in_p, in_t, d.scores, d.runs, d.offsets,
@@ -421,42 +479,35 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
         for (int i = 0; i < 8; i++) key.p[i] = ptrs[i];
         key.n = N;
         const int ints[12] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g, window, sp.cap,
-                              (int)st.max_p, (int)st.max_t, grid, (int)(bucket ? 1 : 0) | (int)(d.capacity > 0x7fffffff ? 2 : 0)};
+                              (int)st.max_p, (int)st.max_t, grid,
+                              (int)(bucket ? 1 : 0) | (int)(d.capacity > 0x7fffffff ? 2 : 0)};
         for (int i = 0; i < 12; i++) key.ints[i] = ints[i];
-        GraphEntry* hit = nullptr;
         for (auto& g : e->graphs)
             if (g.key == key) hit = &g;
         if (!hit) {
             GraphEntry g;
             g.key = key;
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            int rc = device_phase(s);
-            hipGraph_t gr = nullptr;
-            hipError_t ce = hipStreamEndCapture(s, &gr);
-            if (rc != WFA_OK || ce != hipSuccess || !gr) {
-                (void)hipGetLastError();
-                if (gr) (void)hipGraphDestroy(gr);
-                return rc != WFA_OK ? rc : WFA_E_DEVICE;
-            }
-            g.graph = gr;
-            if (hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0) != hipSuccess) {
-                (void)hipGetLastError();
-                (void)hipGraphDestroy(gr);
-                return WFA_E_DEVICE;
+            int rc = capture_graph(s, phase_pre, &g.graph_pre, &g.exec_pre);
+            if (rc == WFA_OK) rc = capture_graph(s, phase_post, &g.graph_post, &g.exec_post);
+            if (rc != WFA_OK) {
+                destroy_graph(g);
+                return rc;
             }
             if (e->graphs.size() >= 4) {
-                (void)hipGraphExecDestroy(e->graphs.front().exec);
-                (void)hipGraphDestroy(e->graphs.front().graph);
+                destroy_graph(e->graphs.front());
                 e->graphs.erase(e->graphs.begin());
             }
             e->graphs.push_back(g);
             hit = &e->graphs.back();
         }
-        HIPCHK(hipGraphLaunch(hit->exec, s));
         replayed = true;
-    } else {
-        RCCHK(device_phase(s));
     }
+    HIPCHK(hipEventRecord(e->ev[0], s));
+    if (hit) HIPCHK(hipGraphLaunch(hit->exec_pre, s)); else RCCHK(phase_pre(s));
+    HIPCHK(hipEventRecord(e->ev[4], s));
+    RCCHK(phase_kernel(s));
+    HIPCHK(hipEventRecord(e->ev[5], s));
+    if (hit) HIPCHK(hipGraphLaunch(hit->exec_post, s)); else RCCHK(phase_post(s));
     HIPCHK(hipEventRecord(e->ev[1], s));
     DevFlags fl;
     HIPCHK(hipMemcpyAsync(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
@@ -506,7 +557,7 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
                                   d.runs, d.capacity, s));
         if (cigar_needed) *cigar_needed = (size_t)total;
     }
-    HIPCHK(hipEventRecord(e->ev[4], s));
+    HIPCHK(hipEventRecord(e->ev[8], s));
 
     // ---- results to the host --------------------------------------------------
     if (io.mem == WFA_HOST) {
@@ -529,9 +580,10 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     L.step_cap = use_short ? sp.cap : 0;
     L.schedule = !use_short ? WFA_SCHED_GENERAL : (persistent ? WFA_SCHED_PERSISTENT : WFA_SCHED_PLAIN);
     L.graph_replayed = replayed ? 1 : 0;
-    L.ms_align = ev_ms(e->ev[0], e->ev[1]);
+    L.ms_pack = use_short ? ev_ms(e->ev[0], e->ev[4]) : 0.0;
+    L.ms_align = use_short ? ev_ms(e->ev[4], e->ev[5]) : 0.0;
     L.ms_general = ev_ms(e->ev[2], e->ev[3]);
-    L.ms_compact = ev_ms(e->ev[3], e->ev[4]);
+    L.ms_compact = (use_short ? ev_ms(e->ev[5], e->ev[1]) : 0.0) + ev_ms(e->ev[3], e->ev[8]);
     L.ms_total = now_ms() - t_start;
 
     e->last_valid = cigar;

@@ -59,6 +59,7 @@ struct DevFlags {
 
 struct ShortPlan {
     int window = 0, cap = 0, seq_words = 0, ring = 0, group_bytes = 0, slot_cap = 0;
+    int row_bytes = 2;
     int block_threads = 256, lds_per_block = 0;
 };
 
@@ -69,10 +70,12 @@ struct GraphKey {
     bool operator==(const GraphKey& o) const;
 };
 
+// Captured graphs of one plan: the work before the short-pair kernel
+// (counters, packing, bucketing) and after it (CIGAR offsets, compaction).
 struct GraphEntry {
     GraphKey key;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_pre = nullptr, graph_post = nullptr;
+    hipGraphExec_t exec_pre = nullptr, exec_post = nullptr;
 };
 
 // Everything one batch needs: a stream, a workspace, events and options.
@@ -81,7 +84,7 @@ struct Engine {
     int num_cus = 256;
     hipStream_t stream = nullptr;
     Workspace ws;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[10] = {};
     wfa_options opt{};
     wfa_stats last{};
     std::vector<GraphEntry> graphs;
@@ -117,3 +120,4 @@ int short_plan(Engine* ctx, const wfa::Pen& pen, bool cigar, int window, int cap
 int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
                  int64_t* bad_pair);
 void graph_cache_clear(Engine* e);
+void destroy_graph(GraphEntry& g);

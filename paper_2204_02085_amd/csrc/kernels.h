@@ -43,12 +43,14 @@ struct ShortArgs {
     const uint32_t* order;      // queue position -> pair index (NULL: identity)
     uint32_t num;               // pairs in the queue
     uint32_t* queue;            // persistent: next queue position (device counter)
+    int queue_chunk;            // rounds of 64/G pairs a wave claims per atomic
     Pen pen;
     int cap;                    // last step s' held
     int ring;                   // rows held (cap + 1 + pre in CIGAR mode, pre + 1 otherwise)
     int seq_words;              // 64-bit words of LDS per sequence
     int group_bytes;            // LDS bytes per lane group
     int slot_cap;               // runs per pair slot
+    int row_bytes;              // 1: int8 offsets (sequences < 128 bases), 2: int16
     int32_t* scores;            // [pairs]
     uint32_t* nruns;            // [pairs] runs written
     uint64_t* run_src;          // [pairs] where the reversed runs live
@@ -105,7 +107,8 @@ hipError_t launch_pack_seqs(const uint8_t* ascii, const uint64_t* starts, const 
 hipError_t launch_short(const ShortArgs& a, int window, bool cigar, bool persistent,
                         int block_threads, int grid, hipStream_t s);
 int short_groups_per_block(int window, int block_threads);
-int short_max_blocks_per_cu(int window, bool cigar, int block_threads, int lds_per_block);
+int short_max_blocks_per_cu(int window, bool cigar, int block_threads, int lds_per_block,
+                            int row_bytes);
 
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds,
                           int lds_bytes, hipStream_t s);

@@ -293,9 +293,11 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
 // through scores together.  Lane l of a group owns diagonals
 // kmin + l + d*G (d < DPL), a window of W = G*DPL diagonals centred between
 // diagonal 0 and the target diagonal m-n.  Row r of the LDS history holds,
-// for one score step, the int16 offsets of M (after extension), I and D on
-// the W diagonals plus a NULL pad on each side, so neighbouring diagonals
-// are read without bounds checks.  Rows for steps -pre..-1 hold NULL.
+// for one score step, the offsets of M (after extension), I and D on the W
+// diagonals plus a NULL pad on each side, so neighbouring diagonals are read
+// without bounds checks.  Rows for steps -pre..-1 hold NULL.  Offsets are
+// int8 when both sequences are shorter than 128 bases (twice the lane groups
+// per CU), int16 otherwise.
 //
 // A pair leaves the kernel through the overflow list (and is finished by the
 // general kernel) when its wavefront touches a window edge before reaching
@@ -303,13 +305,26 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
 // the LDS words, or when its runs overflow the slot.  Values are never
 // computed from an incomplete window.
 // ---------------------------------------------------------------------------
-template <int G, int DPL, bool CIGAR>
+template <class RowT>
+struct RowNull;
+template <>
+struct RowNull<int8_t> {
+    static constexpr int value = -128;
+};
+template <>
+struct RowNull<int16_t> {
+    static constexpr int value = -16384;
+};
+
+template <int G, int DPL, bool CIGAR, class RowT>
 __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int W = G * DPL;
     constexpr int RW = W + 2;
     constexpr int GPW = 64 / G;
     constexpr uint64_t GMASK = G == 64 ? ~0ULL : ((1ULL << G) - 1ULL);
+    // NULL, and how far below zero a NULL may drift (+1 per step at most)
+    constexpr int NUL = RowNull<RowT>::value;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -319,10 +334,10 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     const int gshift = grp * G;
 
     unsigned char* gbase = lds + (size_t)(wave * GPW + grp) * a.group_bytes;
-    int16_t* RM = (int16_t*)gbase;
-    int16_t* RI = RM + a.ring * RW;
-    int16_t* RD = RI + a.ring * RW;
-    const int rows_bytes = ((3 * a.ring * RW * 2) + 15) & ~15;
+    RowT* RM = (RowT*)gbase;
+    RowT* RI = RM + a.ring * RW;
+    RowT* RD = RI + a.ring * RW;
+    const int rows_bytes = ((3 * a.ring * RW * (int)sizeof(RowT)) + 15) & ~15;
     uint64_t* SP64 = (uint64_t*)(gbase + rows_bytes);
     uint64_t* ST64 = SP64 + a.seq_words;
     const uint32_t* SP = (const uint32_t*)SP64;
@@ -333,29 +348,37 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
 
     // side pads of every row stay NULL for the life of the kernel
     for (int r = gl; r < ring; r += G) {
-        RM[r * RW] = RM[r * RW + RW - 1] = (int16_t)NUL16;
-        RI[r * RW] = RI[r * RW + RW - 1] = (int16_t)NUL16;
-        RD[r * RW] = RD[r * RW + RW - 1] = (int16_t)NUL16;
+        RM[r * RW] = RM[r * RW + RW - 1] = (RowT)NUL;
+        RI[r * RW] = RI[r * RW + RW - 1] = (RowT)NUL;
+        RD[r * RW] = RD[r * RW + RW - 1] = (RowT)NUL;
     }
 
+    // persistent: a wave claims `queue_chunk` rounds of GPW queue entries per
+    // atomic and works through them before claiming again
+    uint32_t claim = 0, claim_left = 0;
     for (uint32_t iter = 0;; iter++) {
         uint32_t qbase;
         if (persistent) {
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(a.queue, (uint32_t)GPW);
-            qbase = __builtin_amdgcn_readfirstlane(t);
+            if (claim_left == 0) {
+                uint32_t t = 0;
+                if (lane == 0) t = atomicAdd(a.queue, (uint32_t)(GPW * a.queue_chunk));
+                claim = __builtin_amdgcn_readfirstlane(t);
+                claim_left = (uint32_t)a.queue_chunk;
+            }
+            qbase = claim;
+            claim += GPW;
+            claim_left--;
         } else {
             if (iter) break;
             qbase = (blockIdx.x * wpb + wave) * GPW;
         }
         if (qbase >= a.num) break;
         const uint32_t q = qbase + grp;
-        const bool active = q < a.num;
         uint32_t pair = 0;
         int n = 0, m = 0;
         uint64_t ps = 0, ts = 0;
-        bool active_ok = active;
-        if (active) {
+        bool active_ok = q < a.num;
+        if (active_ok) {
             pair = a.order ? a.order[q] : q;
             if (pair >= a.num) {  // a corrupt permutation must not fault: skip the entry
                 active_ok = false;
@@ -375,7 +398,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
         // 0 running, 1 finished or idle, 2 overflow
         int st = active_ok ? 0 : 1;
         if (active_ok && !(kmin <= 0 && 0 < kmin + W && kmin <= kt && kt < kmin + W &&
-                        nwp + 1 <= a.seq_words && nwt + 1 <= a.seq_words))
+                           nwp + 1 <= a.seq_words && nwt + 1 <= a.seq_words))
             st = 2;
 
         // stage both sequences (zero past their ends)
@@ -386,33 +409,27 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
         // rows of steps -pre .. -1
         for (int idx = gl; idx < PRE * W; idx += G) {
             const int r = idx / W, j = idx - (idx / W) * W;
-            RM[r * RW + 1 + j] = (int16_t)NUL16;
-            RI[r * RW + 1 + j] = (int16_t)NUL16;
-            RD[r * RW + 1 + j] = (int16_t)NUL16;
+            RM[r * RW + 1 + j] = (RowT)NUL;
+            RI[r * RW + 1 + j] = (RowT)NUL;
+            RD[r * RW + 1 + j] = (RowT)NUL;
         }
         wave_sync();
 
         int lim[DPL];
 #pragma unroll
-        for (int d = 0; d < DPL; d++) {
-            const int k = kmin + gl + d * G;
-            lim[d] = min(m, n + k);
-        }
+        for (int d = 0; d < DPL; d++) lim[d] = min(m, n + kmin + gl + d * G);
         const int jt = kt - kmin;  // window index of the target diagonal
         int S = 0;
         int cur = PRE;             // row of step 0
         for (int s = 0;; s++) {
-            const uint64_t running = __ballot(st == 0);
-            if (running == 0) break;
-            const bool run = st == 0;
+            if (__ballot(st == 0) == 0) break;
             int Mv[DPL], Iv[DPL], Dv[DPL];
             if (s == 0) {
 #pragma unroll
                 for (int d = 0; d < DPL; d++) {
-                    const int k = kmin + gl + d * G;
-                    Mv[d] = (run && k == 0) ? 0 : NUL16;
-                    Iv[d] = NUL16;
-                    Dv[d] = NUL16;
+                    Mv[d] = (kmin + gl + d * G == 0) ? 0 : NUL;
+                    Iv[d] = NUL;
+                    Dv[d] = NUL;
                 }
             } else {
                 cur = cur + 1 == ring ? 0 : cur + 1;
@@ -420,33 +437,33 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 ix += ix < 0 ? ring : 0;
                 io += io < 0 ? ring : 0;
                 ie += ie < 0 ? ring : 0;
-                const int16_t* mx = RM + ix * RW + 1;
-                const int16_t* mo = RM + io * RW + 1;
-                const int16_t* il = RI + ie * RW + 1;
-                const int16_t* dr = RD + ie * RW + 1;
+                const RowT* mx = RM + ix * RW + 1;
+                const RowT* mo = RM + io * RW + 1;
+                const RowT* il = RI + ie * RW + 1;
+                const RowT* dr = RD + ie * RW + 1;
 #pragma unroll
                 for (int d = 0; d < DPL; d++) {
                     const int j = gl + d * G;
                     const int L = lim[d];
+                    // NULL sources stay negative through +1 and never beat a real cell
                     const int a1 = mo[j - 1] + 1, a2 = il[j - 1] + 1;
-                    const int iv = max(a1 <= L ? a1 : NUL16, a2 <= L ? a2 : NUL16);
+                    const int iv = max(a1 <= L ? a1 : NUL, a2 <= L ? a2 : NUL);
                     const int c1 = mo[j + 1], c2 = dr[j + 1];
-                    const int dv = max(c1 <= L ? c1 : NUL16, c2 <= L ? c2 : NUL16);
+                    const int dv = max(c1 <= L ? c1 : NUL, c2 <= L ? c2 : NUL);
                     const int xv = mx[j] + 1;
-                    Mv[d] = max(max(xv <= L ? xv : NUL16, iv), dv);
+                    Mv[d] = max(max(xv <= L ? xv : NUL, iv), dv);
                     Iv[d] = iv;
                     Dv[d] = dv;
                 }
             }
             // extend along matches, 32 bases per compare
-            int hv[DPL];
+            const bool run = st == 0;
             bool go[DPL];
             bool any_go = false;
 #pragma unroll
             for (int d = 0; d < DPL; d++) {
                 const int k = kmin + gl + d * G;
-                hv[d] = Mv[d];
-                go[d] = run && hv[d] >= 0 && hv[d] - k < n && hv[d] < m;
+                go[d] = run && Mv[d] >= 0 && Mv[d] - k < n && Mv[d] < m;
                 any_go |= go[d];
             }
             while (__ballot(any_go)) {
@@ -455,118 +472,92 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 for (int d = 0; d < DPL; d++) {
                     if (go[d]) {
                         const int k = kmin + gl + d * G;
-                        const int h = hv[d], v = h - k;
+                        const int h = Mv[d], v = h - k;
                         int r = common_prefix(window32(SP, v), window32(ST, h));
                         r = min(r, min(n - v, m - h));
-                        hv[d] = h + r;
+                        Mv[d] = h + r;
                         go[d] = r == 32 && v + r < n && h + r < m;
                         any_go |= go[d];
                     }
                 }
             }
-            // store the step's rows
+            // store the step's rows (groups that stopped write rows nobody reads)
             bool term = false, edge = false;
 #pragma unroll
             for (int d = 0; d < DPL; d++) {
                 const int j = gl + d * G;
-                if (run) {
-                    RM[cur * RW + 1 + j] = (int16_t)hv[d];
-                    RI[cur * RW + 1 + j] = (int16_t)Iv[d];
-                    RD[cur * RW + 1 + j] = (int16_t)Dv[d];
-                }
-                term |= (j == jt) && hv[d] == m;
-                edge |= (j == 0 || j == W - 1) && (hv[d] >= 0 || Iv[d] >= 0 || Dv[d] >= 0);
+                RM[cur * RW + 1 + j] = (RowT)Mv[d];
+                RI[cur * RW + 1 + j] = (RowT)Iv[d];
+                RD[cur * RW + 1 + j] = (RowT)Dv[d];
+                term |= (j == jt) & (Mv[d] == m);
+                if (d == 0) edge |= (j == 0) & (max(max(Mv[d], Iv[d]), Dv[d]) >= 0);
+                if (d == DPL - 1) edge |= (j == W - 1) & (max(max(Mv[d], Iv[d]), Dv[d]) >= 0);
             }
-            const bool gterm = ((__ballot(run && term) >> gshift) & GMASK) != 0;
-            const bool gedge = ((__ballot(run && edge) >> gshift) & GMASK) != 0;
-            if (run) {
-                if (gterm) {
-                    st = 1;
-                    S = s;
-                } else if (gedge || s >= a.cap) {
-                    st = 2;
-                }
-            }
+            const bool gterm = ((__ballot(term) >> gshift) & GMASK) != 0;
+            const bool gedge = ((__ballot(edge) >> gshift) & GMASK) != 0;
+            S = (run && gterm) ? s : S;
+            st = run ? (gterm ? 1 : ((gedge || s >= a.cap) ? 2 : 0)) : st;
             wave_sync();
         }
 
-        // results
+        // results: the group leader walks the backtrace
         if (active_ok && gl == 0) {
             bool overflow = st == 2;
             if (!overflow && CIGAR) {
                 uint32_t* out = a.slots + (uint64_t)pair * a.slot_cap;
-                int nr = 0, cop = -1, clen = 0;
                 const int cap_runs = a.slot_cap;
-                auto emit = [&](int op, int len) {
-                    if (len <= 0) return;
-                    if (op == cop) {
-                        clen += len;
-                    } else {
-                        if (cop >= 0) {
-                            if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
-                            nr++;
-                        }
-                        cop = op;
-                        clen = len;
-                    }
-                };
-                int s = S, k = kt, h = m, comp = 0;
+                int nr = 0, cop = -1, clen = 0;
+                int s = S, k = kt, h = m, comp = 0;  // comp: 0 M, 1 I, 2 D
                 int guard = 2 * S + 4;  // every two iterations lower s by at least 1
-                // rows of step s live at index s + PRE (no wrap in CIGAR mode)
+                // rows of step s live at index s + PRE (no wrap in CIGAR mode).
+                // Each iteration reads every candidate it may need and picks
+                // the next state with selects (the walk has no divergent
+                // branches besides the run stores).
                 for (;;) {
                     const int j = k - kmin;
                     if (s < 0 || j < 0 || j >= W || h < 0 || --guard < 0) {
                         overflow = true;  // inconsistent walk: leave it to the general kernel
                         break;
                     }
-                    if (comp == 0) {
-                        int h0, xv = NUL16, iv = NUL16, dv = NUL16;
-                        if (s == 0) {
-                            h0 = 0;
-                        } else {
-                            const int L = min(m, n + k);
-                            xv = RM[(s - X + PRE) * RW + 1 + j] + 1;
-                            if (xv < 0 || xv > L) xv = NUL16;
-                            iv = RI[(s + PRE) * RW + 1 + j];
-                            dv = RD[(s + PRE) * RW + 1 + j];
-                            h0 = max(xv, max(iv, dv));
+                    const int rs = (s + PRE) * RW + 1 + j;
+                    const int rx = (max(s - X, -PRE) + PRE) * RW + 1 + j;
+                    const int ro = (max(s - OE, -PRE) + PRE) * RW + 1 + j;
+                    const int bx = RM[rx], bi = RI[rs], bd = RD[rs];
+                    const int bl = RM[ro - 1], br = RM[ro + 1];
+                    const int L = min(m, n + k);
+                    int xv = bx + 1;
+                    xv = (xv >= 0 && xv <= L) ? xv : NUL;
+                    const int h0 = s == 0 ? 0 : max(xv, max(bi, bd));
+                    const bool isM = comp == 0, isI = comp == 1, isD = comp == 2;
+                    const bool takeX = isM && s > 0 && xv == h0;
+                    const bool toI = isM && s > 0 && !takeX && bi == h0;
+                    const int a1 = bl + 1;
+                    const bool openI = isI && a1 >= 0 && a1 <= L && a1 == h;
+                    const bool openD = isD && br >= 0 && br <= L && br == h;
+                    // ops of this iteration: a run of matches (M state), then one edit
+                    const int mlen = isM ? h - h0 : 0;
+                    const int op2 = takeX ? OP_X : (isI ? OP_I : (isD ? OP_D : -1));
+#pragma unroll
+                    for (int t = 0; t < 2; t++) {
+                        const int op = t == 0 ? OP_M : op2;
+                        const int len = t == 0 ? mlen : (op2 >= 0 ? 1 : 0);
+                        if (len > 0) {
+                            if (op != cop && cop >= 0) {
+                                if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                                nr++;
+                            }
+                            clen = op == cop ? clen + len : len;
+                            cop = op;
                         }
-                        emit(OP_M, h - h0);
-                        h = h0;
-                        if (s == 0) break;
-                        if (xv >= 0 && xv == h0) {
-                            emit(OP_X, 1);
-                            s -= X;
-                            h -= 1;
-                        } else if (iv == h0) {
-                            comp = 1;
-                        } else {
-                            comp = 2;
-                        }
-                    } else if (comp == 1) {
-                        emit(OP_I, 1);
-                        const int L = min(m, n + k);
-                        const int a1 = RM[(s - OE + PRE) * RW + j] + 1;  // diagonal k-1
-                        if (a1 >= 0 && a1 <= L && a1 == h) {
-                            s -= OE;
-                            comp = 0;
-                        } else {
-                            s -= E;
-                        }
-                        k -= 1;
-                        h -= 1;
-                    } else {
-                        emit(OP_D, 1);
-                        const int L = min(m, n + k);
-                        const int c1 = RM[(s - OE + PRE) * RW + 2 + j];  // diagonal k+1
-                        if (c1 >= 0 && c1 <= L && c1 == h) {
-                            s -= OE;
-                            comp = 0;
-                        } else {
-                            s -= E;
-                        }
-                        k += 1;
                     }
+                    if (isM && s == 0) break;
+                    const int s_gap = (openI || openD) ? s - OE : s - E;
+                    const int s_next = isM ? (takeX ? s - X : s) : s_gap;
+                    const int c_next = isM ? (takeX ? 0 : (toI ? 1 : 2)) : ((openI || openD) ? 0 : comp);
+                    h = isM ? (takeX ? h0 - 1 : h0) : (isI ? h - 1 : h);
+                    k = isI ? k - 1 : (isD ? k + 1 : k);
+                    s = s_next;
+                    comp = c_next;
                 }
                 if (cop >= 0) {
                     if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
@@ -949,26 +940,58 @@ __global__ void k_compact(const uint32_t* __restrict__ nruns, const uint64_t* __
 // Bucket key: longer pairs and larger length differences (more expected
 // work) first, so a persistent grid starts the long jobs early and lane
 // groups sharing a wave hold pairs of similar cost.
-__global__ void k_bucket_keys(const PairDesc* __restrict__ pairs, size_t n,
-                              uint32_t* __restrict__ keys, uint32_t* __restrict__ hist) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t p = pairs[i].p_len, t = pairs[i].t_len;
-        const uint32_t len = max(p, t), diff = p > t ? p - t : t - p;
-        const uint32_t k = min(len >> 5, 63u) * 64u + min(diff, 63u);
-        const uint32_t key = (BUCKET_KEYS - 1) - k;
-        keys[i] = key;
-        atomicAdd(&hist[key], 1u);
-    }
+__device__ __forceinline__ uint32_t bucket_key(const PairDesc& d) {
+    const uint32_t p = d.p_len, t = d.t_len;
+    const uint32_t len = max(p, t), diff = p > t ? p - t : t - p;
+    const uint32_t k = min(len >> 5, 63u) * 64u + min(diff, 63u);
+    return (BUCKET_KEYS - 1) - k;
 }
 
-__global__ void k_bucket_scatter(const uint32_t* __restrict__ keys, size_t n,
-                                 unsigned long long* __restrict__ cursor,
-                                 uint32_t* __restrict__ order) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const unsigned long long at = atomicAdd(&cursor[keys[i]], 1ull);
-        order[at] = (uint32_t)i;
+// Each block owns BUCKET_CHUNK consecutive pairs.  Counting goes through an
+// LDS histogram first, so the global histogram sees one atomic per
+// (block, key) instead of one per pair.
+constexpr int BUCKET_CHUNK = 8192;
+
+__global__ __launch_bounds__(256) void k_bucket_keys(const PairDesc* __restrict__ pairs, size_t n,
+                                                     uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ hist) {
+    __shared__ uint32_t local[BUCKET_KEYS];
+    for (int i = threadIdx.x; i < BUCKET_KEYS; i += blockDim.x) local[i] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * BUCKET_CHUNK;
+    const size_t end = min(n, base + BUCKET_CHUNK);
+    for (size_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+        const uint32_t key = bucket_key(pairs[i]);
+        keys[i] = key;
+        atomicAdd(&local[key], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < BUCKET_KEYS; i += blockDim.x)
+        if (local[i]) atomicAdd(&hist[i], local[i]);
+}
+
+// cursor[key] starts as the exclusive scan of the histogram; each block
+// reserves one range per key it holds and places its pairs inside it.
+__global__ __launch_bounds__(256) void k_bucket_scatter(const uint32_t* __restrict__ keys, size_t n,
+                                                        unsigned long long* __restrict__ cursor,
+                                                        uint32_t* __restrict__ order) {
+    __shared__ uint32_t count[BUCKET_KEYS];
+    __shared__ unsigned long long start[BUCKET_KEYS];
+    for (int i = threadIdx.x; i < BUCKET_KEYS; i += blockDim.x) count[i] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * BUCKET_CHUNK;
+    const size_t end = min(n, base + BUCKET_CHUNK);
+    for (size_t i = base + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&count[keys[i]], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < BUCKET_KEYS; i += blockDim.x) {
+        start[i] = count[i] ? atomicAdd(&cursor[i], (unsigned long long)count[i]) : 0ull;
+        count[i] = 0;
+    }
+    __syncthreads();
+    for (size_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+        const uint32_t key = keys[i];
+        const uint32_t r = atomicAdd(&count[key], 1u);
+        order[start[key] + r] = (uint32_t)i;
     }
 }
 
@@ -1051,50 +1074,64 @@ int short_groups_per_block(int window, int block_threads) {
     return (block_threads / 64) * (64 / G);
 }
 
-template <int G, int DPL>
+template <int G, int DPL, class RowT>
 static hipError_t launch_short_t(const ShortArgs& a, bool cigar, bool persistent, int bt, int grid,
                                  hipStream_t s) {
     const size_t lds = (size_t)short_groups_per_block(G * DPL, bt) * a.group_bytes;
     if (cigar)
-        hipLaunchKernelGGL((k_short<G, DPL, true>), dim3(grid), dim3(bt), lds, s, a,
+        hipLaunchKernelGGL((k_short<G, DPL, true, RowT>), dim3(grid), dim3(bt), lds, s, a,
                            persistent ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_short<G, DPL, false>), dim3(grid), dim3(bt), lds, s, a,
+        hipLaunchKernelGGL((k_short<G, DPL, false, RowT>), dim3(grid), dim3(bt), lds, s, a,
                            persistent ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_short(const ShortArgs& a, int window, bool cigar, bool persistent,
-                        int block_threads, int grid, hipStream_t s) {
+template <class RowT>
+static hipError_t launch_short_w(const ShortArgs& a, int window, bool cigar, bool persistent,
+                                 int bt, int grid, hipStream_t s) {
     switch (window) {
-    case 16: return launch_short_t<16, 1>(a, cigar, persistent, block_threads, grid, s);
-    case 32: return launch_short_t<32, 1>(a, cigar, persistent, block_threads, grid, s);
-    case 64: return launch_short_t<64, 1>(a, cigar, persistent, block_threads, grid, s);
-    case 128: return launch_short_t<64, 2>(a, cigar, persistent, block_threads, grid, s);
-    case 256: return launch_short_t<64, 4>(a, cigar, persistent, block_threads, grid, s);
+    case 16: return launch_short_t<16, 1, RowT>(a, cigar, persistent, bt, grid, s);
+    case 32: return launch_short_t<32, 1, RowT>(a, cigar, persistent, bt, grid, s);
+    case 64: return launch_short_t<64, 1, RowT>(a, cigar, persistent, bt, grid, s);
+    case 128: return launch_short_t<64, 2, RowT>(a, cigar, persistent, bt, grid, s);
+    case 256: return launch_short_t<64, 4, RowT>(a, cigar, persistent, bt, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int G, int DPL>
+hipError_t launch_short(const ShortArgs& a, int window, bool cigar, bool persistent,
+                        int block_threads, int grid, hipStream_t s) {
+    if (a.row_bytes == 1)
+        return launch_short_w<int8_t>(a, window, cigar, persistent, block_threads, grid, s);
+    return launch_short_w<int16_t>(a, window, cigar, persistent, block_threads, grid, s);
+}
+
+template <int G, int DPL, class RowT>
 static int occ_t(bool cigar, int bt, int lds) {
     int blocks = 0;
     hipError_t e = cigar ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &blocks, (const void*)k_short<G, DPL, true>, bt, lds)
+                               &blocks, (const void*)k_short<G, DPL, true, RowT>, bt, lds)
                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &blocks, (const void*)k_short<G, DPL, false>, bt, lds);
+                               &blocks, (const void*)k_short<G, DPL, false, RowT>, bt, lds);
     return e == hipSuccess ? blocks : 0;
 }
 
-int short_max_blocks_per_cu(int window, bool cigar, int bt, int lds_per_block) {
+template <class RowT>
+static int occ_w(int window, bool cigar, int bt, int lds) {
     switch (window) {
-    case 16: return occ_t<16, 1>(cigar, bt, lds_per_block);
-    case 32: return occ_t<32, 1>(cigar, bt, lds_per_block);
-    case 64: return occ_t<64, 1>(cigar, bt, lds_per_block);
-    case 128: return occ_t<64, 2>(cigar, bt, lds_per_block);
-    case 256: return occ_t<64, 4>(cigar, bt, lds_per_block);
+    case 16: return occ_t<16, 1, RowT>(cigar, bt, lds);
+    case 32: return occ_t<32, 1, RowT>(cigar, bt, lds);
+    case 64: return occ_t<64, 1, RowT>(cigar, bt, lds);
+    case 128: return occ_t<64, 2, RowT>(cigar, bt, lds);
+    case 256: return occ_t<64, 4, RowT>(cigar, bt, lds);
     default: return 0;
     }
+}
+
+int short_max_blocks_per_cu(int window, bool cigar, int bt, int lds_per_block, int row_bytes) {
+    return row_bytes == 1 ? occ_w<int8_t>(window, cigar, bt, lds_per_block)
+                          : occ_w<int16_t>(window, cigar, bt, lds_per_block);
 }
 
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds, int lds_bytes,
@@ -1130,16 +1167,17 @@ hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const 
 hipError_t launch_bucket_keys(const PairDesc* pairs, size_t n, uint32_t* keys, uint32_t* hist,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, s, hist, 0u, (size_t)BUCKET_KEYS);
+    const size_t blocks = (n + BUCKET_CHUNK - 1) / BUCKET_CHUNK;
     if (n)
-        hipLaunchKernelGGL(k_bucket_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, pairs, n, keys,
-                           hist);
+        hipLaunchKernelGGL(k_bucket_keys, dim3(blocks), dim3(256), 0, s, pairs, n, keys, hist);
     return hipGetLastError();
 }
 
 hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, uint64_t* cursor, uint32_t* order,
                                  hipStream_t s) {
+    const size_t blocks = (n + BUCKET_CHUNK - 1) / BUCKET_CHUNK;
     if (n)
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, n,
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, s, keys, n,
                            (unsigned long long*)cursor, order);
     return hipGetLastError();
 }

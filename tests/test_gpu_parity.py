@@ -110,3 +110,44 @@ def test_host_memory_path(aligner, oracle_lib, synth_lib):
     b = synth_lib.workload("pairs100_e4_5m", 5000, first=1000)
     got = aligner.align_host(b, PEN)
     assert_same(got, oracle_of(oracle_lib, b), b, "host")
+
+
+def test_graph_replays_match_eager(aligner, oracle_lib, synth_lib, wfa):
+    """The captured-graph path, replayed several times with other device work
+    in between, gives the eager path's bytes on every replay."""
+    import torch
+
+    say("case: graph replays vs eager, pairs100_e4 30k")
+    b = synth_lib.workload("pairs100_e4_5m", 30_000, first=123)
+    n = len(b)
+    pat, txt, pairs = aligner.to_device(b)
+    scores, runs, offsets = aligner.alloc_outputs(n, n * 40)
+    aligner.set_options(schedule=wfa.WFA_SCHED_PERSISTENT, use_graph=-1)
+    need = aligner.align_device(pat, txt, pairs, n, scores, runs, offsets)
+    eager = (scores.cpu().numpy().copy(), runs[:need].cpu().numpy().copy(),
+             offsets.cpu().numpy().copy())
+    aligner.set_options(schedule=wfa.WFA_SCHED_PERSISTENT, use_graph=1)
+    for rep in range(4):
+        scores.fill_(-7)
+        runs.fill_(0)
+        junk = torch.randn(1 << 20, device=scores.device).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        need2 = aligner.align_device(pat, txt, pairs, n, scores, runs, offsets)
+        assert aligner.stats()["graph_replayed"] == 1
+        assert need2 == need
+        assert np.array_equal(scores.cpu().numpy(), eager[0]), f"replay {rep} scores"
+        assert np.array_equal(runs[:need].cpu().numpy(), eager[1]), f"replay {rep} runs"
+        assert np.array_equal(offsets.cpu().numpy(), eager[2]), f"replay {rep} offsets"
+        del junk
+    ref = oracle_of(oracle_lib, b)
+    assert_same((eager[0], eager[1].view(np.uint32), eager[2].view(np.uint64)), ref, b, "eager")
+
+
+def test_repeat_runs_identical(aligner, synth_lib, wfa):
+    say("case: 5 repeated runs, uneven workload, byte-identical")
+    b = synth_lib.workload("uneven50_300_2m", 20_000, first=999)
+    first = aligner.align(b, PEN)
+    for _ in range(4):
+        again = aligner.align(b, PEN)
+        for a_, b_ in zip(first, again):
+            assert np.array_equal(a_, b_)
