@@ -414,11 +414,10 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
         if (ascii) {
             HIPCHK(launch_scan(SCAN_WORDS_P, in_pairs, N, ws.ws_p.as<uint64_t>(), ws.scan_tmp.ptr, q));
             HIPCHK(launch_scan(SCAN_WORDS_T, in_pairs, N, ws.ws_t.as<uint64_t>(), ws.scan_tmp.ptr, q));
-            HIPCHK(launch_pack_pairs(in_pairs, N, (const uint8_t*)in_p, 0, ws.ws_p.as<uint64_t>(),
-                                     (st.max_p + 31) / 32, ws.words_p.as<uint64_t>(),
-                                     ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
-            HIPCHK(launch_pack_pairs(in_pairs, N, (const uint8_t*)in_t, 1, ws.ws_t.as<uint64_t>(),
-                                     (st.max_t + 31) / 32, ws.words_t.as<uint64_t>(),
+            HIPCHK(launch_pack_pairs(in_pairs, N, (const uint8_t*)in_p, (const uint8_t*)in_t,
+                                     ws.ws_p.as<uint64_t>(), ws.ws_t.as<uint64_t>(),
+                                     (st.max_p + 31) / 32, (st.max_t + 31) / 32,
+                                     ws.words_p.as<uint64_t>(), ws.words_t.as<uint64_t>(),
                                      ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
         }
         HIPCHK(launch_fill_u32(ws.nruns.as<uint32_t>(), 0u, N, q));

@@ -91,12 +91,15 @@ size_t scan_temp_bytes(size_t n);
 hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, void* temp,
                        hipStream_t s);
 
-// ASCII -> PACKED2 for the pattern (which = 0) or text (which = 1) side of
-// `pairs`, writing new descriptors with word starts.  Sets *err_pair to the
-// lowest pair index holding a non-ACGT byte (initialise to UINT64_MAX).
-hipError_t launch_pack_pairs(const PairDesc* pairs, size_t n, const uint8_t* ascii, int which,
-                             const uint64_t* word_starts, uint32_t max_words, uint64_t* words,
-                             PairDesc* packed_pairs, unsigned long long* err_pair, hipStream_t s);
+// ASCII -> PACKED2 for both sides of `pairs` (word starts from the scans of
+// ceil(len/32)), writing descriptors with word starts into packed_pairs.
+// Sets *err_pair to the lowest pair index holding a non-ACGT byte
+// (initialise to UINT64_MAX).
+hipError_t launch_pack_pairs(const PairDesc* pairs, size_t n, const uint8_t* pascii,
+                             const uint8_t* tascii, const uint64_t* ws_p, const uint64_t* ws_t,
+                             uint32_t max_words_p, uint32_t max_words_t, uint64_t* words_p,
+                             uint64_t* words_t, PairDesc* packed_pairs, unsigned long long* err_pair,
+                             hipStream_t s);
 // ASCII -> PACKED2 for independent sequences (public wfa_pack2bit);
 // word_starts[0..n] is the exclusive scan of ceil(len/32), total_words its end.
 hipError_t launch_pack_seqs(const uint8_t* ascii, const uint64_t* starts, const uint32_t* lens,

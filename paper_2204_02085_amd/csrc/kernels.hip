@@ -64,8 +64,8 @@ __device__ __forceinline__ uint32_t cdiv32(uint32_t a) { return (a + 31u) >> 5; 
 // ---------------------------------------------------------------------------
 // planning
 // ---------------------------------------------------------------------------
-__global__ void k_batch_stats(const PairDesc* __restrict__ pairs, size_t n, BatchStats* out,
-                              uint32_t max_len) {
+__global__ __launch_bounds__(256) void k_batch_stats(const PairDesc* __restrict__ pairs, size_t n,
+                                                     BatchStats* out, uint32_t max_len) {
     uint32_t mp = 0, mt = 0, md = 0, tl = 0;
     unsigned long long wp = 0, wt = 0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -89,11 +89,33 @@ __global__ void k_batch_stats(const PairDesc* __restrict__ pairs, size_t n, Batc
         wp += __shfl_xor(wp, off);
         wt += __shfl_xor(wt, off);
     }
+    // one set of atomics per block
+    __shared__ uint32_t smax[3][4], sor[4];
+    __shared__ unsigned long long ssum[2][4];
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        smax[0][wave] = mp;
+        smax[1][wave] = mt;
+        smax[2][wave] = md;
+        sor[wave] = tl;
+        ssum[0][wave] = wp;
+        ssum[1][wave] = wt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int w = 1; w < nw; w++) {
+            mp = max(mp, smax[0][w]);
+            mt = max(mt, smax[1][w]);
+            md = max(md, smax[2][w]);
+            tl |= sor[w];
+            wp += ssum[0][w];
+            wt += ssum[1][w];
+        }
         atomicMax(&out->max_p, mp);
         atomicMax(&out->max_t, mt);
         atomicMax(&out->max_absdiff, md);
-        atomicOr(&out->too_long, tl);
+        if (tl) atomicOr(&out->too_long, tl);
         atomicAdd((unsigned long long*)&out->words_p, wp);
         atomicAdd((unsigned long long*)&out->words_t, wt);
     }
@@ -212,16 +234,22 @@ __device__ __forceinline__ uint32_t pack4(uint32_t x, int cnt, bool& ok) {
 }
 
 __device__ __forceinline__ uint64_t pack_word(const uint8_t* __restrict__ ascii, uint64_t b0,
-                                              int cnt, bool& ok) {
+                                              int cnt, bool& ok, bool interior) {
     // aligned dwords covering [b0, b0 + cnt); only dwords holding a byte of the
-    // range are read
+    // range are read (an interior word's 36-byte span lies inside its sequence
+    // whenever the next word exists, so it is read without guards)
     const uintptr_t first = (uintptr_t)ascii + b0;
     const uintptr_t a0 = first & ~(uintptr_t)3;
     const uintptr_t last = (first + cnt - 1) >> 2;
     const uint32_t* src = (const uint32_t*)a0;
     uint32_t raw[9];
+    if (interior) {
 #pragma unroll
-    for (int d = 0; d < 9; d++) raw[d] = ((a0 >> 2) + d <= last) ? src[d] : 0u;
+        for (int d = 0; d < 9; d++) raw[d] = (d < 8 || (a0 >> 2) + 8 <= last) ? src[d] : 0u;
+    } else {
+#pragma unroll
+        for (int d = 0; d < 9; d++) raw[d] = ((a0 >> 2) + d <= last) ? src[d] : 0u;
+    }
     const uint32_t sh = (uint32_t)(first & 3);
     uint64_t word = 0;
 #pragma unroll
@@ -234,11 +262,18 @@ __device__ __forceinline__ uint64_t pack_word(const uint8_t* __restrict__ ascii,
     return word;
 }
 
+// blockIdx.y selects the side: 0 patterns, 1 texts
 __global__ void k_pack_pairs(const PairDesc* __restrict__ pairs, size_t n,
-                             const uint8_t* __restrict__ ascii, int which,
-                             const uint64_t* __restrict__ word_starts, uint32_t max_words,
-                             uint64_t* __restrict__ words, PairDesc* __restrict__ packed,
-                             unsigned long long* err_pair) {
+                             const uint8_t* __restrict__ pascii, const uint8_t* __restrict__ tascii,
+                             const uint64_t* __restrict__ ws_p, const uint64_t* __restrict__ ws_t,
+                             uint32_t max_words_p, uint32_t max_words_t,
+                             uint64_t* __restrict__ words_p, uint64_t* __restrict__ words_t,
+                             PairDesc* __restrict__ packed, unsigned long long* err_pair) {
+    const int which = blockIdx.y;
+    const uint8_t* ascii = which ? tascii : pascii;
+    const uint64_t* word_starts = which ? ws_t : ws_p;
+    const uint32_t max_words = which ? max_words_t : max_words_p;
+    uint64_t* words = which ? words_t : words_p;
     const size_t total = n * (size_t)max_words;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
@@ -256,10 +291,11 @@ __global__ void k_pack_pairs(const PairDesc* __restrict__ pairs, size_t n,
                 packed[i].p_len = d.p_len;
             }
         }
-        if (w >= cdiv32(len)) continue;
+        const uint32_t nw = cdiv32(len);
+        if (w >= nw) continue;
         int cnt = (int)min(32u, len - 32u * w);
         bool ok = true;
-        words[word_starts[i] + w] = pack_word(ascii, start + 32ull * w, cnt, ok);
+        words[word_starts[i] + w] = pack_word(ascii, start + 32ull * w, cnt, ok, w + 1 < nw);
         if (!ok) atomicMin(err_pair, (unsigned long long)i);
     }
 }
@@ -281,7 +317,7 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
         const uint32_t len = lens[i];
         int cnt = (int)min(32u, len - 32u * w);
         bool ok = true;
-        words[t] = pack_word(ascii, starts[i] + 32ull * w, cnt, ok);
+        words[t] = pack_word(ascii, starts[i] + 32ull * w, cnt, ok, false);
         if (!ok) atomicMin(err_index, (unsigned long long)i);
     }
 }
@@ -921,19 +957,26 @@ __global__ void k_gather_general(const uint32_t* __restrict__ jobs, size_t njobs
 }
 
 // reversed runs -> caller buffer in alignment order (nothing is written if
-// the total exceeds the capacity)
+// the total exceeds the capacity).  COMPACT_LANES consecutive threads share a
+// pair, so slot reads and output writes of a pair are contiguous.
+constexpr int COMPACT_LANES = 16;
+
 __global__ void k_compact(const uint32_t* __restrict__ nruns, const uint64_t* __restrict__ run_src,
                           const uint32_t* __restrict__ slots, const uint32_t* __restrict__ gen_runs,
                           const uint64_t* __restrict__ offsets, size_t n,
                           uint32_t* __restrict__ out, uint64_t capacity) {
     if (offsets[n] > capacity) return;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
+    const size_t total = n * COMPACT_LANES;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = t / COMPACT_LANES;
+        const uint32_t r0 = (uint32_t)(t % COMPACT_LANES);
         const uint32_t cnt = nruns[i];
+        if (r0 >= cnt) continue;
         const uint64_t src = run_src[i];
         const uint32_t* s = (src & GEN_BIT) ? gen_runs + (src & ~GEN_BIT) : slots + src;
-        uint32_t* o = out + offsets[i];
-        for (uint32_t r = 0; r < cnt; r++) o[cnt - 1 - r] = s[r];
+        uint32_t* o = out + offsets[i] + (cnt - 1);
+        for (uint32_t r = r0; r < cnt; r += COMPACT_LANES) o[-(int64_t)r] = s[r];
     }
 }
 
@@ -1018,7 +1061,7 @@ hipError_t launch_batch_stats(const PairDesc* pairs, size_t n, BatchStats* out, 
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out,
                        0u, sizeof(BatchStats) / 4);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &out->first_too_long, ~0ull, (size_t)1);
-    if (n) hipLaunchKernelGGL(k_batch_stats, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, pairs, n,
+    if (n) hipLaunchKernelGGL(k_batch_stats, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n,
                               out, max_len);
     return hipGetLastError();
 }
@@ -1049,14 +1092,17 @@ hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, v
     return hipGetLastError();
 }
 
-hipError_t launch_pack_pairs(const PairDesc* pairs, size_t n, const uint8_t* ascii, int which,
-                             const uint64_t* word_starts, uint32_t max_words, uint64_t* words,
-                             PairDesc* packed_pairs, unsigned long long* err_pair, hipStream_t s) {
-    const size_t total = n * (size_t)(max_words ? max_words : 1);
+hipError_t launch_pack_pairs(const PairDesc* pairs, size_t n, const uint8_t* pascii,
+                             const uint8_t* tascii, const uint64_t* ws_p, const uint64_t* ws_t,
+                             uint32_t max_words_p, uint32_t max_words_t, uint64_t* words_p,
+                             uint64_t* words_t, PairDesc* packed_pairs, unsigned long long* err_pair,
+                             hipStream_t s) {
+    const uint32_t mw = max(max(max_words_p, max_words_t), 1u);
+    const size_t total = n * (size_t)mw;
     if (n)
-        hipLaunchKernelGGL(k_pack_pairs, dim3(grid_for(total, 256, 1 << 20)), dim3(256), 0, s, pairs,
-                           n, ascii, which, word_starts, max_words ? max_words : 1, words,
-                           packed_pairs, err_pair);
+        hipLaunchKernelGGL(k_pack_pairs, dim3(grid_for(total, 256, 1 << 19), 2), dim3(256), 0, s,
+                           pairs, n, pascii, tascii, ws_p, ws_t, max(max_words_p, 1u),
+                           max(max_words_t, 1u), words_p, words_t, packed_pairs, err_pair);
     return hipGetLastError();
 }
 
@@ -1159,8 +1205,8 @@ hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const 
                           const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
                           uint32_t* out, uint64_t capacity, hipStream_t s) {
     if (n)
-        hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256)), dim3(256), 0, s, nruns, run_src, slots,
-                           gen_runs, offsets, n, out, capacity);
+        hipLaunchKernelGGL(k_compact, dim3(grid_for(n * COMPACT_LANES, 256, 1 << 20)), dim3(256), 0, s,
+                           nruns, run_src, slots, gen_runs, offsets, n, out, capacity);
     return hipGetLastError();
 }
 

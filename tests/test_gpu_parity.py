@@ -151,3 +151,147 @@ def test_repeat_runs_identical(aligner, synth_lib, wfa):
         again = aligner.align(b, PEN)
         for a_, b_ in zip(first, again):
             assert np.array_equal(a_, b_)
+
+
+def _subset_result(res, idx):
+    """(scores, runs, offsets) of the pairs at `idx`, compacted."""
+    sc, runs, off = res
+    parts = [runs[int(off[i]):int(off[i + 1])] for i in idx]
+    counts = np.array([len(p) for p in parts], dtype=np.uint64)
+    o = np.zeros(len(idx) + 1, dtype=np.uint64)
+    np.cumsum(counts, out=o[1:])
+    r = np.concatenate(parts).astype(np.uint32) if parts else np.zeros(0, np.uint32)
+    return sc[idx], r, o
+
+
+def _full_size_check(aligner, oracle_lib, synth_lib, name, count, sample, seed):
+    b = synth_lib.workload(name, count)
+    say(f"case: {name} full size {len(b)} pairs, default schedule (the benchmarked launch)")
+    got = aligner.align(b, PEN, capacity=len(b) * 40 + 1024)
+    st = aligner.stats()
+    say(f"  stats: {st}")
+    check_invariants_vectorized(b, *got, PEN)
+    rng = np.random.default_rng(seed)
+    top = np.argsort(got[0], kind="stable")[-500:]
+    idx = np.unique(np.concatenate([rng.choice(len(b), sample, replace=False), top,
+                                    [0, len(b) - 1]]))
+    sub = b.subset(idx)
+    ref = oracle_of(oracle_lib, sub)
+    assert_same(_subset_result(got, idx), ref, sub, f"{name} sample")
+    check_sample_cigars(sub, *_subset_result(got, idx), PEN, range(0, len(sub), 25))
+    return st
+
+
+def test_pairs100_e4_full_size(aligner, oracle_lib, synth_lib):
+    """5,000,000 pairs of 100 bp at E = 4 % (the benchmark workload)."""
+    st = _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e4_5m", None, 50_000, 1)
+    assert st["short_pairs"] == st["pairs"]
+
+
+def test_pairs100_e2_full_size(aligner, oracle_lib, synth_lib):
+    """5,000,000 pairs of 100 bp at E = 2 %."""
+    _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e2_5m", None, 50_000, 2)
+
+
+def test_uneven_full_size(aligner, oracle_lib, synth_lib):
+    """2,000,000 uneven pairs (50-300 bp, 0-5 % edits) in one batch."""
+    _full_size_check(aligner, oracle_lib, synth_lib, "uneven50_300_2m", None, 20_000, 3)
+
+
+def test_long_reads_sample(aligner, oracle_lib, synth_lib, wfa):
+    """1-10 kbp pairs with 5-10 % events and indel runs (general kernel,
+    wavefront history in the HBM arena): score-only and CIGAR."""
+    say("case: long reads 1-10 kbp, score-only 192 pairs")
+    b = synth_lib.workload("long1k_10k_100k", 192)
+    got = aligner.align(b, PEN, cigar=False)
+    assert_same(got, oracle_of(oracle_lib, b, cigar=False), b, "long score")
+    say("case: long reads, CIGAR on the 48 shortest of them")
+    order = np.argsort(b.p_len, kind="stable")[:48]
+    sub = b.subset(order)
+    got = aligner.align(sub, PEN, capacity=200_000)
+    assert_same(got, oracle_of(oracle_lib, sub), sub, "long cigar")
+    check_invariants_vectorized(sub, *got, PEN)
+
+
+def test_capacity_error_then_copy(aligner, oracle_lib, synth_lib, wfa):
+    """A too-small CIGAR buffer returns WFA_E_CAPACITY with the needed size;
+    wfa_copy_last_cigars then delivers the same runs."""
+    say("case: capacity error path")
+    b = synth_lib.workload("pairs100_e4_5m", 2000, first=77)
+    got = aligner.align(b, PEN, capacity=10)  # the wrapper handles E_CAPACITY
+    assert aligner.last_needed() == len(got[1])
+    assert_same(got, oracle_of(oracle_lib, b), b, "capacity")
+
+
+def test_alphabet_error(aligner, synth_lib, wfa):
+    say("case: non-ACGT byte")
+    pairs = [(b"ACGT", b"ACGT"), (b"ACGTACGT", b"ACGNACGT"), (b"acgt", b"ACGT")]
+    b = synth_lib.from_pairs(pairs)
+    with pytest.raises(wfa.WFAError) as ei:
+        aligner.align(b, PEN)
+    assert ei.value.status == wfa.WFA_E_ALPHABET and ei.value.bad == 1
+
+
+def test_too_long_rejected(aligner, wfa):
+    """A descriptor over the length limit is rejected before any byte is read."""
+    import torch
+
+    say("case: length over WFA_MAX_LENGTH")
+    pairs = wfa.pairs_array(np.zeros(3, np.uint64), np.array([4, 4, wfa.WFA_MAX_LENGTH + 1], np.uint32),
+                            np.zeros(3, np.uint64), np.array([4, 4, 4], np.uint32))
+    dev = torch.from_numpy(pairs.view(np.uint8).copy()).cuda()
+    seq = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    scores, runs, offsets = aligner.alloc_outputs(3, 100)
+    with pytest.raises(wfa.WFAError) as ei:
+        aligner.align_device(seq, seq, dev, 3, scores, runs, offsets)
+    assert ei.value.status == wfa.WFA_E_TOO_LONG and ei.value.bad == 2
+
+
+def test_packed_input_and_pack_api(aligner, oracle_lib, synth_lib, wfa):
+    """PACKED2 input built with the oracle's plain packer gives the same
+    results as ASCII input; wfa_pack2bit reproduces the plain packer."""
+    import ctypes
+
+    import torch
+
+    say("case: PACKED2 input path and wfa_pack2bit")
+    b = synth_lib.workload("uneven50_300_2m", 3000, first=31)
+    n = len(b)
+    pw, tw, pst, tst = [], [], [], []
+    off_p = off_t = 0
+    for i in range(n):
+        p, t = b.pair(i)
+        wp_, wt_ = oracle_lib.pack2bit(p), oracle_lib.pack2bit(t)
+        pst.append(off_p)
+        tst.append(off_t)
+        pw.append(wp_)
+        tw.append(wt_)
+        off_p += len(wp_)
+        off_t += len(wt_)
+    pwords = np.concatenate(pw + [np.zeros(1, np.uint64)])
+    twords = np.concatenate(tw + [np.zeros(1, np.uint64)])
+    pairs = wfa.pairs_array(np.array(pst, np.uint64), b.p_len, np.array(tst, np.uint64), b.t_len)
+    dp = torch.from_numpy(pwords.view(np.uint8).copy()).cuda()
+    dt = torch.from_numpy(twords.view(np.uint8).copy()).cuda()
+    dpairs = torch.from_numpy(pairs.view(np.uint8).copy()).cuda()
+    scores, runs, offsets = aligner.alloc_outputs(n, n * 60)
+    need = aligner.align_device(dp, dt, dpairs, n, scores, runs, offsets, encoding=wfa.WFA_PACKED2)
+    got = (scores.cpu().numpy(), runs[:need].cpu().numpy().view(np.uint32),
+           offsets.cpu().numpy().view(np.uint64))
+    assert_same(got, oracle_of(oracle_lib, b), b, "packed2")
+
+    # wfa_pack2bit on the pattern side
+    ascii = torch.from_numpy(b.patterns.copy()).cuda()
+    starts = torch.from_numpy(b.p_off.view(np.int64).copy()).cuda()
+    lens = torch.from_numpy(b.p_len.view(np.int32).copy()).cuda()
+    words = torch.zeros(len(pwords) + 8, dtype=torch.int64, device="cuda")
+    ws = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    total = ctypes.c_size_t(0)
+    bad = ctypes.c_int64(0)
+    rc = wfa.wfa_pack2bit(aligner.ctx, ascii.data_ptr(), starts.data_ptr(), lens.data_ptr(), n,
+                          words.data_ptr(), words.numel(), ws.data_ptr(), ctypes.byref(total),
+                          ctypes.byref(bad), None)
+    assert rc == wfa.WFA_OK and bad.value == -1
+    assert total.value == len(pwords) - 1
+    assert np.array_equal(words[: total.value].cpu().numpy().view(np.uint64), pwords[:-1])
+    assert np.array_equal(ws[:n].cpu().numpy(), np.array(pst, np.int64))
