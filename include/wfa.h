@@ -217,25 +217,20 @@ const char *wfa_strerror(int status);
  * Serving: continuous batching of alignment requests.
  *
  * Requests (each a set of pairs) are submitted from any thread and get a
- * ticket.  A scheduler thread admits requests in arrival order while their
- * estimated device memory fits the budget (large requests are admitted in
- * chunks), launches admitted work as it arrives on several streams so that
- * requests overlap on the device, and completes each request when all its
- * chunks are done.  Results equal those of wfa_align_batch on the same pairs
- * alone.
+ * ticket.  One worker per stream forms a batch whenever it is free: it takes
+ * pending pairs in arrival order -- the rest of a request already running,
+ * then whole or partial later requests -- while the batch stays under
+ * max_chunk_pairs and the estimated device memory of everything admitted
+ * stays under the budget.  Batches of different workers run concurrently on
+ * their own streams, so requests that arrive while others are on the GPU
+ * join as soon as a worker and memory free up.  A request completes when its
+ * last pair does.  Results equal those of wfa_align_batch on the same pairs
+ * alone: every pair is aligned independently and deterministically.
  * ------------------------------------------------------------------------- */
 typedef struct wfa_server wfa_server;
 
-typedef struct {
-    size_t hbm_budget_bytes;  /* admission budget (0: 64 GiB)                   */
-    int32_t streams;          /* concurrent device streams (0: 4)               */
-    int32_t max_chunk_pairs;  /* pairs per launched chunk (0: 65536)            */
-    int32_t queue_limit;      /* requests waiting for admission (0: 1 << 20)     */
-    int32_t mode;             /* wfa_mode for every request                     */
-    wfa_penalties pen;
-} wfa_server_cfg;
-
-/* A request: host ASCII sequences, copied by wfa_server_submit. */
+/* A request: host ASCII sequences (p_start / t_start are byte offsets into
+ * `patterns` / `texts`).  wfa_server_submit copies everything it needs. */
 typedef struct {
     const uint8_t *patterns;
     const uint8_t *texts;
@@ -243,28 +238,63 @@ typedef struct {
     size_t num_pairs;
 } wfa_request;
 
+/* Optional replacement for the GPU engine (used to test the scheduler on a
+ * CPU, or to plug in another executor).  It aligns one merged batch in host
+ * memory with the server's penalties and mode and returns a WFA_* status;
+ * `runs` holds `capacity` words, *needed receives the runs required. */
+typedef int (*wfa_executor_fn)(void *user, const wfa_request *batch, int32_t *scores,
+                               uint32_t *runs, size_t capacity, uint64_t *offsets,
+                               size_t *needed);
+
+typedef struct {
+    size_t hbm_budget_bytes;   /* admission budget (0: 64 GiB)                   */
+    int32_t streams;           /* concurrent device streams, one worker each (0: 4) */
+    int32_t max_chunk_pairs;   /* pairs per launched batch (0: 65536)            */
+    int32_t queue_limit;       /* requests waiting for admission (0: 1 << 20)     */
+    int32_t mode;              /* wfa_mode for every request                     */
+    wfa_penalties pen;
+    wfa_executor_fn executor;  /* NULL: the GPU engine of `ctx`                  */
+    void *executor_user;
+} wfa_server_cfg;
+
 /* A finished request: host arrays owned by the server until the ticket is
  * released (wfa_server_release) or the server closes. */
 typedef struct {
     size_t num_pairs;
     const int32_t *scores;
     const uint32_t *cigar_runs;
-    const uint64_t *cigar_offsets; /* [num_pairs + 1]                           */
-    double submit_time_s;          /* seconds since the server opened           */
-    double admit_time_s;
-    double done_time_s;
-    int32_t status;
+    const uint64_t *cigar_offsets; /* [num_pairs + 1] (CIGAR mode)               */
+    double submit_time_s;          /* seconds since the server opened            */
+    double admit_time_s;           /* first pair admitted to the device          */
+    double done_time_s;            /* last pair finished                         */
+    int32_t status;                /* WFA_OK or the error of a batch it was in   */
 } wfa_result;
 
+typedef struct {
+    uint64_t submitted, completed, batches, pairs;
+    size_t budget_bytes;
+    size_t reserved_bytes;       /* reserved now                                  */
+    size_t max_reserved_bytes;   /* high-water mark (never above budget_bytes,
+                                    except a lone request larger than the budget) */
+    double busy_s;               /* summed engine time                            */
+} wfa_server_stats;
+
+/* Open a server on `ctx` (which must outlive it; NULL only with an executor).
+ * Each stream gets its own device workspace of budget/streams bytes. */
 int wfa_server_open(wfa_ctx *ctx, const wfa_server_cfg *cfg, wfa_server **out);
+/* Queue a request; *ticket identifies it.  WFA_E_BUSY if the queue is full. */
 int wfa_server_submit(wfa_server *srv, const wfa_request *req, uint64_t *ticket);
 /* Wait up to timeout_us (negative: forever) for a ticket.  Returns WFA_OK and
- * fills *out, or WFA_E_BUSY on time-out. */
+ * fills *out, WFA_E_BUSY on time-out, WFA_E_NOTFOUND for an unknown ticket. */
 int wfa_server_poll(wfa_server *srv, uint64_t ticket, int64_t timeout_us, wfa_result *out);
+/* Free a finished request's results. */
 int wfa_server_release(wfa_server *srv, uint64_t ticket);
-/* Bytes of device memory the admission controller reserves for a request. */
+/* Device bytes the admission controller reserves for a request: staged
+ * sequences and results plus the wavefront memory of each pair, estimated
+ * as O(s^2) from its length assuming up to 10 % divergence. */
 size_t wfa_server_estimate_bytes(const wfa_server *srv, const wfa_request *req);
-/* Finish all submitted work, stop the scheduler and free the server. */
+int wfa_server_get_stats(const wfa_server *srv, wfa_server_stats *out);
+/* Finish all submitted work, stop the workers and free the server. */
 int wfa_server_close(wfa_server *srv);
 
 #ifdef __cplusplus

@@ -34,7 +34,7 @@ EXPORTED = [
     "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_align_batch",
     "wfa_copy_last_cigars", "wfa_pack2bit", "wfa_last_stats", "wfa_strerror",
     "wfa_server_open", "wfa_server_submit", "wfa_server_poll", "wfa_server_release",
-    "wfa_server_estimate_bytes", "wfa_server_close",
+    "wfa_server_estimate_bytes", "wfa_server_get_stats", "wfa_server_close",
 ]
 
 PAIR_DTYPE = np.dtype([("p_start", "<u8"), ("t_start", "<u8"), ("p_len", "<u4"),
@@ -66,15 +66,32 @@ class wfa_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-class wfa_server_cfg(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int32),
-                ("max_chunk_pairs", ctypes.c_int32), ("queue_limit", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("pen", wfa_penalties)]
-
-
 class wfa_request(ctypes.Structure):
     _fields_ = [("patterns", ctypes.c_void_p), ("texts", ctypes.c_void_p),
                 ("pairs", ctypes.c_void_p), ("num_pairs", ctypes.c_size_t)]
+
+
+wfa_executor_fn = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(wfa_request),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32),
+                                   ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_size_t))
+
+
+class wfa_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int32),
+                ("max_chunk_pairs", ctypes.c_int32), ("queue_limit", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("pen", wfa_penalties),
+                ("executor", wfa_executor_fn), ("executor_user", ctypes.c_void_p)]
+
+
+class wfa_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("pairs", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_size_t), ("reserved_bytes", ctypes.c_size_t),
+                ("max_reserved_bytes", ctypes.c_size_t), ("busy_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class wfa_result(ctypes.Structure):
@@ -112,6 +129,7 @@ def _load():
         "wfa_server_poll": ([p, u64, i64, ctypes.POINTER(wfa_result)], ctypes.c_int),
         "wfa_server_release": ([p, u64], ctypes.c_int),
         "wfa_server_estimate_bytes": ([p, ctypes.POINTER(wfa_request)], sz),
+        "wfa_server_get_stats": ([p, ctypes.POINTER(wfa_server_stats)], ctypes.c_int),
         "wfa_server_close": ([p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -138,6 +156,7 @@ wfa_server_submit = lib.wfa_server_submit
 wfa_server_poll = lib.wfa_server_poll
 wfa_server_release = lib.wfa_server_release
 wfa_server_estimate_bytes = lib.wfa_server_estimate_bytes
+wfa_server_get_stats = lib.wfa_server_get_stats
 wfa_server_close = lib.wfa_server_close
 
 
@@ -288,3 +307,125 @@ class Aligner:
         if not cigar:
             return scores, None, None
         return scores, runs[:needed.value].copy(), offsets
+
+
+class Server:
+    """Continuous-batching alignment server (wraps wfa_server_*).
+
+    ``aligner`` supplies the GPU context; with ``executor`` (a Python callable
+    ``f(batch_dict) -> (scores, runs, offsets)``) the scheduler runs without a
+    GPU, which is how its admission and batching logic is tested on a CPU.
+    """
+
+    def __init__(self, aligner=None, hbm_budget_bytes=0, streams=4, max_chunk_pairs=65536,
+                 penalties=(4, 6, 2), cigar=True, executor=None, queue_limit=0):
+        cfg = wfa_server_cfg()
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        cfg.streams = streams
+        cfg.max_chunk_pairs = max_chunk_pairs
+        cfg.queue_limit = queue_limit
+        cfg.mode = WFA_CIGAR if cigar else WFA_SCORE
+        cfg.pen = wfa_penalties(*penalties)
+        self.cigar = cigar
+        self._keep = []
+        if executor is not None:
+            def trampoline(user, req, scores, runs, cap, offsets, needed):
+                try:
+                    r = req.contents
+                    n = r.num_pairs
+                    pairs = np.ctypeslib.as_array(
+                        ctypes.cast(r.pairs, ctypes.POINTER(ctypes.c_uint8)),
+                        shape=(n * PAIR_DTYPE.itemsize,)).view(PAIR_DTYPE)
+                    plen_total = int((pairs["p_start"] + pairs["p_len"]).max(initial=0))
+                    tlen_total = int((pairs["t_start"] + pairs["t_len"]).max(initial=0))
+                    pat = np.ctypeslib.as_array(ctypes.cast(r.patterns, ctypes.POINTER(ctypes.c_uint8)),
+                                                shape=(max(plen_total, 1),))
+                    txt = np.ctypeslib.as_array(ctypes.cast(r.texts, ctypes.POINTER(ctypes.c_uint8)),
+                                                shape=(max(tlen_total, 1),))
+                    sc, rr, off = executor(dict(patterns=pat, texts=txt, pairs=pairs.copy()))
+                    for i in range(n):
+                        scores[i] = int(sc[i])
+                    if self.cigar:
+                        needed[0] = len(rr)
+                        if len(rr) > cap:
+                            return WFA_E_CAPACITY
+                        for i in range(len(rr)):
+                            runs[i] = int(rr[i])
+                        for i in range(n + 1):
+                            offsets[i] = int(off[i])
+                    return WFA_OK
+                except Exception:  # noqa: BLE001 - reported as a device error
+                    import traceback
+
+                    traceback.print_exc()
+                    return WFA_E_DEVICE
+
+            fn = wfa_executor_fn(trampoline)
+            self._keep.append(fn)
+            cfg.executor = fn
+        ctx = aligner.ctx if aligner is not None else None
+        srv = ctypes.c_void_p()
+        rc = wfa_server_open(ctx, ctypes.byref(cfg), ctypes.byref(srv))
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_server_open")
+        self.srv = srv
+
+    def _request(self, batch):
+        pairs = pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len)
+        pat = np.ascontiguousarray(batch.patterns)
+        txt = np.ascontiguousarray(batch.texts)
+        req = wfa_request(pat.ctypes.data, txt.ctypes.data, pairs.ctypes.data, len(pairs))
+        return req, (pat, txt, pairs)
+
+    def submit(self, batch) -> int:
+        req, keep = self._request(batch)
+        t = ctypes.c_uint64(0)
+        rc = wfa_server_submit(self.srv, ctypes.byref(req), ctypes.byref(t))
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_server_submit")
+        del keep  # the server copied the request
+        return t.value
+
+    def estimate_bytes(self, batch) -> int:
+        req, keep = self._request(batch)
+        return int(wfa_server_estimate_bytes(self.srv, ctypes.byref(req)))
+
+    def poll(self, ticket: int, timeout_us: int = -1):
+        """Result dict of a finished ticket, or None on time-out."""
+        res = wfa_result()
+        rc = wfa_server_poll(self.srv, ticket, timeout_us, ctypes.byref(res))
+        if rc == WFA_E_BUSY:
+            return None
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_server_poll")
+        n = res.num_pairs
+        out = {"status": res.status, "submit": res.submit_time_s, "admit": res.admit_time_s,
+               "done": res.done_time_s, "num_pairs": n}
+        out["scores"] = np.ctypeslib.as_array(res.scores, shape=(n,)).copy() if n else \
+            np.zeros(0, np.int32)
+        if self.cigar:
+            off = np.ctypeslib.as_array(res.cigar_offsets, shape=(n + 1,)).copy()
+            total = int(off[-1])
+            out["offsets"] = off
+            out["runs"] = np.ctypeslib.as_array(res.cigar_runs, shape=(total,)).copy() if total \
+                else np.zeros(0, np.uint32)
+        return out
+
+    def release(self, ticket: int):
+        wfa_server_release(self.srv, ticket)
+
+    def stats(self) -> dict:
+        st = wfa_server_stats()
+        wfa_server_get_stats(self.srv, ctypes.byref(st))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "srv", None):
+            wfa_server_close(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -89,52 +89,66 @@ int Workspace::ensure_pinned(size_t bytes) {
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
-extern "C" int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx** out) {
-    if (!out) return WFA_E_INVAL;
-    *out = nullptr;
+int engine_init(Engine* e, int device, size_t budget) {
     int ndev = 0;
     hipError_t he = hipGetDeviceCount(&ndev);
     if (he != hipSuccess || device < 0 || device >= ndev) {
         if (std::getenv("WFA_DEBUG"))
-            std::fprintf(stderr, "wfa_ctx_create: hipGetDeviceCount -> %s, %d devices\n",
+            std::fprintf(stderr, "libwfa: hipGetDeviceCount -> %s, %d devices\n",
                          hipGetErrorString(he), ndev);
         (void)hipGetLastError();
         return WFA_E_DEVICE;
     }
     he = hipSetDevice(device);
     if (he != hipSuccess) {
-        if (std::getenv("WFA_DEBUG"))
-            std::fprintf(stderr, "wfa_ctx_create: hipSetDevice -> %s\n", hipGetErrorString(he));
+        std::fprintf(stderr, "libwfa: hipSetDevice -> %s\n", hipGetErrorString(he));
         return WFA_E_DEVICE;
     }
-    wfa_ctx* c = new wfa_ctx();
-    c->device = device;
-    c->ws.budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)64 << 30);
-    he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    e->device = device;
+    e->ws.budget = budget ? budget : ((size_t)64 << 30);
+    // default priority: every stream of the library runs at the same priority
+    he = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking);
     if (he != hipSuccess) {
-        if (std::getenv("WFA_DEBUG"))
-            std::fprintf(stderr, "wfa_ctx_create: hipStreamCreate -> %s\n", hipGetErrorString(he));
-        delete c;
+        std::fprintf(stderr, "libwfa: hipStreamCreate -> %s\n", hipGetErrorString(he));
+        e->stream = nullptr;
         return WFA_E_DEVICE;
     }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
-    if (c->num_cus <= 0) c->num_cus = 256;
-    for (auto& e : c->ev) (void)hipEventCreate(&e);
-    std::memset(&c->opt, 0, sizeof(c->opt));
-    std::memset(&c->last, 0, sizeof(c->last));
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) e->num_cus = prop.multiProcessorCount;
+    if (e->num_cus <= 0) e->num_cus = 256;
+    for (auto& ev : e->ev) (void)hipEventCreate(&ev);
+    std::memset(&e->opt, 0, sizeof(e->opt));
+    std::memset(&e->last, 0, sizeof(e->last));
+    return WFA_OK;
+}
+
+void engine_destroy(Engine* e) {
+    (void)hipSetDevice(e->device);
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    graph_cache_clear(e);
+    e->ws.release_all();
+    for (auto& ev : e->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    e->stream = nullptr;
+}
+
+extern "C" int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx** out) {
+    if (!out) return WFA_E_INVAL;
+    *out = nullptr;
+    wfa_ctx* c = new wfa_ctx();
+    const int rc = engine_init(c, device, hbm_budget_bytes);
+    if (rc != WFA_OK) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return WFA_OK;
 }
 
 extern "C" void wfa_ctx_destroy(wfa_ctx* ctx) {
     if (!ctx) return;
-    (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
-    graph_cache_clear(ctx);
-    ctx->ws.release_all();
-    for (auto& e : ctx->ev) (void)hipEventDestroy(e);
-    (void)hipStreamDestroy(ctx->stream);
+    engine_destroy(ctx);
     delete ctx;
 }
 

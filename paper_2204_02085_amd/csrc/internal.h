@@ -120,4 +120,6 @@ int short_plan(Engine* ctx, const wfa::Pen& pen, bool cigar, int window, int cap
 int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
                  int64_t* bad_pair);
 void graph_cache_clear(Engine* e);
+int engine_init(Engine* e, int device, size_t budget);
+void engine_destroy(Engine* e);
 void destroy_graph(GraphEntry& g);
