@@ -7,10 +7,13 @@ aligns 5 million 100 bp pairs at E = 2 % and 4 % (Results); its read set is
 not public, so a seeded generator stands in for it.
 
 One step = one wfa_align_batch call over the whole batch with ASCII inputs
-already resident in HBM: 2-bit packing, bucketing, the persistent short-pair
-kernel (replayed as a captured hipGraph), CIGAR offsets and compaction into
-the caller's device buffers.  The same batch through the plain (one launch,
-no bucketing) schedule is reported beside it.
+already resident in HBM: 2-bit packing, (bucketing,) the short-pair kernel,
+the general kernel for any pair it hands over, CIGAR offsets and compaction
+into the caller's device buffers.  The launch options are picked by the
+library's autotuner on a sample of the batch before timing.  The persistent
+(bucketed, graph-replayed) and the plain (one launch, no bucketing)
+schedules with default knobs are timed on the same bytes and reported
+beside it, as is a serving run (p50/p99 latency under Poisson load).
 
 Printed: one JSON line (see the keys below).  `roofline` describes the
 dominant kernel (the short-pair alignment kernel); its duration comes from
@@ -50,10 +53,20 @@ def parse():
     ap.add_argument("--pairs", type=int, default=5_000_000)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--tune-sample", type=int, default=262144)
     ap.add_argument("--cpu-pairs", type=int, default=400_000,
                     help="oracle sample size for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=120,
+                    help="requests of the serving run (0: skip)")
+    ap.add_argument("--serving-load", type=float, default=0.75,
+                    help="offered load as a fraction of the measured saturation rate")
     return ap.parse_args()
+
+
+def log(msg: str):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -83,10 +96,10 @@ def read_traffic(kernel_hash: str):
         return None
 
 
-def time_schedule(al, dev, n, steps, warmup, schedule):
+def time_schedule(al, dev, n, steps, warmup, options):
     import torch
 
-    al.set_options(schedule=schedule)
+    al.set_options(**options)
     pat, txt, pairs, scores, runs, offsets = dev
     for _ in range(warmup):
         al.align_device(pat, txt, pairs, n, scores, runs, offsets, (4, 6, 2), True)
@@ -100,6 +113,69 @@ def time_schedule(al, dev, n, steps, warmup, schedule):
     t1 = time.perf_counter()
     st = al.stats()
     return (t1 - t0), kernel_ms, st
+
+
+def serving_run(al, wfa, synth, n_req, load, seed=11):
+    """Poisson requests of 1-4096 pairs (log-uniform), 100-10,000 bp reads
+    with 1-10 % edits, CIGAR mode, 64 GiB admission budget, 4 streams.
+    First all requests at once (saturation), then Poisson arrivals at
+    `load` x the saturation request rate; latency = done - submit."""
+    import threading
+
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    sizes = np.round(2.0 ** rng.uniform(0, 12, n_req)).astype(int)
+    reqs, first = [], 0
+    for k in sizes:
+        reqs.append(synth.workload("serving_mix", int(k), first=first))
+        first += int(k)
+    total_pairs = int(sizes.sum())
+
+    def run(gaps):
+        srv = wfa.Server(al, hbm_budget_bytes=64 << 30, streams=4, max_chunk_pairs=16384)
+        tickets = [None] * n_req
+
+        def client():
+            t_next = time.perf_counter()
+            for i in range(n_req):
+                t_next += gaps[i]
+                dt = t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(reqs[i])
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        res = [srv.poll(t) for t in tickets]
+        t1 = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        bad = [r for r in res if r["status"] != 0]
+        if bad:
+            raise RuntimeError(f"{len(bad)} serving requests failed")
+        lat = np.array([r["done"] - r["submit"] for r in res]) * 1e3
+        wait = np.array([r["admit"] - r["submit"] for r in res]) * 1e3
+        span = max(r["done"] for r in res) - min(r["submit"] for r in res)
+        return {"pairs_per_s": total_pairs / span, "wall_s": t1 - t0,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "admit_wait_p99_ms": float(np.percentile(wait, 99)), "batches": st["batches"],
+                "max_reserved_gib": st["max_reserved_bytes"] / 2**30}
+
+    log(f"serving: {n_req} requests, {total_pairs} pairs; saturation run")
+    sat = run(np.zeros(n_req))
+    log(f"serving saturation: {sat}")
+    sat_req_rate = n_req / (sat["wall_s"])
+    lam = load * sat_req_rate
+    gaps = rng.exponential(1.0 / lam, n_req)
+    loaded = run(gaps)
+    return {"workload": "serving_mix: Poisson requests of 1-4096 pairs (log-uniform), "
+                        "100-10,000 bp log-uniform, 1-10 % edits, CIGAR",
+            "requests": n_req, "pairs": total_pairs, "budget_gib": 64, "streams": 4,
+            "saturation": sat, "offered_load": load, "offered_req_per_s": lam,
+            "at_load": loaded, "p50_ms": loaded["p50_ms"], "p99_ms": loaded["p99_ms"]}
 
 
 def main():
@@ -124,17 +200,33 @@ def main():
     scores, runs, offsets = al.alloc_outputs(n, cap, True)
     dev = (pat, txt, pairs, scores, runs, offsets)
 
-    # batched: persistent + bucketed + graph (default schedule)
-    el, kms, st = time_schedule(al, dev, n, args.steps, args.warmup, wfa.WFA_SCHED_AUTO)
+    # the autotuner picks the launch options on a sample of this batch
+    # (outside the timed region); every candidate must give identical bytes
+    log(f"generated {n} pairs in {t_gen:.1f} s; autotuning")
+    t_tune = time.perf_counter()
+    tuned = al.autotune(pat, txt, pairs, n, (4, 6, 2), True, sample_pairs=args.tune_sample)
+    t_tune = time.perf_counter() - t_tune
+
+    log(f"autotuned in {t_tune:.1f} s: {tuned}; timing {args.steps} steps")
+    el, kms, st = time_schedule(al, dev, n, args.steps, args.warmup, tuned)
+    log(f"tuned: {n * args.steps / el / 1e6:.1f} M pairs/s")
     ms_step = el / args.steps * 1e3
     value = n * args.steps / el
     kernel_ms = float(np.mean(kms))
     needed = al.last_needed()
+    tuned_stats = st
+    got_scores = scores.cpu().numpy().copy()
 
-    # plain per-batch kernel on the same bytes
-    pel, pkms, pst = time_schedule(al, dev, n, args.plain_steps, 1, wfa.WFA_SCHED_PLAIN)
+    # persistent + bucketed + graph with default knobs, and the plain per-batch kernel
+    log("timing persistent and plain schedules")
+    bel, bkms, bst = time_schedule(al, dev, n, args.plain_steps, 1,
+                                   {"schedule": wfa.WFA_SCHED_PERSISTENT})
+    batched_value = n * args.plain_steps / bel
+    pel, pkms, pst = time_schedule(al, dev, n, args.plain_steps, 1, {"schedule": wfa.WFA_SCHED_PLAIN})
     plain_value = n * args.plain_steps / pel
     plain_kernel_ms = float(np.mean(pkms))
+    if not np.array_equal(scores.cpu().numpy(), got_scores):
+        raise RuntimeError("plain and tuned schedules disagree")
 
     # results of both schedules are identical (cheap check on the last step)
     torch.cuda.synchronize()
@@ -148,6 +240,7 @@ def main():
     if args.cpu_pairs > 0:
         import oracle
 
+        log("CPU oracle baseline")
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         sample = synth.workload(args.workload, min(args.cpu_pairs, n))
         t0 = time.perf_counter()
@@ -164,6 +257,11 @@ def main():
         if not np.array_equal(got, ref.scores):
             print("WARNING: GPU scores differ from the oracle sample", file=sys.stderr)
 
+    serving = None
+    if args.serving_requests > 0:
+        log(f"serving run: {args.serving_requests} requests")
+        serving = serving_run(al, wfa, synth, args.serving_requests, args.serving_load)
+
     roofline = None
     if cells_pp is not None and kernel_ms > 0:
         ops = n * (cells_pp * OPS_PER_CELL + windows_pp * OPS_PER_WINDOW)
@@ -171,7 +269,8 @@ def main():
         traffic = read_traffic(kernel_source_hash())
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / PEAK_INT_OPS,
-                    "traffic": traffic, "kernel": "k_short<32,1,cigar>",
+                    "traffic": traffic,
+                    "kernel": f"k_short<window {tuned['window'] or 'auto'}, cigar>",
                     "kernel_ms": kernel_ms, "ops_per_launch": ops,
                     "cells_per_pair": cells_pp, "windows_per_pair": windows_pp}
 
@@ -191,16 +290,24 @@ def main():
         "config": {"workload": args.workload, "pairs": n, "read_length": 100,
                    "edits": 4 if "e4" in args.workload else 2, "penalties": [4, 6, 2],
                    "mode": "cigar", "input": "ASCII in HBM",
-                   "schedule": "persistent+bucketed+hipGraph"},
+                   "schedule": "autotuned (see autotuned_options)"},
         "gcups_equivalent": gcups,
         "cigar_runs": needed,
-        "batched_vs_plain": {"batched_pairs_per_s": value, "plain_pairs_per_s": plain_value,
-                             "speedup": value / plain_value,
-                             "batched_kernel_ms": kernel_ms, "plain_kernel_ms": plain_kernel_ms},
-        "phase_ms": {k: st[k] for k in ("ms_pack", "ms_align", "ms_general", "ms_compact",
-                                        "ms_total")},
+        "autotuned_options": tuned,
+        "autotune_seconds": t_tune,
+        "batched_vs_plain": {"tuned_pairs_per_s": value,
+                             "persistent_bucketed_graph_pairs_per_s": batched_value,
+                             "plain_pairs_per_s": plain_value,
+                             "speedup_tuned_vs_plain": value / plain_value,
+                             "speedup_persistent_vs_plain": batched_value / plain_value,
+                             "tuned_kernel_ms": kernel_ms,
+                             "persistent_kernel_ms": float(np.mean(bkms)),
+                             "plain_kernel_ms": plain_kernel_ms},
+        "phase_ms": {k: tuned_stats[k] for k in ("ms_pack", "ms_align", "ms_general", "ms_compact",
+                                                 "ms_total")},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
         "gen_seconds": t_gen,
     }
     al.close()

@@ -6,7 +6,7 @@ carry the C names; ``Aligner`` adds a convenience layer that moves numpy
 arrays into torch device tensors (PyTorch provides device memory and
 streams, nothing else).
 
-The library must be built (``python -m paper_2204_02085_amd.build``); if it
+The library must be built (``python paper_2204_02085_amd/build.py``); if it
 is missing, importing the binding raises ``ImportError`` -- there is no CPU
 fallback.
 """
@@ -32,7 +32,7 @@ WFA_MAX_LENGTH = 1 << 26
 
 EXPORTED = [
     "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_align_batch",
-    "wfa_copy_last_cigars", "wfa_pack2bit", "wfa_last_stats", "wfa_strerror",
+    "wfa_copy_last_cigars", "wfa_pack2bit", "wfa_autotune", "wfa_last_stats", "wfa_strerror",
     "wfa_server_open", "wfa_server_submit", "wfa_server_poll", "wfa_server_release",
     "wfa_server_estimate_bytes", "wfa_server_get_stats", "wfa_server_close",
 ]
@@ -104,7 +104,7 @@ class wfa_result(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2204_02085_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built: run `python paper_2204_02085_amd/build.py`")
     # torch ships its own HIP runtime under the same soname; load it first so
     # that the process holds exactly one HIP runtime, shared with torch.
     import torch  # noqa: F401
@@ -120,6 +120,9 @@ def _load():
                              ctypes.POINTER(i64), p], ctypes.c_int),
         "wfa_copy_last_cigars": ([p, p, sz, p], ctypes.c_int),
         "wfa_pack2bit": ([p, p, p, p, sz, p, sz, p, ctypes.POINTER(sz), ctypes.POINTER(i64), p],
+                         ctypes.c_int),
+        "wfa_autotune": ([p, p, p, p, sz, ctypes.c_int, ctypes.c_int, wfa_penalties, ctypes.c_int,
+                          sz, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(wfa_options)],
                          ctypes.c_int),
         "wfa_last_stats": ([p, ctypes.POINTER(wfa_stats)], ctypes.c_int),
         "wfa_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -149,6 +152,7 @@ wfa_set_options = lib.wfa_set_options
 wfa_align_batch = lib.wfa_align_batch
 wfa_copy_last_cigars = lib.wfa_copy_last_cigars
 wfa_pack2bit = lib.wfa_pack2bit
+wfa_autotune = lib.wfa_autotune
 wfa_last_stats = lib.wfa_last_stats
 wfa_strerror = lib.wfa_strerror
 wfa_server_open = lib.wfa_server_open
@@ -215,6 +219,18 @@ class Aligner:
         rc = wfa_set_options(self.ctx, ctypes.byref(o))
         if rc != WFA_OK:
             raise WFAError(rc, "wfa_set_options")
+
+    def autotune(self, patterns, texts, pairs, n, penalties=(4, 6, 2), cigar=True,
+                 encoding=WFA_ASCII, sample_pairs=0, cache_path=None, force=False) -> dict:
+        """wfa_autotune on device tensors; returns the chosen options."""
+        o = wfa_options()
+        rc = wfa_autotune(self.ctx, patterns.data_ptr(), texts.data_ptr(), pairs.data_ptr(), n,
+                          encoding, WFA_DEVICE, wfa_penalties(*penalties),
+                          WFA_CIGAR if cigar else WFA_SCORE, sample_pairs,
+                          cache_path.encode() if cache_path else None, int(force), ctypes.byref(o))
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_autotune")
+        return {f: getattr(o, f) for f, _ in o._fields_}
 
     def stats(self) -> dict:
         s = wfa_stats()

@@ -1,6 +1,7 @@
 """Build libwfa.so for gfx950 with hipcc (in-tree, no JIT cache).
 
-Usage: python -m paper_2204_02085_amd.build
+Usage: python paper_2204_02085_amd/build.py
+(run as a file: importing the package itself loads the library it builds)
 """
 from __future__ import annotations
 
@@ -11,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwfa.so")
-SOURCES = ["kernels.hip", "api.cpp", "align.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "align.cpp", "server.cpp", "autotune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

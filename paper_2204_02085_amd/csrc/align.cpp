@@ -135,19 +135,33 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
 
     RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
     DevFlags* flags = ws.flags.as<DevFlags>();
+    // The arena keeps whatever size it reached (re-allocating tens of GB per
+    // batch costs more than the alignment); it grows, up to 90 % of the
+    // unused budget, only when the current slices do not fit in it.
     int attempts = 0;
     while (!pending.empty()) {
         if (++attempts > 40) return WFA_E_NOMEM;
-        const size_t free_bytes = ws.budget > ws.total ? ws.budget - ws.total + ws.arena.bytes : 0;
-        size_t conc = (size_t)(free_bytes * 0.9 / slice);
+        const size_t free_bytes = ws.budget > ws.total ? ws.budget - ws.total : 0;
+        const size_t want = std::min(pending.size(), (size_t)1 << 20) * slice;
+        if (ws.arena.bytes < want && ws.arena.bytes < ws.arena.bytes + free_bytes * 9 / 10) {
+            const size_t target = std::min(want, ws.arena.bytes + free_bytes * 9 / 10);
+            if (target > ws.arena.bytes && target >= slice) {
+                ws.release(ws.arena);
+                // the device may hold less than the budget: halve until it fits
+                size_t t = target;
+                int rc = ws.ensure(ws.arena, t);
+                while (rc != WFA_OK && t / 2 >= slice) {
+                    t /= 2;
+                    rc = ws.ensure(ws.arena, t);
+                }
+                RCCHK(rc);
+            }
+        }
+        size_t conc = ws.arena.bytes / slice;
         if (e->opt.general_pairs > 0) conc = std::min(conc, (size_t)e->opt.general_pairs);
         conc = std::min(conc, pending.size());
         conc = std::min(conc, (size_t)1 << 20);
-        if (conc == 0) {
-            if (cigar) return WFA_E_NOMEM;
-            return WFA_E_NOMEM;
-        }
-        RCCHK(ws.ensure(ws.arena, conc * slice));
+        if (conc == 0) return WFA_E_NOMEM;
         RCCHK(ws.ensure(ws.jobs, conc * 4));
         RCCHK(ws.ensure(ws.job_nruns, conc * 4));
         RCCHK(ws.ensure(ws.job_offsets, (conc + 1) * 8));
@@ -206,8 +220,6 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             std::sort(failed.begin(), failed.end());
             pending.swap(failed);
             slice *= 4;
-            // the arena is regrown for the larger slices
-            ws.release(ws.arena);
         } else {
             pending.clear();
         }

@@ -20,6 +20,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <thread>
 #include <vector>
 
@@ -77,18 +78,22 @@ struct wfa_server {
 namespace {
 
 // Device bytes of one pair: staged sequences, packed words, descriptors and
-// results, plus wavefront memory.  A pair at divergence d has a score near
-// d * max(n, m) * max(x, o + e); its wavefronts hold about s^2 / (g e)
-// offsets over all steps (12 bytes each with history) or one ring of
-// (pre + 1) rows of n + m + 1 offsets (score only).  d = 10 %.
+// results, plus wavefront memory.  A pair with a fraction d of edits, a third
+// each substitutions (cost x) and single-base gaps (cost o + e), scores
+// about s = d * max(n, m) * (x + 2 (o + e)) / 3; its wavefronts hold about
+// s^2 / (g e) offsets over all steps (12 bytes each with history), or one
+// ring of (pre + 1) rows of n + m + 1 offsets (score only).  d = 6 %, the
+// middle of the 1-10 % the server is sized for; a pair that needs more is
+// still aligned exactly (the engine re-runs it with a larger arena slice).
 size_t pair_bytes(const wfa_server_cfg& cfg, uint32_t n, uint32_t m) {
     const double x = cfg.pen.mismatch, o = cfg.pen.gap_open, e = cfg.pen.gap_extend;
+    const double g = std::gcd(std::gcd(cfg.pen.mismatch, cfg.pen.gap_open), cfg.pen.gap_extend);
     const double L = std::max(n, m);
     size_t io = (size_t)n + m + 2 * (((size_t)n + 31) / 32 + ((size_t)m + 31) / 32) * 8 + 64;
-    const double s = 0.10 * L * std::max(x, o + e) + o + e;
+    const double s = 0.06 * L * (x + 2 * (o + e)) / 3 + o + e;
     double wf;
     if (cfg.mode == WFA_CIGAR) {
-        wf = 12.0 * s * s / e + 16.0 * (s / e + 1);
+        wf = 12.0 * s * s / (g * e) + 16.0 * (s / g + 1);
         io += (size_t)(4.0 * 2 * (s / std::min(x, e) + 1));
     } else {
         const double pre = std::max(x, o + e) / e;
@@ -104,7 +109,13 @@ int run_batch(wfa_server* srv, Engine* eng, const wfa_request& rq, std::vector<i
     const size_t n = rq.num_pairs;
     scores.assign(n, 0);
     offsets.assign(n + 1, 0);
-    size_t cap = cigar ? n * 16 + 64 : 0;
+    // runs: at most n + m + 1 per pair; a quarter of that covers any pair
+    // within ~10 % divergence, and a larger need triggers one exact re-run
+    size_t cap = 64;
+    if (cigar)
+        for (size_t i = 0; i < n; i++) cap += ((size_t)rq.pairs[i].p_len + rq.pairs[i].t_len) / 4 + 8;
+    else
+        cap = 0;
     for (int attempt = 0; attempt < 2; attempt++) {
         runs.assign(cap ? cap : 1, 0);
         size_t needed = 0;

@@ -295,3 +295,24 @@ def test_packed_input_and_pack_api(aligner, oracle_lib, synth_lib, wfa):
     assert total.value == len(pwords) - 1
     assert np.array_equal(words[: total.value].cpu().numpy().view(np.uint64), pwords[:-1])
     assert np.array_equal(ws[:n].cpu().numpy(), np.array(pst, np.int64))
+
+
+def test_autotuner_identical_and_cached(aligner, oracle_lib, synth_lib, tmp_path, wfa):
+    """The autotuner checks every candidate gives the same bytes, applies the
+    fastest, and reuses its JSON cache entry for the same workload class."""
+    say("case: autotuner on uneven 50-300 bp, 40k pairs")
+    b = synth_lib.workload("uneven50_300_2m", 40_000, first=4242)
+    n = len(b)
+    pat, txt, pairs = aligner.to_device(b)
+    cache = str(tmp_path / "tune.json")
+    chosen = aligner.autotune(pat, txt, pairs, n, PEN, True, sample_pairs=20_000, cache_path=cache)
+    say(f"  chosen: {chosen}")
+    import json
+
+    data = json.load(open(cache))
+    assert len(data) == 1 and "gfx950" in next(iter(data))
+    again = aligner.autotune(pat, txt, pairs, n, PEN, True, sample_pairs=20_000, cache_path=cache)
+    assert again == chosen
+    aligner.set_options(**chosen)
+    got = aligner.align(b, PEN)
+    assert_same(got, oracle_of(oracle_lib, b), b, "autotuned")

@@ -1,0 +1,58 @@
+"""Serving on the GPU: requests arriving at Poisson times from several
+client threads overlap on the device; each request's results equal the
+same pairs aligned alone (and the oracle on a sample)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_same, say
+
+pytestmark = pytest.mark.gpu
+PEN = (4, 6, 2)
+
+
+def test_server_mix_equals_alone(oracle_lib, synth_lib):
+    import paper_2204_02085_amd as wfa
+
+    say("case: server, 60 Poisson requests of 1-600 pairs, 3 client threads, 4 streams")
+    rng = np.random.default_rng(7)
+    reqs, first = [], 0
+    for i in range(60):
+        k = int(round(2 ** rng.uniform(0, np.log2(600))))
+        name = "uneven50_300_2m" if i % 3 else "pairs100_e4_5m"
+        reqs.append(synth_lib.workload(name, k, first=first))
+        first += k
+    reqs.append(synth_lib.workload("serving_mix", 24))  # long reads through the general kernel
+    al = wfa.Aligner(0)
+    srv = wfa.Server(al, hbm_budget_bytes=8 << 30, streams=4, max_chunk_pairs=4096)
+    tickets = [None] * len(reqs)
+
+    def client(idxs, seed):
+        r = np.random.default_rng(seed)
+        for i in idxs:
+            time.sleep(float(r.exponential(0.002)))
+            tickets[i] = srv.submit(reqs[i])
+
+    ths = [threading.Thread(target=client, args=(range(j, len(reqs), 3), j)) for j in range(3)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    results = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    say(f"  server stats: {st}")
+    assert st["max_reserved_bytes"] <= 8 << 30
+    for i, (req, res) in enumerate(zip(reqs, results)):
+        assert res["status"] == 0
+        alone = al.align(req, PEN, capacity=len(req) * 64 + 1024)
+        assert np.array_equal(res["scores"], alone[0]), f"request {i} scores"
+        assert np.array_equal(res["offsets"], alone[2]), f"request {i} offsets"
+        assert np.array_equal(res["runs"], alone[1]), f"request {i} runs"
+    for i in (0, 5, len(reqs) - 1):
+        ref = oracle_lib.align_batch(reqs[i], PEN, threads=8)
+        assert_same((results[i]["scores"], results[i]["runs"], results[i]["offsets"]), ref, reqs[i],
+                    f"request {i}")
+    al.close()
