@@ -155,7 +155,8 @@ def serving_run(al, wfa, synth, n_req, load, seed=11):
         srv.close()
         bad = [r for r in res if r["status"] != 0]
         if bad:
-            raise RuntimeError(f"{len(bad)} serving requests failed")
+            codes = sorted({int(r["status"]) for r in bad})
+            raise RuntimeError(f"{len(bad)} serving requests failed with status {codes}")
         lat = np.array([r["done"] - r["submit"] for r in res]) * 1e3
         wait = np.array([r["admit"] - r["submit"] for r in res]) * 1e3
         span = max(r["done"] for r in res) - min(r["submit"] for r in res)

@@ -67,6 +67,7 @@ int ensure_keep(Workspace& ws, Buf& b, size_t bytes, size_t keep, hipStream_t s)
     if (b.bytes >= bytes) return WFA_OK;
     Buf nb;
     int rc = ws.ensure(nb, std::max(bytes, b.bytes * 2));
+    if (rc != WFA_OK) rc = ws.ensure(nb, bytes);
     if (rc != WFA_OK) return rc;
     if (keep) HIPCHK(hipMemcpyAsync(nb.ptr, b.ptr, keep, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -121,8 +122,13 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     const uint64_t R = (uint64_t)pen.pre + 1;
     uint64_t slice;
     if (cigar) {
-        const double est = 12.0 * (double)nm1 * (double)nm1 / 64.0;
-        slice = (uint64_t)std::min(std::max(est, 256.0 * 1024), 64.0 * 1024 * 1024);
+        // first guess: a pair at 10 % divergence (score about 0.1 * L times the
+        // mean edit cost) holds ~s'^2 / e' offsets of 12 bytes plus a 16-byte
+        // step-table entry per step; pairs that need more are re-run with 4x
+        const double L = std::max(st.max_p, st.max_t);
+        const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
+        const double est = 12.0 * sg * sg / pen.e + 16.0 * sg + 8.0 * (double)nm1 + 4096.0;
+        slice = (uint64_t)std::min(std::max(est, 16.0 * 1024), 64.0 * 1024 * 1024);
     } else {
         slice = R * 3 * 4 * nm1;
     }
@@ -136,15 +142,21 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
     DevFlags* flags = ws.flags.as<DevFlags>();
     // The arena keeps whatever size it reached (re-allocating tens of GB per
-    // batch costs more than the alignment); it grows, up to 90 % of the
-    // unused budget, only when the current slices do not fit in it.
+    // batch costs more than the alignment); it grows only when the current
+    // slices do not fit, and never past 3/4 of the budget left by the other
+    // buffers, so staging and run buffers of later batches still fit.
     int attempts = 0;
     while (!pending.empty()) {
-        if (++attempts > 40) return WFA_E_NOMEM;
-        const size_t free_bytes = ws.budget > ws.total ? ws.budget - ws.total : 0;
+        if (++attempts > 40) {
+            std::fprintf(stderr, "libwfa: %zu pairs still failing after 40 attempts\n",
+                         pending.size());
+            return WFA_E_NOMEM;
+        }
+        const size_t others = ws.total - ws.arena.bytes;
+        const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
         const size_t want = std::min(pending.size(), (size_t)1 << 20) * slice;
-        if (ws.arena.bytes < want && ws.arena.bytes < ws.arena.bytes + free_bytes * 9 / 10) {
-            const size_t target = std::min(want, ws.arena.bytes + free_bytes * 9 / 10);
+        if (ws.arena.bytes < want && ws.arena.bytes < arena_cap) {
+            const size_t target = std::min(want, arena_cap);
             if (target > ws.arena.bytes && target >= slice) {
                 ws.release(ws.arena);
                 // the device may hold less than the budget: halve until it fits
@@ -161,7 +173,11 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         if (e->opt.general_pairs > 0) conc = std::min(conc, (size_t)e->opt.general_pairs);
         conc = std::min(conc, pending.size());
         conc = std::min(conc, (size_t)1 << 20);
-        if (conc == 0) return WFA_E_NOMEM;
+        if (conc == 0) {
+            std::fprintf(stderr, "libwfa: general kernel slice %zu B exceeds the arena (%zu B, "
+                                 "budget %zu B)\n", (size_t)slice, ws.arena.bytes, ws.budget);
+            return WFA_E_NOMEM;
+        }
         RCCHK(ws.ensure(ws.jobs, conc * 4));
         RCCHK(ws.ensure(ws.job_nruns, conc * 4));
         RCCHK(ws.ensure(ws.job_offsets, (conc + 1) * 8));

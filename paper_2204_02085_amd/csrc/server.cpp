@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -215,6 +216,9 @@ void worker_main(wfa_server* srv, Engine* eng) {
         std::vector<uint64_t> offsets;
         const double t_run = srv->now();
         const int rc = run_batch(srv, eng, rq, scores, runs, offsets);
+        if (rc != WFA_OK)
+            std::fprintf(stderr, "libwfa server: batch of %zu pairs failed: %s\n", pairs.size(),
+                         wfa_strerror(rc));
         const double t_end = srv->now();
         {
             std::unique_lock<std::mutex> lk(srv->mu);
