@@ -53,7 +53,11 @@ def parse():
     ap.add_argument("--pairs", type=int, default=5_000_000)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--plain-steps", type=int, default=5)
-    ap.add_argument("--tune-sample", type=int, default=262144)
+    ap.add_argument("--tune-sample", type=int, default=1_000_000)
+    ap.add_argument("--options", default="",
+                    help="JSON launch options instead of autotuning (profiling runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (PMC scale calibration)")
     ap.add_argument("--cpu-pairs", type=int, default=400_000,
                     help="oracle sample size for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -191,6 +195,17 @@ def main():
     import synth
     import paper_2204_02085_amd as wfa
 
+    if args.calib_copy_mib:
+        # a plain copy of known size, for scaling the HBM byte counters
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {args.calib_copy_mib} MiB device to device")
+        del src, dst
+
     t_gen = time.perf_counter()
     batch = synth.workload(args.workload, args.pairs)
     t_gen = time.perf_counter() - t_gen
@@ -205,7 +220,10 @@ def main():
     # (outside the timed region); every candidate must give identical bytes
     log(f"generated {n} pairs in {t_gen:.1f} s; autotuning")
     t_tune = time.perf_counter()
-    tuned = al.autotune(pat, txt, pairs, n, (4, 6, 2), True, sample_pairs=args.tune_sample)
+    if args.options:
+        tuned = {k: int(v) for k, v in json.loads(args.options).items()}
+    else:
+        tuned = al.autotune(pat, txt, pairs, n, (4, 6, 2), True, sample_pairs=args.tune_sample)
     t_tune = time.perf_counter() - t_tune
 
     log(f"autotuned in {t_tune:.1f} s: {tuned}; timing {args.steps} steps")

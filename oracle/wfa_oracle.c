@@ -51,6 +51,14 @@
  *     recurrences (scores s - max(x, o+e) and later).
  *
  * The oracle accepts any byte values; characters compare as raw bytes.
+ *
+ * Pins (tests/test_oracle_pins.py): scores against exhaustive enumeration and
+ * the textbook Gotoh DP, the Levenshtein special case and closed forms;
+ * CIGARs against Gotoh's traceback wherever the optimal alignment is unique,
+ * and against spelling / re-scoring invariants everywhere.  Which of several
+ * optimal alignments is reported follows only the tie-break reading above:
+ * for pairs with more than one optimum the CIGAR choice is "parity unpinned"
+ * (fixed by this oracle, with no outside reference).
  */
 #include <limits.h>
 #include <pthread.h>

@@ -219,13 +219,16 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int cap, uin
     sp->window = window;
     sp->cap = cap;
     sp->seq_words = (int)((max_len + 31) / 32) + 1;
-    sp->ring = cigar ? cap + 1 + pen.pre : pen.pre + 1;
+    // offsets: a ring of the pre + 1 newest rows; CIGAR mode adds one 16-bit
+    // backtrace record per cell and step
+    sp->ring = pen.pre + 1;
     // int8 offsets hold lengths up to 127; a NULL (-128) drifts up by at most
     // one per step, so it stays negative for caps below 100
     sp->row_bytes = (max_len <= 127 && cap < 100) ? 1 : 2;
     const int RW = window + 2;
     const int rows_bytes = ((3 * sp->ring * RW * sp->row_bytes) + 15) & ~15;
-    sp->group_bytes = rows_bytes + 2 * sp->seq_words * 8;
+    const int rec_bytes = cigar ? (((cap + 1) * window * 2) + 15) & ~15 : 0;
+    sp->group_bytes = rows_bytes + rec_bytes + 2 * sp->seq_words * 8;
     sp->group_bytes = (sp->group_bytes + 15) & ~15;
     // runs: every non-match op costs at least min(x, e) (in units of g)
     const int minc = std::min(pen.x, pen.e);

@@ -341,6 +341,21 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
 // the LDS words, or when its runs overflow the slot.  Values are never
 // computed from an incomplete window.
 // ---------------------------------------------------------------------------
+// Whether any lane of the caller's lane group (64/G groups per wave) has its
+// bit set in the wave-wide ballot `b`.  The per-group tests are scalar; only
+// the final pick by group index is per lane.
+template <int G>
+__device__ __forceinline__ bool group_any(uint64_t b, int grp) {
+    if (G == 64) return b != 0;
+    if (G == 32) {
+        const bool lo = (uint32_t)b != 0, hi = (uint32_t)(b >> 32) != 0;
+        return grp ? hi : lo;
+    }
+    const bool g0 = (b & 0xFFFFull) != 0, g1 = (b & 0xFFFF0000ull) != 0;
+    const bool g2 = (b & 0xFFFF00000000ull) != 0, g3 = (b >> 48) != 0;
+    return grp < 2 ? (grp ? g1 : g0) : (grp == 2 ? g2 : g3);
+}
+
 template <class RowT>
 struct RowNull;
 template <>
@@ -369,12 +384,18 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     const int gl = lane - grp * G;
     const int gshift = grp * G;
 
-    unsigned char* gbase = lds + (size_t)(wave * GPW + grp) * a.group_bytes;
+    unsigned char* gbase = lds + (wave * GPW + grp) * a.group_bytes;
     RowT* RM = (RowT*)gbase;
     RowT* RI = RM + a.ring * RW;
     RowT* RD = RI + a.ring * RW;
     const int rows_bytes = ((3 * a.ring * RW * (int)sizeof(RowT)) + 15) & ~15;
-    uint64_t* SP64 = (uint64_t*)(gbase + rows_bytes);
+    // CIGAR mode: one 16-bit backtrace record per cell and step (0..cap):
+    // bits 0-11 the M offset before extension, 12-13 its source (0 mismatch,
+    // 1 end of insertion, 2 end of deletion), 14 insertion opened from M,
+    // 15 deletion opened from M
+    uint16_t* REC = (uint16_t*)(gbase + rows_bytes);
+    const int rec_bytes = CIGAR ? (((a.cap + 1) * W * 2) + 15) & ~15 : 0;
+    uint64_t* SP64 = (uint64_t*)(gbase + rows_bytes + rec_bytes);
     uint64_t* ST64 = SP64 + a.seq_words;
     const uint32_t* SP = (const uint32_t*)SP64;
     const uint32_t* ST = (const uint32_t*)ST64;
@@ -460,12 +481,14 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
         for (int s = 0;; s++) {
             if (__ballot(st == 0) == 0) break;
             int Mv[DPL], Iv[DPL], Dv[DPL];
+            int rec[DPL];
             if (s == 0) {
 #pragma unroll
                 for (int d = 0; d < DPL; d++) {
                     Mv[d] = (kmin + gl + d * G == 0) ? 0 : NUL;
                     Iv[d] = NUL;
                     Dv[d] = NUL;
+                    rec[d] = 0;
                 }
             } else {
                 cur = cur + 1 == ring ? 0 : cur + 1;
@@ -483,13 +506,23 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                     const int L = lim[d];
                     // NULL sources stay negative through +1 and never beat a real cell
                     const int a1 = mo[j - 1] + 1, a2 = il[j - 1] + 1;
-                    const int iv = max(a1 <= L ? a1 : NUL, a2 <= L ? a2 : NUL);
+                    const int ia = a1 <= L ? a1 : NUL;
+                    const int iv = max(ia, a2 <= L ? a2 : NUL);
                     const int c1 = mo[j + 1], c2 = dr[j + 1];
-                    const int dv = max(c1 <= L ? c1 : NUL, c2 <= L ? c2 : NUL);
-                    const int xv = mx[j] + 1;
-                    Mv[d] = max(max(xv <= L ? xv : NUL, iv), dv);
+                    const int da = c1 <= L ? c1 : NUL;
+                    const int dv = max(da, c2 <= L ? c2 : NUL);
+                    const int xv0 = mx[j] + 1;
+                    const int xv = xv0 <= L ? xv0 : NUL;
+                    const int m0 = max(max(xv, iv), dv);
+                    Mv[d] = m0;
                     Iv[d] = iv;
                     Dv[d] = dv;
+                    if (CIGAR) {
+                        // decisions the backtrace replays (tie-break: mismatch,
+                        // then insertion, then deletion; gap open before extend)
+                        const int msrc = xv == m0 ? 0 : (iv == m0 ? 1 : 2);
+                        rec[d] = (m0 & 0xFFF) | (msrc << 12) | ((ia == iv) << 14) | ((da == dv) << 15);
+                    }
                 }
             }
             // extend along matches, 32 bases per compare
@@ -525,6 +558,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 RM[cur * RW + 1 + j] = (RowT)Mv[d];
                 RI[cur * RW + 1 + j] = (RowT)Iv[d];
                 RD[cur * RW + 1 + j] = (RowT)Dv[d];
+                if (CIGAR && s <= a.cap) REC[s * W + j] = (uint16_t)rec[d];
                 term |= (j == jt) & (Mv[d] == m);
                 if (d == 0) edge |= (j == 0) & (max(max(Mv[d], Iv[d]), Dv[d]) >= 0);
                 if (d == DPL - 1) edge |= (j == W - 1) & (max(max(Mv[d], Iv[d]), Dv[d]) >= 0);
@@ -544,59 +578,53 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 const int cap_runs = a.slot_cap;
                 int nr = 0, cop = -1, clen = 0;
                 int s = S, k = kt, h = m, comp = 0;  // comp: 0 M, 1 I, 2 D
-                int guard = 2 * S + 4;  // every two iterations lower s by at least 1
-                // rows of step s live at index s + PRE (no wrap in CIGAR mode).
-                // Each iteration reads every candidate it may need and picks
-                // the next state with selects (the walk has no divergent
-                // branches besides the run stores).
+                int guard = S + 2;  // every iteration lowers s by at least 1
+                // Replays the decisions recorded in the forward pass.  Each
+                // iteration reads one record and emits the run of matches of
+                // an M cell (if the walk is in M) followed by exactly one edit:
+                // a mismatch, or an insertion / deletion taken from the same
+                // cell's record whether the walk enters the gap here or is
+                // already inside it.  A match run is complete at once (runs of
+                // matches are separated by edits) and closes the open edit
+                // run; an edit extends the open run when it has the same op.
+                // Stores past the slot land on its last word, and the pair is
+                // then re-run elsewhere.
                 for (;;) {
                     const int j = k - kmin;
-                    if (s < 0 || j < 0 || j >= W || h < 0 || --guard < 0) {
+                    if (s < 0 || (unsigned)j >= (unsigned)W || --guard < 0) {
                         overflow = true;  // inconsistent walk: leave it to the general kernel
                         break;
                     }
-                    const int rs = (s + PRE) * RW + 1 + j;
-                    const int rx = (max(s - X, -PRE) + PRE) * RW + 1 + j;
-                    const int ro = (max(s - OE, -PRE) + PRE) * RW + 1 + j;
-                    const int bx = RM[rx], bi = RI[rs], bd = RD[rs];
-                    const int bl = RM[ro - 1], br = RM[ro + 1];
-                    const int L = min(m, n + k);
-                    int xv = bx + 1;
-                    xv = (xv >= 0 && xv <= L) ? xv : NUL;
-                    const int h0 = s == 0 ? 0 : max(xv, max(bi, bd));
-                    const bool isM = comp == 0, isI = comp == 1, isD = comp == 2;
-                    const bool takeX = isM && s > 0 && xv == h0;
-                    const bool toI = isM && s > 0 && !takeX && bi == h0;
-                    const int a1 = bl + 1;
-                    const bool openI = isI && a1 >= 0 && a1 <= L && a1 == h;
-                    const bool openD = isD && br >= 0 && br <= L && br == h;
-                    // ops of this iteration: a run of matches (M state), then one edit
-                    const int mlen = isM ? h - h0 : 0;
-                    const int op2 = takeX ? OP_X : (isI ? OP_I : (isD ? OP_D : -1));
-#pragma unroll
-                    for (int t = 0; t < 2; t++) {
-                        const int op = t == 0 ? OP_M : op2;
-                        const int len = t == 0 ? mlen : (op2 >= 0 ? 1 : 0);
-                        if (len > 0) {
-                            if (op != cop && cop >= 0) {
-                                if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
-                                nr++;
-                            }
-                            clen = op == cop ? clen + len : len;
-                            cop = op;
-                        }
+                    const int r = REC[s * W + j];
+                    const bool isM = comp == 0;
+                    const int h0 = r & 0xFFF;
+                    const int mlen = isM ? h - (s == 0 ? 0 : h0) : 0;
+                    const bool last = isM && s == 0;
+                    // edit of this iteration: 0 mismatch, 1 insertion, 2 deletion
+                    const int ed = isM ? ((r >> 12) & 3) : comp;
+                    const int hb = isM ? h0 : h;  // offset where the edit ends
+                    const bool hasM = mlen > 0;
+                    const bool same = !hasM && !last && cop == ed + 1;  // op codes: X=1 I=2 D=3
+                    const bool flush = cop >= 0 && !same && (hasM || !last);
+                    const uint32_t pend = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    if (flush) out[min(nr, cap_runs - 1)] = pend;
+                    nr += flush;
+                    if (hasM) out[min(nr, cap_runs - 1)] = ((uint32_t)mlen << 4) | (uint32_t)OP_M;
+                    nr += hasM;
+                    if (last) {
+                        if (hasM) cop = -1;  // else the open edit run is flushed below
+                        break;
                     }
-                    if (isM && s == 0) break;
-                    const int s_gap = (openI || openD) ? s - OE : s - E;
-                    const int s_next = isM ? (takeX ? s - X : s) : s_gap;
-                    const int c_next = isM ? (takeX ? 0 : (toI ? 1 : 2)) : ((openI || openD) ? 0 : comp);
-                    h = isM ? (takeX ? h0 - 1 : h0) : (isI ? h - 1 : h);
-                    k = isI ? k - 1 : (isD ? k + 1 : k);
-                    s = s_next;
-                    comp = c_next;
+                    clen = same ? clen + 1 : 1;
+                    cop = ed + 1;
+                    const bool open = ed == 1 ? ((r >> 14) & 1) : ((r >> 15) & 1);
+                    s = ed == 0 ? s - X : (open ? s - OE : s - E);
+                    comp = (ed == 0 || open) ? 0 : ed;
+                    k = ed == 1 ? k - 1 : (ed == 2 ? k + 1 : k);
+                    h = ed == 2 ? hb : hb - 1;  // mismatches and insertions consume a text base
                 }
                 if (cop >= 0) {
-                    if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    out[min(nr, cap_runs - 1)] = ((uint32_t)clen << 4) | (uint32_t)cop;
                     nr++;
                 }
                 if (overflow || nr > cap_runs) {
