@@ -117,8 +117,10 @@ typedef struct {
     int32_t use_graph;      /* 1: replay a captured hipGraph; -1: never; 0: auto */
     int32_t bucket;         /* 1: sort pairs by (length, length difference); -1: off */
     int32_t general_pairs;  /* concurrent pairs of the general kernel; 0: by budget */
-    int32_t block_threads;  /* threads per workgroup of the short kernel: 64..1024 */
-    int32_t reserved;
+    int32_t block_threads;  /* threads per workgroup of the short kernel: 64..256 */
+    int32_t lanes_per_pair; /* lanes of a wavefront per pair in the short kernel
+                               (16, 32 or 64, at most the window): 64 / lanes
+                               pairs share a wavefront */
 } wfa_options;
 
 /* Counters of the last wfa_align_batch call on a context. */
@@ -130,6 +132,8 @@ typedef struct {
                                     memory limit (results are unaffected)            */
     uint64_t cigar_runs;         /* total runs written                               */
     int32_t window;              /* short-kernel window used                         */
+    int32_t lanes_per_pair;      /* short-kernel lanes per pair used                 */
+    int32_t pad_;
     int32_t step_cap;            /* short-kernel step cap used                       */
     int32_t schedule;            /* schedule used                                    */
     int32_t graph_replayed;      /* 1 if a captured graph was replayed               */

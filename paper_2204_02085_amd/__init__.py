@@ -50,13 +50,14 @@ class wfa_options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("step_cap", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("bucket", ctypes.c_int32), ("general_pairs", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32)]
 
 
 class wfa_stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_uint64), ("short_pairs", ctypes.c_uint64),
                 ("general_pairs", ctypes.c_uint64), ("requeued", ctypes.c_uint64),
                 ("cigar_runs", ctypes.c_uint64), ("window", ctypes.c_int32),
+                ("lanes_per_pair", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("step_cap", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("graph_replayed", ctypes.c_int32), ("ms_pack", ctypes.c_double),
                 ("ms_align", ctypes.c_double), ("ms_general", ctypes.c_double),

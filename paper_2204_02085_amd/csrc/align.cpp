@@ -370,9 +370,12 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     int window = e->opt.window ? e->opt.window : auto_window(max_len);
     ShortPlan sp;
     bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN;
+    int lanes = 0;
     if (use_short) {
         const int cap = e->opt.step_cap ? e->opt.step_cap : default_cap(pen, window);
-        if (short_plan(e, pen, cigar, window, cap, max_len, &sp) != WFA_OK) use_short = false;
+        lanes = e->opt.lanes_per_pair ? e->opt.lanes_per_pair : default_lanes(window);
+        if (!short_shape_supported(window, lanes)) lanes = default_lanes(window);
+        if (short_plan(e, pen, cigar, window, lanes, cap, max_len, &sp) != WFA_OK) use_short = false;
     }
     const bool persistent = use_short && schedule != WFA_SCHED_PLAIN;
     const bool bucket = persistent && e->opt.bucket >= 0;
@@ -413,10 +416,10 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     int grid = 1;
     int queue_chunk = 1;
     if (use_short) {
-        const int gpb = short_groups_per_block(window, sp.block_threads);
+        const int gpb = short_groups_per_block(lanes, sp.block_threads);
         if (persistent) {
-            int bpc = short_max_blocks_per_cu(window, cigar, sp.block_threads, sp.lds_per_block,
-                                              sp.row_bytes);
+            int bpc = short_max_blocks_per_cu(window, lanes, cigar, sp.block_threads,
+                                              sp.lds_per_block, sp.row_bytes);
             if (bpc < 1) bpc = 1;
             grid = e->num_cus * bpc;
             const size_t needed = (N + gpb - 1) / gpb;
@@ -481,7 +484,7 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
             a.slots = ws.slots.as<uint32_t>();
             a.ovf_list = ws.ovf_list.as<uint32_t>();
             a.ovf_count = &flags->ovf_count;
-            HIPCHK(launch_short(a, window, cigar, persistent, sp.block_threads, grid, q));
+            HIPCHK(launch_short(a, window, lanes, cigar, persistent, sp.block_threads, grid, q));
         }
         return WFA_OK;
     };
@@ -505,7 +508,8 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
                                (const void*)(uintptr_t)ws.generation, nullptr};
         for (int i = 0; i < 8; i++) key.p[i] = ptrs[i];
         key.n = N;
-        const int ints[12] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g, window, sp.cap,
+        const int ints[12] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g,
+                              window * 256 + lanes, sp.cap,
                               (int)st.max_p, (int)st.max_t, grid,
                               (int)(bucket ? 1 : 0) | (int)(d.capacity > 0x7fffffff ? 2 : 0)};
         for (int i = 0; i < 12; i++) key.ints[i] = ints[i];
@@ -604,6 +608,7 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     L.requeued = requeued;
     L.cigar_runs = total;
     L.window = use_short ? window : 0;
+    L.lanes_per_pair = use_short ? lanes : 0;
     L.step_cap = use_short ? sp.cap : 0;
     L.schedule = !use_short ? WFA_SCHED_GENERAL : (persistent ? WFA_SCHED_PERSISTENT : WFA_SCHED_PLAIN);
     L.graph_replayed = replayed ? 1 : 0;

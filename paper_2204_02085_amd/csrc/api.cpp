@@ -162,6 +162,11 @@ extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
     if (opt->window && opt->window != 16 && opt->window != 32 && opt->window != 64 &&
         opt->window != 128 && opt->window != 256)
         return WFA_E_INVAL;
+    if (opt->lanes_per_pair && opt->lanes_per_pair != 16 && opt->lanes_per_pair != 32 &&
+        opt->lanes_per_pair != 64)
+        return WFA_E_INVAL;
+    if (opt->window && opt->lanes_per_pair && !short_shape_supported(opt->window, opt->lanes_per_pair))
+        return WFA_E_INVAL;
     if (opt->step_cap < 0 || opt->step_cap > 4096) return WFA_E_INVAL;
     if (opt->block_threads && (opt->block_threads < 64 || opt->block_threads > 256 ||
                                opt->block_threads % 64))
@@ -214,9 +219,15 @@ int make_pen(const wfa_penalties& p, Pen* out) {
 // each); a mismatch step beyond that adds nothing that stays in the window.
 int default_cap(const Pen& pen, int window) { return pen.oe + (window / 2) * pen.e + pen.x; }
 
-int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int cap, uint32_t max_len,
-               ShortPlan* sp) {
+// Two diagonals per lane by default: the outer layer is computed only once
+// the wavefront reaches it, so narrow score steps cost half a window.
+int default_lanes(int window) { return window >= 128 ? 64 : (window >= 32 ? window / 2 : window); }
+
+int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, int cap,
+               uint32_t max_len, ShortPlan* sp) {
+    if (!short_shape_supported(window, lanes)) return WFA_E_INVAL;
     sp->window = window;
+    sp->lanes = lanes;
     sp->cap = cap;
     sp->seq_words = (int)((max_len + 31) / 32) + 1;
     // offsets: a ring of the pre + 1 newest rows; CIGAR mode adds one 16-bit
@@ -234,11 +245,11 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int cap, uin
     const int minc = std::min(pen.x, pen.e);
     sp->slot_cap = 2 * ((cap / minc) + 1) + 2;
     int bt = ctx->opt.block_threads ? ctx->opt.block_threads : 256;
-    while (bt > 64 && (size_t)short_groups_per_block(window, bt) * sp->group_bytes > 64 * 1024)
+    while (bt > 64 && (size_t)short_groups_per_block(lanes, bt) * sp->group_bytes > 64 * 1024)
         bt -= 64;
-    if ((size_t)short_groups_per_block(window, bt) * sp->group_bytes > 64 * 1024) return WFA_E_NOMEM;
+    if ((size_t)short_groups_per_block(lanes, bt) * sp->group_bytes > 64 * 1024) return WFA_E_NOMEM;
     sp->block_threads = bt;
-    sp->lds_per_block = short_groups_per_block(window, bt) * sp->group_bytes;
+    sp->lds_per_block = short_groups_per_block(lanes, bt) * sp->group_bytes;
     return WFA_OK;
 }
 

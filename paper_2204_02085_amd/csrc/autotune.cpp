@@ -53,6 +53,7 @@ bool load_entry(const char* path, const std::string& key, wfa_options* out) {
         };
         o.schedule = get("schedule");
         o.window = get("window");
+        o.lanes_per_pair = get("lanes_per_pair");
         o.step_cap = get("step_cap");
         o.block_threads = get("block_threads");
         o.bucket = get("bucket");
@@ -76,6 +77,7 @@ void store_entry(const char* path, const std::string& key, const Candidate& c) {
     }
     std::ostringstream e;
     e << "  \"" << key << "\": {\"schedule\": " << c.opt.schedule << ", \"window\": " << c.opt.window
+      << ", \"lanes_per_pair\": " << c.opt.lanes_per_pair
       << ", \"step_cap\": " << c.opt.step_cap << ", \"block_threads\": " << c.opt.block_threads
       << ", \"bucket\": " << c.opt.bucket << ", \"use_graph\": " << c.opt.use_graph
       << ", \"ms_per_million_pairs\": " << c.ms << "}";
@@ -141,17 +143,21 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
     for (int w : windows) {
         if (w < 2 * (int)max_diff + 4 && w != 256) continue;  // the target must fit the window
         const int cap0 = default_cap(P, w);
-        for (int bt : {64, 128, 256}) {
-            for (int sched : {WFA_SCHED_PLAIN, WFA_SCHED_PERSISTENT}) {
-                for (int capx : {cap0, std::max(P.oe + P.x, cap0 * 2 / 3)}) {
-                    Candidate c{};
-                    c.opt.schedule = sched;
-                    c.opt.window = w;
-                    c.opt.step_cap = capx;
-                    c.opt.block_threads = bt;
-                    c.opt.bucket = sched == WFA_SCHED_PERSISTENT ? 1 : -1;
-                    c.opt.use_graph = sched == WFA_SCHED_PERSISTENT ? 1 : -1;
-                    cands.push_back(c);
+        for (int g : {16, 32, 64}) {
+            if (!wfa::short_shape_supported(w, g)) continue;
+            for (int bt : {64, 128, 256}) {
+                for (int sched : {WFA_SCHED_PLAIN, WFA_SCHED_PERSISTENT}) {
+                    for (int capx : {cap0, std::max(P.oe + P.x, cap0 * 2 / 3)}) {
+                        Candidate c{};
+                        c.opt.schedule = sched;
+                        c.opt.window = w;
+                        c.opt.lanes_per_pair = g;
+                        c.opt.step_cap = capx;
+                        c.opt.block_threads = bt;
+                        c.opt.bucket = sched == WFA_SCHED_PERSISTENT ? 1 : -1;
+                        c.opt.use_graph = sched == WFA_SCHED_PERSISTENT ? 1 : -1;
+                        cands.push_back(c);
+                    }
                 }
             }
         }

@@ -58,7 +58,7 @@ struct DevFlags {
 };
 
 struct ShortPlan {
-    int window = 0, cap = 0, seq_words = 0, ring = 0, group_bytes = 0, slot_cap = 0;
+    int window = 0, lanes = 32, cap = 0, seq_words = 0, ring = 0, group_bytes = 0, slot_cap = 0;
     int row_bytes = 2;
     int block_threads = 256, lds_per_block = 0;
 };
@@ -115,7 +115,8 @@ struct BatchIO {
 
 int make_pen(const wfa_penalties& p, wfa::Pen* out);
 int default_cap(const wfa::Pen& pen, int window);
-int short_plan(Engine* ctx, const wfa::Pen& pen, bool cigar, int window, int cap,
+int default_lanes(int window);
+int short_plan(Engine* ctx, const wfa::Pen& pen, bool cigar, int window, int lanes, int cap,
                uint32_t max_len, ShortPlan* sp);
 int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
                  int64_t* bad_pair);

@@ -106,12 +106,14 @@ hipError_t launch_pack_seqs(const uint8_t* ascii, const uint64_t* starts, const 
                             size_t n, const uint64_t* word_starts, uint64_t total_words,
                             uint64_t* words, unsigned long long* err_index, hipStream_t s);
 
-// Short-pair kernel.  window in {16, 32, 64, 128, 256}.
-hipError_t launch_short(const ShortArgs& a, int window, bool cigar, bool persistent,
+// Short-pair kernel: a window of `window` diagonals held by `lanes` lanes per
+// pair (window / lanes diagonals per lane); see short_shape_supported.
+bool short_shape_supported(int window, int lanes);
+hipError_t launch_short(const ShortArgs& a, int window, int lanes, bool cigar, bool persistent,
                         int block_threads, int grid, hipStream_t s);
-int short_groups_per_block(int window, int block_threads);
-int short_max_blocks_per_cu(int window, bool cigar, int block_threads, int lds_per_block,
-                            int row_bytes);
+int short_groups_per_block(int lanes, int block_threads);
+int short_max_blocks_per_cu(int window, int lanes, bool cigar, int block_threads,
+                            int lds_per_block, int row_bytes);
 
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds,
                           int lds_bytes, hipStream_t s);

@@ -326,14 +326,21 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
 // Short-pair kernel.
 //
 // A lane group of G lanes aligns one pair; 64/G groups share a wave and step
-// through scores together.  Lane l of a group owns diagonals
-// kmin + l + d*G (d < DPL), a window of W = G*DPL diagonals centred between
-// diagonal 0 and the target diagonal m-n.  Row r of the LDS history holds,
-// for one score step, the offsets of M (after extension), I and D on the W
-// diagonals plus a NULL pad on each side, so neighbouring diagonals are read
-// without bounds checks.  Rows for steps -pre..-1 hold NULL.  Offsets are
-// int8 when both sequences are shorter than 128 bases (twice the lane groups
-// per CU), int16 otherwise.
+// through scores together.  The group holds a window of W = G*DPL diagonals
+// kmin .. kmin+W-1, centred between diagonal 0 and the target diagonal m-n,
+// as DPL layers of G diagonals: layer 0 is the middle G, each further layer
+// adds G/2 diagonals on each side.  A layer is computed only once the
+// wavefront has reached the edge of the layer inside it -- until then every
+// cell in it is NULL -- and a wave skips the layers none of its groups needs,
+// so early (narrow) score steps cost one layer.
+//
+// Row r of the LDS history holds, for one score step, the offsets of M
+// (after extension), I and D on the W diagonals plus a NULL pad on each side,
+// so neighbouring diagonals are read without bounds checks.  The rows form a
+// ring of pre + 1 steps; every row starts NULL.  Offsets are int8 when both
+// sequences are shorter than 128 bases (twice the lane groups per CU), int16
+// otherwise.  In CIGAR mode each cell of each step also gets a 16-bit record
+// of the decisions the backtrace replays.
 //
 // A pair leaves the kernel through the overflow list (and is finished by the
 // general kernel) when its wavefront touches a window edge before reaching
@@ -341,19 +348,22 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
 // the LDS words, or when its runs overflow the slot.  Values are never
 // computed from an incomplete window.
 // ---------------------------------------------------------------------------
+
 // Whether any lane of the caller's lane group (64/G groups per wave) has its
-// bit set in the wave-wide ballot `b`.  The per-group tests are scalar; only
-// the final pick by group index is per lane.
+// bit set in the wave-wide ballot `b`.
 template <int G>
-__device__ __forceinline__ bool group_any(uint64_t b, int grp) {
-    if (G == 64) return b != 0;
-    if (G == 32) {
-        const bool lo = (uint32_t)b != 0, hi = (uint32_t)(b >> 32) != 0;
-        return grp ? hi : lo;
-    }
-    const bool g0 = (b & 0xFFFFull) != 0, g1 = (b & 0xFFFF0000ull) != 0;
-    const bool g2 = (b & 0xFFFF00000000ull) != 0, g3 = (b >> 48) != 0;
-    return grp < 2 ? (grp ? g1 : g0) : (grp == 2 ? g2 : g3);
+__device__ __forceinline__ bool group_any(uint64_t b, int gshift) {
+    constexpr uint64_t GMASK = G == 64 ? ~0ULL : ((1ULL << G) - 1ULL);
+    return ((b >> gshift) & GMASK) != 0;
+}
+
+// Window index of lane l's diagonal in layer d (see above).
+template <int G, int DPL>
+__device__ __forceinline__ int layer_index(int l, int d) {
+    constexpr int W = G * DPL;
+    if (DPL == 1) return l;
+    if (d == 0) return W / 2 - G / 2 + l;
+    return l < G / 2 ? W / 2 - G / 2 - d * (G / 2) + l : W / 2 + G / 2 + (d - 1) * (G / 2) + (l - G / 2);
 }
 
 template <class RowT>
@@ -373,8 +383,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     constexpr int W = G * DPL;
     constexpr int RW = W + 2;
     constexpr int GPW = 64 / G;
-    constexpr uint64_t GMASK = G == 64 ? ~0ULL : ((1ULL << G) - 1ULL);
-    // NULL, and how far below zero a NULL may drift (+1 per step at most)
+    // NULL; it drifts up by at most one per step and stays negative
     constexpr int NUL = RowNull<RowT>::value;
 
     const int lane = threadIdx.x & 63;
@@ -400,15 +409,12 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     const uint32_t* SP = (const uint32_t*)SP64;
     const uint32_t* ST = (const uint32_t*)ST64;
 
-    const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
+    const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e;
     const int ring = a.ring;
 
-    // side pads of every row stay NULL for the life of the kernel
-    for (int r = gl; r < ring; r += G) {
-        RM[r * RW] = RM[r * RW + RW - 1] = (RowT)NUL;
-        RI[r * RW] = RI[r * RW + RW - 1] = (RowT)NUL;
-        RD[r * RW] = RD[r * RW + RW - 1] = (RowT)NUL;
-    }
+    int jl[DPL];  // window index of each of this lane's diagonals
+#pragma unroll
+    for (int d = 0; d < DPL; d++) jl[d] = layer_index<G, DPL>(gl, d);
 
     // persistent: a wave claims `queue_chunk` rounds of GPW queue entries per
     // atomic and works through them before claiming again
@@ -463,47 +469,63 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
             SP64[w] = (st == 0 && w < nwp) ? a.pw[ps + w] : 0ULL;
             ST64[w] = (st == 0 && w < nwt) ? a.tw[ts + w] : 0ULL;
         }
-        // rows of steps -pre .. -1
-        for (int idx = gl; idx < PRE * W; idx += G) {
-            const int r = idx / W, j = idx - (idx / W) * W;
-            RM[r * RW + 1 + j] = (RowT)NUL;
-            RI[r * RW + 1 + j] = (RowT)NUL;
-            RD[r * RW + 1 + j] = (RowT)NUL;
+        // every ring row starts NULL (pads included); the three arrays are
+        // contiguous and padded to 16 bytes
+        {
+            constexpr uint32_t NW = sizeof(RowT) == 1 ? 0x80808080u : 0xC000C000u;
+            static_assert(sizeof(RowT) == 1 ? (int8_t)0x80 == NUL : (int16_t)0xC000 == NUL,
+                          "fill word must repeat NULL");
+            uint4* f = (uint4*)gbase;
+            for (int idx = gl; idx < rows_bytes / 16; idx += G) f[idx] = make_uint4(NW, NW, NW, NW);
         }
         wave_sync();
 
         int lim[DPL];
 #pragma unroll
-        for (int d = 0; d < DPL; d++) lim[d] = min(m, n + kmin + gl + d * G);
+        for (int d = 0; d < DPL; d++) lim[d] = min(m, n + kmin + jl[d]);
         const int jt = kt - kmin;  // window index of the target diagonal
         int S = 0;
-        int cur = PRE;             // row of step 0
+        // layers this group computes: at first the fewest that hold diagonal 0
+        int lay = 1;
+        {
+            const int j0 = -kmin;
+            while (lay < DPL && (j0 < W / 2 - G / 2 - (lay - 1) * (G / 2) ||
+                                 j0 > W / 2 + G / 2 - 1 + (lay - 1) * (G / 2)))
+                lay++;
+        }
+        int cur = ring - 1;        // ring row of step 0 (the rows before it are NULL)
         for (int s = 0;; s++) {
             if (__ballot(st == 0) == 0) break;
-            int Mv[DPL], Iv[DPL], Dv[DPL];
-            int rec[DPL];
-            if (s == 0) {
+            // layers the wave computes this step: the most any of its groups needs
+            int nlay = 1;
 #pragma unroll
-                for (int d = 0; d < DPL; d++) {
-                    Mv[d] = (kmin + gl + d * G == 0) ? 0 : NUL;
-                    Iv[d] = NUL;
-                    Dv[d] = NUL;
-                    rec[d] = 0;
-                }
-            } else {
-                cur = cur + 1 == ring ? 0 : cur + 1;
-                int ix = cur - X, io = cur - OE, ie = cur - E;
-                ix += ix < 0 ? ring : 0;
-                io += io < 0 ? ring : 0;
-                ie += ie < 0 ? ring : 0;
-                const RowT* mx = RM + ix * RW + 1;
-                const RowT* mo = RM + io * RW + 1;
-                const RowT* il = RI + ie * RW + 1;
-                const RowT* dr = RD + ie * RW + 1;
+            for (int d = 1; d < DPL; d++) nlay += __ballot(st == 0 && lay > d) != 0 ? 1 : 0;
+            if (s > 0) cur = cur + 1 == ring ? 0 : cur + 1;
+            int ix = cur - X, io = cur - OE, ie = cur - E;
+            ix += ix < 0 ? ring : 0;
+            io += io < 0 ? ring : 0;
+            ie += ie < 0 ? ring : 0;
+            const RowT* mx = RM + ix * RW + 1;
+            const RowT* mo = RM + io * RW + 1;
+            const RowT* il = RI + ie * RW + 1;
+            const RowT* dr = RD + ie * RW + 1;
+            const bool run = st == 0;
+            int Mv[DPL], Iv[DPL], Dv[DPL], rec[DPL];
+            bool go[DPL];
+            bool any_go = false;
 #pragma unroll
-                for (int d = 0; d < DPL; d++) {
-                    const int j = gl + d * G;
-                    const int L = lim[d];
+            for (int d = 0; d < DPL; d++) {
+                Mv[d] = NUL;
+                Iv[d] = NUL;
+                Dv[d] = NUL;
+                rec[d] = 0;
+                go[d] = false;
+                if (d >= nlay) continue;
+                const int j = jl[d];
+                const int L = lim[d];
+                if (s == 0) {
+                    Mv[d] = (kmin + j == 0) ? 0 : NUL;
+                } else {
                     // NULL sources stay negative through +1 and never beat a real cell
                     const int a1 = mo[j - 1] + 1, a2 = il[j - 1] + 1;
                     const int ia = a1 <= L ? a1 : NUL;
@@ -524,23 +546,17 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                         rec[d] = (m0 & 0xFFF) | (msrc << 12) | ((ia == iv) << 14) | ((da == dv) << 15);
                     }
                 }
-            }
-            // extend along matches, 32 bases per compare
-            const bool run = st == 0;
-            bool go[DPL];
-            bool any_go = false;
-#pragma unroll
-            for (int d = 0; d < DPL; d++) {
-                const int k = kmin + gl + d * G;
+                const int k = kmin + j;
                 go[d] = run && Mv[d] >= 0 && Mv[d] - k < n && Mv[d] < m;
                 any_go |= go[d];
             }
+            // extend along matches, 32 bases per compare
             while (__ballot(any_go)) {
                 any_go = false;
 #pragma unroll
                 for (int d = 0; d < DPL; d++) {
                     if (go[d]) {
-                        const int k = kmin + gl + d * G;
+                        const int k = kmin + jl[d];
                         const int h = Mv[d], v = h - k;
                         int r = common_prefix(window32(SP, v), window32(ST, h));
                         r = min(r, min(n - v, m - h));
@@ -551,22 +567,27 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 }
             }
             // store the step's rows (groups that stopped write rows nobody reads)
-            bool term = false, edge = false;
+            bool term = false, edge = false, grow = false;
 #pragma unroll
             for (int d = 0; d < DPL; d++) {
-                const int j = gl + d * G;
+                if (d >= nlay) continue;
+                const int j = jl[d];
                 RM[cur * RW + 1 + j] = (RowT)Mv[d];
                 RI[cur * RW + 1 + j] = (RowT)Iv[d];
                 RD[cur * RW + 1 + j] = (RowT)Dv[d];
                 if (CIGAR && s <= a.cap) REC[s * W + j] = (uint16_t)rec[d];
+                const bool live = max(max(Mv[d], Iv[d]), Dv[d]) >= 0;
+                const bool bnd = gl == 0 || gl == G - 1;  // a layer's outermost diagonals
                 term |= (j == jt) & (Mv[d] == m);
-                if (d == 0) edge |= (j == 0) & (max(max(Mv[d], Iv[d]), Dv[d]) >= 0);
-                if (d == DPL - 1) edge |= (j == W - 1) & (max(max(Mv[d], Iv[d]), Dv[d]) >= 0);
+                if (d == DPL - 1) edge |= bnd & live;
+                if (d < DPL - 1) grow |= (d == lay - 1) & bnd & live;
             }
-            const bool gterm = ((__ballot(term) >> gshift) & GMASK) != 0;
-            const bool gedge = ((__ballot(edge) >> gshift) & GMASK) != 0;
+            const bool gterm = group_any<G>(__ballot(term), gshift);
+            const bool gedge = group_any<G>(__ballot(edge), gshift);
+            const bool ggrow = DPL > 1 && group_any<G>(__ballot(grow), gshift);
             S = (run && gterm) ? s : S;
             st = run ? (gterm ? 1 : ((gedge || s >= a.cap) ? 2 : 0)) : st;
+            lay += (run && ggrow) ? 1 : 0;
             wave_sync();
         }
 
@@ -1143,15 +1164,14 @@ hipError_t launch_pack_seqs(const uint8_t* ascii, const uint64_t* starts, const 
     return hipGetLastError();
 }
 
-int short_groups_per_block(int window, int block_threads) {
-    const int G = window >= 64 ? 64 : window;
-    return (block_threads / 64) * (64 / G);
+int short_groups_per_block(int lanes, int block_threads) {
+    return (block_threads / 64) * (64 / lanes);
 }
 
 template <int G, int DPL, class RowT>
 static hipError_t launch_short_t(const ShortArgs& a, bool cigar, bool persistent, int bt, int grid,
                                  hipStream_t s) {
-    const size_t lds = (size_t)short_groups_per_block(G * DPL, bt) * a.group_bytes;
+    const size_t lds = (size_t)short_groups_per_block(G, bt) * a.group_bytes;
     if (cigar)
         hipLaunchKernelGGL((k_short<G, DPL, true, RowT>), dim3(grid), dim3(bt), lds, s, a,
                            persistent ? 1 : 0);
@@ -1159,26 +1179,6 @@ static hipError_t launch_short_t(const ShortArgs& a, bool cigar, bool persistent
         hipLaunchKernelGGL((k_short<G, DPL, false, RowT>), dim3(grid), dim3(bt), lds, s, a,
                            persistent ? 1 : 0);
     return hipGetLastError();
-}
-
-template <class RowT>
-static hipError_t launch_short_w(const ShortArgs& a, int window, bool cigar, bool persistent,
-                                 int bt, int grid, hipStream_t s) {
-    switch (window) {
-    case 16: return launch_short_t<16, 1, RowT>(a, cigar, persistent, bt, grid, s);
-    case 32: return launch_short_t<32, 1, RowT>(a, cigar, persistent, bt, grid, s);
-    case 64: return launch_short_t<64, 1, RowT>(a, cigar, persistent, bt, grid, s);
-    case 128: return launch_short_t<64, 2, RowT>(a, cigar, persistent, bt, grid, s);
-    case 256: return launch_short_t<64, 4, RowT>(a, cigar, persistent, bt, grid, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_short(const ShortArgs& a, int window, bool cigar, bool persistent,
-                        int block_threads, int grid, hipStream_t s) {
-    if (a.row_bytes == 1)
-        return launch_short_w<int8_t>(a, window, cigar, persistent, block_threads, grid, s);
-    return launch_short_w<int16_t>(a, window, cigar, persistent, block_threads, grid, s);
 }
 
 template <int G, int DPL, class RowT>
@@ -1191,21 +1191,56 @@ static int occ_t(bool cigar, int bt, int lds) {
     return e == hipSuccess ? blocks : 0;
 }
 
-template <class RowT>
-static int occ_w(int window, bool cigar, int bt, int lds) {
-    switch (window) {
-    case 16: return occ_t<16, 1, RowT>(cigar, bt, lds);
-    case 32: return occ_t<32, 1, RowT>(cigar, bt, lds);
-    case 64: return occ_t<64, 1, RowT>(cigar, bt, lds);
-    case 128: return occ_t<64, 2, RowT>(cigar, bt, lds);
-    case 256: return occ_t<64, 4, RowT>(cigar, bt, lds);
-    default: return 0;
-    }
+// (window, lanes per pair) shapes the short kernel is built for
+#define WFA_SHORT_SHAPES(X) \
+    X(16, 16, 1)            \
+    X(32, 32, 1)            \
+    X(32, 16, 2)            \
+    X(64, 64, 1)            \
+    X(64, 32, 2)            \
+    X(64, 16, 4)            \
+    X(128, 64, 2)           \
+    X(128, 32, 4)           \
+    X(256, 64, 4)
+
+bool short_shape_supported(int window, int lanes) {
+#define WFA_CASE(w, g, dpl) \
+    if (window == w && lanes == g) return true;
+    WFA_SHORT_SHAPES(WFA_CASE)
+#undef WFA_CASE
+    return false;
 }
 
-int short_max_blocks_per_cu(int window, bool cigar, int bt, int lds_per_block, int row_bytes) {
-    return row_bytes == 1 ? occ_w<int8_t>(window, cigar, bt, lds_per_block)
-                          : occ_w<int16_t>(window, cigar, bt, lds_per_block);
+template <class RowT>
+static hipError_t launch_short_w(const ShortArgs& a, int window, int lanes, bool cigar,
+                                 bool persistent, int bt, int grid, hipStream_t s) {
+#define WFA_CASE(w, g, dpl) \
+    if (window == w && lanes == g) return launch_short_t<g, dpl, RowT>(a, cigar, persistent, bt, grid, s);
+    WFA_SHORT_SHAPES(WFA_CASE)
+#undef WFA_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_short(const ShortArgs& a, int window, int lanes, bool cigar, bool persistent,
+                        int block_threads, int grid, hipStream_t s) {
+    if (a.row_bytes == 1)
+        return launch_short_w<int8_t>(a, window, lanes, cigar, persistent, block_threads, grid, s);
+    return launch_short_w<int16_t>(a, window, lanes, cigar, persistent, block_threads, grid, s);
+}
+
+template <class RowT>
+static int occ_w(int window, int lanes, bool cigar, int bt, int lds) {
+#define WFA_CASE(w, g, dpl) \
+    if (window == w && lanes == g) return occ_t<g, dpl, RowT>(cigar, bt, lds);
+    WFA_SHORT_SHAPES(WFA_CASE)
+#undef WFA_CASE
+    return 0;
+}
+
+int short_max_blocks_per_cu(int window, int lanes, bool cigar, int bt, int lds_per_block,
+                            int row_bytes) {
+    return row_bytes == 1 ? occ_w<int8_t>(window, lanes, cigar, bt, lds_per_block)
+                          : occ_w<int16_t>(window, lanes, cigar, bt, lds_per_block);
 }
 
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds, int lds_bytes,

@@ -58,15 +58,28 @@ def test_pairs100_e4_schedules(aligner, oracle_lib, synth_lib, wfa, schedule):
     assert_same(got, oracle_of(oracle_lib, b), b, f"e4/{schedule}")
 
 
-@pytest.mark.parametrize("window", [16, 32, 64, 128, 256])
-def test_windows_identical(aligner, oracle_lib, synth_lib, wfa, window):
-    """Every short-kernel window gives the oracle's bytes (narrow windows
-    hand most pairs to the general kernel)."""
-    say(f"case: window {window}")
-    b = synth_lib.workload("pairs100_e4_5m", 3000, first=50_000)
-    aligner.set_options(window=window, schedule=wfa.WFA_SCHED_PERSISTENT)
-    got = aligner.align(b, PEN)
-    assert_same(got, oracle_of(oracle_lib, b), b, f"window {window}")
+SHAPES = [(16, 16), (32, 32), (32, 16), (64, 64), (64, 32), (64, 16), (128, 64), (128, 32),
+          (256, 64)]
+
+
+@pytest.mark.parametrize("window,lanes", SHAPES)
+def test_windows_identical(aligner, oracle_lib, synth_lib, wfa, window, lanes):
+    """Every short-kernel shape (window, lanes per pair) gives the oracle's
+    bytes: 100 bp pairs (int8 rows) and uneven 50-300 bp pairs (int16 rows,
+    target diagonals far from diagonal 0, so the first layers computed are
+    outer ones), in CIGAR and score mode.  Narrow windows hand most pairs to
+    the general kernel."""
+    say(f"case: window {window} lanes {lanes}")
+    aligner.set_options(window=window, lanes_per_pair=lanes, schedule=wfa.WFA_SCHED_PLAIN)
+    for name, first in [("pairs100_e4_5m", 50_000), ("uneven50_300_2m", 1000)]:
+        b = synth_lib.workload(name, 3000, first=first)
+        got = aligner.align(b, PEN)
+        assert_same(got, oracle_of(oracle_lib, b), b, f"{name} window {window} lanes {lanes}")
+        got = aligner.align(b, PEN, cigar=False)
+        assert_same(got, oracle_of(oracle_lib, b, cigar=False), b,
+                    f"{name} score window {window} lanes {lanes}")
+        st = aligner.stats()
+        assert st["window"] == window and st["lanes_per_pair"] == lanes
 
 
 def test_score_only(aligner, oracle_lib, synth_lib):
