@@ -137,17 +137,59 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         return WFA_OK;
     }
 
+    // outputs of the sample (device)
+    Workspace tmp;
+    tmp.budget = (size_t)16 << 30;
+    Buf d_scores, d_runs, d_off;
+    const size_t cap = cigar ? n * 64 + 1024 : 1;
+    int rc = tmp.ensure(d_scores, n * 4);
+    if (rc == WFA_OK) rc = tmp.ensure(d_runs, cap * 4);
+    if (rc == WFA_OK) rc = tmp.ensure(d_off, (n + 1) * 8);
+    if (rc != WFA_OK) {
+        tmp.release_all();
+        return rc;
+    }
+    std::vector<int32_t> ref_scores, scores(n);
+    const wfa_options saved = ctx->opt;
+
+    // Largest score step of the sample (a score-only pass with the default
+    // options): step caps just above it keep the LDS per pair small without
+    // sending the sample's pairs to the general kernel.
+    int sample_steps = -1;
+    {
+        ctx->opt = wfa_options{};
+        BatchIO io{patterns, texts, pairs, n, enc, mem, pen, WFA_SCORE,
+                   mem == WFA_DEVICE ? d_scores.as<int32_t>() : scores.data(), nullptr, 0, nullptr};
+        size_t needed = 0;
+        int64_t bad = -1;
+        rc = engine_align(ctx, io, nullptr, &needed, &bad);
+        ctx->opt = saved;
+        if (rc != WFA_OK) {
+            tmp.release_all();
+            return rc;
+        }
+        if (mem == WFA_DEVICE &&
+            hipMemcpy(scores.data(), d_scores.ptr, n * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            tmp.release_all();
+            return WFA_E_DEVICE;
+        }
+        for (int32_t v : scores) sample_steps = std::max(sample_steps, v / P.g);
+    }
+
     // candidates
     std::vector<Candidate> cands;
     const int windows[] = {16, 32, 64, 128, 256};
     for (int w : windows) {
         if (w < 2 * (int)max_diff + 4 && w != 256) continue;  // the target must fit the window
         const int cap0 = default_cap(P, w);
+        std::vector<int> caps{cap0};
+        if (sample_steps >= 0 && sample_steps < cap0) caps.push_back(std::max(sample_steps, 1));
+        else caps.push_back(std::max(P.oe + P.x, cap0 * 2 / 3));
         for (int g : {16, 32, 64}) {
             if (!wfa::short_shape_supported(w, g)) continue;
             for (int bt : {64, 128, 256}) {
                 for (int sched : {WFA_SCHED_PLAIN, WFA_SCHED_PERSISTENT}) {
-                    for (int capx : {cap0, std::max(P.oe + P.x, cap0 * 2 / 3)}) {
+                    for (int capx : caps) {
                         Candidate c{};
                         c.opt.schedule = sched;
                         c.opt.window = w;
@@ -169,22 +211,8 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         cands.push_back(g);
     }
 
-    // outputs of the sample (device)
-    Workspace tmp;
-    tmp.budget = (size_t)16 << 30;
-    Buf d_scores, d_runs, d_off;
-    const size_t cap = cigar ? n * 64 + 1024 : 1;
-    int rc = tmp.ensure(d_scores, n * 4);
-    if (rc == WFA_OK) rc = tmp.ensure(d_runs, cap * 4);
-    if (rc == WFA_OK) rc = tmp.ensure(d_off, (n + 1) * 8);
-    if (rc != WFA_OK) {
-        tmp.release_all();
-        return rc;
-    }
-    std::vector<int32_t> ref_scores, scores(n);
     std::vector<uint64_t> ref_off, off(n + 1);
     std::vector<uint32_t> ref_runs, runs;
-    const wfa_options saved = ctx->opt;
     Candidate best;
     int status = WFA_OK;
     for (auto& c : cands) {

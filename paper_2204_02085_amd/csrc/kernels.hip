@@ -511,15 +511,21 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
             const RowT* dr = RD + ie * RW + 1;
             const bool run = st == 0;
             int Mv[DPL], Iv[DPL], Dv[DPL], rec[DPL];
-            bool go[DPL];
-            bool any_go = false;
+            // extension state: text and pattern positions (0 for cells that do
+            // not extend, so their compares stay in bounds) and bases left
+            // before either sequence ends (0: not extending)
+            int hp[DPL], vp[DPL], rem[DPL];
+            uint64_t gm[DPL];
 #pragma unroll
             for (int d = 0; d < DPL; d++) {
                 Mv[d] = NUL;
                 Iv[d] = NUL;
                 Dv[d] = NUL;
                 rec[d] = 0;
-                go[d] = false;
+                hp[d] = 0;
+                vp[d] = 0;
+                rem[d] = 0;
+                gm[d] = 0;
                 if (d >= nlay) continue;
                 const int j = jl[d];
                 const int L = lim[d];
@@ -547,25 +553,35 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                     }
                 }
                 const int k = kmin + j;
-                go[d] = run && Mv[d] >= 0 && Mv[d] - k < n && Mv[d] < m;
-                any_go |= go[d];
+                const int h = Mv[d], v = h - k;
+                const int left = min(n - v, m - h);
+                const bool go = run && h >= 0 && left > 0;
+                hp[d] = go ? h : 0;
+                vp[d] = go ? v : 0;
+                rem[d] = go ? left : 0;
+                gm[d] = __ballot(go);
             }
-            // extend along matches, 32 bases per compare
-            while (__ballot(any_go)) {
-                any_go = false;
+            // extend along matches, 32 bases per compare.  The loop is
+            // wave-uniform: while any lane of a layer extends, every lane of
+            // the layer runs the compare, and lanes with nothing left add 0.
+            for (;;) {
+                bool more = false;
 #pragma unroll
                 for (int d = 0; d < DPL; d++) {
-                    if (go[d]) {
-                        const int k = kmin + jl[d];
-                        const int h = Mv[d], v = h - k;
-                        int r = common_prefix(window32(SP, v), window32(ST, h));
-                        r = min(r, min(n - v, m - h));
-                        Mv[d] = h + r;
-                        go[d] = r == 32 && v + r < n && h + r < m;
-                        any_go |= go[d];
+                    if (gm[d]) {
+                        const int r = min(common_prefix(window32(SP, vp[d]), window32(ST, hp[d])), rem[d]);
+                        hp[d] += r;
+                        vp[d] += r;
+                        rem[d] = r == 32 ? rem[d] - 32 : 0;
+                        gm[d] = __ballot(rem[d] > 0);
+                        more |= gm[d] != 0;
                     }
                 }
+                if (!more) break;
             }
+#pragma unroll
+            for (int d = 0; d < DPL; d++)
+                if (d < nlay) Mv[d] = Mv[d] >= 0 && hp[d] > 0 ? hp[d] : Mv[d];
             // store the step's rows (groups that stopped write rows nobody reads)
             bool term = false, edge = false, grow = false;
 #pragma unroll
