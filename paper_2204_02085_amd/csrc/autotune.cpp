@@ -188,7 +188,9 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         for (int g : {16, 32, 64}) {
             if (!wfa::short_shape_supported(w, g)) continue;
             for (int bt : {64, 128, 256}) {
-                for (int sched : {WFA_SCHED_PLAIN, WFA_SCHED_PERSISTENT}) {
+                // plain; persistent with and without bucketing
+                for (int form : {0, 1, 2}) {
+                    const int sched = form == 0 ? WFA_SCHED_PLAIN : WFA_SCHED_PERSISTENT;
                     for (int capx : caps) {
                         Candidate c{};
                         c.opt.schedule = sched;
@@ -196,8 +198,8 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
                         c.opt.lanes_per_pair = g;
                         c.opt.step_cap = capx;
                         c.opt.block_threads = bt;
-                        c.opt.bucket = sched == WFA_SCHED_PERSISTENT ? 1 : -1;
-                        c.opt.use_graph = sched == WFA_SCHED_PERSISTENT ? 1 : -1;
+                        c.opt.bucket = form == 1 ? 1 : -1;
+                        c.opt.use_graph = form == 0 ? -1 : 1;
                         cands.push_back(c);
                     }
                 }

@@ -532,24 +532,30 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 if (s == 0) {
                     Mv[d] = (kmin + j == 0) ? 0 : NUL;
                 } else {
-                    // NULL sources stay negative through +1 and never beat a real cell
-                    const int a1 = mo[j - 1] + 1, a2 = il[j - 1] + 1;
-                    const int ia = a1 <= L ? a1 : NUL;
-                    const int iv = max(ia, a2 <= L ? a2 : NUL);
-                    const int c1 = mo[j + 1], c2 = dr[j + 1];
-                    const int da = c1 <= L ? c1 : NUL;
-                    const int dv = max(da, c2 <= L ? c2 : NUL);
-                    const int xv0 = mx[j] + 1;
-                    const int xv = xv0 <= L ? xv0 : NUL;
-                    const int m0 = max(max(xv, iv), dv);
-                    Mv[d] = m0;
-                    Iv[d] = iv;
-                    Dv[d] = dv;
+                    // Candidates as distances t = L - c below the diagonal's limit
+                    // L: an admissible offset has 0 <= t <= L, a NULL source
+                    // (negative, drifting up by at most one per step) has
+                    // L < t <= L - NUL, and an offset past L has t < 0, which
+                    // is huge as unsigned.  So the largest admissible candidate
+                    // is the unsigned minimum, floored at NULL (t = L - NUL),
+                    // and over-long candidates are dropped before the maximum.
+                    const uint32_t tn = (uint32_t)(L - NUL);
+                    const uint32_t ta = (uint32_t)(L - 1 - mo[j - 1]);  // open from M
+                    const uint32_t tb = (uint32_t)(L - 1 - il[j - 1]);  // extend I
+                    const uint32_t tc = (uint32_t)(L - mo[j + 1]);      // open from M
+                    const uint32_t te = (uint32_t)(L - dr[j + 1]);      // extend D
+                    const uint32_t tx = (uint32_t)(L - 1 - mx[j]);      // mismatch
+                    const uint32_t ti = min(min(ta, tb), tn);
+                    const uint32_t td = min(min(tc, te), tn);
+                    const uint32_t tm = min(min(tx, ti), td);
+                    Mv[d] = L - (int)tm;
+                    Iv[d] = L - (int)ti;
+                    Dv[d] = L - (int)td;
                     if (CIGAR) {
                         // decisions the backtrace replays (tie-break: mismatch,
                         // then insertion, then deletion; gap open before extend)
-                        const int msrc = xv == m0 ? 0 : (iv == m0 ? 1 : 2);
-                        rec[d] = (m0 & 0xFFF) | (msrc << 12) | ((ia == iv) << 14) | ((da == dv) << 15);
+                        const int msrc = tx == tm ? 0 : (ti == tm ? 1 : 2);
+                        rec[d] = (Mv[d] & 0xFFF) | (msrc << 12) | ((ta == ti) << 14) | ((tc == td) << 15);
                     }
                 }
                 const int k = kmin + j;
@@ -592,7 +598,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 RI[cur * RW + 1 + j] = (RowT)Iv[d];
                 RD[cur * RW + 1 + j] = (RowT)Dv[d];
                 if (CIGAR && s <= a.cap) REC[s * W + j] = (uint16_t)rec[d];
-                const bool live = max(max(Mv[d], Iv[d]), Dv[d]) >= 0;
+                const bool live = Mv[d] >= 0;  // M is at least I and D
                 const bool bnd = gl == 0 || gl == G - 1;  // a layer's outermost diagonals
                 term |= (j == jt) & (Mv[d] == m);
                 if (d == DPL - 1) edge |= bnd & live;
