@@ -247,6 +247,40 @@ class Aligner:
                 t.from_numpy(np.ascontiguousarray(batch.texts)).to(dev),
                 t.from_numpy(pairs.view(np.uint8).copy()).to(dev))
 
+    def pack2bit(self, ascii, starts, lens):
+        """wfa_pack2bit on device tensors (uint8 ASCII, int64 starts, int32
+        lengths); returns (int64 words, int64 word starts) on the device."""
+        t = self.torch
+        n = int(lens.numel())
+        nwords = int(((lens.to(t.int64) + 31) // 32).sum().item()) + 8
+        words = t.empty(nwords, dtype=t.int64, device=ascii.device)
+        ws = t.empty(n + 1, dtype=t.int64, device=ascii.device)
+        total = ctypes.c_size_t(0)
+        bad = ctypes.c_int64(-1)
+        rc = wfa_pack2bit(self.ctx, ascii.data_ptr(), starts.data_ptr(), lens.data_ptr(), n,
+                          words.data_ptr(), nwords, ws.data_ptr(), ctypes.byref(total),
+                          ctypes.byref(bad), t.cuda.current_stream(self.device).cuda_stream)
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_pack2bit", bad.value)
+        return words, ws
+
+    def to_device_packed(self, batch):
+        """Device tensors (pattern words, text words, pairs) with both sides
+        packed to 2-bit words by the library; pair starts are word indices."""
+        t = self.torch
+        dev = f"cuda:{self.device}"
+        out = []
+        for seqs, off, ln in ((batch.patterns, batch.p_off, batch.p_len),
+                              (batch.texts, batch.t_off, batch.t_len)):
+            ascii = t.from_numpy(np.ascontiguousarray(seqs)).to(dev)
+            starts = t.from_numpy(np.ascontiguousarray(off).view(np.int64)).to(dev)
+            lens = t.from_numpy(np.ascontiguousarray(ln).view(np.int32)).to(dev)
+            words, ws = self.pack2bit(ascii, starts, lens)
+            del ascii
+            out.append((words, ws[: len(ln)].cpu().numpy().view(np.uint64)))
+        pairs = pairs_array(out[0][1], batch.p_len, out[1][1], batch.t_len)
+        return out[0][0], out[1][0], t.from_numpy(pairs.view(np.uint8).copy()).to(dev)
+
     def alloc_outputs(self, n: int, capacity: int, cigar: bool = True):
         t = self.torch
         dev = f"cuda:{self.device}"

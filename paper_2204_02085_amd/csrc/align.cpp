@@ -353,7 +353,7 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     }
 
     // ---- batch facts -------------------------------------------------------
-    RCCHK(ws.ensure(ws.stats, sizeof(BatchStats)));
+    RCCHK(ws.ensure(ws.stats, sizeof(BatchStats) * (1 + STATS_BLOCKS)));
     RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
     BatchStats st;
     HIPCHK(launch_batch_stats(in_pairs, N, ws.stats.as<BatchStats>(), WFA_MAX_LENGTH, s));
@@ -476,6 +476,7 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
             a.ring = sp.ring;
             a.seq_words = sp.seq_words;
             a.group_bytes = sp.group_bytes;
+            a.rows_bytes = sp.rows_bytes;
             a.slot_cap = sp.slot_cap;
             a.row_bytes = sp.row_bytes;
             a.scores = d.scores;
@@ -542,6 +543,10 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     HIPCHK(hipEventRecord(e->ev[1], s));
     DevFlags fl;
     HIPCHK(hipMemcpyAsync(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    // the run total of the short kernel's pairs comes back with the flags
+    uint64_t short_total = 0;
+    if (cigar && use_short)
+        HIPCHK(hipMemcpyAsync(&short_total, d.offsets + N, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (fl.err_pair != ~0ull) {
         if (bad_pair) *bad_pair = (int64_t)fl.err_pair;
@@ -575,8 +580,12 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
             RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64));
             HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, s));
         }
-        HIPCHK(hipMemcpyAsync(&total, d.offsets + N, 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        if (rescan) {
+            HIPCHK(hipMemcpyAsync(&total, d.offsets + N, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } else {
+            total = short_total;
+        }
         if (io.mem == WFA_HOST) {
             RCCHK(ws.ensure(ws.out_runs, total * 4 + 4));
             d.runs = ws.out_runs.as<uint32_t>();

@@ -237,13 +237,15 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, i
     // one per step, so it stays negative for caps below 100
     sp->row_bytes = (max_len <= 127 && cap < 100) ? 1 : 2;
     const int RW = window + 2;
-    const int rows_bytes = ((3 * sp->ring * RW * sp->row_bytes) + 15) & ~15;
-    const int rec_bytes = cigar ? (((cap + 1) * window * 2) + 15) & ~15 : 0;
-    sp->group_bytes = rows_bytes + rec_bytes + 2 * sp->seq_words * 8;
-    sp->group_bytes = (sp->group_bytes + 15) & ~15;
     // runs: every non-match op costs at least min(x, e) (in units of g)
     const int minc = std::min(pen.x, pen.e);
     sp->slot_cap = 2 * ((cap / minc) + 1) + 2;
+    // the ring is free during the backtrace, which stages the runs there
+    const int ring_bytes = std::max(3 * sp->ring * RW * sp->row_bytes, cigar ? 4 * sp->slot_cap : 0);
+    sp->rows_bytes = (ring_bytes + 15) & ~15;
+    const int rec_bytes = cigar ? (((cap + 1) * window * 2) + 15) & ~15 : 0;
+    sp->group_bytes = sp->rows_bytes + rec_bytes + 2 * sp->seq_words * 8;
+    sp->group_bytes = (sp->group_bytes + 15) & ~15;
     int bt = ctx->opt.block_threads ? ctx->opt.block_threads : 256;
     while (bt > 64 && (size_t)short_groups_per_block(lanes, bt) * sp->group_bytes > 64 * 1024)
         bt -= 64;

@@ -24,6 +24,10 @@ struct BatchStats {
     uint64_t first_too_long;  // lowest pair index over the length limit, or ~0
 };
 
+// Blocks of the first batch-statistics pass; the statistics buffer holds
+// 1 + STATS_BLOCKS records (result, then the partials).
+constexpr int STATS_BLOCKS = 1024;
+
 // Largest pre + 1 (rows a step reads back, plus the current one) the kernels hold.
 constexpr int GENERAL_MAX_RING = 512;
 
@@ -46,15 +50,16 @@ struct ShortArgs {
     int queue_chunk;            // rounds of 64/G pairs a wave claims per atomic
     Pen pen;
     int cap;                    // last step s' held
-    int ring;                   // rows held (cap + 1 + pre in CIGAR mode, pre + 1 otherwise)
+    int ring;                   // rows of the offset ring (pre + 1)
     int seq_words;              // 64-bit words of LDS per sequence
     int group_bytes;            // LDS bytes per lane group
-    int slot_cap;               // runs per pair slot
+    int rows_bytes;             // LDS bytes of the ring (it also stages the runs)
+    int slot_cap;               // most runs a pair may have in the kernel
     int row_bytes;              // 1: int8 offsets (sequences < 128 bases), 2: int16
     int32_t* scores;            // [pairs]
     uint32_t* nruns;            // [pairs] runs written
     uint64_t* run_src;          // [pairs] where the reversed runs live
-    uint32_t* slots;            // [pairs * slot_cap] reversed runs
+    uint32_t* slots;            // [pairs * slot_cap] reversed runs, packed per wave
     uint32_t* ovf_list;         // pairs the kernel could not hold
     uint32_t* ovf_count;
 };

@@ -64,61 +64,70 @@ __device__ __forceinline__ uint32_t cdiv32(uint32_t a) { return (a + 31u) >> 5; 
 // ---------------------------------------------------------------------------
 // planning
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_batch_stats(const PairDesc* __restrict__ pairs, size_t n,
-                                                     BatchStats* out, uint32_t max_len) {
-    uint32_t mp = 0, mt = 0, md = 0, tl = 0;
-    unsigned long long wp = 0, wt = 0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t p = pairs[i].p_len, t = pairs[i].t_len;
-        mp = max(mp, p);
-        mt = max(mt, t);
-        md = max(md, p > t ? p - t : t - p);
-        if (p > max_len || t > max_len) {
-            tl = 1u;
-            atomicMin((unsigned long long*)&out->first_too_long, (unsigned long long)i);
-        }
-        wp += cdiv32(p);
-        wt += cdiv32(t);
-    }
+// Two passes without atomics: every block reduces a grid-strided share of the
+// pairs into its own partial, then one block reduces the partials.
+__device__ __forceinline__ void stats_reduce_block(BatchStats& v, BatchStats* out) {
     for (int off = 32; off > 0; off >>= 1) {
-        mp = max(mp, (uint32_t)__shfl_xor((int)mp, off));
-        mt = max(mt, (uint32_t)__shfl_xor((int)mt, off));
-        md = max(md, (uint32_t)__shfl_xor((int)md, off));
-        tl |= (uint32_t)__shfl_xor((int)tl, off);
-        wp += __shfl_xor(wp, off);
-        wt += __shfl_xor(wt, off);
+        v.max_p = max(v.max_p, (uint32_t)__shfl_xor((int)v.max_p, off));
+        v.max_t = max(v.max_t, (uint32_t)__shfl_xor((int)v.max_t, off));
+        v.max_absdiff = max(v.max_absdiff, (uint32_t)__shfl_xor((int)v.max_absdiff, off));
+        v.too_long |= (uint32_t)__shfl_xor((int)v.too_long, off);
+        v.words_p += __shfl_xor(v.words_p, off);
+        v.words_t += __shfl_xor(v.words_t, off);
+        v.first_too_long = min(v.first_too_long, (uint64_t)__shfl_xor(v.first_too_long, off));
     }
-    // one set of atomics per block
-    __shared__ uint32_t smax[3][4], sor[4];
-    __shared__ unsigned long long ssum[2][4];
+    __shared__ BatchStats sh[4];
     const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        smax[0][wave] = mp;
-        smax[1][wave] = mt;
-        smax[2][wave] = md;
-        sor[wave] = tl;
-        ssum[0][wave] = wp;
-        ssum[1][wave] = wt;
-    }
+    if ((threadIdx.x & 63) == 0) sh[wave] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int nw = blockDim.x >> 6;
-        for (int w = 1; w < nw; w++) {
-            mp = max(mp, smax[0][w]);
-            mt = max(mt, smax[1][w]);
-            md = max(md, smax[2][w]);
-            tl |= sor[w];
-            wp += ssum[0][w];
-            wt += ssum[1][w];
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) {
+            v.max_p = max(v.max_p, sh[w].max_p);
+            v.max_t = max(v.max_t, sh[w].max_t);
+            v.max_absdiff = max(v.max_absdiff, sh[w].max_absdiff);
+            v.too_long |= sh[w].too_long;
+            v.words_p += sh[w].words_p;
+            v.words_t += sh[w].words_t;
+            v.first_too_long = min(v.first_too_long, sh[w].first_too_long);
         }
-        atomicMax(&out->max_p, mp);
-        atomicMax(&out->max_t, mt);
-        atomicMax(&out->max_absdiff, md);
-        if (tl) atomicOr(&out->too_long, tl);
-        atomicAdd((unsigned long long*)&out->words_p, wp);
-        atomicAdd((unsigned long long*)&out->words_t, wt);
+        *out = v;
     }
+}
+
+__global__ __launch_bounds__(256) void k_batch_stats(const PairDesc* __restrict__ pairs, size_t n,
+                                                     BatchStats* __restrict__ partial,
+                                                     uint32_t max_len) {
+    BatchStats v{0u, 0u, 0u, 0u, 0ull, 0ull, ~0ull};
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+#pragma unroll 4
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t p = pairs[i].p_len, t = pairs[i].t_len;
+        v.max_p = max(v.max_p, p);
+        v.max_t = max(v.max_t, t);
+        v.max_absdiff = max(v.max_absdiff, p > t ? p - t : t - p);
+        const bool tl = p > max_len || t > max_len;
+        v.too_long |= tl ? 1u : 0u;
+        v.first_too_long = tl ? min(v.first_too_long, (uint64_t)i) : v.first_too_long;
+        v.words_p += cdiv32(p);
+        v.words_t += cdiv32(t);
+    }
+    stats_reduce_block(v, partial + blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_batch_stats_final(const BatchStats* __restrict__ partial,
+                                                           int nb, BatchStats* __restrict__ out) {
+    BatchStats v{0u, 0u, 0u, 0u, 0ull, 0ull, ~0ull};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const BatchStats q = partial[b];
+        v.max_p = max(v.max_p, q.max_p);
+        v.max_t = max(v.max_t, q.max_t);
+        v.max_absdiff = max(v.max_absdiff, q.max_absdiff);
+        v.too_long |= q.too_long;
+        v.words_p += q.words_p;
+        v.words_t += q.words_t;
+        v.first_too_long = min(v.first_too_long, q.first_too_long);
+    }
+    stats_reduce_block(v, out);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
@@ -397,13 +406,15 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     RowT* RM = (RowT*)gbase;
     RowT* RI = RM + a.ring * RW;
     RowT* RD = RI + a.ring * RW;
-    const int rows_bytes = ((3 * a.ring * RW * (int)sizeof(RowT)) + 15) & ~15;
+    const int rows_bytes = a.rows_bytes;
     // CIGAR mode: one 16-bit backtrace record per cell and step (0..cap):
     // bits 0-11 the M offset before extension, 12-13 its source (0 mismatch,
     // 1 end of insertion, 2 end of deletion), 14 insertion opened from M,
     // 15 deletion opened from M
     uint16_t* REC = (uint16_t*)(gbase + rows_bytes);
     const int rec_bytes = CIGAR ? (((a.cap + 1) * W * 2) + 15) & ~15 : 0;
+    // CIGAR mode: the backtrace stages its runs over the ring (free by then)
+    uint32_t* STAGE = (uint32_t*)gbase;
     uint64_t* SP64 = (uint64_t*)(gbase + rows_bytes + rec_bytes);
     uint64_t* ST64 = SP64 + a.seq_words;
     const uint32_t* SP = (const uint32_t*)SP64;
@@ -417,8 +428,11 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     for (int d = 0; d < DPL; d++) jl[d] = layer_index<G, DPL>(gl, d);
 
     // persistent: a wave claims `queue_chunk` rounds of GPW queue entries per
-    // atomic and works through them before claiming again
+    // atomic and works through them before claiming again.  The runs of the
+    // pairs of a claim go, packed, into the claim's share of the slots
+    // (slot_cap words per entry): `wbump` is the next free word.
     uint32_t claim = 0, claim_left = 0;
+    uint64_t wbump = 0;
     for (uint32_t iter = 0;; iter++) {
         uint32_t qbase;
         if (persistent) {
@@ -427,6 +441,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 if (lane == 0) t = atomicAdd(a.queue, (uint32_t)(GPW * a.queue_chunk));
                 claim = __builtin_amdgcn_readfirstlane(t);
                 claim_left = (uint32_t)a.queue_chunk;
+                wbump = (uint64_t)claim * a.slot_cap;
             }
             qbase = claim;
             claim += GPW;
@@ -434,6 +449,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
         } else {
             if (iter) break;
             qbase = (blockIdx.x * wpb + wave) * GPW;
+            wbump = (uint64_t)qbase * a.slot_cap;
         }
         if (qbase >= a.num) break;
         const uint32_t q = qbase + grp;
@@ -614,10 +630,10 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
         }
 
         // results: the group leader walks the backtrace
+        int cnt = 0;  // runs the group copies out (CIGAR, pair finished here)
         if (active_ok && gl == 0) {
             bool overflow = st == 2;
             if (!overflow && CIGAR) {
-                uint32_t* out = a.slots + (uint64_t)pair * a.slot_cap;
                 const int cap_runs = a.slot_cap;
                 int nr = 0, cop = -1, clen = 0;
                 int s = S, k = kt, h = m, comp = 0;  // comp: 0 M, 1 I, 2 D
@@ -630,8 +646,9 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 // already inside it.  A match run is complete at once (runs of
                 // matches are separated by edits) and closes the open edit
                 // run; an edit extends the open run when it has the same op.
-                // Stores past the slot land on its last word, and the pair is
-                // then re-run elsewhere.
+                // Runs go to the LDS stage in backtrace order; stores past its
+                // end land on its last word, and the pair is then re-run
+                // elsewhere.
                 for (;;) {
                     const int j = k - kmin;
                     if (s < 0 || (unsigned)j >= (unsigned)W || --guard < 0) {
@@ -650,9 +667,9 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                     const bool same = !hasM && !last && cop == ed + 1;  // op codes: X=1 I=2 D=3
                     const bool flush = cop >= 0 && !same && (hasM || !last);
                     const uint32_t pend = ((uint32_t)clen << 4) | (uint32_t)cop;
-                    if (flush) out[min(nr, cap_runs - 1)] = pend;
+                    if (flush) STAGE[min(nr, cap_runs - 1)] = pend;
                     nr += flush;
-                    if (hasM) out[min(nr, cap_runs - 1)] = ((uint32_t)mlen << 4) | (uint32_t)OP_M;
+                    if (hasM) STAGE[min(nr, cap_runs - 1)] = ((uint32_t)mlen << 4) | (uint32_t)OP_M;
                     nr += hasM;
                     if (last) {
                         if (hasM) cop = -1;  // else the open edit run is flushed below
@@ -667,15 +684,11 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                     h = ed == 2 ? hb : hb - 1;  // mismatches and insertions consume a text base
                 }
                 if (cop >= 0) {
-                    out[min(nr, cap_runs - 1)] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    STAGE[min(nr, cap_runs - 1)] = ((uint32_t)clen << 4) | (uint32_t)cop;
                     nr++;
                 }
-                if (overflow || nr > cap_runs) {
-                    overflow = true;
-                } else {
-                    a.nruns[pair] = (uint32_t)nr;
-                    a.run_src[pair] = (uint64_t)pair * a.slot_cap;
-                }
+                if (overflow || nr > cap_runs) overflow = true;
+                else cnt = nr;
             }
             if (overflow) {
                 const uint32_t at = atomicAdd(a.ovf_count, 1u);
@@ -684,6 +697,28 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 a.scores[pair] = S * a.pen.g;
                 if (!CIGAR) a.nruns[pair] = 0;
             }
+            if (CIGAR && !overflow) cnt = max(cnt, 0) | (1 << 30);  // mark: finished here
+        }
+        if (CIGAR) {
+            // copy the groups' staged runs out, packed one after another
+            wave_sync();
+            const bool done = (cnt >> 30) & 1;
+            cnt &= (1 << 30) - 1;
+            int pre = 0, tot = 0;
+#pragma unroll
+            for (int g2 = 0; g2 < GPW; g2++) {
+                const int cg = __shfl(cnt, g2 * G);
+                pre += g2 < grp ? cg : 0;
+                tot += cg;
+            }
+            const int mine = __shfl(cnt, gshift);
+            const uint64_t base = wbump + (uint64_t)pre;
+            for (int r = gl; r < mine; r += G) a.slots[base + r] = STAGE[r];
+            if (done) {
+                a.nruns[pair] = (uint32_t)cnt;
+                a.run_src[pair] = base;
+            }
+            wbump += (uint64_t)tot;
         }
         wave_sync();
     }
@@ -1129,11 +1164,10 @@ int grid_for(size_t n, int block, int max_blocks = 65536) {
 // ---------------------------------------------------------------------------
 hipError_t launch_batch_stats(const PairDesc* pairs, size_t n, BatchStats* out, uint32_t max_len,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out,
-                       0u, sizeof(BatchStats) / 4);
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, &out->first_too_long, ~0ull, (size_t)1);
-    if (n) hipLaunchKernelGGL(k_batch_stats, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, pairs, n,
-                              out, max_len);
+    // out[1 .. STATS_BLOCKS] hold the per-block partials
+    const int nb = n ? grid_for(n, 256 * 8, STATS_BLOCKS) : 1;
+    hipLaunchKernelGGL(k_batch_stats, dim3(nb), dim3(256), 0, s, pairs, n, out + 1, max_len);
+    hipLaunchKernelGGL(k_batch_stats_final, dim3(1), dim3(256), 0, s, out + 1, nb, out);
     return hipGetLastError();
 }
 
