@@ -1063,26 +1063,34 @@ __global__ void k_gather_general(const uint32_t* __restrict__ jobs, size_t njobs
 }
 
 // reversed runs -> caller buffer in alignment order (nothing is written if
-// the total exceeds the capacity).  COMPACT_LANES consecutive threads share a
-// pair, so slot reads and output writes of a pair are contiguous.
-constexpr int COMPACT_LANES = 16;
+// the total exceeds the capacity).  One thread per pair: its counters load
+// together and its runs move COMPACT_UNROLL at a time, so a wave keeps many
+// independent loads in flight (neighbouring pairs' runs are neighbours in
+// the slots and in the output).
+constexpr int COMPACT_UNROLL = 8;
 
-__global__ void k_compact(const uint32_t* __restrict__ nruns, const uint64_t* __restrict__ run_src,
-                          const uint32_t* __restrict__ slots, const uint32_t* __restrict__ gen_runs,
-                          const uint64_t* __restrict__ offsets, size_t n,
-                          uint32_t* __restrict__ out, uint64_t capacity) {
+__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ nruns,
+                                                 const uint64_t* __restrict__ run_src,
+                                                 const uint32_t* __restrict__ slots,
+                                                 const uint32_t* __restrict__ gen_runs,
+                                                 const uint64_t* __restrict__ offsets, size_t n,
+                                                 uint32_t* __restrict__ out, uint64_t capacity) {
     if (offsets[n] > capacity) return;
-    const size_t total = n * COMPACT_LANES;
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = t / COMPACT_LANES;
-        const uint32_t r0 = (uint32_t)(t % COMPACT_LANES);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
         const uint32_t cnt = nruns[i];
-        if (r0 >= cnt) continue;
         const uint64_t src = run_src[i];
-        const uint32_t* s = (src & GEN_BIT) ? gen_runs + (src & ~GEN_BIT) : slots + src;
-        uint32_t* o = out + offsets[i] + (cnt - 1);
-        for (uint32_t r = r0; r < cnt; r += COMPACT_LANES) o[-(int64_t)r] = s[r];
+        const uint64_t dst = offsets[i];
+        const uint32_t* sp = (src & GEN_BIT) ? gen_runs + (src & ~GEN_BIT) : slots + src;
+        uint32_t* o = out + dst + cnt - 1;
+        for (uint32_t r0 = 0; r0 < cnt; r0 += COMPACT_UNROLL) {
+            uint32_t v[COMPACT_UNROLL];
+#pragma unroll
+            for (int u = 0; u < COMPACT_UNROLL; u++) v[u] = r0 + u < cnt ? sp[r0 + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < COMPACT_UNROLL; u++)
+                if (r0 + u < cnt) o[-(int64_t)(r0 + u)] = v[u];
+        }
     }
 }
 
@@ -1324,7 +1332,7 @@ hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const 
                           const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
                           uint32_t* out, uint64_t capacity, hipStream_t s) {
     if (n)
-        hipLaunchKernelGGL(k_compact, dim3(grid_for(n * COMPACT_LANES, 256, 1 << 20)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s,
                            nruns, run_src, slots, gen_runs, offsets, n, out, capacity);
     return hipGetLastError();
 }
