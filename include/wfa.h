@@ -119,7 +119,7 @@ typedef struct {
     int32_t general_pairs;  /* concurrent pairs of the general kernel; 0: by budget */
     int32_t block_threads;  /* threads per workgroup of the short kernel: 64..256 */
     int32_t lanes_per_pair; /* lanes of a wavefront per pair in the short kernel
-                               (16, 32 or 64, at most the window): 64 / lanes
+                               (8, 16, 32 or 64, at most the window): 64 / lanes
                                pairs share a wavefront */
 } wfa_options;
 

@@ -185,7 +185,7 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         std::vector<int> caps{cap0};
         if (sample_steps >= 0 && sample_steps < cap0) caps.push_back(std::max(sample_steps, 1));
         else caps.push_back(std::max(P.oe + P.x, cap0 * 2 / 3));
-        for (int g : {16, 32, 64}) {
+        for (int g : {8, 16, 32, 64}) {
             if (!wfa::short_shape_supported(w, g)) continue;
             for (int bt : {64, 128, 256}) {
                 // plain; persistent with and without bucketing

@@ -1257,7 +1257,9 @@ static int occ_t(bool cigar, int bt, int lds) {
 
 // (window, lanes per pair) shapes the short kernel is built for
 #define WFA_SHORT_SHAPES(X) \
+    X(16, 8, 2)             \
     X(16, 16, 1)            \
+    X(32, 8, 4)             \
     X(32, 32, 1)            \
     X(32, 16, 2)            \
     X(64, 64, 1)            \
