@@ -241,7 +241,9 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, i
     const int minc = std::min(pen.x, pen.e);
     sp->slot_cap = 2 * ((cap / minc) + 1) + 2;
     // the ring is free during the backtrace, which stages the runs there
-    const int ring_bytes = std::max(3 * sp->ring * RW * sp->row_bytes, cigar ? 4 * sp->slot_cap : 0);
+    // (two spare words take the stores of a walk that overflows)
+    const int ring_bytes =
+        std::max(3 * sp->ring * RW * sp->row_bytes, cigar ? 4 * (sp->slot_cap + 2) : 0);
     sp->rows_bytes = (ring_bytes + 15) & ~15;
     const int rec_bytes = cigar ? (((cap + 1) * window * 2) + 15) & ~15 : 0;
     sp->group_bytes = sp->rows_bytes + rec_bytes + 2 * sp->seq_words * 8;

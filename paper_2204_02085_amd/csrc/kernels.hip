@@ -423,6 +423,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
     const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e;
     const int ring = a.ring;
 
+    const bool bnd = gl == 0 || gl == G - 1;  // lanes on a layer's outermost diagonals
     int jl[DPL];  // window index of each of this lane's diagonals
 #pragma unroll
     for (int d = 0; d < DPL; d++) jl[d] = layer_index<G, DPL>(gl, d);
@@ -496,9 +497,15 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
         }
         wave_sync();
 
-        int lim[DPL];
+        // per diagonal: the largest admissible offset min(m, n + k) (negative
+        // off the matrix), the same floored at 0, and the diagonal itself
+        int lim[DPL], limz[DPL], kd[DPL];
 #pragma unroll
-        for (int d = 0; d < DPL; d++) lim[d] = min(m, n + kmin + jl[d]);
+        for (int d = 0; d < DPL; d++) {
+            kd[d] = kmin + jl[d];
+            lim[d] = min(m, n + kd[d]);
+            limz[d] = max(lim[d], 0);
+        }
         const int jt = kt - kmin;  // window index of the target diagonal
         int S = 0;
         // layers this group computes: at first the fewest that hold diagonal 0
@@ -516,6 +523,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
             int nlay = 1;
 #pragma unroll
             for (int d = 1; d < DPL; d++) nlay += __ballot(st == 0 && lay > d) != 0 ? 1 : 0;
+            const bool growable = DPL > 1 && __ballot(st == 0 && lay < DPL) != 0;
             if (s > 0) cur = cur + 1 == ring ? 0 : cur + 1;
             int ix = cur - X, io = cur - OE, ie = cur - E;
             ix += ix < 0 ? ring : 0;
@@ -574,13 +582,12 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                         rec[d] = (Mv[d] & 0xFFF) | (msrc << 12) | ((ta == ti) << 14) | ((tc == td) << 15);
                     }
                 }
-                const int k = kmin + j;
-                const int h = Mv[d], v = h - k;
-                const int left = min(n - v, m - h);
-                const bool go = run && h >= 0 && left > 0;
+                // bases before either sequence ends: min(n - v, m - h) = L - h
+                const int h = Mv[d];
+                const bool go = run && (unsigned)h < (unsigned)limz[d];
                 hp[d] = go ? h : 0;
-                vp[d] = go ? v : 0;
-                rem[d] = go ? left : 0;
+                vp[d] = go ? h - kd[d] : 0;
+                rem[d] = go ? limz[d] - h : 0;
                 gm[d] = __ballot(go);
             }
             // extend along matches, 32 bases per compare.  The loop is
@@ -613,16 +620,18 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 RM[cur * RW + 1 + j] = (RowT)Mv[d];
                 RI[cur * RW + 1 + j] = (RowT)Iv[d];
                 RD[cur * RW + 1 + j] = (RowT)Dv[d];
-                if (CIGAR && s <= a.cap) REC[s * W + j] = (uint16_t)rec[d];
+                if (CIGAR) REC[s * W + j] = (uint16_t)rec[d];  // s <= cap here
                 const bool live = Mv[d] >= 0;  // M is at least I and D
-                const bool bnd = gl == 0 || gl == G - 1;  // a layer's outermost diagonals
                 term |= (j == jt) & (Mv[d] == m);
                 if (d == DPL - 1) edge |= bnd & live;
                 if (d < DPL - 1) grow |= (d == lay - 1) & bnd & live;
             }
             const bool gterm = group_any<G>(__ballot(term), gshift);
-            const bool gedge = group_any<G>(__ballot(edge), gshift);
-            const bool ggrow = DPL > 1 && group_any<G>(__ballot(grow), gshift);
+            // the outermost layer can only be live once it is computed, and a
+            // layer is only added while some running group has one to add
+            bool gedge = false, ggrow = false;
+            if (nlay == DPL) gedge = group_any<G>(__ballot(edge), gshift);
+            if (DPL > 1 && growable) ggrow = group_any<G>(__ballot(grow), gshift);
             S = (run && gterm) ? s : S;
             st = run ? (gterm ? 1 : ((gedge || s >= a.cap) ? 2 : 0)) : st;
             lay += (run && ggrow) ? 1 : 0;
@@ -637,7 +646,6 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 const int cap_runs = a.slot_cap;
                 int nr = 0, cop = -1, clen = 0;
                 int s = S, k = kt, h = m, comp = 0;  // comp: 0 M, 1 I, 2 D
-                int guard = S + 2;  // every iteration lowers s by at least 1
                 // Replays the decisions recorded in the forward pass.  Each
                 // iteration reads one record and emits the run of matches of
                 // an M cell (if the walk is in M) followed by exactly one edit:
@@ -646,46 +654,40 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 // already inside it.  A match run is complete at once (runs of
                 // matches are separated by edits) and closes the open edit
                 // run; an edit extends the open run when it has the same op.
-                // Runs go to the LDS stage in backtrace order; stores past its
-                // end land on its last word, and the pair is then re-run
-                // elsewhere.
+                // Both candidate runs are stored every iteration, at the next
+                // free stage word, and only kept (the count advanced) when
+                // they are real; stores of a walk past the stage's end land on
+                // its two spare words, and the pair is then re-run elsewhere.
+                // Every iteration lowers s, so the walk ends.
                 for (;;) {
                     const int j = k - kmin;
-                    if (s < 0 || (unsigned)j >= (unsigned)W || --guard < 0) {
+                    if (s < 0 || (unsigned)j >= (unsigned)W) {
                         overflow = true;  // inconsistent walk: leave it to the general kernel
                         break;
                     }
                     const int r = REC[s * W + j];
                     const bool isM = comp == 0;
-                    const int h0 = r & 0xFFF;
-                    const int mlen = isM ? h - (s == 0 ? 0 : h0) : 0;
                     const bool last = isM && s == 0;
+                    const int h0 = s == 0 ? 0 : (r & 0xFFF);
+                    const int mlen = isM ? h - h0 : 0;
                     // edit of this iteration: 0 mismatch, 1 insertion, 2 deletion
                     const int ed = isM ? ((r >> 12) & 3) : comp;
-                    const int hb = isM ? h0 : h;  // offset where the edit ends
+                    const int op = last ? OP_M : ed + 1;  // op codes: X=1 I=2 D=3
                     const bool hasM = mlen > 0;
-                    const bool same = !hasM && !last && cop == ed + 1;  // op codes: X=1 I=2 D=3
-                    const bool flush = cop >= 0 && !same && (hasM || !last);
-                    const uint32_t pend = ((uint32_t)clen << 4) | (uint32_t)cop;
-                    if (flush) STAGE[min(nr, cap_runs - 1)] = pend;
-                    nr += flush;
-                    if (hasM) STAGE[min(nr, cap_runs - 1)] = ((uint32_t)mlen << 4) | (uint32_t)OP_M;
-                    nr += hasM;
-                    if (last) {
-                        if (hasM) cop = -1;  // else the open edit run is flushed below
-                        break;
-                    }
-                    clen = same ? clen + 1 : 1;
-                    cop = ed + 1;
-                    const bool open = ed == 1 ? ((r >> 14) & 1) : ((r >> 15) & 1);
-                    s = ed == 0 ? s - X : (open ? s - OE : s - E);
+                    const bool flush = cop >= 0 && (hasM || cop != op);
+                    STAGE[min(nr, cap_runs + 1)] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    nr += flush ? 1 : 0;
+                    STAGE[min(nr, cap_runs + 1)] = ((uint32_t)mlen << 4) | (uint32_t)OP_M;
+                    nr += hasM ? 1 : 0;
+                    if (last) break;
+                    clen = (flush || hasM) ? 1 : clen + 1;
+                    cop = op;
+                    const int hb = isM ? h0 : h;  // offset where the edit ends
+                    const bool open = (r >> (13 + ed)) & 1;  // bit 14: I opened, 15: D opened
+                    s -= ed == 0 ? X : (open ? OE : E);
                     comp = (ed == 0 || open) ? 0 : ed;
-                    k = ed == 1 ? k - 1 : (ed == 2 ? k + 1 : k);
+                    k += (ed == 2 ? 1 : 0) - (ed == 1 ? 1 : 0);
                     h = ed == 2 ? hb : hb - 1;  // mismatches and insertions consume a text base
-                }
-                if (cop >= 0) {
-                    STAGE[min(nr, cap_runs - 1)] = ((uint32_t)clen << 4) | (uint32_t)cop;
-                    nr++;
                 }
                 if (overflow || nr > cap_runs) overflow = true;
                 else cnt = nr;
