@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--encoding", choices=["packed2", "ascii"], default="packed2",
                     help="input encoding resident in HBM")
-    ap.add_argument("--tune-sample", type=int, default=1_000_000)
+    ap.add_argument("--tune-sample", type=int, default=0,
+                    help="pairs the autotuner times candidates on (0: the whole batch)")
     ap.add_argument("--options", default="",
                     help="JSON launch options instead of autotuning (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -234,7 +235,7 @@ def main():
         tuned = {k: int(v) for k, v in json.loads(args.options).items()}
     else:
         tuned = al.autotune(pat, txt, pairs, n, (4, 6, 2), True, encoding=enc,
-                            sample_pairs=args.tune_sample)
+                            sample_pairs=args.tune_sample or n)
     t_tune = time.perf_counter() - t_tune
 
     log(f"autotuned in {t_tune:.1f} s: {tuned}; timing {args.steps} steps")

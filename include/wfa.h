@@ -211,16 +211,20 @@ int wfa_pack2bit(wfa_ctx *ctx, const uint8_t *ascii, const uint64_t *starts,
                  const uint32_t *lens, size_t count, uint64_t *words, size_t words_capacity,
                  uint64_t *word_starts, size_t *total_words, int64_t *bad_index, void *stream);
 
-/* Autotuner.  Times candidate options (short-kernel window, i.e. lane
- * groups per wavefront and diagonals per lane; step cap, i.e. LDS rows per
- * pair; workgroup size; plain or persistent schedule; bucketing) on the first
- * `sample_pairs` pairs (0: 262144) of the given batch, checks that every
- * candidate returns byte-identical results, and applies the fastest to the
- * context.  The winner is cached in the JSON file `cache_path` (NULL: no
- * cache) under a key of device architecture, penalties, mode and the
- * batch's length / length-difference / size classes; a later call with the
- * same key reuses it unless `force` is set.  Arguments as wfa_align_batch;
- * *chosen receives the options.  WFA_E_DEVICE if two candidates disagree. */
+/* Autotuner.  Times candidate options on the first `sample_pairs` pairs
+ * (0: 262144) of the given batch, in two stages: first every short-kernel
+ * shape (window, lanes per pair) whose window can hold the sample's length
+ * differences, plain schedule, plus the general kernel; then, for the two
+ * fastest shapes, every workgroup size (64, 128, 256), schedule form (plain;
+ * persistent with and without bucketing) and step cap (the default, and the
+ * largest score step of the sample, found by a score-only pass).  A
+ * candidate's time is the fastest of several calls.  Every candidate must
+ * return byte-identical results; the fastest is applied to the context and
+ * cached in the JSON file `cache_path` (NULL: no cache) under a key of device
+ * architecture, penalties, mode and the batch's length / length-difference /
+ * size classes; a later call with the same key reuses it unless `force` is
+ * set.  Arguments as wfa_align_batch; *chosen receives the options.
+ * WFA_E_DEVICE if two candidates disagree. */
 int wfa_autotune(wfa_ctx *ctx, const void *patterns, const void *texts, const wfa_pair *pairs,
                  size_t num_pairs, wfa_encoding enc, wfa_memspace mem, wfa_penalties pen,
                  wfa_mode mode, size_t sample_pairs, const char *cache_path, int force,

@@ -176,48 +176,15 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         for (int32_t v : scores) sample_steps = std::max(sample_steps, v / P.g);
     }
 
-    // candidates
-    std::vector<Candidate> cands;
-    const int windows[] = {16, 32, 64, 128, 256};
-    for (int w : windows) {
-        if (w < 2 * (int)max_diff + 4 && w != 256) continue;  // the target must fit the window
-        const int cap0 = default_cap(P, w);
-        std::vector<int> caps{cap0};
-        if (sample_steps >= 0 && sample_steps < cap0) caps.push_back(std::max(sample_steps, 1));
-        else caps.push_back(std::max(P.oe + P.x, cap0 * 2 / 3));
-        for (int g : {8, 16, 32, 64}) {
-            if (!wfa::short_shape_supported(w, g)) continue;
-            for (int bt : {64, 128, 256}) {
-                // plain; persistent with and without bucketing
-                for (int form : {0, 1, 2}) {
-                    const int sched = form == 0 ? WFA_SCHED_PLAIN : WFA_SCHED_PERSISTENT;
-                    for (int capx : caps) {
-                        Candidate c{};
-                        c.opt.schedule = sched;
-                        c.opt.window = w;
-                        c.opt.lanes_per_pair = g;
-                        c.opt.step_cap = capx;
-                        c.opt.block_threads = bt;
-                        c.opt.bucket = form == 1 ? 1 : -1;
-                        c.opt.use_graph = form == 0 ? -1 : 1;
-                        cands.push_back(c);
-                    }
-                }
-            }
-        }
-    }
-    {
-        Candidate g{};
-        g.opt.schedule = WFA_SCHED_GENERAL;
-        g.opt.use_graph = -1;
-        cands.push_back(g);
-    }
-
     std::vector<uint64_t> ref_off, off(n + 1);
     std::vector<uint32_t> ref_runs, runs;
     Candidate best;
     int status = WFA_OK;
-    for (auto& c : cands) {
+
+    // Times one candidate (fastest of `reps` calls after a warm-up call) and
+    // checks that its results equal the first candidate's.  Returns WFA_OK,
+    // WFA_E_NOMEM for a candidate that does not fit (skipped), or an error.
+    auto evaluate = [&](Candidate& c, int reps) -> int {
         ctx->opt = c.opt;
         BatchIO io{patterns, texts, pairs, n, enc, mem, pen, mode,
                    mem == WFA_DEVICE ? d_scores.as<int32_t>() : scores.data(),
@@ -235,21 +202,17 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         }
         size_t needed = 0;
         int64_t bad = -1;
-        rc = engine_align(ctx, io, nullptr, &needed, &bad);  // warm-up (plans, graphs)
-        if (rc != WFA_OK) {
-            if (rc == WFA_E_NOMEM) continue;  // candidate does not fit: skip it
-            status = rc;
-            break;
+        int r = engine_align(ctx, io, nullptr, &needed, &bad);  // warm-up (plans, graphs)
+        if (r != WFA_OK) return r;
+        double bestrep = 1e30;
+        for (int k = 0; k < reps; k++) {
+            const double t0 = now_ms();
+            r = engine_align(ctx, io, nullptr, &needed, &bad);  // synchronous
+            const double t1 = now_ms();
+            if (r != WFA_OK) return r == WFA_E_NOMEM ? WFA_E_DEVICE : r;
+            bestrep = std::min(bestrep, t1 - t0);
         }
-        const double t0 = now_ms();
-        const int reps = 3;
-        for (int r = 0; r < reps && rc == WFA_OK; r++) rc = engine_align(ctx, io, nullptr, &needed, &bad);
-        const double t1 = now_ms();
-        if (rc != WFA_OK) {
-            status = rc;
-            break;
-        }
-        c.ms = (t1 - t0) / reps / (double)n * 1e6;
+        c.ms = bestrep / (double)n * 1e6;
         // results of every candidate must be identical
         if (mem == WFA_DEVICE) {
             (void)hipMemcpy(scores.data(), d_scores.ptr, n * 4, hipMemcpyDeviceToHost);
@@ -267,13 +230,81 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
             ref_off = off;
             ref_runs = runs;
         } else if (scores != ref_scores || (cigar && (off != ref_off || runs != ref_runs))) {
-            std::fprintf(stderr, "libwfa autotune: candidate window=%d cap=%d bt=%d sched=%d "
-                                 "changed the results\n",
-                         c.opt.window, c.opt.step_cap, c.opt.block_threads, c.opt.schedule);
-            status = WFA_E_DEVICE;
-            break;
+            std::fprintf(stderr, "libwfa autotune: candidate window=%d lanes=%d cap=%d bt=%d "
+                                 "sched=%d changed the results\n",
+                         c.opt.window, c.opt.lanes_per_pair, c.opt.step_cap, c.opt.block_threads,
+                         c.opt.schedule);
+            return WFA_E_DEVICE;
         }
         if (c.ms < best.ms) best = c;
+        return WFA_OK;
+    };
+
+    // Stage 1: every short-kernel shape (window, lanes per pair) whose window
+    // can hold the target diagonal, plain schedule, and the general kernel.
+    struct Shape {
+        int w, g, cap0, caps;
+        double ms;
+    };
+    std::vector<Shape> shapes;
+    const int windows[] = {16, 32, 64, 128, 256};
+    for (int w : windows) {
+        if (w < 2 * (int)max_diff + 4 && w != 256) continue;  // the target must fit the window
+        const int cap0 = default_cap(P, w);
+        const int caps = (sample_steps >= 0 && sample_steps < cap0)
+                             ? std::max(sample_steps, 1)
+                             : std::max(P.oe + P.x, cap0 * 2 / 3);
+        for (int g : {8, 16, 32, 64})
+            if (wfa::short_shape_supported(w, g)) shapes.push_back({w, g, cap0, caps, 1e30});
+    }
+    for (auto& sh : shapes) {
+        Candidate c{};
+        c.opt.schedule = WFA_SCHED_PLAIN;
+        c.opt.window = sh.w;
+        c.opt.lanes_per_pair = sh.g;
+        c.opt.step_cap = sh.caps;
+        c.opt.block_threads = 128;
+        c.opt.bucket = -1;
+        c.opt.use_graph = -1;
+        const int r = evaluate(c, 3);
+        if (r == WFA_OK) sh.ms = c.ms;
+        else if (r != WFA_E_NOMEM) { status = r; break; }
+    }
+    if (status == WFA_OK) {
+        Candidate g{};
+        g.opt.schedule = WFA_SCHED_GENERAL;
+        g.opt.use_graph = -1;
+        const int r = evaluate(g, 1);
+        if (r != WFA_OK && r != WFA_E_NOMEM) status = r;
+    }
+    // Stage 2: the two fastest shapes, every workgroup size, schedule form
+    // (plain; persistent with and without bucketing) and step cap.
+    std::sort(shapes.begin(), shapes.end(), [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
+    for (size_t i = 0; i < shapes.size() && i < 2 && status == WFA_OK; i++) {
+        const Shape& sh = shapes[i];
+        if (sh.ms >= 1e30) break;
+        for (int bt : {64, 128, 256}) {
+            for (int form : {0, 1, 2}) {
+                for (int capx : {sh.caps, sh.cap0}) {
+                    if (capx == sh.cap0 && sh.cap0 == sh.caps) continue;
+                    Candidate c{};
+                    c.opt.schedule = form == 0 ? WFA_SCHED_PLAIN : WFA_SCHED_PERSISTENT;
+                    c.opt.window = sh.w;
+                    c.opt.lanes_per_pair = sh.g;
+                    c.opt.step_cap = capx;
+                    c.opt.block_threads = bt;
+                    c.opt.bucket = form == 1 ? 1 : -1;
+                    c.opt.use_graph = form == 0 ? -1 : 1;
+                    const int r = evaluate(c, 5);
+                    if (r != WFA_OK && r != WFA_E_NOMEM) {
+                        status = r;
+                        break;
+                    }
+                }
+                if (status != WFA_OK) break;
+            }
+            if (status != WFA_OK) break;
+        }
     }
     tmp.release_all();
     if (status != WFA_OK || best.ms >= 1e30) {
