@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--encoding", choices=["packed2", "ascii"], default="packed2",
                     help="input encoding resident in HBM")
+    ap.add_argument("--host-steps", type=int, default=2,
+                    help="calls timed with host ASCII inputs and host outputs (PCIe "
+                         "included; 0: skip)")
     ap.add_argument("--tune-sample", type=int, default=0,
                     help="pairs the autotuner times candidates on (0: the whole batch)")
     ap.add_argument("--options", default="",
@@ -122,6 +125,42 @@ def time_schedule(al, dev, n, steps, warmup, options, enc):
     t1 = time.perf_counter()
     st = al.stats()
     return (t1 - t0), kernel_ms, st
+
+
+def host_path_run(al, wfa, batch, steps, options):
+    """Whole calls with host memory on both sides: ASCII pairs in pageable host
+    buffers, results back in host buffers (the library stages through the
+    device).  PCIe is included; this is never the headline value."""
+    import ctypes
+
+    import numpy as np
+
+    n = len(batch.p_len)
+    pairs = wfa.pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len)
+    scores = np.empty(n, np.int32)
+    offsets = np.empty(n + 1, np.uint64)
+    cap = n * 40 + 1024
+    runs = np.empty(cap, np.uint32)
+    needed = ctypes.c_size_t(0)
+    bad = ctypes.c_int64(-1)
+    al.set_options(**options)
+
+    def call():
+        rc = wfa.wfa_align_batch(al.ctx, batch.patterns.ctypes.data, batch.texts.ctypes.data,
+                                 pairs.ctypes.data, n, wfa.WFA_ASCII, wfa.WFA_HOST,
+                                 wfa.wfa_penalties(4, 6, 2), wfa.WFA_CIGAR, scores.ctypes.data,
+                                 runs.ctypes.data, cap, offsets.ctypes.data,
+                                 ctypes.byref(needed), ctypes.byref(bad), None)
+        if rc != wfa.WFA_OK:
+            raise wfa.WFAError(rc, "wfa_align_batch (host)", bad.value)
+
+    call()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    el = time.perf_counter() - t0
+    return {"pairs_per_s": n * steps / el, "ms_per_call": el / steps * 1e3, "steps": steps,
+            "input": "ASCII in pageable host memory", "output": "host memory"}, scores
 
 
 def serving_run(al, wfa, synth, n_req, load, seed=11):
@@ -248,17 +287,33 @@ def main():
     tuned_stats = st
     got_scores = scores.cpu().numpy().copy()
 
-    # persistent + bucketed + graph with default knobs, and the plain per-batch kernel
-    log("timing persistent and plain schedules")
-    bel, bkms, bst = time_schedule(al, dev, n, args.plain_steps, 1,
-                                   {"schedule": wfa.WFA_SCHED_PERSISTENT}, enc)
-    batched_value = n * args.plain_steps / bel
-    pel, pkms, pst = time_schedule(al, dev, n, args.plain_steps, 1,
-                                   {"schedule": wfa.WFA_SCHED_PLAIN}, enc)
-    plain_value = n * args.plain_steps / pel
-    plain_kernel_ms = float(np.mean(pkms))
-    if not np.array_equal(scores.cpu().numpy(), got_scores):
-        raise RuntimeError("plain and tuned schedules disagree")
+    # the same launch shape (window, lanes, step cap, workgroup size) as one
+    # persistent bucketed launch replayed through graphs, and as the plain
+    # per-batch kernel
+    batched = None
+    if args.plain_steps > 0:
+        log("timing persistent and plain schedules")
+        shape = {k: tuned.get(k, 0) for k in ("window", "lanes_per_pair", "step_cap",
+                                              "block_threads")}
+        bel, bkms, bst = time_schedule(al, dev, n, args.plain_steps, 1,
+                                       {**shape, "schedule": wfa.WFA_SCHED_PERSISTENT,
+                                        "bucket": 1, "use_graph": 1}, enc)
+        batched_value = n * args.plain_steps / bel
+        pel, pkms, pst = time_schedule(al, dev, n, args.plain_steps, 1,
+                                       {**shape, "schedule": wfa.WFA_SCHED_PLAIN,
+                                        "bucket": -1, "use_graph": -1}, enc)
+        plain_value = n * args.plain_steps / pel
+        if not np.array_equal(scores.cpu().numpy(), got_scores):
+            raise RuntimeError("plain and tuned schedules disagree")
+        batched = {"tuned_pairs_per_s": value,
+                   "persistent_bucketed_graph_pairs_per_s": batched_value,
+                   "plain_pairs_per_s": plain_value,
+                   "speedup_persistent_vs_plain": batched_value / plain_value,
+                   "speedup_tuned_vs_plain": value / plain_value,
+                   "tuned_kernel_ms": kernel_ms,
+                   "persistent_kernel_ms": float(np.mean(bkms)),
+                   "plain_kernel_ms": float(np.mean(pkms)),
+                   "launch_shape": shape}
 
     # results of both schedules are identical (cheap check on the last step)
     torch.cuda.synchronize()
@@ -288,6 +343,13 @@ def main():
         got = scores[: len(sample)].cpu().numpy()
         if not np.array_equal(got, ref.scores):
             print("WARNING: GPU scores differ from the oracle sample", file=sys.stderr)
+
+    host_path = None
+    if args.host_steps > 0:
+        log(f"host-memory path: {args.host_steps} calls")
+        host_path, host_scores = host_path_run(al, wfa, batch, args.host_steps, tuned)
+        if not np.array_equal(host_scores, got_scores):
+            raise RuntimeError("host-memory path and device path disagree")
 
     serving = None
     if args.serving_requests > 0:
@@ -329,16 +391,10 @@ def main():
         "cigar_runs": needed,
         "autotuned_options": tuned,
         "autotune_seconds": t_tune,
-        "batched_vs_plain": {"tuned_pairs_per_s": value,
-                             "persistent_bucketed_graph_pairs_per_s": batched_value,
-                             "plain_pairs_per_s": plain_value,
-                             "speedup_tuned_vs_plain": value / plain_value,
-                             "speedup_persistent_vs_plain": batched_value / plain_value,
-                             "tuned_kernel_ms": kernel_ms,
-                             "persistent_kernel_ms": float(np.mean(bkms)),
-                             "plain_kernel_ms": plain_kernel_ms},
+        "batched_vs_plain": batched,
         "phase_ms": {k: tuned_stats[k] for k in ("ms_pack", "ms_align", "ms_general", "ms_compact",
                                                  "ms_total")},
+        "host_path": host_path,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
