@@ -112,7 +112,8 @@ typedef enum {
  * any result. */
 typedef struct {
     int32_t schedule;       /* wfa_schedule                                      */
-    int32_t window;         /* diagonals held per pair by the short kernel: 16, 32, 64, 128, 256 */
+    int32_t window;         /* diagonals held per pair by the short kernel:
+                               16, 24, 32, 48, 64, 128, 256 */
     int32_t step_cap;       /* score steps (in units of gcd(x,o,e)) held in LDS  */
     int32_t use_graph;      /* 1: replay a captured hipGraph; -1: never; 0: auto */
     int32_t bucket;         /* 1: sort pairs by (length, length difference); -1: off */

@@ -159,8 +159,8 @@ extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
         return WFA_OK;
     }
     if (opt->schedule < 0 || opt->schedule > WFA_SCHED_GENERAL) return WFA_E_INVAL;
-    if (opt->window && opt->window != 16 && opt->window != 32 && opt->window != 64 &&
-        opt->window != 128 && opt->window != 256)
+    if (opt->window && opt->window != 16 && opt->window != 24 && opt->window != 32 &&
+        opt->window != 48 && opt->window != 64 && opt->window != 128 && opt->window != 256)
         return WFA_E_INVAL;
     if (opt->lanes_per_pair && opt->lanes_per_pair != 8 && opt->lanes_per_pair != 16 &&
         opt->lanes_per_pair != 32 && opt->lanes_per_pair != 64)

@@ -247,7 +247,7 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         double ms;
     };
     std::vector<Shape> shapes;
-    const int windows[] = {16, 32, 64, 128, 256};
+    const int windows[] = {16, 24, 32, 48, 64, 128, 256};
     for (int w : windows) {
         if (w < 2 * (int)max_diff + 4 && w != 256) continue;  // the target must fit the window
         const int cap0 = default_cap(P, w);

@@ -1261,9 +1261,11 @@ static int occ_t(bool cigar, int bt, int lds) {
 #define WFA_SHORT_SHAPES(X) \
     X(16, 8, 2)             \
     X(16, 16, 1)            \
+    X(24, 8, 3)             \
     X(32, 8, 4)             \
     X(32, 32, 1)            \
     X(32, 16, 2)            \
+    X(48, 16, 3)            \
     X(64, 64, 1)            \
     X(64, 32, 2)            \
     X(64, 16, 4)            \

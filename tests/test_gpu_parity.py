@@ -58,8 +58,8 @@ def test_pairs100_e4_schedules(aligner, oracle_lib, synth_lib, wfa, schedule):
     assert_same(got, oracle_of(oracle_lib, b), b, f"e4/{schedule}")
 
 
-SHAPES = [(16, 8), (16, 16), (32, 32), (32, 16), (32, 8), (64, 64), (64, 32), (64, 16),
-          (128, 64), (128, 32), (256, 64)]
+SHAPES = [(16, 8), (16, 16), (24, 8), (32, 32), (32, 16), (32, 8), (48, 16), (64, 64), (64, 32),
+          (64, 16), (128, 64), (128, 32), (256, 64)]
 
 
 @pytest.mark.parametrize("window,lanes", SHAPES)
