@@ -474,6 +474,8 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
             a.pen = pen;
             a.cap = sp.cap;
             a.ring = sp.ring;
+            a.ring2 = sp.ring2;
+            a.id_off = sp.id_off;
             a.seq_words = sp.seq_words;
             a.group_bytes = sp.group_bytes;
             a.rows_bytes = sp.rows_bytes;

@@ -230,9 +230,12 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, i
     sp->lanes = lanes;
     sp->cap = cap;
     sp->seq_words = (int)((max_len + 31) / 32) + 1;
-    // offsets: a ring of the pre + 1 newest rows; CIGAR mode adds one 16-bit
-    // backtrace record per cell and step
-    sp->ring = pen.pre + 1;
+    // offsets: I and D rows in rings of e + 1 (a step reads them back e
+    // steps); M rows in a ring of pre + 1 in score mode, all of them (after
+    // pre NULL rows) in CIGAR mode, which adds a 4-bit decision record per
+    // cell and step for the backtrace
+    sp->ring = cigar ? pen.pre + cap + 1 : pen.pre + 1;
+    sp->ring2 = pen.e + 1;
     // int8 offsets hold lengths up to 127; a NULL (-128) drifts up by at most
     // one per step, so it stays negative for caps below 100
     sp->row_bytes = (max_len <= 127 && cap < 100) ? 1 : 2;
@@ -240,12 +243,13 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, i
     // runs: every non-match op costs at least min(x, e) (in units of g)
     const int minc = std::min(pen.x, pen.e);
     sp->slot_cap = 2 * ((cap / minc) + 1) + 2;
-    // the ring is free during the backtrace, which stages the runs there
-    // (two spare words take the stores of a walk that overflows)
-    const int ring_bytes =
-        std::max(3 * sp->ring * RW * sp->row_bytes, cigar ? 4 * (sp->slot_cap + 2) : 0);
-    sp->rows_bytes = (ring_bytes + 15) & ~15;
-    const int rec_bytes = cigar ? (((cap + 1) * window * 2) + 15) & ~15 : 0;
+    // the I/D rings are free during the backtrace, which stages the runs
+    // there (two spare words take the stores of a walk that overflows)
+    sp->id_off = (sp->ring * RW * sp->row_bytes + 15) & ~15;
+    const int id_bytes =
+        std::max(2 * sp->ring2 * RW * sp->row_bytes, cigar ? 4 * (sp->slot_cap + 2) : 0);
+    sp->rows_bytes = (sp->id_off + id_bytes + 15) & ~15;
+    const int rec_bytes = cigar ? (((cap + 1) * (window / 2)) + 15) & ~15 : 0;
     sp->group_bytes = sp->rows_bytes + rec_bytes + 2 * sp->seq_words * 8;
     sp->group_bytes = (sp->group_bytes + 15) & ~15;
     int bt = ctx->opt.block_threads ? ctx->opt.block_threads : 256;

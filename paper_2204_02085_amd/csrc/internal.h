@@ -59,7 +59,7 @@ struct DevFlags {
 
 struct ShortPlan {
     int window = 0, lanes = 32, cap = 0, seq_words = 0, ring = 0, group_bytes = 0, slot_cap = 0;
-    int rows_bytes = 0;
+    int rows_bytes = 0, ring2 = 0, id_off = 0;
     int row_bytes = 2;
     int block_threads = 256, lds_per_block = 0;
 };

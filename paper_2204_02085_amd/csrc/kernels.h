@@ -50,10 +50,12 @@ struct ShortArgs {
     int queue_chunk;            // rounds of 64/G pairs a wave claims per atomic
     Pen pen;
     int cap;                    // last step s' held
-    int ring;                   // rows of the offset ring (pre + 1)
+    int ring;                   // M rows: a ring of pre + 1 (score), or pre + cap + 1 (CIGAR)
+    int ring2;                  // I and D rows: rings of e + 1
+    int id_off;                 // LDS byte offset of the I rows (the D rows follow)
     int seq_words;              // 64-bit words of LDS per sequence
     int group_bytes;            // LDS bytes per lane group
-    int rows_bytes;             // LDS bytes of the ring (it also stages the runs)
+    int rows_bytes;             // LDS bytes of all offset rows (the I/D rings also stage runs)
     int slot_cap;               // most runs a pair may have in the kernel
     int row_bytes;              // 1: int8 offsets (sequences < 128 bases), 2: int16
     int32_t* scores;            // [pairs]

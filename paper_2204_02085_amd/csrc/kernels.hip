@@ -343,13 +343,17 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
 // cell in it is NULL -- and a wave skips the layers none of its groups needs,
 // so early (narrow) score steps cost one layer.
 //
-// Row r of the LDS history holds, for one score step, the offsets of M
-// (after extension), I and D on the W diagonals plus a NULL pad on each side,
-// so neighbouring diagonals are read without bounds checks.  The rows form a
-// ring of pre + 1 steps; every row starts NULL.  Offsets are int8 when both
-// sequences are shorter than 128 bases (twice the lane groups per CU), int16
-// otherwise.  In CIGAR mode each cell of each step also gets a 16-bit record
-// of the decisions the backtrace replays.
+// LDS per lane group.  Row r of an offset store holds, for one score step,
+// the offsets of the W diagonals plus a NULL pad on each side, so
+// neighbouring diagonals are read without bounds checks.  I and D rows form
+// rings of e + 1 steps (a step reads them back e steps).  M rows form a ring
+// of max(x, o + e) + 1 steps in score mode; in CIGAR mode every M row of the
+// pair is kept (steps 0..cap after max(x, o + e) NULL rows), and each cell of
+// each step gets a 4-bit decision record (two cells per byte): the source of
+// M before extension (mismatch, end of insertion, end of deletion) and
+// whether I and D opened from M.  Every row starts NULL.  Offsets are int8
+// when both sequences are shorter than 128 bases (twice the lane groups per
+// CU), int16 otherwise.
 //
 // A pair leaves the kernel through the overflow list (and is finished by the
 // general kernel) when its wavefront touches a window edge before reaching
@@ -404,24 +408,24 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
 
     unsigned char* gbase = lds + (wave * GPW + grp) * a.group_bytes;
     RowT* RM = (RowT*)gbase;
-    RowT* RI = RM + a.ring * RW;
-    RowT* RD = RI + a.ring * RW;
+    RowT* RI = (RowT*)(gbase + a.id_off);
+    RowT* RD = RI + a.ring2 * RW;
     const int rows_bytes = a.rows_bytes;
-    // CIGAR mode: one 16-bit backtrace record per cell and step (0..cap):
-    // bits 0-11 the M offset before extension, 12-13 its source (0 mismatch,
-    // 1 end of insertion, 2 end of deletion), 14 insertion opened from M,
-    // 15 deletion opened from M
-    uint16_t* REC = (uint16_t*)(gbase + rows_bytes);
-    const int rec_bytes = CIGAR ? (((a.cap + 1) * W * 2) + 15) & ~15 : 0;
-    // CIGAR mode: the backtrace stages its runs over the ring (free by then)
-    uint32_t* STAGE = (uint32_t*)gbase;
+    // CIGAR mode: 4-bit decision records of steps 0..cap, two cells per byte
+    // (cell j in the low nibble when j is even): bits 0-1 the source of M
+    // (0 mismatch, 1 end of insertion, 2 end of deletion), bit 2 insertion
+    // opened from M, bit 3 deletion opened from M
+    uint8_t* FL = (uint8_t*)(gbase + rows_bytes);
+    const int rec_bytes = CIGAR ? (((a.cap + 1) * (W / 2)) + 15) & ~15 : 0;
+    // CIGAR mode: the backtrace stages its runs over the I/D rings (free by then)
+    uint32_t* STAGE = (uint32_t*)(gbase + a.id_off);
     uint64_t* SP64 = (uint64_t*)(gbase + rows_bytes + rec_bytes);
     uint64_t* ST64 = SP64 + a.seq_words;
     const uint32_t* SP = (const uint32_t*)SP64;
     const uint32_t* ST = (const uint32_t*)ST64;
 
-    const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e;
-    const int ring = a.ring;
+    const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
+    const int ring = a.ring, ring2 = a.ring2;
 
     const bool bnd = gl == 0 || gl == G - 1;  // lanes on a layer's outermost diagonals
     int jl[DPL];  // window index of each of this lane's diagonals
@@ -486,8 +490,8 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
             SP64[w] = (st == 0 && w < nwp) ? a.pw[ps + w] : 0ULL;
             ST64[w] = (st == 0 && w < nwt) ? a.tw[ts + w] : 0ULL;
         }
-        // every ring row starts NULL (pads included); the three arrays are
-        // contiguous and padded to 16 bytes
+        // every offset row starts NULL (pads included); the M rows and the
+        // I/D rings are contiguous and padded to 16 bytes
         {
             constexpr uint32_t NW = sizeof(RowT) == 1 ? 0x80808080u : 0xC000C000u;
             static_assert(sizeof(RowT) == 1 ? (int8_t)0x80 == NUL : (int16_t)0xC000 == NUL,
@@ -516,7 +520,8 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                                  j0 > W / 2 + G / 2 - 1 + (lay - 1) * (G / 2)))
                 lay++;
         }
-        int cur = ring - 1;        // ring row of step 0 (the rows before it are NULL)
+        int cur = PRE;             // M row of step 0 (the rows before it are NULL)
+        int cur2 = ring2 - 1;      // I/D row of step 0
         for (int s = 0;; s++) {
             if (__ballot(st == 0) == 0) break;
             // layers the wave computes this step: the most any of its groups needs
@@ -524,11 +529,14 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
 #pragma unroll
             for (int d = 1; d < DPL; d++) nlay += __ballot(st == 0 && lay > d) != 0 ? 1 : 0;
             const bool growable = DPL > 1 && __ballot(st == 0 && lay < DPL) != 0;
-            if (s > 0) cur = cur + 1 == ring ? 0 : cur + 1;
-            int ix = cur - X, io = cur - OE, ie = cur - E;
+            if (s > 0) {
+                cur = cur + 1 == ring ? 0 : cur + 1;  // never wraps in CIGAR mode
+                cur2 = cur2 + 1 == ring2 ? 0 : cur2 + 1;
+            }
+            int ix = cur - X, io = cur - OE, ie = cur2 - E;
             ix += ix < 0 ? ring : 0;
             io += io < 0 ? ring : 0;
-            ie += ie < 0 ? ring : 0;
+            ie += ie < 0 ? ring2 : 0;
             const RowT* mx = RM + ix * RW + 1;
             const RowT* mo = RM + io * RW + 1;
             const RowT* il = RI + ie * RW + 1;
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                         // decisions the backtrace replays (tie-break: mismatch,
                         // then insertion, then deletion; gap open before extend)
                         const int msrc = tx == tm ? 0 : (ti == tm ? 1 : 2);
-                        rec[d] = (Mv[d] & 0xFFF) | (msrc << 12) | ((ta == ti) << 14) | ((tc == td) << 15);
+                        rec[d] = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
                     }
                 }
                 // bases before either sequence ends: min(n - v, m - h) = L - h
@@ -618,9 +626,16 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 if (d >= nlay) continue;
                 const int j = jl[d];
                 RM[cur * RW + 1 + j] = (RowT)Mv[d];
-                RI[cur * RW + 1 + j] = (RowT)Iv[d];
-                RD[cur * RW + 1 + j] = (RowT)Dv[d];
-                if (CIGAR) REC[s * W + j] = (uint16_t)rec[d];  // s <= cap here
+                RI[cur2 * RW + 1 + j] = (RowT)Iv[d];
+                RD[cur2 * RW + 1 + j] = (RowT)Dv[d];
+                if (CIGAR) {
+                    // neighbouring lanes hold neighbouring diagonals (even j on
+                    // even lanes): both write the byte of the pair of cells
+                    const int other = __builtin_amdgcn_update_dpp(0, rec[d], 0xB1, 0xF, 0xF, false);
+                    const int lo = (gl & 1) ? other : rec[d];
+                    const int hi = (gl & 1) ? rec[d] : other;
+                    FL[(s * W + j) >> 1] = (uint8_t)(lo | (hi << 4));  // s <= cap here
+                }
                 const bool live = Mv[d] >= 0;  // M is at least I and D
                 term |= (j == jt) & (Mv[d] == m);
                 if (d == DPL - 1) edge |= bnd & live;
@@ -645,49 +660,74 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
             if (!overflow && CIGAR) {
                 const int cap_runs = a.slot_cap;
                 int nr = 0, cop = -1, clen = 0;
-                int s = S, k = kt, h = m, comp = 0;  // comp: 0 M, 1 I, 2 D
-                // Replays the decisions recorded in the forward pass.  Each
-                // iteration reads one record and emits the run of matches of
-                // an M cell (if the walk is in M) followed by exactly one edit:
-                // a mismatch, or an insertion / deletion taken from the same
-                // cell's record whether the walk enters the gap here or is
-                // already inside it.  A match run is complete at once (runs of
-                // matches are separated by edits) and closes the open edit
-                // run; an edit extends the open run when it has the same op.
-                // Both candidate runs are stored every iteration, at the next
-                // free stage word, and only kept (the count advanced) when
-                // they are real; stores of a walk past the stage's end land on
-                // its two spare words, and the pair is then re-run elsewhere.
-                // Every iteration lowers s, so the walk ends.
+                int s = S, k = kt, h = m;  // an M cell and its offset after extension
+                // Replays the decisions recorded in the forward pass, one event
+                // per iteration: at M cell (s, k) it finds where M came from
+                // (a mismatch from M at s - x, or the end of a gap whose chain
+                // of I or D cells it follows back to where the gap opened from
+                // an M cell), emits the cell's match run (its offset minus the
+                // offset before extension, which the source gives) and the
+                // event's edit run, and moves to the source M cell.  An edit
+                // run extends the open run when nothing matched in between and
+                // the op is the same.  Both candidate runs are stored every
+                // iteration at the next free stage word and only kept (the
+                // count advanced) when real; stores of a walk past the stage's
+                // end land on its two spare words, and the pair is then re-run
+                // elsewhere.  Every iteration lowers s, so the walk ends.
                 for (;;) {
                     const int j = k - kmin;
                     if (s < 0 || (unsigned)j >= (unsigned)W) {
                         overflow = true;  // inconsistent walk: leave it to the general kernel
                         break;
                     }
-                    const int r = REC[s * W + j];
-                    const bool isM = comp == 0;
-                    const bool last = isM && s == 0;
-                    const int h0 = s == 0 ? 0 : (r & 0xFFF);
-                    const int mlen = isM ? h - h0 : 0;
-                    // edit of this iteration: 0 mismatch, 1 insertion, 2 deletion
-                    const int ed = isM ? ((r >> 12) & 3) : comp;
-                    const int op = last ? OP_M : ed + 1;  // op codes: X=1 I=2 D=3
+                    int h0 = 0, hn = 0, L = 1, op = OP_M, s2 = 0, dk = 0;
+                    if (s > 0) {
+                        const int f = (FL[(s * W + j) >> 1] >> ((j & 1) << 2)) & 15;
+                        const int ms = f & 3;
+                        if (ms == 0) {
+                            hn = RM[(s - X + PRE) * RW + 1 + j];
+                            h0 = hn + 1;
+                            s2 = s - X;
+                        } else {
+                            const int bit = ms == 1 ? 4 : 8;
+                            const int dj = ms == 1 ? -1 : 1;
+                            int sc = s, jc = j, fc = f;
+                            while (!(fc & bit)) {  // still extending: one step back
+                                sc -= E;
+                                jc += dj;
+                                if (sc <= 0 || (unsigned)jc >= (unsigned)W) break;
+                                L++;
+                                fc = (FL[(sc * W + jc) >> 1] >> ((jc & 1) << 2)) & 15;
+                            }
+                            if (!(fc & bit)) {
+                                overflow = true;  // a gap with no opening: inconsistent
+                                break;
+                            }
+                            hn = RM[(sc - OE + PRE) * RW + 1 + jc + dj];
+                            h0 = ms == 1 ? hn + L : hn;  // insertions consume text
+                            s2 = sc - OE;
+                            dk = dj * L;
+                        }
+                        op = ms + 1;  // op codes: X=1 I=2 D=3
+                    }
+                    const int mlen = h - h0;
+                    if (mlen < 0 || hn < 0) {
+                        overflow = true;
+                        break;
+                    }
                     const bool hasM = mlen > 0;
-                    const bool flush = cop >= 0 && (hasM || cop != op);
+                    const bool last = s == 0;
+                    const bool flush = cop >= 0 && (hasM || last || cop != op);
                     STAGE[min(nr, cap_runs + 1)] = ((uint32_t)clen << 4) | (uint32_t)cop;
                     nr += flush ? 1 : 0;
                     STAGE[min(nr, cap_runs + 1)] = ((uint32_t)mlen << 4) | (uint32_t)OP_M;
                     nr += hasM ? 1 : 0;
                     if (last) break;
-                    clen = (flush || hasM) ? 1 : clen + 1;
+                    clen = (flush || hasM) ? L : clen + L;
                     cop = op;
-                    const int hb = isM ? h0 : h;  // offset where the edit ends
-                    const bool open = (r >> (13 + ed)) & 1;  // bit 14: I opened, 15: D opened
-                    s -= ed == 0 ? X : (open ? OE : E);
-                    comp = (ed == 0 || open) ? 0 : ed;
-                    k += (ed == 2 ? 1 : 0) - (ed == 1 ? 1 : 0);
-                    h = ed == 2 ? hb : hb - 1;  // mismatches and insertions consume a text base
+                    s = s2;
+                    k += dk;
+                    h = hn;
                 }
                 if (overflow || nr > cap_runs) overflow = true;
                 else cnt = nr;
