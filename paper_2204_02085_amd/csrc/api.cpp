@@ -232,9 +232,9 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, i
     sp->seq_words = (int)((max_len + 31) / 32) + 1;
     // offsets: I and D rows in rings of e + 1 (a step reads them back e
     // steps); M rows in a ring of pre + 1 in score mode, all of them (after
-    // pre NULL rows) in CIGAR mode, which adds a 4-bit decision record per
+    // one NULL row) in CIGAR mode, which adds a 4-bit decision record per
     // cell and step for the backtrace
-    sp->ring = cigar ? pen.pre + cap + 1 : pen.pre + 1;
+    sp->ring = cigar ? cap + 2 : pen.pre + 1;
     sp->ring2 = pen.e + 1;
     // int8 offsets hold lengths up to 127; a NULL (-128) drifts up by at most
     // one per step, so it stays negative for caps below 100

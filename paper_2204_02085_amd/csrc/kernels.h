@@ -50,7 +50,7 @@ struct ShortArgs {
     int queue_chunk;            // rounds of 64/G pairs a wave claims per atomic
     Pen pen;
     int cap;                    // last step s' held
-    int ring;                   // M rows: a ring of pre + 1 (score), or pre + cap + 1 (CIGAR)
+    int ring;                   // M rows: a ring of pre + 1 (score), or cap + 2 (CIGAR)
     int ring2;                  // I and D rows: rings of e + 1
     int id_off;                 // LDS byte offset of the I rows (the D rows follow)
     int seq_words;              // 64-bit words of LDS per sequence

@@ -348,7 +348,8 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
 // neighbouring diagonals are read without bounds checks.  I and D rows form
 // rings of e + 1 steps (a step reads them back e steps).  M rows form a ring
 // of max(x, o + e) + 1 steps in score mode; in CIGAR mode every M row of the
-// pair is kept (steps 0..cap after max(x, o + e) NULL rows), and each cell of
+// pair is kept (steps 0..cap after one NULL row, which stands for every step
+// before 0), and each cell of
 // each step gets a 4-bit decision record (two cells per byte): the source of
 // M before extension (mismatch, end of insertion, end of deletion) and
 // whether I and D opened from M.  Every row starts NULL.  Offsets are int8
@@ -391,7 +392,8 @@ struct RowNull<int16_t> {
 };
 
 template <int G, int DPL, bool CIGAR, class RowT>
-__global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_short(
+    ShortArgs a, int persistent) {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int W = G * DPL;
     constexpr int RW = W + 2;
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                                  j0 > W / 2 + G / 2 - 1 + (lay - 1) * (G / 2)))
                 lay++;
         }
-        int cur = PRE;             // M row of step 0 (the rows before it are NULL)
+        int cur = CIGAR ? 1 : PRE;  // M row of step 0 (the rows before it are NULL)
         int cur2 = ring2 - 1;      // I/D row of step 0
         for (int s = 0;; s++) {
             if (__ballot(st == 0) == 0) break;
@@ -534,35 +536,32 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                 cur2 = cur2 + 1 == ring2 ? 0 : cur2 + 1;
             }
             int ix = cur - X, io = cur - OE, ie = cur2 - E;
-            ix += ix < 0 ? ring : 0;
-            io += io < 0 ? ring : 0;
+            if (CIGAR) {  // steps before 0 read the NULL row
+                ix = max(ix, 0);
+                io = max(io, 0);
+            } else {
+                ix += ix < 0 ? ring : 0;
+                io += io < 0 ? ring : 0;
+            }
             ie += ie < 0 ? ring2 : 0;
             const RowT* mx = RM + ix * RW + 1;
             const RowT* mo = RM + io * RW + 1;
             const RowT* il = RI + ie * RW + 1;
             const RowT* dr = RD + ie * RW + 1;
             const bool run = st == 0;
-            int Mv[DPL], Iv[DPL], Dv[DPL], rec[DPL];
-            // extension state: text and pattern positions (0 for cells that do
-            // not extend, so their compares stay in bounds) and bases left
-            // before either sequence ends (0: not extending)
-            int hp[DPL], vp[DPL], rem[DPL];
-            uint64_t gm[DPL];
+            // Layers one after another (cells of a step read only earlier
+            // steps' rows, so the order does not matter): compute the cells,
+            // extend them, store the row and the decision records, and note
+            // termination, window-edge and layer-growth conditions.
+            bool term = false, edge = false, grow = false;
 #pragma unroll
             for (int d = 0; d < DPL; d++) {
-                Mv[d] = NUL;
-                Iv[d] = NUL;
-                Dv[d] = NUL;
-                rec[d] = 0;
-                hp[d] = 0;
-                vp[d] = 0;
-                rem[d] = 0;
-                gm[d] = 0;
-                if (d >= nlay) continue;
+                if (d >= nlay) break;
                 const int j = jl[d];
                 const int L = lim[d];
+                int Mv, Iv = NUL, Dv = NUL, rec = 0;
                 if (s == 0) {
-                    Mv[d] = (kmin + j == 0) ? 0 : NUL;
+                    Mv = (kmin + j == 0) ? 0 : NUL;
                 } else {
                     // Candidates as distances t = L - c below the diagonal's limit
                     // L: an admissible offset has 0 <= t <= L, a NULL source
@@ -580,64 +579,50 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                     const uint32_t ti = min(min(ta, tb), tn);
                     const uint32_t td = min(min(tc, te), tn);
                     const uint32_t tm = min(min(tx, ti), td);
-                    Mv[d] = L - (int)tm;
-                    Iv[d] = L - (int)ti;
-                    Dv[d] = L - (int)td;
+                    Mv = L - (int)tm;
+                    Iv = L - (int)ti;
+                    Dv = L - (int)td;
                     if (CIGAR) {
                         // decisions the backtrace replays (tie-break: mismatch,
                         // then insertion, then deletion; gap open before extend)
                         const int msrc = tx == tm ? 0 : (ti == tm ? 1 : 2);
-                        rec[d] = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
+                        rec = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
                     }
                 }
-                // bases before either sequence ends: min(n - v, m - h) = L - h
-                const int h = Mv[d];
-                const bool go = run && (unsigned)h < (unsigned)limz[d];
-                hp[d] = go ? h : 0;
-                vp[d] = go ? h - kd[d] : 0;
-                rem[d] = go ? limz[d] - h : 0;
-                gm[d] = __ballot(go);
-            }
-            // extend along matches, 32 bases per compare.  The loop is
-            // wave-uniform: while any lane of a layer extends, every lane of
-            // the layer runs the compare, and lanes with nothing left add 0.
-            for (;;) {
-                bool more = false;
-#pragma unroll
-                for (int d = 0; d < DPL; d++) {
-                    if (gm[d]) {
-                        const int r = min(common_prefix(window32(SP, vp[d]), window32(ST, hp[d])), rem[d]);
-                        hp[d] += r;
-                        vp[d] += r;
-                        rem[d] = r == 32 ? rem[d] - 32 : 0;
-                        gm[d] = __ballot(rem[d] > 0);
-                        more |= gm[d] != 0;
+                // Extend along matches, 32 bases per compare.  The loop is
+                // wave-uniform: while any lane extends, every lane runs the
+                // compare, lanes that do not extend at offset 0 (in bounds)
+                // with nothing left (rem: bases before either sequence ends,
+                // min(n - v, m - h) = L - h).
+                {
+                    const bool go = run && (unsigned)Mv < (unsigned)limz[d];
+                    int hp = go ? Mv : 0;
+                    int vp = go ? Mv - kd[d] : 0;
+                    int rem = go ? limz[d] - Mv : 0;
+                    uint64_t gm = __ballot(go);
+                    while (gm) {
+                        const int r = min(common_prefix(window32(SP, vp), window32(ST, hp)), rem);
+                        hp += r;
+                        vp += r;
+                        rem = r == 32 ? rem - 32 : 0;
+                        gm = __ballot(rem > 0);
                     }
+                    Mv = go ? hp : Mv;
                 }
-                if (!more) break;
-            }
-#pragma unroll
-            for (int d = 0; d < DPL; d++)
-                if (d < nlay) Mv[d] = Mv[d] >= 0 && hp[d] > 0 ? hp[d] : Mv[d];
-            // store the step's rows (groups that stopped write rows nobody reads)
-            bool term = false, edge = false, grow = false;
-#pragma unroll
-            for (int d = 0; d < DPL; d++) {
-                if (d >= nlay) continue;
-                const int j = jl[d];
-                RM[cur * RW + 1 + j] = (RowT)Mv[d];
-                RI[cur2 * RW + 1 + j] = (RowT)Iv[d];
-                RD[cur2 * RW + 1 + j] = (RowT)Dv[d];
+                // store the step's row (groups that stopped write rows nobody reads)
+                RM[cur * RW + 1 + j] = (RowT)Mv;
+                RI[cur2 * RW + 1 + j] = (RowT)Iv;
+                RD[cur2 * RW + 1 + j] = (RowT)Dv;
                 if (CIGAR) {
                     // neighbouring lanes hold neighbouring diagonals (even j on
                     // even lanes): both write the byte of the pair of cells
-                    const int other = __builtin_amdgcn_update_dpp(0, rec[d], 0xB1, 0xF, 0xF, false);
-                    const int lo = (gl & 1) ? other : rec[d];
-                    const int hi = (gl & 1) ? rec[d] : other;
+                    const int other = __builtin_amdgcn_update_dpp(0, rec, 0xB1, 0xF, 0xF, false);
+                    const int lo = (gl & 1) ? other : rec;
+                    const int hi = (gl & 1) ? rec : other;
                     FL[(s * W + j) >> 1] = (uint8_t)(lo | (hi << 4));  // s <= cap here
                 }
-                const bool live = Mv[d] >= 0;  // M is at least I and D
-                term |= (j == jt) & (Mv[d] == m);
+                const bool live = Mv >= 0;  // M is at least I and D
+                term |= (j == jt) & (Mv == m);
                 if (d == DPL - 1) edge |= bnd & live;
                 if (d < DPL - 1) grow |= (d == lay - 1) & bnd & live;
             }
@@ -685,7 +670,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                         const int f = (FL[(s * W + j) >> 1] >> ((j & 1) << 2)) & 15;
                         const int ms = f & 3;
                         if (ms == 0) {
-                            hn = RM[(s - X + PRE) * RW + 1 + j];
+                            hn = RM[max(s - X + 1, 0) * RW + 1 + j];
                             h0 = hn + 1;
                             s2 = s - X;
                         } else {
@@ -703,7 +688,7 @@ __global__ __launch_bounds__(256) void k_short(ShortArgs a, int persistent) {
                                 overflow = true;  // a gap with no opening: inconsistent
                                 break;
                             }
-                            hn = RM[(sc - OE + PRE) * RW + 1 + jc + dj];
+                            hn = RM[max(sc - OE + 1, 0) * RW + 1 + jc + dj];
                             h0 = ms == 1 ? hn + L : hn;  // insertions consume text
                             s2 = sc - OE;
                             dk = dj * L;
