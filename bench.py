@@ -66,8 +66,9 @@ def parse():
                     help="JSON launch options instead of autotuning (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (PMC scale calibration)")
-    ap.add_argument("--cpu-pairs", type=int, default=400_000,
-                    help="oracle sample size for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-pairs", type=int, default=2_000_000,
+                    help="oracle sample size for the CPU baseline, about 15 s of CPU time "
+                         "on 16 threads (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=120,
                     help="requests of the serving run (0: skip)")
@@ -336,7 +337,8 @@ def main():
         cpu = {"value": len(sample) / (t1 - t0), "unit": "pairs/s", "cores": threads,
                "kind": "oracle",
                "sample": f"first {len(sample)} pairs of the same workload, score + CIGAR, "
-                         f"{threads} threads, {t1 - t0:.2f} s wall"}
+                         f"{threads} threads, {t1 - t0:.2f} s wall "
+                         f"({(t1 - t0) * threads:.1f} thread-seconds)"}
         cells_pp = ref.stats["cells"] / len(sample)
         windows_pp = ref.stats["ext_windows"] / len(sample)
         # parity spot check of the benchmarked batch against the sample
