@@ -89,24 +89,28 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_hash: str):
-    """HBM bytes per launch of the short-pair kernel from the committed PMC
-    summary, if it was taken on the current kernel source."""
+def read_profile(kernel_hash: str) -> dict:
+    """Figures of the committed PMC summary of the short-pair kernel (HBM
+    bytes per launch, VALU issue rate), if it was taken on the current kernel
+    source; empty otherwise."""
     path = os.path.join(ROOT, "profiles", "k_short_pairs100_e4_5m_pmc.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as f:
         for line in f:
-            if "=" in line and not line.startswith("#"):
-                k, v = line.split("=", 1)
+            if " = " in line and not line.startswith("#"):
+                k, v = line.split(" = ", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_hash:
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for k in ("hbm_bytes_per_launch", "valu_issue_per_cu_cycle"):
+        try:
+            out[k] = float(vals[k])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def time_schedule(al, dev, n, steps, warmup, options, enc):
@@ -362,10 +366,11 @@ def main():
     if cells_pp is not None and kernel_ms > 0:
         ops = n * (cells_pp * OPS_PER_CELL + windows_pp * OPS_PER_WINDOW)
         achieved = ops / (kernel_ms * 1e-3)
-        traffic = read_traffic(kernel_source_hash())
+        prof = read_profile(kernel_source_hash())
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / PEAK_INT_OPS,
-                    "traffic": traffic,
+                    "traffic": prof.get("hbm_bytes_per_launch"),
+                    "valu_issue_frac": prof.get("valu_issue_per_cu_cycle"),
                     "kernel": f"k_short<window {tuned['window'] or 'auto'}, cigar>",
                     "kernel_ms": kernel_ms, "ops_per_launch": ops,
                     "cells_per_pair": cells_pp, "windows_per_pair": windows_pp}

@@ -219,9 +219,13 @@ int make_pen(const wfa_penalties& p, Pen* out) {
 // each); a mismatch step beyond that adds nothing that stays in the window.
 int default_cap(const Pen& pen, int window) { return pen.oe + (window / 2) * pen.e + pen.x; }
 
-// Two diagonals per lane by default: the outer layer is computed only once
-// the wavefront reaches it, so narrow score steps cost half a window.
-int default_lanes(int window) { return window >= 128 ? 64 : (window >= 32 ? window / 2 : window); }
+// Several diagonals per lane by default: outer layers are computed only once
+// the wavefront reaches them, so narrow score steps cost one layer; windows
+// up to 32 use 8-lane groups (8 pairs per wavefront).
+int default_lanes(int window) {
+    if (window <= 32) return 8;
+    return window >= 128 ? 64 : window / 2;
+}
 
 int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, int cap,
                uint32_t max_len, ShortPlan* sp) {
