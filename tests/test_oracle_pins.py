@@ -240,7 +240,13 @@ def test_planted_mistake_is_caught(tmp_path, name):
 
     ctx = mp.get_context("fork")
     q = ctx.Queue()
-    proc = ctx.Process(target=lambda: q.put(_mutant_caught(so)))
+    def child():
+        import faulthandler
+
+        faulthandler.disable()  # a mutant that crashes is caught; no traceback dump
+        q.put(_mutant_caught(so))
+
+    proc = ctx.Process(target=child)
     proc.start()
     proc.join(5)
     if proc.is_alive():
