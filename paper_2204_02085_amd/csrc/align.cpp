@@ -137,7 +137,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     const bool seq_lds = (uint64_t)lds_words * 8 <= 48 * 1024;
     const int lds_bytes = seq_lds ? (int)(lds_words * 8) : 0;
     const uint32_t max_len = std::max(st.max_p, st.max_t);
-    const int bt = max_len > 3000 ? 1024 : (max_len > 600 ? 256 : 64);
+    const int bt = max_len > 3000 ? 512 : (max_len > 600 ? 256 : 64);
 
     RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
     DevFlags* flags = ws.flags.as<DevFlags>();

@@ -862,6 +862,11 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             if (tid == 0) sh_fail = 2;
             break;
         }
+        // the source rows of this step (metadata ring entry of step t: t % R)
+        RowMeta sx{0, -1, -1}, so{0, -1, -1}, se{0, -1, -1};
+        if (s >= X) sx = meta[(int)((s - X) % R)];
+        if (s >= OE) so = meta[(int)((s - OE) % R)];
+        if (s >= E) se = meta[(int)((s - E) % R)];
         int lo, hi;
         bool present;
         if (s == 0) {
@@ -870,13 +875,10 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         } else {
             lo = 1 << 30;
             hi = -(1 << 30);
-            const long long src[3] = {s - X, s - OE, s - E};
-            for (int i = 0; i < 3; i++) {
-                if (src[i] < 0) continue;
-                const RowMeta& mm = meta[src[i] % R];
-                if (mm.off < 0) continue;
-                lo = min(lo, mm.lo);
-                hi = max(hi, mm.hi);
+            for (const RowMeta* mm : {&sx, &so, &se}) {
+                if (mm->off < 0) continue;
+                lo = min(lo, mm->lo);
+                hi = max(hi, mm->hi);
             }
             present = lo <= hi;
             lo = max(lo - 1, -n);
@@ -902,31 +904,39 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             int* rowM = (int*)(slice + off);
             int* rowI = rowM + w;
             int* rowD = rowI + w;
+            // source components (M of s - x and s - o - e, I and D of s - e);
+            // a diagonal outside a source row's range reads NULL
+            const int* MX = sx.off >= 0 ? (const int*)(slice + sx.off) : nullptr;
+            const int* MO = so.off >= 0 ? (const int*)(slice + so.off) : nullptr;
+            const int* IE = se.off >= 0 ? (const int*)(slice + se.off) + (se.hi - se.lo + 1) : nullptr;
+            const int* DE = IE ? IE + (se.hi - se.lo + 1) : nullptr;
+            auto rd = [](const int* base, const RowMeta& mm, int kk) -> int {
+                return (base && kk >= mm.lo && kk <= mm.hi) ? base[kk - mm.lo] : NUL32;
+            };
             for (int k = lo + tid; k <= hi; k += BT) {
                 int mval;
                 int ival = NUL32, dval = NUL32;
                 if (s == 0) {
                     mval = 0;
                 } else {
+                    // candidates as unsigned distances t = L - c below the
+                    // diagonal's limit L = min(m, n + k): admissible offsets
+                    // 0 <= t <= L, NULL sources L < t <= L - NULL, offsets past
+                    // L negative (huge); the maximum admissible candidate is
+                    // the minimum t, floored at NULL
                     const int L = min(m, n + k);
-                    auto get = [&](long long ss, int comp, int kk) -> int {
-                        if (ss < 0) return NUL32;
-                        const RowMeta& mm = meta[ss % R];
-                        if (mm.off < 0 || kk < mm.lo || kk > mm.hi) return NUL32;
-                        const int ww = mm.hi - mm.lo + 1;
-                        const int* base = (const int*)(slice + mm.off) + comp * ww;
-                        return base[kk - mm.lo];
-                    };
-                    const int mo_l = get(s - OE, 0, k - 1), i_l = get(s - E, 1, k - 1);
-                    const int mo_r = get(s - OE, 0, k + 1), d_r = get(s - E, 2, k + 1);
-                    const int mx = get(s - X, 0, k);
-                    const int a1 = mo_l == NUL32 ? NUL32 : mo_l + 1;
-                    const int a2 = i_l == NUL32 ? NUL32 : i_l + 1;
-                    ival = max(a1 >= 0 && a1 <= L ? a1 : NUL32, a2 >= 0 && a2 <= L ? a2 : NUL32);
-                    dval = max(mo_r >= 0 && mo_r <= L ? mo_r : NUL32,
-                               d_r >= 0 && d_r <= L ? d_r : NUL32);
-                    const int xv = mx == NUL32 ? NUL32 : mx + 1;
-                    mval = max(max(xv >= 0 && xv <= L ? xv : NUL32, ival), dval);
+                    const uint32_t tn = (uint32_t)(L - NUL32);
+                    const uint32_t ta = (uint32_t)(L - 1 - rd(MO, so, k - 1));
+                    const uint32_t tb = (uint32_t)(L - 1 - rd(IE, se, k - 1));
+                    const uint32_t tc = (uint32_t)(L - rd(MO, so, k + 1));
+                    const uint32_t te = (uint32_t)(L - rd(DE, se, k + 1));
+                    const uint32_t tx = (uint32_t)(L - 1 - rd(MX, sx, k));
+                    const uint32_t ti = min(min(ta, tb), tn);
+                    const uint32_t td = min(min(tc, te), tn);
+                    const uint32_t tm = min(min(tx, ti), td);
+                    mval = L - (int)tm;
+                    ival = L - (int)ti;
+                    dval = L - (int)td;
                 }
                 if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
                 rowM[k - lo] = mval;
