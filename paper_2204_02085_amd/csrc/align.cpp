@@ -117,76 +117,114 @@ struct Dev {
 int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const BatchStats& st,
                 std::vector<uint32_t> pending, uint64_t& gen_used, hipStream_t s,
                 uint64_t* general_done, uint64_t* requeued) {
+    (void)st;
     Workspace& ws = e->ws;
-    const uint64_t nm1 = (uint64_t)st.max_p + st.max_t + 1;
     const uint64_t R = (uint64_t)pen.pre + 1;
-    uint64_t slice;
-    if (cigar) {
-        // first guess: a pair at 10 % divergence (score about 0.1 * L times the
-        // mean edit cost) holds ~s'^2 / e' offsets of 12 bytes plus a 16-byte
-        // step-table entry per step; pairs that need more are re-run with 4x
-        const double L = std::max(st.max_p, st.max_t);
-        const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
-        const double est = 12.0 * sg * sg / pen.e + 16.0 * sg + 8.0 * (double)nm1 + 4096.0;
-        slice = (uint64_t)std::min(std::max(est, 16.0 * 1024), 64.0 * 1024 * 1024);
-    } else {
-        slice = R * 3 * 4 * nm1;
-    }
-    slice = (slice + 255) & ~(uint64_t)255;
-    const uint32_t lds_words = (st.max_p + 31) / 32 + 1 + (st.max_t + 31) / 32 + 1;
-    const bool seq_lds = (uint64_t)lds_words * 8 <= 48 * 1024;
-    const int lds_bytes = seq_lds ? (int)(lds_words * 8) : 0;
-    const uint32_t max_len = std::max(st.max_p, st.max_t);
-    const int bt = max_len > 3000 ? 512 : (max_len > 600 ? 256 : 64);
-
     RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
     DevFlags* flags = ws.flags.as<DevFlags>();
+
+    // lengths of the pending pairs (the descriptors live on the device)
+    std::vector<uint32_t> plen(pending.size()), tlen(pending.size());
+    {
+        RCCHK(ws.ensure(ws.jobs, pending.size() * 4));
+        RCCHK(ws.ensure(ws.gen_tmp, pending.size() * 8));
+        HIPCHK(hipMemcpyAsync(ws.jobs.ptr, pending.data(), pending.size() * 4,
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(launch_pair_lengths(d.pairs, ws.jobs.as<uint32_t>(), pending.size(),
+                                   ws.gen_tmp.as<uint32_t>(), s));
+        std::vector<uint32_t> lens(2 * pending.size());
+        HIPCHK(hipMemcpyAsync(lens.data(), ws.gen_tmp.ptr, lens.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t i = 0; i < pending.size(); i++) {
+            plen[i] = lens[2 * i];
+            tlen[i] = lens[2 * i + 1];
+        }
+    }
+    // Longest pairs first: a launch then holds pairs of similar size, its
+    // slices are sized for its own longest pair (short pairs run many at a
+    // time), and the long pairs start early.
+    struct Job {
+        uint32_t pair, n, m;
+    };
+    std::vector<Job> jobs(pending.size());
+    for (size_t i = 0; i < pending.size(); i++) jobs[i] = {pending[i], plen[i], tlen[i]};
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
+        return (uint64_t)a.n + a.m > (uint64_t)b.n + b.m;
+    });
+    auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult) -> uint64_t {
+        const uint64_t nm1 = (uint64_t)n + m + 1;
+        uint64_t sl;
+        if (cigar) {
+            // first guess: a pair at 10 % divergence (score about 0.1 * L times
+            // the mean edit cost) holds ~s'^2 / e' offsets of 12 bytes plus a
+            // 16-byte step-table entry per step; pairs that need more are
+            // re-run with 4x
+            const double L = std::max(n, m);
+            const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
+            const double est = 12.0 * sg * sg / pen.e + 16.0 * sg + 8.0 * (double)nm1 + 4096.0;
+            sl = (uint64_t)std::min(std::max(est, 16.0 * 1024), 64.0 * 1024 * 1024) * mult;
+        } else {
+            sl = R * 3 * 4 * nm1;
+        }
+        return (sl + 255) & ~(uint64_t)255;
+    };
+
     // The arena keeps whatever size it reached (re-allocating tens of GB per
     // batch costs more than the alignment); it grows only when the current
     // slices do not fit, and never past 3/4 of the budget left by the other
     // buffers, so staging and run buffers of later batches still fit.
+    uint64_t mult = 1;
     int attempts = 0;
-    while (!pending.empty()) {
+    while (!jobs.empty()) {
         if (++attempts > 40) {
-            std::fprintf(stderr, "libwfa: %zu pairs still failing after 40 attempts\n",
-                         pending.size());
+            std::fprintf(stderr, "libwfa: %zu pairs still failing after 40 attempts\n", jobs.size());
             return WFA_E_NOMEM;
         }
-        const size_t others = ws.total - ws.arena.bytes;
-        const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
-        const size_t want = std::min(pending.size(), (size_t)1 << 20) * slice;
-        if (ws.arena.bytes < want && ws.arena.bytes < arena_cap) {
-            const size_t target = std::min(want, arena_cap);
-            if (target > ws.arena.bytes && target >= slice) {
-                ws.release(ws.arena);
-                // the device may hold less than the budget: halve until it fits
-                size_t t = target;
-                int rc = ws.ensure(ws.arena, t);
-                while (rc != WFA_OK && t / 2 >= slice) {
-                    t /= 2;
-                    rc = ws.ensure(ws.arena, t);
+        std::vector<Job> failed;
+        for (size_t off = 0; off < jobs.size();) {
+            const Job& head = jobs[off];  // the longest pair left
+            const uint64_t slice = slice_for(head.n, head.m, mult);
+            const size_t others = ws.total - ws.arena.bytes;
+            const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
+            const size_t want = std::min(jobs.size() - off, (size_t)1 << 20) * slice;
+            if (ws.arena.bytes < want && ws.arena.bytes < arena_cap) {
+                const size_t target = std::min(want, arena_cap);
+                if (target > ws.arena.bytes && target >= slice) {
+                    ws.release(ws.arena);
+                    // the device may hold less than the budget: halve until it fits
+                    size_t t = target;
+                    int rc = ws.ensure(ws.arena, t);
+                    while (rc != WFA_OK && t / 2 >= slice) {
+                        t /= 2;
+                        rc = ws.ensure(ws.arena, t);
+                    }
+                    RCCHK(rc);
                 }
-                RCCHK(rc);
             }
-        }
-        size_t conc = ws.arena.bytes / slice;
-        if (e->opt.general_pairs > 0) conc = std::min(conc, (size_t)e->opt.general_pairs);
-        conc = std::min(conc, pending.size());
-        conc = std::min(conc, (size_t)1 << 20);
-        if (conc == 0) {
-            std::fprintf(stderr, "libwfa: general kernel slice %zu B exceeds the arena (%zu B, "
-                                 "budget %zu B)\n", (size_t)slice, ws.arena.bytes, ws.budget);
-            return WFA_E_NOMEM;
-        }
-        RCCHK(ws.ensure(ws.jobs, conc * 4));
-        RCCHK(ws.ensure(ws.job_nruns, conc * 4));
-        RCCHK(ws.ensure(ws.job_offsets, (conc + 1) * 8));
-        RCCHK(ws.ensure(ws.fail_list, conc * 4));
-        RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(conc) + 64));
-        std::vector<uint32_t> failed;
-        for (size_t off = 0; off < pending.size(); off += conc) {
-            const size_t nj = std::min(conc, pending.size() - off);
-            HIPCHK(hipMemcpyAsync(ws.jobs.ptr, pending.data() + off, nj * 4, hipMemcpyHostToDevice, s));
+            size_t conc = ws.arena.bytes / slice;
+            if (e->opt.general_pairs > 0) conc = std::min(conc, (size_t)e->opt.general_pairs);
+            conc = std::min(conc, jobs.size() - off);
+            conc = std::min(conc, (size_t)1 << 20);
+            if (conc == 0) {
+                std::fprintf(stderr, "libwfa: general kernel slice %zu B exceeds the arena (%zu B, "
+                                     "budget %zu B)\n", (size_t)slice, ws.arena.bytes, ws.budget);
+                return WFA_E_NOMEM;
+            }
+            const size_t nj = conc;
+            const uint32_t max_len = std::max(head.n, head.m);
+            const uint32_t lds_words = (head.n + 31) / 32 + 1 + (head.m + 31) / 32 + 1;
+            const bool seq_lds = (uint64_t)lds_words * 8 <= 48 * 1024;
+            const int lds_bytes = seq_lds ? (int)(lds_words * 8) : 0;
+            const int bt = max_len > 3000 ? 512 : (max_len > 600 ? 256 : 64);
+
+            std::vector<uint32_t> ids(nj);
+            for (size_t i = 0; i < nj; i++) ids[i] = jobs[off + i].pair;
+            RCCHK(ws.ensure(ws.jobs, nj * 4));
+            RCCHK(ws.ensure(ws.job_nruns, nj * 4));
+            RCCHK(ws.ensure(ws.job_offsets, (nj + 1) * 8));
+            RCCHK(ws.ensure(ws.fail_list, nj * 4));
+            RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(nj) + 64));
+            HIPCHK(hipMemcpyAsync(ws.jobs.ptr, ids.data(), nj * 4, hipMemcpyHostToDevice, s));
             HIPCHK(launch_fill_u32(ws.job_nruns.as<uint32_t>(), 0u, nj, s));
             HIPCHK(launch_fill_u32(&flags->fail_count, 0u, 1, s));
             GeneralArgs g{};
@@ -212,7 +250,10 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             if (nfail) {
                 std::vector<uint32_t> f(nfail);
                 HIPCHK(hipMemcpy(f.data(), ws.fail_list.ptr, nfail * 4ull, hipMemcpyDeviceToHost));
-                failed.insert(failed.end(), f.begin(), f.end());
+                std::sort(f.begin(), f.end());
+                for (size_t i = 0; i < nj; i++)
+                    if (std::binary_search(f.begin(), f.end(), jobs[off + i].pair))
+                        failed.push_back(jobs[off + i]);
             }
             *general_done += nj - nfail;
             if (cigar) {
@@ -230,15 +271,11 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
                                              ws.gen_runs.as<uint32_t>(), s));
                 gen_used += chunk_runs;
             }
+            off += nj;
         }
-        if (!failed.empty()) {
-            *requeued += failed.size();
-            std::sort(failed.begin(), failed.end());
-            pending.swap(failed);
-            slice *= 4;
-        } else {
-            pending.clear();
-        }
+        *requeued += failed.size();
+        jobs.swap(failed);
+        mult *= 4;
     }
     return WFA_OK;
 }

@@ -139,6 +139,9 @@ hipError_t launch_bucket_keys(const PairDesc* pairs, size_t n, uint32_t* keys, u
 hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, uint64_t* cursor, uint32_t* order,
                                  hipStream_t s);
 // Gather runs of finished general jobs from the arena into gen_runs.
+// out[2i], out[2i+1] = lengths of pair idx[i] (pattern, text)
+hipError_t launch_pair_lengths(const PairDesc* pairs, const uint32_t* idx, size_t n, uint32_t* out,
+                               hipStream_t s);
 hipError_t launch_gather_general(const uint32_t* jobs, size_t njobs, const uint32_t* nruns,
                                  uint64_t* run_src, const uint8_t* arena, uint64_t slice_bytes,
                                  const uint64_t* job_offsets, uint64_t gen_base,

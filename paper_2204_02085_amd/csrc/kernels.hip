@@ -1099,6 +1099,16 @@ __global__ void k_gather_general(const uint32_t* __restrict__ jobs, size_t njobs
     if (threadIdx.x == 0) run_src[pair] = GEN_BIT | dst;
 }
 
+__global__ void k_pair_lengths(const PairDesc* __restrict__ pairs, const uint32_t* __restrict__ idx,
+                               size_t n, uint32_t* __restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const PairDesc d = pairs[idx[i]];
+        out[2 * i] = d.p_len;
+        out[2 * i + 1] = d.t_len;
+    }
+}
+
 // reversed runs -> caller buffer in alignment order (nothing is written if
 // the total exceeds the capacity).  One thread per pair: its counters load
 // together and its runs move COMPACT_UNROLL at a time, so a wave keeps many
@@ -1366,6 +1376,12 @@ hipError_t launch_gather_general(const uint32_t* jobs, size_t njobs, const uint3
     if (njobs)
         hipLaunchKernelGGL(k_gather_general, dim3(njobs), dim3(256), 0, s, jobs, njobs, nruns,
                            run_src, (const uint32_t*)arena, job_offsets, gen_base, gen_runs);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_lengths(const PairDesc* pairs, const uint32_t* idx, size_t n, uint32_t* out,
+                               hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_pair_lengths, dim3(grid_for(n, 256)), dim3(256), 0, s, pairs, idx, n, out);
     return hipGetLastError();
 }
 
