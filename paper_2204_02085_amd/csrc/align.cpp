@@ -154,17 +154,16 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult) -> uint64_t {
         const uint64_t nm1 = (uint64_t)n + m + 1;
         uint64_t sl;
+        sl = R * 3 * 4 * nm1;  // the ring of full-width rows
         if (cigar) {
-            // first guess: a pair at 10 % divergence (score about 0.1 * L times
-            // the mean edit cost) holds ~s'^2 / e' offsets of 12 bytes plus a
-            // 16-byte step-table entry per step; pairs that need more are
-            // re-run with 4x
+            // history, first guess: a pair at 10 % divergence (score about
+            // 0.1 * L times the mean edit cost) keeps ~s'^2 / e' cells of 4.5
+            // bytes (offset and record) plus a 16-byte step-table entry per
+            // step, and its runs; pairs that need more are re-run with 4x
             const double L = std::max(n, m);
             const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
-            const double est = 12.0 * sg * sg / pen.e + 16.0 * sg + 8.0 * (double)nm1 + 4096.0;
-            sl = (uint64_t)std::min(std::max(est, 16.0 * 1024), 64.0 * 1024 * 1024) * mult;
-        } else {
-            sl = R * 3 * 4 * nm1;
+            const double est = 4.5 * sg * sg / pen.e + 32.0 * sg + 4.0 * (double)nm1 + 4096.0;
+            sl += (uint64_t)std::min(std::max(est, 16.0 * 1024), 64.0 * 1024 * 1024) * mult;
         }
         return (sl + 255) & ~(uint64_t)255;
     };

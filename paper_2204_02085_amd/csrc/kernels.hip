@@ -754,9 +754,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // ---------------------------------------------------------------------------
 // General kernel: one workgroup per pair, any length, any score.
 //
-// Slice layout (bytes): wavefront rows grow up from 0; in CIGAR mode the
-// step table {lo, hi, offset} grows down from the end.  In score mode the
-// rows form a ring of pre+1 full-width rows (k in [-n, m]).
+// Slice layout (bytes): a ring of pre + 1 full-width rows of M, I and D
+// (int32, diagonals [-n, m]) that the score steps work in.  CIGAR mode adds,
+// after the ring, one history row per step that grows towards the end of
+// the slice: the step's M offsets (int32) and a 4-bit decision record per
+// diagonal (as in the short kernel); the step table {lo, hi, offset} grows
+// down from the end, and the backtrace writes reversed runs into the gap.
 // ---------------------------------------------------------------------------
 struct RowMeta {
     int lo, hi;
@@ -852,7 +855,14 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     // slice_bytes - 16 * (s + 1)
     RowMeta* table = (RowMeta*)(slice + slice_bytes) - 1;
     const long long full_row = 3LL * 4 * (n + m + 1);
-    long long bump = 0;
+    long long bump = R * full_row;  // CIGAR history starts after the ring
+    if (bump > slice_bytes) {
+        if (tid == 0) {
+            const uint32_t at = atomicAdd(a.fail_count, 1u);
+            a.fail_list[at] = pair;
+        }
+        return;
+    }
     // a hard bound on steps: deleting all of P and inserting all of T
     const long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
 
@@ -884,19 +894,14 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             lo = max(lo - 1, -n);
             hi = min(hi + 1, m);
         }
-        long long off = -1;
+        long long off = -1, hoff = -1;
         if (present) {
             const int w = hi - lo + 1;
+            off = (s % R) * full_row;
             if (a.cigar) {
-                off = bump;
-                bump += ((3LL * 4 * w) + 15) & ~15LL;
+                hoff = bump;
+                bump += (4LL * w + (w + 1) / 2 + 15) & ~15LL;
                 if (bump > slice_bytes - 16LL * (s + 2)) {
-                    if (tid == 0) sh_fail = 1;
-                    break;
-                }
-            } else {
-                off = (s % R) * full_row;
-                if (R * full_row > slice_bytes) {
                     if (tid == 0) sh_fail = 1;
                     break;
                 }
@@ -904,6 +909,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             int* rowM = (int*)(slice + off);
             int* rowI = rowM + w;
             int* rowD = rowI + w;
+            int* histM = a.cigar ? (int*)(slice + hoff) : nullptr;
+            uint8_t* histF = a.cigar ? (uint8_t*)(histM + w) : nullptr;
             // source components (M of s - x and s - o - e, I and D of s - e);
             // a diagonal outside a source row's range reads NULL
             const int* MX = sx.off >= 0 ? (const int*)(slice + sx.off) : nullptr;
@@ -915,7 +922,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             };
             for (int k = lo + tid; k <= hi; k += BT) {
                 int mval;
-                int ival = NUL32, dval = NUL32;
+                int ival = NUL32, dval = NUL32, rec = 0;
                 if (s == 0) {
                     mval = 0;
                 } else {
@@ -937,18 +944,32 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     mval = L - (int)tm;
                     ival = L - (int)ti;
                     dval = L - (int)td;
+                    // decisions the backtrace replays (tie-break: mismatch,
+                    // then insertion, then deletion; gap open before extend)
+                    const int msrc = tx == tm ? 0 : (ti == tm ? 1 : 2);
+                    rec = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
                 }
                 if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
                 rowM[k - lo] = mval;
                 rowI[k - lo] = ival;
                 rowD[k - lo] = dval;
+                if (a.cigar) {
+                    histM[k - lo] = mval;
+                    // lanes hold neighbouring diagonals (k - lo has the lane's
+                    // parity): both write the byte of the pair of cells; a
+                    // partner past hi reads 0
+                    const int other = __builtin_amdgcn_update_dpp(0, rec, 0xB1, 0xF, 0xF, false);
+                    const int lo4 = (tid & 1) ? other : rec;
+                    const int hi4 = (tid & 1) ? rec : other;
+                    histF[(k - lo) >> 1] = (uint8_t)(lo4 | (hi4 << 4));
+                }
                 if (k == kt && mval == m) sh_flag = 1;
             }
         }
         __syncthreads();
         if (tid == 0) {
             meta[s % R] = RowMeta{lo, hi, off};
-            if (a.cigar) table[-s] = RowMeta{lo, hi, off};
+            if (a.cigar) table[-s] = RowMeta{lo, hi, hoff};
         }
         __syncthreads();
         if (sh_flag) {
@@ -978,7 +999,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         }
         return;
     }
-    // backtrace by one thread over the step table and rows
+    // backtrace by one thread over the step table and the history rows, one
+    // event per iteration (as in the short kernel)
     if (tid != 0) return;
     uint32_t* out = (uint32_t*)(slice + bump);
     const long long table_bottom = slice_bytes - 16LL * (S + 1);
@@ -999,72 +1021,81 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             clen = len;
         }
     };
-    auto get = [&](long long ss, int comp, int kk) -> int {
+    // M offset after extension of (ss, kk), NULL outside the step's range
+    auto getM = [&](long long ss, int kk) -> int {
         if (ss < 0) return NUL32;
         const RowMeta mm = table[-ss];
         if (mm.off < 0 || kk < mm.lo || kk > mm.hi) return NUL32;
-        const int ww = mm.hi - mm.lo + 1;
-        return ((const int*)(slice + mm.off))[comp * ww + kk - mm.lo];
+        return ((const int*)(slice + mm.off))[kk - mm.lo];
+    };
+    // decision record of (ss, kk); -1 outside the step's range
+    auto getF = [&](long long ss, int kk) -> int {
+        if (ss <= 0) return -1;
+        const RowMeta mm = table[-ss];
+        if (mm.off < 0 || kk < mm.lo || kk > mm.hi) return -1;
+        const int w = mm.hi - mm.lo + 1;
+        const uint8_t* f = (const uint8_t*)((const int*)(slice + mm.off) + w);
+        return (f[(kk - mm.lo) >> 1] >> (((kk - mm.lo) & 1) << 2)) & 15;
     };
     long long s = S;
-    int k = kt, h = m, comp = 0;
-    long long guard = 2LL * S + 4;
+    int k = kt, h = m;
+    bool bad = false;
     for (;;) {
-        if (s < 0 || h < 0 || --guard < 0) {  // inconsistent walk: invalid score, no loop
-            a.scores[pair] = -2;
-            a.nruns[pair] = 0;
-            return;
+        if (s < 0 || h < 0) {
+            bad = true;
+            break;
         }
-        if (comp == 0) {
-            int h0, xv = NUL32, iv = NUL32, dv = NUL32;
-            if (s == 0) {
-                h0 = 0;
-            } else {
-                const int L = min(m, n + k);
-                const int mx = get(s - X, 0, k);
-                xv = mx == NUL32 ? NUL32 : mx + 1;
-                if (xv < 0 || xv > L) xv = NUL32;
-                iv = get(s, 1, k);
-                dv = get(s, 2, k);
-                h0 = max(xv, max(iv, dv));
-            }
-            emit(OP_M, h - h0);
-            h = h0;
-            if (s == 0) break;
-            if (xv >= 0 && xv == h0) {
-                emit(OP_X, 1);
-                s -= X;
-                h -= 1;
-            } else if (iv == h0) {
-                comp = 1;
-            } else {
-                comp = 2;
-            }
-        } else if (comp == 1) {
-            emit(OP_I, 1);
-            const int L = min(m, n + k);
-            const int mo = get(s - OE, 0, k - 1);
-            const int a1 = mo == NUL32 ? NUL32 : mo + 1;
-            if (a1 >= 0 && a1 <= L && a1 == h) {
-                s -= OE;
-                comp = 0;
-            } else {
-                s -= E;
-            }
-            k -= 1;
-            h -= 1;
+        if (s == 0) {
+            emit(OP_M, h);
+            break;
+        }
+        const int f = getF(s, k);
+        if (f < 0) {
+            bad = true;
+            break;
+        }
+        const int ms = f & 3;
+        int hn, h0, L = 1, dk = 0;
+        long long s2;
+        if (ms == 0) {
+            hn = getM(s - X, k);
+            h0 = hn + 1;
+            s2 = s - X;
         } else {
-            emit(OP_D, 1);
-            const int L = min(m, n + k);
-            const int c1 = get(s - OE, 0, k + 1);
-            if (c1 >= 0 && c1 <= L && c1 == h) {
-                s -= OE;
-                comp = 0;
-            } else {
-                s -= E;
+            // follow the gap back along its chain to where it opened from M
+            const int bit = ms == 1 ? 4 : 8;
+            const int dj = ms == 1 ? -1 : 1;
+            long long sc = s;
+            int kc = k, fc = f;
+            while (fc >= 0 && !(fc & bit)) {
+                sc -= E;
+                kc += dj;
+                L++;
+                fc = getF(sc, kc);
             }
-            k += 1;
+            if (fc < 0) {
+                bad = true;
+                break;
+            }
+            hn = getM(sc - OE, kc + dj);
+            h0 = ms == 1 ? hn + L : hn;  // insertions consume text
+            s2 = sc - OE;
+            dk = dj * L;
         }
+        if (hn < 0 || h0 > h) {
+            bad = true;
+            break;
+        }
+        emit(OP_M, h - h0);
+        emit(ms + 1, L);  // op codes: X=1 I=2 D=3
+        s = s2;
+        k += dk;
+        h = hn;
+    }
+    if (bad) {  // inconsistent walk: invalid score, no loop
+        a.scores[pair] = -2;
+        a.nruns[pair] = 0;
+        return;
     }
     if (cop >= 0) {
         if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
