@@ -314,8 +314,9 @@ int wfa_server_poll(wfa_server *srv, uint64_t ticket, int64_t timeout_us, wfa_re
 /* Free a finished request's results. */
 int wfa_server_release(wfa_server *srv, uint64_t ticket);
 /* Device bytes the admission controller reserves for a request: staged
- * sequences and results plus the wavefront memory of each pair, estimated
- * as O(s^2) from its length assuming up to 10 % divergence. */
+ * sequences and results plus the wavefront memory of each pair (a ring of
+ * full-width rows, and in CIGAR mode an O(s^2) history) with s the score
+ * its length would have at 6 % divergence. */
 size_t wfa_server_estimate_bytes(const wfa_server *srv, const wfa_request *req);
 int wfa_server_get_stats(const wfa_server *srv, wfa_server_stats *out);
 /* Finish all submitted work, stop the workers and free the server. */

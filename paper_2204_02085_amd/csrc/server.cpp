@@ -92,13 +92,14 @@ size_t pair_bytes(const wfa_server_cfg& cfg, uint32_t n, uint32_t m) {
     const double L = std::max(n, m);
     size_t io = (size_t)n + m + 2 * (((size_t)n + 31) / 32 + ((size_t)m + 31) / 32) * 8 + 64;
     const double s = 0.06 * L * (x + 2 * (o + e)) / 3 + o + e;
-    double wf;
+    // a ring of full-width M/I/D rows of the score steps (all modes), and in
+    // CIGAR mode the history: an offset and a 4-bit record per cell (about
+    // s'^2 / e' cells) and a 16-byte table entry per step, plus the runs
+    const double pre = std::max(x, o + e) / g;
+    double wf = 12.0 * (pre + 1) * ((double)n + m + 1);
     if (cfg.mode == WFA_CIGAR) {
-        wf = 12.0 * s * s / (g * e) + 16.0 * (s / g + 1);
+        wf += 4.5 * s * s / (g * e) + 16.0 * (s / g + 1);
         io += (size_t)(4.0 * 2 * (s / std::min(x, e) + 1));
-    } else {
-        const double pre = std::max(x, o + e) / e;
-        wf = 12.0 * (pre + 1) * ((double)n + m + 1);
     }
     return io + (size_t)wf;
 }
