@@ -421,11 +421,17 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
 
     // ---- buffers -----------------------------------------------------------
     const bool ascii = io.enc == WFA_ASCII;
+    // ASCII sides whose sequences all need about the same number of words are
+    // packed at a fixed stride (no word-start scan); others by scan
+    const uint64_t mw_p = std::max<uint64_t>((st.max_p + 31) / 32, 1);
+    const uint64_t mw_t = std::max<uint64_t>((st.max_t + 31) / 32, 1);
+    const bool stride_p = ascii && N * mw_p <= st.words_p + st.words_p / 4 + 64;
+    const bool stride_t = ascii && N * mw_t <= st.words_t + st.words_t / 4 + 64;
     if (ascii) {
         RCCHK(ws.ensure(ws.ws_p, (N + 1) * 8));
         RCCHK(ws.ensure(ws.ws_t, (N + 1) * 8));
-        RCCHK(ws.ensure(ws.words_p, st.words_p * 8 + 8));
-        RCCHK(ws.ensure(ws.words_t, st.words_t * 8 + 8));
+        RCCHK(ws.ensure(ws.words_p, (stride_p ? N * mw_p : st.words_p) * 8 + 8));
+        RCCHK(ws.ensure(ws.words_t, (stride_t ? N * mw_t : st.words_t) * 8 + 8));
         RCCHK(ws.ensure(ws.packed_pairs, N * sizeof(PairDesc)));
         d.pairs = ws.packed_pairs.as<PairDesc>();
         d.pw = ws.words_p.as<uint64_t>();
@@ -479,10 +485,13 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
         HIPCHK(launch_fill_u32((uint32_t*)flags, 0u, sizeof(DevFlags) / 4, q));
         HIPCHK(launch_fill_u64((uint64_t*)&flags->err_pair, ~0ull, 1, q));
         if (ascii) {
-            HIPCHK(launch_scan(SCAN_WORDS_P, in_pairs, N, ws.ws_p.as<uint64_t>(), ws.scan_tmp.ptr, q));
-            HIPCHK(launch_scan(SCAN_WORDS_T, in_pairs, N, ws.ws_t.as<uint64_t>(), ws.scan_tmp.ptr, q));
+            if (!stride_p)
+                HIPCHK(launch_scan(SCAN_WORDS_P, in_pairs, N, ws.ws_p.as<uint64_t>(), ws.scan_tmp.ptr, q));
+            if (!stride_t)
+                HIPCHK(launch_scan(SCAN_WORDS_T, in_pairs, N, ws.ws_t.as<uint64_t>(), ws.scan_tmp.ptr, q));
             HIPCHK(launch_pack_pairs(in_pairs, N, (const uint8_t*)in_p, (const uint8_t*)in_t,
-                                     ws.ws_p.as<uint64_t>(), ws.ws_t.as<uint64_t>(),
+                                     stride_p ? nullptr : ws.ws_p.as<uint64_t>(),
+                                     stride_t ? nullptr : ws.ws_t.as<uint64_t>(),
                                      (st.max_p + 31) / 32, (st.max_t + 31) / 32,
                                      ws.words_p.as<uint64_t>(), ws.words_t.as<uint64_t>(),
                                      ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
@@ -550,7 +559,8 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
         const int ints[12] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g,
                               window * 256 + lanes, sp.cap,
                               (int)st.max_p, (int)st.max_t, grid,
-                              (int)(bucket ? 1 : 0) | (int)(d.capacity > 0x7fffffff ? 2 : 0)};
+                              (int)(bucket ? 1 : 0) | (int)(d.capacity > 0x7fffffff ? 2 : 0) |
+                                  (stride_p ? 4 : 0) | (stride_t ? 8 : 0)};
         for (int i = 0; i < 12; i++) key.ints[i] = ints[i];
         for (auto& g : e->graphs)
             if (g.key == key) hit = &g;

@@ -102,6 +102,8 @@ hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, v
 // ceil(len/32)), writing descriptors with word starts into packed_pairs.
 // Sets *err_pair to the lowest pair index holding a non-ACGT byte
 // (initialise to UINT64_MAX).
+// ASCII pairs -> 2-bit words and word-start descriptors.  A side whose
+// word-start array is NULL is laid out at a fixed stride of its max words.
 hipError_t launch_pack_pairs(const PairDesc* pairs, size_t n, const uint8_t* pascii,
                              const uint8_t* tascii, const uint64_t* ws_p, const uint64_t* ws_t,
                              uint32_t max_words_p, uint32_t max_words_t, uint64_t* words_p,

@@ -224,50 +224,49 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_final(ScanKind kind, const void
 // ---------------------------------------------------------------------------
 // ASCII -> 2-bit packing.  One thread per output word (32 bases).
 // ---------------------------------------------------------------------------
-// codes of the 4 bytes of x (A/a=0, C/c=1, G/g=2, T/t=3) in 8 bits, and a
-// validity flag for the first `cnt` (0..4) bytes
-__device__ __forceinline__ uint32_t pack4(uint32_t x, int cnt, bool& ok) {
-    for (int b = 0; b < 4; b++) {
-        if (b < cnt) {
-            const uint32_t c = ((x >> (8 * b)) & 0xFFu) | 0x20u;
-            const uint32_t d = (c - 0x61u) & 0xFFu;  // 'a' -> 0, 'c' -> 2, 'g' -> 6, 't' -> 19
-            ok = ok && d < 20u && ((0x80045u >> d) & 1u);
-        }
-    }
-    uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
-    const uint32_t keep = cnt >= 4 ? 0xFFFFFFFFu : ((1u << (8 * cnt)) - 1u);
-    c &= keep;
-    c = (c | (c >> 6)) & 0x000F000Fu;
-    c = (c | (c >> 12)) & 0xFFu;
-    return c;
+// Codes of the 4 bytes of x (A/a=0, C/c=1, G/g=2, T/t=3) in 8 bits; `bad`
+// collects the bits of bytes (among the low `keep` mask) that are not one of
+// those letters.  The code of an ASCII letter is bits 1-2 of the byte folded
+// ((c >> 1) ^ (c >> 2)) & 3; a byte is valid when the lowercase letter of its
+// code (looked up bytewise with v_perm_b32) equals the byte in lowercase.
+__device__ __forceinline__ uint32_t pack4(uint32_t x, uint32_t keep, uint32_t& bad) {
+    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    // bytes 'a' 'c' 'g' 't' selected by c (selector values 0..3 pick bytes of src1)
+    const uint32_t letters = __builtin_amdgcn_perm(0u, 0x74676361u, c);
+    bad |= (letters ^ (x | 0x20202020u)) & keep;
+    uint32_t v = c & keep;
+    v = (v | (v >> 6)) & 0x000F000Fu;
+    return (v | (v >> 12)) & 0xFFu;
 }
 
+// 32 bases starting at byte b0 of `ascii` (cnt of them valid, 1..32) as one
+// 2-bit word.  Reads the aligned dwords covering the bases; near the end of
+// the sequence the dword index is clamped to the last one holding a base,
+// so no byte past the sequence is read.
 __device__ __forceinline__ uint64_t pack_word(const uint8_t* __restrict__ ascii, uint64_t b0,
-                                              int cnt, bool& ok, bool interior) {
-    // aligned dwords covering [b0, b0 + cnt); only dwords holding a byte of the
-    // range are read (an interior word's 36-byte span lies inside its sequence
-    // whenever the next word exists, so it is read without guards)
-    const uintptr_t first = (uintptr_t)ascii + b0;
-    const uintptr_t a0 = first & ~(uintptr_t)3;
-    const uintptr_t last = (first + cnt - 1) >> 2;
-    const uint32_t* src = (const uint32_t*)a0;
+                                              int cnt, bool& ok) {
+    const uint8_t* first = ascii + b0;
+    const uint32_t sh = (uint32_t)((uintptr_t)first & 3u);
+    const uint32_t* src = (const uint32_t*)(first - sh);
+    const int lastd = (int)((sh + cnt - 1) >> 2);  // last dword holding a base
     uint32_t raw[9];
-    if (interior) {
+    if (lastd == 8) {
 #pragma unroll
-        for (int d = 0; d < 9; d++) raw[d] = (d < 8 || (a0 >> 2) + 8 <= last) ? src[d] : 0u;
+        for (int d = 0; d < 9; d++) raw[d] = src[d];
     } else {
 #pragma unroll
-        for (int d = 0; d < 9; d++) raw[d] = ((a0 >> 2) + d <= last) ? src[d] : 0u;
+        for (int d = 0; d < 9; d++) raw[d] = src[min(d, lastd)];
     }
-    const uint32_t sh = (uint32_t)(first & 3);
     uint64_t word = 0;
+    uint32_t bad = 0;
 #pragma unroll
     for (int d = 0; d < 8; d++) {
         const uint32_t x = __builtin_amdgcn_alignbyte(raw[d + 1], raw[d], sh);
-        int c = cnt - 4 * d;
-        c = c < 0 ? 0 : (c > 4 ? 4 : c);
-        word |= (uint64_t)pack4(x, c, ok) << (8 * d);
+        const int c = min(max(cnt - 4 * d, 0), 4);
+        const uint32_t keep = c >= 4 ? 0xFFFFFFFFu : ((1u << (8 * c)) - 1u);
+        word |= (uint64_t)pack4(x, keep, bad) << (8 * d);
     }
+    ok = bad == 0;
     return word;
 }
 
@@ -291,12 +290,14 @@ __global__ void k_pack_pairs(const PairDesc* __restrict__ pairs, size_t n,
         const PairDesc d = pairs[i];
         const uint32_t len = which ? d.t_len : d.p_len;
         const uint64_t start = which ? d.t_start : d.p_start;
+        // word starts: a scan, or (no scan) a fixed stride of max_words
+        const uint64_t ws = word_starts ? word_starts[i] : (uint64_t)i * max_words;
         if (w == 0) {
             if (which) {
-                packed[i].t_start = word_starts[i];
+                packed[i].t_start = ws;
                 packed[i].t_len = d.t_len;
             } else {
-                packed[i].p_start = word_starts[i];
+                packed[i].p_start = ws;
                 packed[i].p_len = d.p_len;
             }
         }
@@ -304,7 +305,7 @@ __global__ void k_pack_pairs(const PairDesc* __restrict__ pairs, size_t n,
         if (w >= nw) continue;
         int cnt = (int)min(32u, len - 32u * w);
         bool ok = true;
-        words[word_starts[i] + w] = pack_word(ascii, start + 32ull * w, cnt, ok, w + 1 < nw);
+        words[ws + w] = pack_word(ascii, start + 32ull * w, cnt, ok);
         if (!ok) atomicMin(err_pair, (unsigned long long)i);
     }
 }
@@ -326,7 +327,7 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
         const uint32_t len = lens[i];
         int cnt = (int)min(32u, len - 32u * w);
         bool ok = true;
-        words[t] = pack_word(ascii, starts[i] + 32ull * w, cnt, ok, false);
+        words[t] = pack_word(ascii, starts[i] + 32ull * w, cnt, ok);
         if (!ok) atomicMin(err_index, (unsigned long long)i);
     }
 }
