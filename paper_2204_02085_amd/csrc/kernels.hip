@@ -283,9 +283,10 @@ __global__ void k_pack_pairs(const PairDesc* __restrict__ pairs, size_t n,
     const uint32_t max_words = which ? max_words_t : max_words_p;
     uint64_t* words = which ? words_t : words_p;
     const size_t total = n * (size_t)max_words;
+    const bool narrow = total <= 0xFFFFFFFFull;  // 32-bit division suffices
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = t / max_words;
+        const size_t i = narrow ? (size_t)((uint32_t)t / max_words) : t / max_words;
         const uint32_t w = (uint32_t)(t - i * max_words);
         const PairDesc d = pairs[i];
         const uint32_t len = which ? d.t_len : d.p_len;
@@ -316,8 +317,31 @@ __global__ void k_pack_seqs(const uint8_t* __restrict__ ascii, const uint64_t* _
                             uint64_t* __restrict__ words, unsigned long long* err_index) {
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total_words;
          t += (uint64_t)gridDim.x * blockDim.x) {
-        // sequence holding word t: the last i with word_starts[i] <= t
-        size_t lo = 0, hi = n;  // invariant: word_starts[lo] <= t < word_starts[hi]
+        // sequence holding word t: the last i with word_starts[i] <= t.  Start
+        // from the guess of equal lengths and widen by doubling steps until
+        // the bracket holds t, then bisect (exact at once for equal lengths).
+        size_t g = (size_t)((double)t * (double)n / (double)total_words);
+        g = g < n ? g : n - 1;
+        size_t lo, hi;  // invariant: word_starts[lo] <= t < word_starts[hi] (hi = n: end)
+        if (word_starts[g] <= t) {
+            lo = g;
+            size_t step = 1;
+            hi = g + 1;
+            while (hi < n && word_starts[hi] <= t) {
+                lo = hi;
+                hi = hi + step < n ? hi + step : n;
+                step <<= 1;
+            }
+        } else {
+            hi = g;
+            size_t step = 1;
+            lo = g >= 1 ? g - 1 : 0;
+            while (lo > 0 && word_starts[lo] > t) {
+                hi = lo;
+                lo = lo >= step ? lo - step : 0;
+                step <<= 1;
+            }
+        }
         while (hi - lo > 1) {
             const size_t mid = (lo + hi) >> 1;
             if (word_starts[mid] <= t) lo = mid; else hi = mid;
