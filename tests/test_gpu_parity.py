@@ -201,6 +201,33 @@ def test_pairs100_e4_full_size(aligner, oracle_lib, synth_lib):
     assert st["short_pairs"] == st["pairs"]
 
 
+def test_pairs100_e4_full_size_tuned_launch(aligner, oracle_lib, synth_lib, wfa):
+    """The same 5,000,000 pairs in the launch the autotuner picks for them
+    (one persistent bucketed launch between replayed graphs, 8 lanes per pair,
+    window 32, step cap 16, 128-thread workgroups) and in the plain launch of
+    that shape: both bit-exact against the oracle on a sample, and identical
+    to each other on every pair."""
+    b = synth_lib.workload("pairs100_e4_5m")
+    shape = dict(window=32, lanes_per_pair=8, step_cap=16, block_threads=128)
+    res = {}
+    for name, extra in [("persistent", dict(schedule=wfa.WFA_SCHED_PERSISTENT, bucket=1, use_graph=1)),
+                        ("plain", dict(schedule=wfa.WFA_SCHED_PLAIN, bucket=-1, use_graph=-1))]:
+        say(f"case: pairs100_e4_5m full size, {name} launch {shape}")
+        aligner.set_options(**shape, **extra)
+        res[name] = aligner.align(b, PEN, capacity=len(b) * 40 + 1024)
+        st = aligner.stats()
+        assert st["short_pairs"] == st["pairs"] and st["lanes_per_pair"] == 8
+    for a_, b_ in zip(res["persistent"], res["plain"]):
+        assert np.array_equal(a_, b_)
+    got = res["persistent"]
+    check_invariants_vectorized(b, *got, PEN)
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([rng.choice(len(b), 30_000, replace=False),
+                                    np.argsort(got[0], kind="stable")[-300:], [0, len(b) - 1]]))
+    sub = b.subset(idx)
+    assert_same(_subset_result(got, idx), oracle_of(oracle_lib, sub), sub, "tuned launch sample")
+
+
 def test_pairs100_e2_full_size(aligner, oracle_lib, synth_lib):
     """5,000,000 pairs of 100 bp at E = 2 %."""
     _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e2_5m", None, 50_000, 2)
@@ -223,6 +250,13 @@ def test_long_reads_sample(aligner, oracle_lib, synth_lib, wfa):
     sub = b.subset(order)
     got = aligner.align(sub, PEN, capacity=200_000)
     assert_same(got, oracle_of(oracle_lib, sub), sub, "long cigar")
+    check_invariants_vectorized(sub, *got, PEN)
+    say("case: long reads, CIGAR on 12 of every length (longest included)")
+    order = np.argsort(np.maximum(b.p_len, b.t_len), kind="stable")
+    pick = np.unique(np.concatenate([order[::16], order[-2:]]))
+    sub = b.subset(pick)
+    got = aligner.align(sub, PEN, capacity=400_000)
+    assert_same(got, oracle_of(oracle_lib, sub), sub, "long cigar, all lengths")
     check_invariants_vectorized(sub, *got, PEN)
 
 
