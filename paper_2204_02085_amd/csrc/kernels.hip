@@ -945,7 +945,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             auto rd = [](const int* base, const RowMeta& mm, int kk) -> int {
                 return (base && kk >= mm.lo && kk <= mm.hi) ? base[kk - mm.lo] : NUL32;
             };
-            for (int k = lo + tid; k <= hi; k += BT) {
+            // one cell from its five source offsets
+            auto cell = [&](int k, int va, int vb, int vc, int ve, int vx) {
                 int mval;
                 int ival = NUL32, dval = NUL32, rec = 0;
                 if (s == 0) {
@@ -958,11 +959,11 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     // the minimum t, floored at NULL
                     const int L = min(m, n + k);
                     const uint32_t tn = (uint32_t)(L - NUL32);
-                    const uint32_t ta = (uint32_t)(L - 1 - rd(MO, so, k - 1));
-                    const uint32_t tb = (uint32_t)(L - 1 - rd(IE, se, k - 1));
-                    const uint32_t tc = (uint32_t)(L - rd(MO, so, k + 1));
-                    const uint32_t te = (uint32_t)(L - rd(DE, se, k + 1));
-                    const uint32_t tx = (uint32_t)(L - 1 - rd(MX, sx, k));
+                    const uint32_t ta = (uint32_t)(L - 1 - va);
+                    const uint32_t tb = (uint32_t)(L - 1 - vb);
+                    const uint32_t tc = (uint32_t)(L - vc);
+                    const uint32_t te = (uint32_t)(L - ve);
+                    const uint32_t tx = (uint32_t)(L - 1 - vx);
                     const uint32_t ti = min(min(ta, tb), tn);
                     const uint32_t td = min(min(tc, te), tn);
                     const uint32_t tm = min(min(tx, ti), td);
@@ -989,6 +990,17 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     histF[(k - lo) >> 1] = (uint8_t)(lo4 | (hi4 << 4));
                 }
                 if (k == kt && mval == m) sh_flag = 1;
+            };
+            // two cells per thread and pass: both cells' sources are read
+            // before either is computed, so their latencies overlap
+            for (int k0 = lo + tid; k0 <= hi; k0 += 2 * BT) {
+                const int k1 = k0 + BT;
+                const int a0 = rd(MO, so, k0 - 1), b0 = rd(IE, se, k0 - 1), c0 = rd(MO, so, k0 + 1),
+                          e0 = rd(DE, se, k0 + 1), x0 = rd(MX, sx, k0);
+                const int a1 = rd(MO, so, k1 - 1), b1 = rd(IE, se, k1 - 1), c1 = rd(MO, so, k1 + 1),
+                          e1 = rd(DE, se, k1 + 1), x1 = rd(MX, sx, k1);
+                cell(k0, a0, b0, c0, e0, x0);
+                if (k1 <= hi) cell(k1, a1, b1, c1, e1, x1);
             }
         }
         __syncthreads();
