@@ -260,6 +260,30 @@ def test_long_reads_sample(aligner, oracle_lib, synth_lib, wfa):
     check_invariants_vectorized(sub, *got, PEN)
 
 
+def test_very_long_pair_sequences_outside_lds(aligner, oracle_lib, synth_lib):
+    """Pairs of 120-150 kbp (sequences too long for the general kernel's LDS
+    copy, so it reads them from HBM): scores and CIGARs bit-exact."""
+    say("case: two pairs of 120-150 kbp, score + CIGAR")
+    rng = np.random.default_rng(21)
+    pairs = []
+    for n in (150_000, 120_000):
+        p = bytearray(rng.choice(list(b"ACGT"), size=n).astype(np.uint8).tobytes())
+        t = bytearray(p)
+        for pos in sorted(rng.choice(n - 100, 12, replace=False), reverse=True):
+            kind = int(pos) % 3
+            if kind == 0:
+                t[pos] = b"ACGT"[(b"ACGT".index(t[pos]) + 1) % 4]
+            elif kind == 1:
+                t[pos:pos] = b"GATTACA"[: 1 + int(pos) % 5]
+            else:
+                del t[pos:pos + 1 + int(pos) % 4]
+        pairs.append((bytes(p), bytes(t)))
+    b = synth_lib.from_pairs(pairs)
+    got = aligner.align(b, PEN, capacity=10_000)
+    assert_same(got, oracle_of(oracle_lib, b), b, "very long")
+    check_invariants_vectorized(b, *got, PEN)
+
+
 def test_capacity_error_then_copy(aligner, oracle_lib, synth_lib, wfa):
     """A too-small CIGAR buffer returns WFA_E_CAPACITY with the needed size;
     wfa_copy_last_cigars then delivers the same runs."""
