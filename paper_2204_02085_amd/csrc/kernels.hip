@@ -44,7 +44,12 @@ __device__ __forceinline__ void wave_sync() {
 
 // 32 bases starting at base `pos` of a 2-bit little-endian sequence held as
 // 32-bit words S[] (16 bases each); dwords S[pos/16 .. pos/16 + 2] must exist.
-__device__ __forceinline__ uint64_t window32(const uint32_t* S, int pos) {
+// Pointers into LDS typed as such, so their arithmetic stays 32-bit.
+template <class T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
+template <class P>
+__device__ __forceinline__ uint64_t window32(P S, int pos) {
     const int q = pos >> 4;
     const uint32_t b = (uint32_t)(pos & 15) << 1;
     const uint32_t w0 = S[q], w1 = S[q + 1], w2 = S[q + 2];
@@ -433,23 +438,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int gl = lane - grp * G;
     const int gshift = grp * G;
 
-    unsigned char* gbase = lds + (wave * GPW + grp) * a.group_bytes;
-    RowT* RM = (RowT*)gbase;
-    RowT* RI = (RowT*)(gbase + a.id_off);
-    RowT* RD = RI + a.ring2 * RW;
+    lds_ptr<unsigned char> gbase = (lds_ptr<unsigned char>)lds + (wave * GPW + grp) * a.group_bytes;
+    lds_ptr<RowT> RM = (lds_ptr<RowT>)gbase;
+    lds_ptr<RowT> RI = (lds_ptr<RowT>)(gbase + a.id_off);
+    lds_ptr<RowT> RD = RI + a.ring2 * RW;
     const int rows_bytes = a.rows_bytes;
     // CIGAR mode: 4-bit decision records of steps 0..cap, two cells per byte
     // (cell j in the low nibble when j is even): bits 0-1 the source of M
     // (0 mismatch, 1 end of insertion, 2 end of deletion), bit 2 insertion
     // opened from M, bit 3 deletion opened from M
-    uint8_t* FL = (uint8_t*)(gbase + rows_bytes);
+    lds_ptr<uint8_t> FL = (lds_ptr<uint8_t>)(gbase + rows_bytes);
     const int rec_bytes = CIGAR ? (((a.cap + 1) * (W / 2)) + 15) & ~15 : 0;
     // CIGAR mode: the backtrace stages its runs over the I/D rings (free by then)
-    uint32_t* STAGE = (uint32_t*)(gbase + a.id_off);
-    uint64_t* SP64 = (uint64_t*)(gbase + rows_bytes + rec_bytes);
-    uint64_t* ST64 = SP64 + a.seq_words;
-    const uint32_t* SP = (const uint32_t*)SP64;
-    const uint32_t* ST = (const uint32_t*)ST64;
+    lds_ptr<uint32_t> STAGE = (lds_ptr<uint32_t>)(gbase + a.id_off);
+    lds_ptr<uint64_t> SP64 = (lds_ptr<uint64_t>)(gbase + rows_bytes + rec_bytes);
+    lds_ptr<uint64_t> ST64 = SP64 + a.seq_words;
+    lds_ptr<const uint32_t> SP = (lds_ptr<const uint32_t>)SP64;
+    lds_ptr<const uint32_t> ST = (lds_ptr<const uint32_t>)ST64;
 
     const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
     const int ring = a.ring, ring2 = a.ring2;
@@ -523,8 +528,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             constexpr uint32_t NW = sizeof(RowT) == 1 ? 0x80808080u : 0xC000C000u;
             static_assert(sizeof(RowT) == 1 ? (int8_t)0x80 == NUL : (int16_t)0xC000 == NUL,
                           "fill word must repeat NULL");
-            uint4* f = (uint4*)gbase;
-            for (int idx = gl; idx < rows_bytes / 16; idx += G) f[idx] = make_uint4(NW, NW, NW, NW);
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            lds_ptr<u32x4> f = (lds_ptr<u32x4>)gbase;
+            for (int idx = gl; idx < rows_bytes / 16; idx += G) f[idx] = u32x4{NW, NW, NW, NW};
         }
         wave_sync();
 
@@ -547,8 +553,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                                  j0 > W / 2 + G / 2 - 1 + (lay - 1) * (G / 2)))
                 lay++;
         }
-        int cur = CIGAR ? 1 : PRE;  // M row of step 0 (the rows before it are NULL)
-        int cur2 = ring2 - 1;      // I/D row of step 0
+        // Offsets (in cells, + 1 for the pad) of the current M and I/D rows,
+        // kept as running sums (scalar adds, no multiplies): M row of step 0
+        // after the NULL rows, I/D row of step 0 last in its ring.
+        const int RINGM = ring * RW, RINGID = ring2 * RW;
+        const int XRW = X * RW, OERW = OE * RW, ERW = E * RW;
+        int ocur = (CIGAR ? 1 : PRE) * RW + 1;
+        int ocur2 = (ring2 - 1) * RW + 1;
         for (int s = 0;; s++) {
             if (__ballot(st == 0) == 0) break;
             // layers the wave computes this step: the most any of its groups needs
@@ -557,22 +568,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             for (int d = 1; d < DPL; d++) nlay += __ballot(st == 0 && lay > d) != 0 ? 1 : 0;
             const bool growable = DPL > 1 && __ballot(st == 0 && lay < DPL) != 0;
             if (s > 0) {
-                cur = cur + 1 == ring ? 0 : cur + 1;  // never wraps in CIGAR mode
-                cur2 = cur2 + 1 == ring2 ? 0 : cur2 + 1;
+                ocur += RW;  // never wraps in CIGAR mode
+                ocur -= ocur > RINGM ? RINGM : 0;
+                ocur2 += RW;
+                ocur2 -= ocur2 > RINGID ? RINGID : 0;
             }
-            int ix = cur - X, io = cur - OE, ie = cur2 - E;
+            int ox = ocur - XRW, oo = ocur - OERW, oe = ocur2 - ERW;
             if (CIGAR) {  // steps before 0 read the NULL row
-                ix = max(ix, 0);
-                io = max(io, 0);
+                ox = max(ox, 1);
+                oo = max(oo, 1);
             } else {
-                ix += ix < 0 ? ring : 0;
-                io += io < 0 ? ring : 0;
+                ox += ox < 1 ? RINGM : 0;
+                oo += oo < 1 ? RINGM : 0;
             }
-            ie += ie < 0 ? ring2 : 0;
-            const RowT* mx = RM + ix * RW + 1;
-            const RowT* mo = RM + io * RW + 1;
-            const RowT* il = RI + ie * RW + 1;
-            const RowT* dr = RD + ie * RW + 1;
+            oe += oe < 1 ? RINGID : 0;
+            lds_ptr<const RowT> mx = RM + ox;
+            lds_ptr<const RowT> mo = RM + oo;
+            lds_ptr<const RowT> il = RI + oe;
+            lds_ptr<const RowT> dr = RD + oe;
             const bool run = st == 0;
             // Layers one after another (cells of a step read only earlier
             // steps' rows, so the order does not matter): compute the cells,
@@ -635,9 +648,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     Mv = go ? hp : Mv;
                 }
                 // store the step's row (groups that stopped write rows nobody reads)
-                RM[cur * RW + 1 + j] = (RowT)Mv;
-                RI[cur2 * RW + 1 + j] = (RowT)Iv;
-                RD[cur2 * RW + 1 + j] = (RowT)Dv;
+                RM[ocur + j] = (RowT)Mv;
+                RI[ocur2 + j] = (RowT)Iv;
+                RD[ocur2 + j] = (RowT)Dv;
                 if (CIGAR) {
                     // neighbouring lanes hold neighbouring diagonals (even j on
                     // even lanes): both write the byte of the pair of cells
