@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--second-set", default="pairs100_e2_5m",
                     help="the configuration's second set (E = 2 %%), timed the same way after "
                          "the main workload; empty: skip")
+    ap.add_argument("--other-configs", type=int, default=1,
+                    help="also time the uneven (2M pairs, autotuned) and long-read (100k pairs, "
+                         "score-only and CIGAR) configurations once each (0: skip)")
     ap.add_argument("--host-steps", type=int, default=2,
                     help="calls timed with host ASCII inputs and host outputs (PCIe "
                          "included; 0: skip)")
@@ -381,6 +384,50 @@ def main():
                   "autotuned_options": tuned2}
         del p2, t2, d2, o2
 
+    # the other configurations, for the record: 2 M uneven pairs (one
+    # persistent bucketed graph-replayed launch, autotuned) and 100 k long
+    # pairs (general kernel), timed after one warm-up call
+    others = None
+    if args.other_configs:
+        others = {}
+        for name, count, tune, modes in [("uneven50_300_2m", 2_000_000, True, ("cigar",)),
+                                         ("long1k_10k_100k", 100_000, False, ("score", "cigar"))]:
+            log(f"configuration {name}: {count} pairs")
+            bo = synth.workload(name, count)
+            no = len(bo)
+            if enc == wfa.WFA_PACKED2:
+                po, to, do_ = al.to_device_packed(bo)
+            else:
+                po, to, do_ = al.to_device(bo)
+            rec = {"pairs": no}
+            for mode in modes:
+                cig = mode == "cigar"
+                runs_cap = no * (40 if no > 1_000_000 else 1500) + 1024
+                oo = al.alloc_outputs(no, runs_cap, cig)
+                if tune:
+                    opts = al.autotune(po, to, do_, no, (4, 6, 2), cig, encoding=enc,
+                                       sample_pairs=no)
+                else:
+                    opts = {}
+                    al.set_options()
+                al.set_options(**opts)
+                steps = 3 if no > 1_000_000 else 1
+                al.align_device(po, to, do_, no, *oo, (4, 6, 2), cig, enc)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    al.align_device(po, to, do_, no, *oo, (4, 6, 2), cig, enc)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t0) / steps
+                st = al.stats()
+                rec[mode] = {"pairs_per_s": no / el, "ms_per_call": el * 1e3,
+                             "short_pairs": st["short_pairs"], "general_pairs": st["general_pairs"],
+                             "ms_short_kernel": st["ms_align"], "ms_general": st["ms_general"],
+                             "options": opts or "defaults"}
+                del oo
+            others[name] = rec
+            del po, to, do_, bo
+
     serving = None
     if args.serving_requests > 0:
         log(f"serving run: {args.serving_requests} requests")
@@ -426,6 +473,7 @@ def main():
         "phase_ms": {k: tuned_stats[k] for k in ("ms_pack", "ms_align", "ms_general", "ms_compact",
                                                  "ms_total")},
         "second_set": second,
+        "other_configs": others,
         "host_path": host_path,
         "roofline": roofline,
         "cpu_baseline": cpu,
