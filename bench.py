@@ -139,39 +139,69 @@ def time_schedule(al, dev, n, steps, warmup, options, enc):
 
 
 def host_path_run(al, wfa, batch, steps, options):
-    """Whole calls with host memory on both sides: ASCII pairs in pageable host
-    buffers, results back in host buffers (the library stages through the
-    device).  PCIe is included; this is never the headline value."""
+    """Whole calls with host memory on both sides: ASCII pairs in host
+    buffers, results back in host buffers, through the library's chunk
+    pipeline (copies in, alignment and copies out of successive chunks
+    overlap).  Timed twice: with pageable numpy buffers and with page-locked
+    buffers from wfa_host_alloc.  PCIe is included; this is never the
+    headline value."""
     import ctypes
 
     import numpy as np
 
     n = len(batch.p_len)
-    pairs = wfa.pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len)
-    scores = np.empty(n, np.int32)
-    offsets = np.empty(n + 1, np.uint64)
     cap = n * 40 + 1024
-    runs = np.empty(cap, np.uint32)
-    needed = ctypes.c_size_t(0)
-    bad = ctypes.c_int64(-1)
     al.set_options(**options)
 
-    def call():
-        rc = wfa.wfa_align_batch(al.ctx, batch.patterns.ctypes.data, batch.texts.ctypes.data,
-                                 pairs.ctypes.data, n, wfa.WFA_ASCII, wfa.WFA_HOST,
-                                 wfa.wfa_penalties(4, 6, 2), wfa.WFA_CIGAR, scores.ctypes.data,
-                                 runs.ctypes.data, cap, offsets.ctypes.data,
-                                 ctypes.byref(needed), ctypes.byref(bad), None)
-        if rc != wfa.WFA_OK:
-            raise wfa.WFAError(rc, "wfa_align_batch (host)", bad.value)
+    ascii_in = (wfa.WFA_ASCII, batch.patterns, batch.texts,
+                wfa.pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len))
 
-    call()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    def run(pinned, inputs):
+        enc = inputs[0]
+        empty = wfa.host_empty if pinned else np.empty
+        copy = wfa.host_copy if pinned else (lambda a: a)
+        pat, txt, pairs = (copy(a) for a in inputs[1:])
+        scores = empty(n, np.int32)
+        offsets = empty(n + 1, np.uint64)
+        runs = empty(cap, np.uint32)
+        needed = ctypes.c_size_t(0)
+        bad = ctypes.c_int64(-1)
+
+        def call():
+            rc = wfa.wfa_align_batch(al.ctx, pat.ctypes.data, txt.ctypes.data, pairs.ctypes.data,
+                                     n, enc, wfa.WFA_HOST, wfa.wfa_penalties(4, 6, 2),
+                                     wfa.WFA_CIGAR, scores.ctypes.data, runs.ctypes.data, cap,
+                                     offsets.ctypes.data, ctypes.byref(needed), ctypes.byref(bad),
+                                     None)
+            if rc != wfa.WFA_OK:
+                raise wfa.WFAError(rc, "wfa_align_batch (host)", bad.value)
+
         call()
-    el = time.perf_counter() - t0
-    return {"pairs_per_s": n * steps / el, "ms_per_call": el / steps * 1e3, "steps": steps,
-            "input": "ASCII in pageable host memory", "output": "host memory"}, scores
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        el = time.perf_counter() - t0
+        st = al.stats()
+        moved = (pat.nbytes + txt.nbytes + pairs.nbytes + scores.nbytes + offsets.nbytes
+                 + needed.value * 4)
+        return {"pairs_per_s": n * steps / el, "ms_per_call": el / steps * 1e3,
+                "chunks": st["host_chunks"], "pcie_gb_per_s": moved * steps / el / 1e9,
+                "bytes_moved_per_call": moved}, np.array(scores)
+
+    pageable, scores = run(False, ascii_in)
+    pinned, scores2 = run(True, ascii_in)
+    # the same pairs as 2-bit words (packed once by the library, then kept in
+    # host memory): a quarter of the sequence bytes cross the link
+    pw, tw, dpairs = al.to_device_packed(batch)
+    packed_in = (wfa.WFA_PACKED2, pw.cpu().numpy(), tw.cpu().numpy(),
+                 dpairs.cpu().numpy().view(wfa.PAIR_DTYPE))
+    del pw, tw, dpairs
+    packed, scores3 = run(True, packed_in)
+    if not (np.array_equal(scores, scores2) and np.array_equal(scores, scores3)):
+        raise SystemExit("host path: pinned, pageable and packed calls disagree")
+    out = {"steps": steps, "input": "ASCII in host memory", "output": "host memory",
+           "pageable": pageable, "pinned": pinned, "pinned_packed2_input": packed}
+    return out, scores
 
 
 def serving_run(al, wfa, synth, n_req, load, seed=11):

@@ -42,10 +42,15 @@
  *                  sequence are read; bits past its end are ignored.
  *
  * Memory spaces.  All buffer arguments of one call live in the space named
- * by `mem`: host memory (WFA_HOST; the library stages to and from the
- * device) or device memory of the context's GPU (WFA_DEVICE, e.g. torch
- * tensors' data pointers).  Scalar out-parameters (cigar_needed, bad_pair,
- * stats, tickets) are always host pointers.
+ * by `mem`: host memory (WFA_HOST) or device memory of the context's GPU
+ * (WFA_DEVICE, e.g. torch tensors' data pointers).  Scalar out-parameters
+ * (cigar_needed, bad_pair, stats, tickets) are always host pointers.
+ * A host-memory batch runs as a pipeline over chunks of consecutive pairs:
+ * while chunk i aligns, one library thread copies chunk i+1's descriptors
+ * and sequence bytes to the device and another copies chunk i-1's scores,
+ * offsets and runs back, each on a stream of its own.  Host buffers from
+ * wfa_host_alloc (page-locked) move at the full link rate; ordinary
+ * pageable buffers work too, through the HIP runtime's staging.
  *
  * Ownership.  The caller owns every input and output buffer; the library
  * keeps no caller pointer after a call returns.  The library owns its
@@ -60,7 +65,9 @@
  *
  * Errors.  Every int-returning function returns WFA_OK (0) or a negative
  * WFA_E_* code; wfa_strerror gives its text.  On a validation error nothing
- * is written except *bad_pair.
+ * is written except *bad_pair, with one exception: a host-memory batch
+ * checks its bytes chunk by chunk, so WFA_E_ALPHABET may leave the scores
+ * and offsets of the chunks before the offending one written.
  */
 #ifndef WFA_H
 #define WFA_H
@@ -122,6 +129,9 @@ typedef struct {
     int32_t lanes_per_pair; /* lanes of a wavefront per pair in the short kernel
                                (8, 16, 32 or 64, at most the window): 64 / lanes
                                pairs share a wavefront */
+    int32_t host_chunk_pairs; /* pairs per chunk of the host-memory pipeline
+                                 (at least 1/1024 of the batch); 0: a quarter
+                                 of the batch, within [262144, 2097152] */
 } wfa_options;
 
 /* Counters of the last wfa_align_batch call on a context. */
@@ -134,7 +144,7 @@ typedef struct {
     uint64_t cigar_runs;         /* total runs written                               */
     int32_t window;              /* short-kernel window used                         */
     int32_t lanes_per_pair;      /* short-kernel lanes per pair used                 */
-    int32_t pad_;
+    int32_t host_chunks;         /* chunks of the host-memory pipeline (0: device call) */
     int32_t step_cap;            /* short-kernel step cap used                       */
     int32_t schedule;            /* schedule used                                    */
     int32_t graph_replayed;      /* 1 if a captured graph was replayed               */
@@ -197,6 +207,16 @@ int wfa_align_batch(wfa_ctx *ctx, const void *patterns, const void *texts,
  * last call's memory space) if `capacity` suffices; offsets are those the
  * last call wrote and may be passed again (NULL: not rewritten). */
 int wfa_copy_last_cigars(wfa_ctx *ctx, uint32_t *runs, size_t capacity, uint64_t *offsets);
+
+/* Page-locked host memory for WFA_HOST batches (inputs and outputs), so
+ * that the host-memory pipeline's copies run at the full link rate.
+ * hipHostMalloc underneath: *out receives `bytes` bytes (0 is allowed and
+ * gives a valid pointer) or NULL with WFA_E_NOMEM.  The caller owns the
+ * block until wfa_host_free; it is not tied to a context.  */
+int wfa_host_alloc(size_t bytes, void **out);
+
+/* Free a block from wfa_host_alloc.  NULL is ignored. */
+void wfa_host_free(void *ptr);
 
 /* Encode ASCII sequences to the PACKED2 layout on the device.
  *   ascii        device bytes

@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -32,7 +33,8 @@ WFA_MAX_LENGTH = 1 << 26
 
 EXPORTED = [
     "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_align_batch",
-    "wfa_copy_last_cigars", "wfa_pack2bit", "wfa_autotune", "wfa_last_stats", "wfa_strerror",
+    "wfa_copy_last_cigars", "wfa_host_alloc", "wfa_host_free", "wfa_pack2bit", "wfa_autotune",
+    "wfa_last_stats", "wfa_strerror",
     "wfa_server_open", "wfa_server_submit", "wfa_server_poll", "wfa_server_release",
     "wfa_server_estimate_bytes", "wfa_server_get_stats", "wfa_server_close",
 ]
@@ -50,14 +52,15 @@ class wfa_options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("step_cap", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("bucket", ctypes.c_int32), ("general_pairs", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32)]
+                ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32),
+                ("host_chunk_pairs", ctypes.c_int32)]
 
 
 class wfa_stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_uint64), ("short_pairs", ctypes.c_uint64),
                 ("general_pairs", ctypes.c_uint64), ("requeued", ctypes.c_uint64),
                 ("cigar_runs", ctypes.c_uint64), ("window", ctypes.c_int32),
-                ("lanes_per_pair", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("lanes_per_pair", ctypes.c_int32), ("host_chunks", ctypes.c_int32),
                 ("step_cap", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("graph_replayed", ctypes.c_int32), ("ms_pack", ctypes.c_double),
                 ("ms_align", ctypes.c_double), ("ms_general", ctypes.c_double),
@@ -120,6 +123,8 @@ def _load():
                              ctypes.c_int, p, p, sz, p, ctypes.POINTER(sz),
                              ctypes.POINTER(i64), p], ctypes.c_int),
         "wfa_copy_last_cigars": ([p, p, sz, p], ctypes.c_int),
+        "wfa_host_alloc": ([sz, ctypes.POINTER(p)], ctypes.c_int),
+        "wfa_host_free": ([p], None),
         "wfa_pack2bit": ([p, p, p, p, sz, p, sz, p, ctypes.POINTER(sz), ctypes.POINTER(i64), p],
                          ctypes.c_int),
         "wfa_autotune": ([p, p, p, p, sz, ctypes.c_int, ctypes.c_int, wfa_penalties, ctypes.c_int,
@@ -152,6 +157,8 @@ wfa_ctx_destroy = lib.wfa_ctx_destroy
 wfa_set_options = lib.wfa_set_options
 wfa_align_batch = lib.wfa_align_batch
 wfa_copy_last_cigars = lib.wfa_copy_last_cigars
+wfa_host_alloc = lib.wfa_host_alloc
+wfa_host_free = lib.wfa_host_free
 wfa_pack2bit = lib.wfa_pack2bit
 wfa_autotune = lib.wfa_autotune
 wfa_last_stats = lib.wfa_last_stats
@@ -171,6 +178,31 @@ class WFAError(RuntimeError):
         super().__init__(f"{what}: {msg} (status {status}{', pair ' + str(bad) if bad >= 0 else ''})")
         self.status = status
         self.bad = bad
+
+
+def host_empty(shape, dtype) -> np.ndarray:
+    """Uninitialised numpy array in page-locked host memory (wfa_host_alloc),
+    released with wfa_host_free once the array and all its views are gone.
+    Host-memory batches whose buffers come from here copy at the full link
+    rate."""
+    dt = np.dtype(dtype)
+    shape = (int(shape),) if np.isscalar(shape) else tuple(int(x) for x in shape)
+    nbytes = int(np.prod(shape, dtype=np.int64)) * dt.itemsize
+    ptr = ctypes.c_void_p()
+    rc = wfa_host_alloc(nbytes, ctypes.byref(ptr))
+    if rc != WFA_OK:
+        raise WFAError(rc, "wfa_host_alloc")
+    buf = (ctypes.c_uint8 * max(nbytes, 1)).from_address(ptr.value)
+    weakref.finalize(buf, wfa_host_free, ptr.value)
+    return np.frombuffer(buf, dtype=np.uint8, count=nbytes).view(dt).reshape(shape)
+
+
+def host_copy(a) -> np.ndarray:
+    """`a` copied into page-locked host memory (see host_empty)."""
+    a = np.ascontiguousarray(a)
+    out = host_empty(a.shape, a.dtype)
+    out[...] = a
+    return out
 
 
 def pairs_array(p_off, p_len, t_off, t_len) -> np.ndarray:
@@ -338,22 +370,36 @@ class Aligner:
     def last_needed(self) -> int:
         return int(getattr(self, "_needed", 0))
 
-    def align_host(self, batch, penalties=(4, 6, 2), cigar=True, encoding=WFA_ASCII):
-        """Host-memory variant: the library stages to and from the device."""
+    def align_host(self, batch, penalties=(4, 6, 2), cigar=True, encoding=WFA_ASCII,
+                   capacity=None, pinned=False, patterns=None, texts=None):
+        """Host-memory variant (the library's chunk pipeline moves the data).
+        `patterns` / `texts` replace the batch's own buffers (e.g. 2-bit
+        words for WFA_PACKED2, with p_off / t_off in words); pinned=True puts
+        the outputs in page-locked memory.  If the runs exceed `capacity` they
+        are fetched with wfa_copy_last_cigars."""
         n = len(batch.p_len)
         pairs = pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len)
-        scores = np.zeros(n, dtype=np.int32)
-        offsets = np.zeros(n + 1, dtype=np.uint64)
-        cap = n * 24 + 1024
-        runs = np.zeros(cap, dtype=np.uint32)
+        pat = batch.patterns if patterns is None else patterns
+        txt = batch.texts if texts is None else texts
+        empty = host_empty if pinned else np.empty
+        scores = empty(n, np.int32)
+        offsets = empty(n + 1, np.uint64)
+        cap = n * 24 + 1024 if capacity is None else int(capacity)
+        runs = empty(max(cap, 1), np.uint32)
         needed = ctypes.c_size_t(0)
         bad = ctypes.c_int64(-1)
         rc = wfa_align_batch(
-            self.ctx, batch.patterns.ctypes.data, batch.texts.ctypes.data, pairs.ctypes.data, n,
+            self.ctx, pat.ctypes.data, txt.ctypes.data, pairs.ctypes.data, n,
             encoding, WFA_HOST, wfa_penalties(*penalties), WFA_CIGAR if cigar else WFA_SCORE,
             scores.ctypes.data, runs.ctypes.data if cigar else None, cap if cigar else 0,
             offsets.ctypes.data if cigar else None, ctypes.byref(needed), ctypes.byref(bad), None)
-        if rc != WFA_OK:
+        self._needed = needed.value
+        if cigar and rc == WFA_E_CAPACITY:
+            runs = empty(max(needed.value, 1), np.uint32)
+            rc = wfa_copy_last_cigars(self.ctx, runs.ctypes.data, needed.value, None)
+            if rc != WFA_OK:
+                raise WFAError(rc, "wfa_copy_last_cigars")
+        elif rc != WFA_OK:
             raise WFAError(rc, "wfa_align_batch", bad.value)
         if not cigar:
             return scores, None, None

@@ -1,6 +1,7 @@
-// One batch: stage, plan, pack, short-pair kernel (plain or persistent, with
-// optional bucketing and graph replay), general kernel for whatever the short
-// kernel hands over, CIGAR offsets and compaction.
+// One batch in device memory: plan, pack, short-pair kernel (plain or
+// persistent, with optional bucketing and graph replay), general kernel for
+// whatever the short kernel hands over, CIGAR offsets and compaction.  Host
+// memory batches go through the chunk pipeline, which calls this per chunk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,20 +61,6 @@ int auto_window(uint32_t max_len) {
     if (max_len <= 1200) return 128;
     if (max_len <= SHORT_MAX_LEN) return 256;
     return 0;
-}
-
-// Grow `b` to `bytes`, keeping its first `keep` bytes.
-int ensure_keep(Workspace& ws, Buf& b, size_t bytes, size_t keep, hipStream_t s) {
-    if (b.bytes >= bytes) return WFA_OK;
-    Buf nb;
-    int rc = ws.ensure(nb, std::max(bytes, b.bytes * 2));
-    if (rc != WFA_OK) rc = ws.ensure(nb, bytes);
-    if (rc != WFA_OK) return rc;
-    if (keep) HIPCHK(hipMemcpyAsync(nb.ptr, b.ptr, keep, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    ws.release(b);
-    b = nb;
-    return WFA_OK;
 }
 
 template <class F>
@@ -263,7 +250,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
                 HIPCHK(hipMemcpyAsync(&chunk_runs, ws.job_offsets.as<uint64_t>() + nj, 8,
                                       hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
-                RCCHK(ensure_keep(ws, ws.gen_runs, (gen_used + chunk_runs + 1) * 4, gen_used * 4, s));
+                RCCHK(ws.grow_keep(ws.gen_runs, (gen_used + chunk_runs + 1) * 4, gen_used * 4, s));
                 HIPCHK(launch_gather_general(ws.jobs.as<uint32_t>(), nj, ws.job_nruns.as<uint32_t>(),
                                              ws.run_src.as<uint64_t>(), ws.arena.as<uint8_t>(), slice,
                                              ws.job_offsets.as<uint64_t>(), gen_used,
@@ -302,15 +289,15 @@ void graph_cache_clear(Engine* e) {
     e->graphs.clear();
 }
 
-int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
-                 int64_t* bad_pair) {
+int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
+                        size_t* cigar_needed, int64_t* bad_pair) {
     const double t_start = now_ms();
     if (bad_pair) *bad_pair = -1;
     if (cigar_needed) *cigar_needed = 0;
     Pen pen;
     RCCHK(make_pen(io.pen, &pen));
     if (io.enc != WFA_ASCII && io.enc != WFA_PACKED2) return WFA_E_INVAL;
-    if (io.mem != WFA_HOST && io.mem != WFA_DEVICE) return WFA_E_INVAL;
+    if (io.mem != WFA_DEVICE) return WFA_E_INVAL;
     if (io.mode != WFA_SCORE && io.mode != WFA_CIGAR) return WFA_E_INVAL;
     const bool cigar = io.mode == WFA_CIGAR;
     const size_t N = io.n;
@@ -337,56 +324,18 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     };
 
     if (N == 0) {
-        if (cigar) {
-            if (io.mem == WFA_HOST) {
-                io.offsets[0] = 0;
-            } else {
-                HIPCHK(launch_fill_u64(io.offsets, 0ull, 1, s));
-            }
-        }
+        if (cigar) HIPCHK(launch_fill_u64(io.offsets, 0ull, 1, s));
         return finish_user();
     }
 
-    // ---- staging (host memory) -------------------------------------------
-    const PairDesc* in_pairs;
-    const void* in_p;
-    const void* in_t;
+    const PairDesc* in_pairs = (const PairDesc*)io.pairs;
+    const void* in_p = io.patterns;
+    const void* in_t = io.texts;
     Dev d{};
-    if (io.mem == WFA_HOST) {
-        uint64_t endp = 0, endt = 0;
-        const bool ascii = io.enc == WFA_ASCII;
-        for (size_t i = 0; i < N; i++) {
-            const wfa_pair& q = io.pairs[i];
-            const uint64_t lp = ascii ? q.p_len : (q.p_len + 31ull) / 32;
-            const uint64_t lt = ascii ? q.t_len : (q.t_len + 31ull) / 32;
-            endp = std::max(endp, q.p_start + lp);
-            endt = std::max(endt, q.t_start + lt);
-        }
-        const size_t unit = ascii ? 1 : 8;
-        RCCHK(ws.ensure(ws.in_pairs, N * sizeof(PairDesc)));
-        RCCHK(ws.ensure(ws.in_p, endp * unit + 8));
-        RCCHK(ws.ensure(ws.in_t, endt * unit + 8));
-        HIPCHK(hipMemcpyAsync(ws.in_pairs.ptr, io.pairs, N * sizeof(PairDesc), hipMemcpyHostToDevice, s));
-        if (endp) HIPCHK(hipMemcpyAsync(ws.in_p.ptr, io.patterns, endp * unit, hipMemcpyHostToDevice, s));
-        if (endt) HIPCHK(hipMemcpyAsync(ws.in_t.ptr, io.texts, endt * unit, hipMemcpyHostToDevice, s));
-        in_pairs = ws.in_pairs.as<PairDesc>();
-        in_p = ws.in_p.ptr;
-        in_t = ws.in_t.ptr;
-        RCCHK(ws.ensure(ws.out_scores, N * 4));
-        d.scores = ws.out_scores.as<int32_t>();
-        if (cigar) {
-            RCCHK(ws.ensure(ws.out_offsets, (N + 1) * 8));
-            d.offsets = ws.out_offsets.as<uint64_t>();
-        }
-    } else {
-        in_pairs = (const PairDesc*)io.pairs;
-        in_p = io.patterns;
-        in_t = io.texts;
-        d.scores = io.scores;
-        d.offsets = io.offsets;
-        d.runs = io.runs;
-        d.capacity = io.capacity;
-    }
+    d.scores = io.scores;
+    d.offsets = io.offsets;
+    d.runs = io.runs;
+    d.capacity = io.capacity;
 
     // ---- batch facts -------------------------------------------------------
     RCCHK(ws.ensure(ws.stats, sizeof(BatchStats) * (1 + STATS_BLOCKS)));
@@ -415,7 +364,8 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     }
     const bool persistent = use_short && schedule != WFA_SCHED_PLAIN;
     const bool bucket = persistent && e->opt.bucket >= 0;
-    const bool graph = use_short && e->opt.use_graph >= 0 && schedule != WFA_SCHED_PLAIN &&
+    const bool graph = use_short && !io.no_graph && e->opt.use_graph >= 0 &&
+                       schedule != WFA_SCHED_PLAIN &&
                        (e->opt.use_graph > 0 || schedule == WFA_SCHED_AUTO ||
                         schedule == WFA_SCHED_PERSISTENT);
 
@@ -540,10 +490,9 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
     auto phase_post = [&](hipStream_t q) -> int {
         if (cigar && use_short) {
             HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, q));
-            if (io.mem == WFA_DEVICE)
-                HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
-                                      ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), d.offsets,
-                                      N, d.runs, d.capacity, q));
+            HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), d.offsets,
+                                  N, d.runs, d.capacity, q));
         }
         return WFA_OK;
     };
@@ -627,35 +576,18 @@ int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* 
         if (rescan) {
             RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64));
             HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, s));
-        }
-        if (rescan) {
             HIPCHK(hipMemcpyAsync(&total, d.offsets + N, 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
         } else {
             total = short_total;
         }
-        if (io.mem == WFA_HOST) {
-            RCCHK(ws.ensure(ws.out_runs, total * 4 + 4));
-            d.runs = ws.out_runs.as<uint32_t>();
-            d.capacity = total;
-        }
-        if ((rescan || io.mem == WFA_HOST) && total <= d.capacity)
+        if (rescan && total <= d.capacity)
             HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), d.offsets, N,
                                   d.runs, d.capacity, s));
         if (cigar_needed) *cigar_needed = (size_t)total;
     }
     HIPCHK(hipEventRecord(e->ev[8], s));
-
-    // ---- results to the host --------------------------------------------------
-    if (io.mem == WFA_HOST) {
-        HIPCHK(hipMemcpyAsync(io.scores, d.scores, N * 4, hipMemcpyDeviceToHost, s));
-        if (cigar) {
-            HIPCHK(hipMemcpyAsync(io.offsets, d.offsets, (N + 1) * 8, hipMemcpyDeviceToHost, s));
-            if (total <= io.capacity && total)
-                HIPCHK(hipMemcpyAsync(io.runs, d.runs, total * 4, hipMemcpyDeviceToHost, s));
-        }
-    }
     RCCHK(finish_user());
 
     wfa_stats& L = e->last;

@@ -56,6 +56,23 @@ int Workspace::ensure(Buf& b, size_t bytes) {
     return WFA_OK;
 }
 
+int Workspace::grow_keep(Buf& b, size_t bytes, size_t keep, hipStream_t s) {
+    if (b.bytes >= bytes) return WFA_OK;
+    Buf nb;
+    int rc = ensure(nb, std::max(bytes, b.bytes * 2));
+    if (rc != WFA_OK) rc = ensure(nb, bytes);
+    if (rc != WFA_OK) return rc;
+    if ((keep && hipMemcpyAsync(nb.ptr, b.ptr, keep, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        release(nb);
+        return WFA_E_DEVICE;
+    }
+    release(b);
+    b = nb;
+    return WFA_OK;
+}
+
 void Workspace::release(Buf& b) {
     if (b.ptr) {
         (void)hipFree(b.ptr);
@@ -113,6 +130,12 @@ int engine_init(Engine* e, int device, size_t budget) {
         e->stream = nullptr;
         return WFA_E_DEVICE;
     }
+    if (hipStreamCreateWithFlags(&e->h2d, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&e->d2h, hipStreamNonBlocking) != hipSuccess) {
+        std::fprintf(stderr, "libwfa: hipStreamCreate (copy streams) failed\n");
+        (void)hipGetLastError();
+        return WFA_E_DEVICE;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) e->num_cus = prop.multiProcessorCount;
     if (e->num_cus <= 0) e->num_cus = 256;
@@ -130,7 +153,9 @@ void engine_destroy(Engine* e) {
     for (auto& ev : e->ev)
         if (ev) (void)hipEventDestroy(ev);
     if (e->stream) (void)hipStreamDestroy(e->stream);
-    e->stream = nullptr;
+    if (e->h2d) (void)hipStreamDestroy(e->h2d);
+    if (e->d2h) (void)hipStreamDestroy(e->d2h);
+    e->stream = e->h2d = e->d2h = nullptr;
 }
 
 extern "C" int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx** out) {
@@ -172,6 +197,7 @@ extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
                                opt->block_threads % 64))
         return WFA_E_INVAL;
     if (opt->general_pairs < 0) return WFA_E_INVAL;
+    if (opt->host_chunk_pairs < 0) return WFA_E_INVAL;
     ctx->opt = *opt;
     return WFA_OK;
 }
@@ -298,31 +324,44 @@ extern "C" int wfa_copy_last_cigars(wfa_ctx* ctx, uint32_t* runs, size_t capacit
     hipStream_t s = ctx->stream;
     const size_t N = ctx->last_n;
     API_HIPCHK(hipSetDevice(ctx->device));
-    int rc = ws.ensure(ws.out_offsets, (N + 1) * 8);
-    if (rc == WFA_OK) rc = ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64);
-    if (rc != WFA_OK) return rc;
-    uint64_t* off = ws.out_offsets.as<uint64_t>();
-    API_HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, off, ws.scan_tmp.ptr, s));
     if (ctx->last_mem == WFA_DEVICE) {
+        int rc = ws.ensure(ws.out_offsets, (N + 1) * 8);
+        if (rc == WFA_OK) rc = ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64);
+        if (rc != WFA_OK) return rc;
+        uint64_t* off = ws.out_offsets.as<uint64_t>();
+        API_HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, off, ws.scan_tmp.ptr, s));
         API_HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), off, N, runs,
                                   capacity, s));
         if (offsets)
             API_HIPCHK(hipMemcpyAsync(offsets, off, (N + 1) * 8, hipMemcpyDeviceToDevice, s));
     } else {
-        rc = ws.ensure(ws.out_runs, ctx->last_total * 4 + 4);
-        if (rc != WFA_OK) return rc;
-        API_HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
-                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), off, N,
-                                  ws.out_runs.as<uint32_t>(), ctx->last_total, s));
+        // the host-memory pipeline keeps the whole batch's runs and offsets
+        // on the device
         if (ctx->last_total)
             API_HIPCHK(hipMemcpyAsync(runs, ws.out_runs.ptr, ctx->last_total * 4,
                                       hipMemcpyDeviceToHost, s));
         if (offsets)
-            API_HIPCHK(hipMemcpyAsync(offsets, off, (N + 1) * 8, hipMemcpyDeviceToHost, s));
+            API_HIPCHK(hipMemcpyAsync(offsets, ws.host_off.ptr, (N + 1) * 8, hipMemcpyDeviceToHost,
+                                      s));
     }
     API_HIPCHK(hipStreamSynchronize(s));
     return WFA_OK;
+}
+
+extern "C" int wfa_host_alloc(size_t bytes, void** out) {
+    if (!out) return WFA_E_INVAL;
+    *out = nullptr;
+    if (hipHostMalloc(out, bytes ? bytes : 1, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return WFA_E_NOMEM;
+    }
+    return WFA_OK;
+}
+
+extern "C" void wfa_host_free(void* ptr) {
+    if (ptr) (void)hipHostFree(ptr);
 }
 
 extern "C" int wfa_pack2bit(wfa_ctx* ctx, const uint8_t* ascii, const uint64_t* starts,

@@ -25,8 +25,9 @@ struct Workspace {
     uint64_t generation = 0;  // bumped whenever a buffer moves (invalidates graphs)
     // planning / packing
     Buf stats, flags, scan_tmp, ws_p, ws_t, words_p, words_t, packed_pairs;
-    // host-mode staging of inputs and outputs
-    Buf in_pairs, in_p, in_t, out_scores, out_runs, out_offsets;
+    // host-memory pipeline: device copies of the whole batch's inputs and
+    // outputs (host_off: offsets of the batch, host_loff: of one chunk)
+    Buf in_pairs, in_p, in_t, out_scores, out_runs, out_offsets, host_off, host_loff;
     // short kernel
     Buf nruns, run_src, slots, ovf_list, order, keys, hist;
     // general kernel
@@ -34,14 +35,17 @@ struct Workspace {
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
 
-    std::array<Buf*, 28> all() {
+    std::array<Buf*, 30> all() {
         return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,
                 &words_t, &packed_pairs, &in_pairs, &in_p,      &in_t,      &out_scores,
-                &out_runs, &out_offsets, &nruns,   &run_src,     &slots,     &ovf_list,
-                &order,   &keys,       &hist,     &jobs,        &job_nruns, &job_offsets,
-                &fail_list, &arena,    &gen_runs, &gen_tmp};
+                &out_runs, &out_offsets, &host_off, &host_loff, &nruns,   &run_src,
+                &slots,   &ovf_list,   &order,    &keys,        &hist,      &jobs,
+                &job_nruns, &job_offsets, &fail_list, &arena,   &gen_runs,  &gen_tmp};
     }
     int ensure(Buf& b, size_t bytes);
+    // grow to at least `bytes`, keeping the first `keep` bytes (copied on `s`,
+    // which is synchronised before the old block is freed)
+    int grow_keep(Buf& b, size_t bytes, size_t keep, hipStream_t s);
     void release(Buf& b);
     void release_all();
     int ensure_pinned(size_t bytes);
@@ -84,6 +88,7 @@ struct Engine {
     int device = 0;
     int num_cus = 256;
     hipStream_t stream = nullptr;
+    hipStream_t h2d = nullptr, d2h = nullptr;  // copy streams of the host-memory pipeline
     Workspace ws;
     hipEvent_t ev[10] = {};
     wfa_options opt{};
@@ -112,6 +117,7 @@ struct BatchIO {
     uint32_t* runs;
     size_t capacity;
     uint64_t* offsets;
+    bool no_graph = false;  // never capture or replay graphs for this call
 };
 
 int make_pen(const wfa_penalties& p, wfa::Pen* out);
@@ -119,8 +125,13 @@ int default_cap(const wfa::Pen& pen, int window);
 int default_lanes(int window);
 int short_plan(Engine* ctx, const wfa::Pen& pen, bool cigar, int window, int lanes, int cap,
                uint32_t max_len, ShortPlan* sp);
+// Any batch: device memory directly, host memory through the chunk pipeline.
 int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
                  int64_t* bad_pair);
+int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
+                        size_t* cigar_needed, int64_t* bad_pair);
+int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
+                      int64_t* bad_pair);
 void graph_cache_clear(Engine* e);
 int engine_init(Engine* e, int device, size_t budget);
 void engine_destroy(Engine* e);

@@ -90,6 +90,9 @@ hipError_t launch_batch_stats(const PairDesc* pairs, size_t n, BatchStats* out, 
                               hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+// dst[i] = src[i] + add for i < n
+hipError_t launch_add_u64(const uint64_t* src, uint64_t add, size_t n, uint64_t* dst,
+                          hipStream_t s);
 
 // Exclusive scan: out[i] = sum_{j<i} in(j), out[n] = total.  `in` selects a
 // per-pair quantity through `kind`.

@@ -141,6 +141,15 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
         p[i] = v;
 }
 
+// dst[i] = src[i] + add: a chunk's offsets, counted from its first run, made
+// relative to the first run of the whole batch
+__global__ void k_add_u64(const uint64_t* __restrict__ src, uint64_t add, size_t n,
+                          uint64_t* __restrict__ dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] + add;
+}
+
 __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
@@ -1314,6 +1323,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_u64(const uint64_t* src, uint64_t add, size_t n, uint64_t* dst,
+                          hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_add_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, src, add, n, dst);
     return hipGetLastError();
 }
 

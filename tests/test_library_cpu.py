@@ -47,8 +47,32 @@ def test_strerror_and_null_context():
     assert wfa.wfa_server_close(None) == wfa.WFA_E_INVAL
 
 
-def test_pair_descriptor_layout():
+def test_pair_descriptor_layout(tmp_path):
+    """The binding's structures match the header's, field by field (sizes and
+    offsets printed by a C program compiled against include/wfa.h)."""
+    import subprocess
+
     import paper_2204_02085_amd as wfa
 
-    assert wfa.PAIR_DTYPE.itemsize == 24
-    assert ctypes.sizeof(wfa.wfa_options) == 32
+    structs = {"wfa_pair": None, "wfa_penalties": wfa.wfa_penalties,
+               "wfa_options": wfa.wfa_options, "wfa_stats": wfa.wfa_stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "wfa.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        if cls is not None:
+            for f, _ in cls._fields_:
+                lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(got["wfa_pair"]) == wfa.PAIR_DTYPE.itemsize == 24
+    for name, cls in structs.items():
+        if cls is None:
+            continue
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
