@@ -59,7 +59,7 @@ def parse():
                     help="input encoding resident in HBM")
     ap.add_argument("--second-set", default="pairs100_e2_5m",
                     help="the configuration's second set (E = 2 %%), timed the same way after "
-                         "the main workload; empty: skip")
+                         "the main workload; 'none' or empty: skip")
     ap.add_argument("--other-configs", type=int, default=1,
                     help="also time the uneven (2M pairs, autotuned) and long-read (100k pairs, "
                          "score-only and CIGAR) configurations once each (0: skip)")
@@ -396,7 +396,7 @@ def main():
     # the second set of the configuration (5 M pairs of 100 bp at E = 2 %),
     # tuned and timed the same way; reported beside the headline
     second = None
-    if args.second_set and args.second_set != args.workload:
+    if args.second_set not in ("", "none") and args.second_set != args.workload:
         log(f"second set: {args.second_set}")
         del dev, pat, txt, pairs, scores, runs, offsets
         b2 = synth.workload(args.second_set, args.pairs)
