@@ -64,9 +64,14 @@ def _load():
         i64 = ctypes.c_int64
         lib.oracle_align.argtypes = [p, i, p, i, i, i, i, i, p, p, i64, p, p]
         lib.oracle_align.restype = i
+        lib.oracle_align_ends.argtypes = [p, i, p, i, i, i, i, i, i, i, i, i, p, p, i64, p, p]
+        lib.oracle_align_ends.restype = i
         lib.oracle_align_batch.argtypes = [p, p, p, p, p, p, i64, i, i, i, i, p, p, i64, p, p,
                                            i, p]
         lib.oracle_align_batch.restype = i
+        lib.oracle_align_batch_ends.argtypes = [p, p, p, p, p, p, i64, i, i, i, i, i, i, i, i, p,
+                                                p, i64, p, p, i, p]
+        lib.oracle_align_batch_ends.restype = i
         lib.oracle_pack2bit.argtypes = [p, i64, p, i64]
         lib.oracle_pack2bit.restype = i64
         _lib = lib
@@ -78,21 +83,25 @@ def _buf(b: bytes):
 
 
 def align(pattern: bytes, text: bytes, penalties=(4, 6, 2), cigar: bool = True,
-          with_stats: bool = False):
+          with_stats: bool = False, ends=None):
     """Align one pair.  Returns (score, runs) or (score, runs, stats).
 
     runs is a list of ``len << 4 | op`` words (empty in score-only mode).
+    ends = (pattern_begin_free, pattern_end_free, text_begin_free,
+    text_end_free) selects ends-free alignment (None: global).
     """
     lib = _load()
     x, o, e = penalties
+    pb, pe, tb, te = (0, 0, 0, 0) if ends is None else ends
     n, m = len(pattern), len(text)
     cap = n + m + 1
     runs = (ctypes.c_uint32 * cap)()
     score = ctypes.c_int32(0)
     nr = ctypes.c_int64(0)
     st = Stats()
-    rc = lib.oracle_align(_buf(pattern), n, _buf(text), m, x, o, e, int(cigar),
-                          ctypes.byref(score), runs, cap, ctypes.byref(nr), ctypes.byref(st))
+    rc = lib.oracle_align_ends(_buf(pattern), n, _buf(text), m, x, o, e, pb, pe, tb, te,
+                               int(cigar), ctypes.byref(score), runs, cap, ctypes.byref(nr),
+                               ctypes.byref(st))
     if rc != 0:
         raise ValueError(f"oracle_align failed with status {rc}")
     out = [int(runs[j]) for j in range(nr.value)]
@@ -110,10 +119,12 @@ class BatchResult:
 
 
 def align_batch(batch, penalties=(4, 6, 2), cigar: bool = True, threads: int = 1,
-                slot: int | None = None) -> BatchResult:
-    """Align every pair of a ``synth.Batch`` on `threads` host threads."""
+                slot: int | None = None, ends=None) -> BatchResult:
+    """Align every pair of a ``synth.Batch`` on `threads` host threads
+    (`ends` as in ``align``)."""
     lib = _load()
     x, o, e = penalties
+    pb, pe, tb, te = (0, 0, 0, 0) if ends is None else ends
     N = len(batch)
     if slot is None:
         slot = int((batch.p_len.astype(np.int64) + batch.t_len.astype(np.int64)).max(initial=0)) + 1
@@ -123,10 +134,10 @@ def align_batch(batch, penalties=(4, 6, 2), cigar: bool = True, threads: int = 1
     status = np.zeros(N, dtype=np.int32)
     runs = np.zeros(N * slot if cigar else 1, dtype=np.uint32)
     st = Stats()
-    rc = lib.oracle_align_batch(batch.patterns.ctypes.data, batch.p_off.ctypes.data,
+    rc = lib.oracle_align_batch_ends(batch.patterns.ctypes.data, batch.p_off.ctypes.data,
                                 batch.p_len.ctypes.data, batch.texts.ctypes.data,
                                 batch.t_off.ctypes.data, batch.t_len.ctypes.data, N, x, o, e,
-                                int(cigar), scores.ctypes.data,
+                                pb, pe, tb, te, int(cigar), scores.ctypes.data,
                                 runs.ctypes.data if cigar else None, slot, nruns.ctypes.data,
                                 status.ctypes.data, threads, ctypes.byref(st))
     if rc != 0:

@@ -33,6 +33,26 @@
  *   - the alignment ends at the first s with M_s[m-n] == m   (WFA, termination)
  *   - the alignment is read back from the kept wavefronts    (WFA, backtrace)
  *
+ * Ends-free variant (global alignment is the case of four zeros).  With
+ * pattern_begin_free pb, pattern_end_free pe, text_begin_free tb and
+ * text_end_free te (each clipped to the sequence's length), an alignment
+ * may leave unaligned at no cost a prefix of at most pb pattern bases or
+ * one of at most tb text bases, and a suffix of at most pe pattern bases or
+ * one of at most te text bases:
+ *
+ *   score = min over the allowed (start, end) of the global score of
+ *           P[vb..ve) against T[hb..he), where (vb, hb) is (v, 0) with
+ *           v <= pb or (0, h) with h <= tb, and (ve, he) is (v, m) with
+ *           v >= n - pe or (n, h) with h >= m - te.
+ *
+ * In wavefront terms: s = 0 holds M_0[k] = max(k, 0) for k in [-pb, tb]
+ * (each extended); the alignment ends at the first s holding an M cell on
+ * the last text column with v >= n - pe or on the last pattern row with
+ * h >= m - te.  Readings: of several such cells the one on the lowest
+ * diagonal ends the alignment; the CIGAR spells both sequences whole, the
+ * free prefix and suffix as I (text) or D (pattern) runs that cost nothing
+ * (a free run and an adjacent paid gap of the same op share one run).
+ *
  * Readings where WFA leaves a choice (each is listed with its reason in the
  * design notes of the repository):
  *   - a candidate offset c on diagonal k is admissible only if it is a real
@@ -158,22 +178,56 @@ static int extend(const uint8_t *P, int n, const uint8_t *T, int m, int k, int h
 
 enum { OP_M = 0, OP_X = 1, OP_I = 2, OP_D = 3 };
 
+/* Whether the M cell at offset h on diagonal k may end an ends-free
+ * alignment: on the last text column with at most pe pattern bases left, or
+ * on the last pattern row with at most te text bases left. */
+static int is_end_cell(int k, int h, int n, int m, int pe, int te) {
+    int v = h - k;
+    return (h == m && v >= n - pe) || (v == n && h >= m - te);
+}
+
+/* Lowest diagonal of wavefront w whose M cell ends the alignment, or
+ * INT_MIN if none does. */
+static int end_diagonal(const wavefront *w, int n, int m, int pe, int te) {
+    for (int k = w->lo; k <= w->hi; k++) {
+        int h = w->M[k - w->lo];
+        if (h != OFF_NULL && is_end_cell(k, h, n, m, pe, te)) return k;
+    }
+    return INT_MIN;
+}
+
+static int clip(int v, int hi) { return v < hi ? v : hi; }
+
 int oracle_align(const uint8_t *P, int n, const uint8_t *T, int m,
                  int x, int o, int e, int want_cigar,
                  int32_t *score_out, uint32_t *runs, int64_t runs_cap, int64_t *nruns_out,
                  oracle_stats *st) {
+    return oracle_align_ends(P, n, T, m, x, o, e, 0, 0, 0, 0, want_cigar, score_out, runs,
+                             runs_cap, nruns_out, st);
+}
+
+int oracle_align_ends(const uint8_t *P, int n, const uint8_t *T, int m,
+                      int x, int o, int e, int pb, int pe, int tb, int te, int want_cigar,
+                      int32_t *score_out, uint32_t *runs, int64_t runs_cap, int64_t *nruns_out,
+                      oracle_stats *st) {
     if (x <= 0 || e <= 0 || o < 0 || n < 0 || m < 0) return ORACLE_E_INVAL;
+    if (pb < 0 || pe < 0 || tb < 0 || te < 0) return ORACLE_E_INVAL;
+    pb = clip(pb, n);
+    pe = clip(pe, n);
+    tb = clip(tb, m);
+    te = clip(te, m);
     wf_table t = {NULL, 0};
     int status = ORACLE_OK;
     int keep = x > o + e ? x : o + e; /* score-only mode: how far back sources reach */
-    int target_k = m - n;
-    int S = -1;
+    int S = -1, end_k = INT_MIN;
 
-    /* s = 0 */
-    if (grow(&t, 0) || wf_alloc(&t.wf[0], 0, 0)) { status = ORACLE_E_NOMEM; goto done; }
-    t.wf[0].M[0] = extend(P, n, T, m, 0, 0, st);
-    if (st) { st->cells += 1; st->steps += 1; }
-    if (target_k == 0 && t.wf[0].M[0] == m) S = 0;
+    /* s = 0: the free starts, each extended */
+    if (grow(&t, 0) || wf_alloc(&t.wf[0], -pb, tb)) { status = ORACLE_E_NOMEM; goto done; }
+    for (int k = -pb; k <= tb; k++)
+        t.wf[0].M[k + pb] = extend(P, n, T, m, k, k > 0 ? k : 0, st);
+    if (st) { st->cells += pb + tb + 1; st->steps += 1; }
+    end_k = end_diagonal(&t.wf[0], n, m, pe, te);
+    if (end_k != INT_MIN) S = 0;
 
     for (int s = 1; S < 0; s++) {
         if (grow(&t, s)) { status = ORACLE_E_NOMEM; goto done; }
@@ -217,7 +271,8 @@ int oracle_align(const uint8_t *P, int n, const uint8_t *T, int m,
             int i = k - lo;
             if (w->M[i] != OFF_NULL) w->M[i] = extend(P, n, T, m, k, w->M[i], st);
         }
-        if (target_k >= lo && target_k <= hi && w->M[target_k - lo] == m) S = s;
+        end_k = end_diagonal(w, n, m, pe, te);
+        if (end_k != INT_MIN) S = s;
         if (!want_cigar && s - keep - 1 >= 0 && s - keep - 1 < t.cap) wf_free(&t.wf[s - keep - 1]);
     }
     *score_out = S;
@@ -228,14 +283,17 @@ int oracle_align(const uint8_t *P, int n, const uint8_t *T, int m,
         uint8_t *ops = (uint8_t *)malloc((size_t)cap);
         int64_t nops = 0;
         if (!ops) { status = ORACLE_E_NOMEM; goto done; }
-        int s = S, k = target_k, h = m;
+        int s = S, k = end_k, h = wf_get(&t, S, 'M', end_k);
+        /* the free suffix (ops are collected last to first) */
+        for (int j = h - k; j < n; j++) ops[nops++] = OP_D;
+        for (int j = h; j < m; j++) ops[nops++] = OP_I;
         char comp = 'M';
         for (;;) {
             if (comp == 'M') {
                 int h0;
                 int xx = OFF_NULL, Iv = OFF_NULL, Dv = OFF_NULL;
                 if (s == 0) {
-                    h0 = 0; /* the only cell at s = 0 is M_0[0] before extension */
+                    h0 = k > 0 ? k : 0; /* M_0[k] before extension */
                 } else {
                     xx = wf_get(&t, s - x, 'M', k);
                     xx = xx == OFF_NULL ? OFF_NULL : xx + 1;
@@ -246,7 +304,12 @@ int oracle_align(const uint8_t *P, int n, const uint8_t *T, int m,
                 }
                 for (int j = 0; j < h - h0; j++) ops[nops++] = OP_M;
                 h = h0;
-                if (s == 0) break;
+                if (s == 0) {
+                    /* the free prefix */
+                    for (int j = 0; j < k; j++) ops[nops++] = OP_I;
+                    for (int j = 0; j < -k; j++) ops[nops++] = OP_D;
+                    break;
+                }
                 if (xx != OFF_NULL && xx == h0) {
                     ops[nops++] = OP_X;
                     s -= x;
@@ -310,6 +373,7 @@ typedef struct {
     const uint64_t *poff, *toff;
     const uint32_t *plen, *tlen;
     int x, o, e, want_cigar;
+    int pb, pe, tb, te;
     int32_t *scores;
     uint32_t *runs;    /* slot-strided: pair i writes runs[i * slot ...] */
     int64_t slot;
@@ -323,9 +387,10 @@ static void *run_job(void *arg) {
     job_t *j = (job_t *)arg;
     for (int64_t i = j->begin; i < j->end; i++) {
         int64_t nr = 0;
-        int rc = oracle_align(j->pbuf + j->poff[i], (int)j->plen[i], j->tbuf + j->toff[i],
-                              (int)j->tlen[i], j->x, j->o, j->e, j->want_cigar, &j->scores[i],
-                              j->runs ? j->runs + i * j->slot : NULL, j->slot, &nr, &j->st);
+        int rc = oracle_align_ends(j->pbuf + j->poff[i], (int)j->plen[i], j->tbuf + j->toff[i],
+                                   (int)j->tlen[i], j->x, j->o, j->e, j->pb, j->pe, j->tb, j->te,
+                                   j->want_cigar, &j->scores[i],
+                                   j->runs ? j->runs + i * j->slot : NULL, j->slot, &nr, &j->st);
         if (j->nruns) j->nruns[i] = nr;
         if (j->status) j->status[i] = rc;
     }
@@ -337,6 +402,15 @@ int oracle_align_batch(const uint8_t *pbuf, const uint64_t *poff, const uint32_t
                        int64_t count, int x, int o, int e, int want_cigar,
                        int32_t *scores, uint32_t *runs, int64_t slot, int64_t *nruns,
                        int32_t *status, int threads, oracle_stats *st) {
+    return oracle_align_batch_ends(pbuf, poff, plen, tbuf, toff, tlen, count, x, o, e, 0, 0, 0,
+                                   0, want_cigar, scores, runs, slot, nruns, status, threads, st);
+}
+
+int oracle_align_batch_ends(const uint8_t *pbuf, const uint64_t *poff, const uint32_t *plen,
+                            const uint8_t *tbuf, const uint64_t *toff, const uint32_t *tlen,
+                            int64_t count, int x, int o, int e, int pb, int pe, int tb, int te,
+                            int want_cigar, int32_t *scores, uint32_t *runs, int64_t slot,
+                            int64_t *nruns, int32_t *status, int threads, oracle_stats *st) {
     if (threads < 1) threads = 1;
     if (threads > 1024) threads = 1024;
     job_t *jobs = (job_t *)calloc((size_t)threads, sizeof(job_t));
@@ -346,6 +420,7 @@ int oracle_align_batch(const uint8_t *pbuf, const uint64_t *poff, const uint32_t
         job_t *j = &jobs[t];
         j->pbuf = pbuf; j->tbuf = tbuf; j->poff = poff; j->toff = toff;
         j->plen = plen; j->tlen = tlen; j->x = x; j->o = o; j->e = e;
+        j->pb = pb; j->pe = pe; j->tb = tb; j->te = te;
         j->want_cigar = want_cigar; j->scores = scores; j->runs = runs; j->slot = slot;
         j->nruns = nruns; j->status = status;
         j->begin = count * t / threads;

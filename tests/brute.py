@@ -219,3 +219,81 @@ def check_cigar(P: bytes, T: bytes, runs, x: int, o: int, e: int):
             v += 1
     assert v == len(P) and h == len(T), "CIGAR does not consume both sequences"
     return alignment_cost(P, T, ops, x, o, e)
+
+
+# ---- ends-free alignment ------------------------------------------------------
+# At most pb leading / pe trailing pattern bases, or tb leading / te trailing
+# text bases, may stay unaligned at no cost; `ends` = (pb, pe, tb, te), each
+# clipped to its sequence's length.  (0, 0, 0, 0) is global alignment.
+
+def _clip_ends(n: int, m: int, ends):
+    pb, pe, tb, te = ends
+    return min(pb, n), min(pe, n), min(tb, m), min(te, m)
+
+
+def ends_free_by_subpairs(P: bytes, T: bytes, x: int, o: int, e: int, ends, global_score):
+    """The definition written out: the least global score, over every allowed
+    start (v, 0) with v <= pb or (0, h) with h <= tb and every allowed end
+    (v, m) with v >= n - pe or (n, h) with h >= m - te, of the pair clipped
+    to that start and end.  `global_score(P, T, x, o, e)` scores a pair."""
+    n, m = len(P), len(T)
+    pb, pe, tb, te = _clip_ends(n, m, ends)
+    starts = {(v, 0) for v in range(pb + 1)} | {(0, h) for h in range(tb + 1)}
+    stops = {(v, m) for v in range(n - pe, n + 1)} | {(n, h) for h in range(m - te, m + 1)}
+    best = INF
+    for vb, hb in starts:
+        for ve, he in stops:
+            if ve >= vb and he >= hb:
+                best = min(best, global_score(P[vb:ve], T[hb:he], x, o, e))
+    return int(best)
+
+
+def gotoh_ends(P: bytes, T: bytes, x: int, o: int, e: int, ends) -> int:
+    """Gotoh's three-state DP with free boundary cells: every allowed start
+    cell holds cost 0 in the diagonal state (a fresh start: a gap after it
+    opens), and the score is the least cost over the allowed end cells."""
+    n, m = len(P), len(T)
+    pb, pe, tb, te = _clip_ends(n, m, ends)
+    Dg = [[INF] * (m + 1) for _ in range(n + 1)]
+    Ig = [[INF] * (m + 1) for _ in range(n + 1)]
+    Dl = [[INF] * (m + 1) for _ in range(n + 1)]
+    for v in range(n + 1):
+        for h in range(m + 1):
+            if (v == 0 and h <= tb) or (h == 0 and v <= pb):
+                Dg[v][h] = 0
+            if v > 0 and h > 0:
+                sub = 0 if P[v - 1] == T[h - 1] else x
+                Dg[v][h] = min(Dg[v][h],
+                               min(Dg[v - 1][h - 1], Ig[v - 1][h - 1], Dl[v - 1][h - 1]) + sub)
+            if h > 0:
+                Ig[v][h] = min(Dg[v][h - 1] + o + e, Ig[v][h - 1] + e, Dl[v][h - 1] + o + e)
+            if v > 0:
+                Dl[v][h] = min(Dg[v - 1][h] + o + e, Ig[v - 1][h] + o + e, Dl[v - 1][h] + e)
+    cells = {(v, m) for v in range(n - pe, n + 1)} | {(n, h) for h in range(m - te, m + 1)}
+    return int(min(min(Dg[v][h], Ig[v][h], Dl[v][h]) for v, h in cells))
+
+
+def check_cigar_ends(P: bytes, T: bytes, runs, x: int, o: int, e: int, ends) -> int:
+    """Validate a run list against both sequences (as check_cigar) and return
+    its ends-free cost: a leading I (D) run is free for up to tb (pb) bases,
+    a trailing I (D) run for up to te (pe) bases, and what is left of such a
+    run is an ordinary gap."""
+    check_cigar(P, T, runs, 0, 0, 1)  # spelling and run rules only
+    n, m = len(P), len(T)
+    pb, pe, tb, te = _clip_ends(n, m, ends)
+    ops = runs_to_ops(runs)
+    vb = hb = 0
+    lead = len(ops) - len(ops.lstrip(ops[:1])) if ops else 0
+    if ops[:1] == "I":
+        hb = min(lead, tb)
+    elif ops[:1] == "D":
+        vb = min(lead, pb)
+    ops = ops[hb + vb:]
+    ve, he = n, m
+    trail = len(ops) - len(ops.rstrip(ops[-1:])) if ops else 0
+    if ops[-1:] == "I":
+        he = m - min(trail, te)
+    elif ops[-1:] == "D":
+        ve = n - min(trail, pe)
+    ops = ops[: len(ops) - (n - ve) - (m - he)]
+    return alignment_cost(P[vb:ve], T[hb:he], ops, x, o, e)

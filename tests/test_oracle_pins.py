@@ -9,6 +9,10 @@
   mismatches, re-scores to the reported optimum),
 * equality with the Gotoh traceback where the optimum is unique,
 * symmetry and the planted-edit upper bound on generated read pairs,
+* ends-free alignment: the definition (least global score over the allowed
+  clipped sub-pairs) by enumeration and by the pinned Gotoh DP, a Gotoh DP
+  with free boundary cells, closed forms (semi-global, overlaps) and the
+  symmetry of swapping the sequences,
 * planted mistakes: mutants of the oracle built on the CPU must fail the
   pins above.
 """
@@ -171,6 +175,87 @@ def test_pack2bit_definition(oracle_lib):
         oracle_lib.pack2bit(b"ACNT")
 
 
+# ---- ends-free alignment -----------------------------------------------------
+# (pattern_begin_free, pattern_end_free, text_begin_free, text_end_free)
+ENDS_SHORT = [(1, 0, 0, 1), (0, 2, 2, 0), (3, 3, 3, 3), (0, 0, 9, 9), (9, 9, 0, 0), (1, 2, 0, 0)]
+
+
+def _gotoh_score(P, T, x, o, e):
+    return brute.gotoh(P, T, x, o, e)[0]
+
+
+def _enum_score(P, T, x, o, e):
+    return brute.enumerate_costs(P, T, x, o, e)[0]
+
+
+@pytest.mark.parametrize("ends", ENDS_SHORT)
+def test_ends_free_exhaustive_short(oracle_lib, ends):
+    """Every pair of strings over {A, C} of up to 3 bases: the oracle's
+    ends-free score is the definition's (least global score over the
+    allowed starts and ends, each global score by the pinned Gotoh DP), and
+    its CIGAR spells both sequences and re-scores to it."""
+    for pen in [(4, 6, 2), (1, 0, 1), (3, 1, 4)]:
+        for P in strings(b"AC", 3):
+            for T in strings(b"AC", 3):
+                s, runs = oracle_lib.align(P, T, pen, ends=ends)
+                assert s == brute.ends_free_by_subpairs(P, T, *pen, ends, _gotoh_score), (P, T)
+                assert brute.check_cigar_ends(P, T, runs, *pen, ends) == s, (P, T, runs)
+
+
+def test_ends_free_dp_matches_definition():
+    """The free-boundary DP equals the definition evaluated by exhaustive
+    enumeration of alignments (no DP) on random tiny pairs."""
+    rng = np.random.default_rng(17)
+    for _ in range(150):
+        P = bytes(rng.choice(list(b"ACG"), int(rng.integers(0, 5))).astype(np.uint8))
+        T = bytes(rng.choice(list(b"ACG"), int(rng.integers(0, 5))).astype(np.uint8))
+        ends = tuple(int(v) for v in rng.integers(0, 5, 4))
+        pen = PENALTIES[int(rng.integers(0, len(PENALTIES)))]
+        assert brute.gotoh_ends(P, T, *pen, ends) == brute.ends_free_by_subpairs(
+            P, T, *pen, ends, _enum_score), (P, T, pen, ends)
+
+
+@pytest.mark.parametrize("pen", [(4, 6, 2), (1, 0, 1), (2, 3, 1), (7, 2, 3)])
+def test_ends_free_random_vs_dp(oracle_lib, synth_lib, pen):
+    """Random related pairs of up to 40 bases with random free ends: score
+    equal to the free-boundary DP, CIGAR re-scores to it; all-zero ends give
+    the global alignment exactly (score and CIGAR)."""
+    rng = np.random.default_rng(hash(pen) % 1000)
+    for P, T in synth_lib.random_pairs(rng, 60, 40):
+        ends = tuple(int(v) for v in rng.integers(0, 12, 4))
+        s, runs = oracle_lib.align(P, T, pen, ends=ends)
+        assert s == brute.gotoh_ends(P, T, *pen, ends), (P, T, ends)
+        assert brute.check_cigar_ends(P, T, runs, *pen, ends) == s
+        assert oracle_lib.align(P, T, pen, ends=(0, 0, 0, 0)) == oracle_lib.align(P, T, pen)
+
+
+def test_ends_free_closed_forms(oracle_lib):
+    """Semi-global and overlap cases whose answer is known outright."""
+    T = b"GGATTACACCGT"
+    # the pattern occurs in the text: free text ends cost nothing
+    s, runs = oracle_lib.align(b"TTACA", T, ends=(0, 0, len(T), len(T)))
+    assert s == 0 and oracle_lib.cigar_string(runs) == "3I5M4I"
+    # a free text prefix shorter than the offset: the rest is a paid gap
+    s, runs = oracle_lib.align(b"TTACA", b"GGATTACA", ends=(0, 0, 1, 0))
+    assert s == 6 + 2 * 2 and oracle_lib.cigar_string(runs) == "3I5M"
+    # suffix of the pattern overlaps a prefix of the text
+    s, runs = oracle_lib.align(b"CCCCACGT", b"ACGTGGGG", ends=(4, 0, 0, 4))
+    assert s == 0 and oracle_lib.cigar_string(runs) == "4D4M4I"
+    # free ends on both sides of an empty pattern
+    s, runs = oracle_lib.align(b"", b"ACGT", ends=(0, 0, 2, 2))
+    assert s == 0 and oracle_lib.cigar_string(runs) == "4I"
+    s, runs = oracle_lib.align(b"", b"ACGTA", ends=(0, 0, 2, 2))
+    assert s == 6 + 2 and oracle_lib.cigar_string(runs) == "5I"
+    # symmetry: swapping the sequences swaps the free pattern and text ends
+    rng = np.random.default_rng(5)
+    for P, T in [(bytes(rng.choice(list(b"ACGT"), 25).astype(np.uint8)),
+                  bytes(rng.choice(list(b"ACGT"), 31).astype(np.uint8))) for _ in range(30)]:
+        for pb, pe, tb, te in [(3, 0, 0, 5), (0, 7, 2, 0), (4, 4, 4, 4)]:
+            a = oracle_lib.align(P, T, ends=(pb, pe, tb, te))[0]
+            b = oracle_lib.align(T, P, ends=(tb, te, pb, pe))[0]
+            assert a == b
+
+
 # ---- planted mistakes ------------------------------------------------------
 # Each mutant changes one line of the oracle's arithmetic the way a plausible
 # slip would; the pins must reject every one of them.
@@ -179,7 +264,14 @@ MUTANTS = {
     "no_open_cost": ("int sx = s - x, so = s - o - e, se = s - e;", "int sx = s - x, so = s - e, se = s - e;"),
     "D_extends_from_I": ("int d = wf_get(&t, se, 'D', k + 1);", "int d = wf_get(&t, se, 'I', k + 1);"),
     "extend_skips_first": ("int v = h - k;\n    int run = 0;", "int v = h - k + 1;\n    int run = 0;"),
-    "target_transposed": ("int target_k = m - n;", "int target_k = n - m;"),
+    "end_row_transposed": ("(v == n && h >= m - te)", "(v == m && h >= m - te)"),
+    "end_column_uses_te": ("(h == m && v >= n - pe)", "(h == m && v >= n - te)"),
+    "free_start_offset_zero": ("extend(P, n, T, m, k, k > 0 ? k : 0, st)",
+                               "extend(P, n, T, m, k, 0 > k ? k : 0, st)"),
+    "free_prefix_op_swapped": ("for (int j = 0; j < k; j++) ops[nops++] = OP_I;",
+                               "for (int j = 0; j < k; j++) ops[nops++] = OP_D;"),
+    "free_suffix_op_swapped": ("for (int j = h - k; j < n; j++) ops[nops++] = OP_D;",
+                               "for (int j = h - k; j < n; j++) ops[nops++] = OP_I;"),
     "mismatch_no_advance": ("xx = xx == OFF_NULL ? OFF_NULL : xx + 1;\n            int Mv",
                             "xx = xx == OFF_NULL ? OFF_NULL : xx;\n            int Mv"),
     "backtrace_D_moves_h": ("                k += 1;\n            }\n        }", "                k += 1;\n                h -= 1;\n            }\n        }"),
@@ -208,6 +300,7 @@ def _mutant_caught(so_path) -> bool:
     lib = ctypes.CDLL(so_path)
     p, i, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     lib.oracle_align.argtypes = [p, i, p, i, i, i, i, i, p, p, i64, p, p]
+    lib.oracle_align_ends.argtypes = [p, i, p, i, i, i, i, i, i, i, i, i, p, p, i64, p, p]
     rng = np.random.default_rng(3)
     cases = [(a, b) for a in strings(b"ACG", 3) for b in strings(b"ACG", 3)]
     cases += [(bytes(rng.choice(list(b"ACGT"), 30).astype(np.uint8)),
@@ -229,6 +322,25 @@ def _mutant_caught(so_path) -> bool:
                     return True
             except AssertionError:
                 return True
+    # ends-free cases
+    for pen in [(4, 6, 2), (1, 0, 1)]:
+        for ends in ENDS_SHORT:
+            for P, T in cases[:200:3] + cases[-6:]:
+                n, m = len(P), len(T)
+                runs = (ctypes.c_uint32 * (n + m + 1))()
+                sc = ctypes.c_int32()
+                nr = ctypes.c_int64()
+                rc = lib.oracle_align_ends(ctypes.create_string_buffer(P, n + 1), n,
+                                           ctypes.create_string_buffer(T, m + 1), m, *pen, *ends,
+                                           1, ctypes.byref(sc), runs, n + m + 1, ctypes.byref(nr),
+                                           None)
+                if rc != 0 or sc.value != brute.gotoh_ends(P, T, *pen, ends):
+                    return True
+                try:
+                    if brute.check_cigar_ends(P, T, list(runs)[:nr.value], *pen, ends) != sc.value:
+                        return True
+                except AssertionError:
+                    return True
     return False
 
 
