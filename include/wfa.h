@@ -134,6 +134,24 @@ typedef struct {
                                  of the batch, within [262144, 2097152] */
 } wfa_options;
 
+/* Ends-free alignment.  Up to pattern_begin_free leading pattern bases OR
+ * up to text_begin_free leading text bases, and up to pattern_end_free
+ * trailing pattern bases OR up to text_end_free trailing text bases, may
+ * stay unaligned at no cost (each bound is clipped to its sequence's length
+ * per pair).  The score is the least gap-affine score over the allowed
+ * starts and ends; the CIGAR still spells both sequences whole, the free
+ * prefix and suffix as I (text) or D (pattern) runs (a free run and a paid
+ * gap of the same op next to it share one run).  Of several optimal end
+ * cells the one on the lowest diagonal (h - v) is taken.  All four zero:
+ * global alignment.  Semi-global alignment of a read inside a reference is
+ * text_begin_free = text_end_free = the text length. */
+typedef struct {
+    uint32_t pattern_begin_free;
+    uint32_t pattern_end_free;
+    uint32_t text_begin_free;
+    uint32_t text_end_free;
+} wfa_ends_free;
+
 /* Counters of the last wfa_align_batch call on a context. */
 typedef struct {
     uint64_t pairs;              /* pairs aligned                                    */
@@ -180,6 +198,12 @@ void wfa_ctx_destroy(wfa_ctx *ctx);
 
 /* Set tuning knobs for later calls (NULL restores the defaults). */
 int wfa_set_options(wfa_ctx *ctx, const wfa_options *opt);
+
+/* Select ends-free alignment (wfa_ends_free) for later wfa_align_batch and
+ * wfa_autotune calls on the context; NULL or all zero selects global
+ * alignment (the default).  Bounds above WFA_MAX_LENGTH are WFA_E_INVAL.
+ * The server (wfa_server_*) always aligns globally. */
+int wfa_set_ends_free(wfa_ctx *ctx, const wfa_ends_free *ends);
 
 /* Align num_pairs pairs.
  *   patterns, texts   sequence buffers in `enc` and `mem`

@@ -32,7 +32,7 @@ WFA_OP_MATCH, WFA_OP_MISMATCH, WFA_OP_INS, WFA_OP_DEL = 0, 1, 2, 3
 WFA_MAX_LENGTH = 1 << 26
 
 EXPORTED = [
-    "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_align_batch",
+    "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_set_ends_free", "wfa_align_batch",
     "wfa_copy_last_cigars", "wfa_host_alloc", "wfa_host_free", "wfa_pack2bit", "wfa_autotune",
     "wfa_last_stats", "wfa_strerror",
     "wfa_server_open", "wfa_server_submit", "wfa_server_poll", "wfa_server_release",
@@ -54,6 +54,11 @@ class wfa_options(ctypes.Structure):
                 ("bucket", ctypes.c_int32), ("general_pairs", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32),
                 ("host_chunk_pairs", ctypes.c_int32)]
+
+
+class wfa_ends_free(ctypes.Structure):
+    _fields_ = [("pattern_begin_free", ctypes.c_uint32), ("pattern_end_free", ctypes.c_uint32),
+                ("text_begin_free", ctypes.c_uint32), ("text_end_free", ctypes.c_uint32)]
 
 
 class wfa_stats(ctypes.Structure):
@@ -119,6 +124,7 @@ def _load():
         "wfa_ctx_create": ([ctypes.c_int, sz, ctypes.POINTER(p)], ctypes.c_int),
         "wfa_ctx_destroy": ([p], None),
         "wfa_set_options": ([p, ctypes.POINTER(wfa_options)], ctypes.c_int),
+        "wfa_set_ends_free": ([p, ctypes.POINTER(wfa_ends_free)], ctypes.c_int),
         "wfa_align_batch": ([p, p, p, p, sz, ctypes.c_int, ctypes.c_int, wfa_penalties,
                              ctypes.c_int, p, p, sz, p, ctypes.POINTER(sz),
                              ctypes.POINTER(i64), p], ctypes.c_int),
@@ -155,6 +161,7 @@ lib = _load()
 wfa_ctx_create = lib.wfa_ctx_create
 wfa_ctx_destroy = lib.wfa_ctx_destroy
 wfa_set_options = lib.wfa_set_options
+wfa_set_ends_free = lib.wfa_set_ends_free
 wfa_align_batch = lib.wfa_align_batch
 wfa_copy_last_cigars = lib.wfa_copy_last_cigars
 wfa_host_alloc = lib.wfa_host_alloc
@@ -252,6 +259,13 @@ class Aligner:
         rc = wfa_set_options(self.ctx, ctypes.byref(o))
         if rc != WFA_OK:
             raise WFAError(rc, "wfa_set_options")
+
+    def set_ends_free(self, pattern_begin=0, pattern_end=0, text_begin=0, text_end=0):
+        """Ends-free alignment for later calls (all zero: global)."""
+        ef = wfa_ends_free(pattern_begin, pattern_end, text_begin, text_end)
+        rc = wfa_set_ends_free(self.ctx, ctypes.byref(ef))
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_set_ends_free")
 
     def autotune(self, patterns, texts, pairs, n, penalties=(4, 6, 2), cigar=True,
                  encoding=WFA_ASCII, sample_pairs=0, cache_path=None, force=False) -> dict:

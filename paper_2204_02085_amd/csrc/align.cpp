@@ -220,6 +220,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.jobs = ws.jobs.as<uint32_t>();
             g.num_jobs = (uint32_t)nj;
             g.pen = pen;
+            g.ends = e->ends;
             g.cigar = cigar ? 1 : 0;
             g.arena = ws.arena.as<uint8_t>();
             g.slice_bytes = slice;
@@ -354,7 +355,9 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     int schedule = e->opt.schedule ? e->opt.schedule : WFA_SCHED_AUTO;
     int window = e->opt.window ? e->opt.window : auto_window(max_len);
     ShortPlan sp;
-    bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN;
+    const bool global = e->ends.pb == 0 && e->ends.pe == 0 && e->ends.tb == 0 && e->ends.te == 0;
+    bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN &&
+                     global;
     int lanes = 0;
     if (use_short) {
         const int cap = e->opt.step_cap ? e->opt.step_cap : default_cap(pen, window);

@@ -202,6 +202,20 @@ extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
     return WFA_OK;
 }
 
+extern "C" int wfa_set_ends_free(wfa_ctx* ctx, const wfa_ends_free* ends) {
+    if (!ctx) return WFA_E_INVAL;
+    if (!ends) {
+        ctx->ends = Ends{0, 0, 0, 0};
+        return WFA_OK;
+    }
+    if (ends->pattern_begin_free > WFA_MAX_LENGTH || ends->pattern_end_free > WFA_MAX_LENGTH ||
+        ends->text_begin_free > WFA_MAX_LENGTH || ends->text_end_free > WFA_MAX_LENGTH)
+        return WFA_E_INVAL;
+    ctx->ends = Ends{(int)ends->pattern_begin_free, (int)ends->pattern_end_free,
+                     (int)ends->text_begin_free, (int)ends->text_end_free};
+    return WFA_OK;
+}
+
 extern "C" int wfa_last_stats(const wfa_ctx* ctx, wfa_stats* out) {
     if (!ctx || !out) return WFA_E_INVAL;
     *out = ctx->last;

@@ -92,6 +92,7 @@ struct Engine {
     Workspace ws;
     hipEvent_t ev[10] = {};
     wfa_options opt{};
+    wfa::Ends ends{};  // free ends of later calls (all zero: global alignment)
     wfa_stats last{};
     std::vector<GraphEntry> graphs;
     // state kept for wfa_copy_last_cigars

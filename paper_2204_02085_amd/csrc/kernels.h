@@ -39,6 +39,13 @@ struct Pen {
     int pre;       // max(x, oe, e): rows a step reads back
 };
 
+// Ends-free alignment: at most pb / tb leading and pe / te trailing pattern /
+// text bases stay unaligned at no cost (each clipped to its sequence's
+// length per pair); all zero is global alignment.
+struct Ends {
+    int pb, pe, tb, te;
+};
+
 // Arguments of the short-pair kernel (all device pointers).
 struct ShortArgs {
     const PairDesc* pairs;
@@ -74,6 +81,7 @@ struct GeneralArgs {
     const uint32_t* jobs;       // pair index per workgroup
     uint32_t num_jobs;
     Pen pen;
+    Ends ends;
     int cigar;
     uint8_t* arena;             // num_jobs slices of slice_bytes
     uint64_t slice_bytes;

@@ -861,7 +861,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int MAXR = GENERAL_MAX_RING;  // metadata ring (pre + 1 <= MAXR)
     __shared__ RowMeta meta[MAXR];
-    __shared__ int sh_flag;
+    __shared__ int sh_end;  // lowest diagonal whose M cell ends the alignment
     __shared__ int sh_fail;
 
     const uint32_t job = blockIdx.x;
@@ -872,7 +872,9 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     const int tid = threadIdx.x, BT = blockDim.x;
     const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
     const int R = PRE + 1;
-    const int kt = m - n;
+    // free ends of this pair (global alignment: all zero)
+    const int pb = min(a.ends.pb, n), pe = min(a.ends.pe, n);
+    const int tb = min(a.ends.tb, m), te = min(a.ends.te, m);
     unsigned char* slice = a.arena + (uint64_t)job * a.slice_bytes;
     const long long slice_bytes = (long long)a.slice_bytes;
 
@@ -893,7 +895,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     sv.nt32 = 2 * nwt;
     for (int r = tid; r < MAXR; r += BT) meta[r] = RowMeta{0, -1, -1};
     if (tid == 0) {
-        sh_flag = 0;
+        sh_end = INT_MAX;
         sh_fail = 0;
     }
     __syncthreads();
@@ -926,8 +928,9 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         if (s >= E) se = meta[(int)((s - E) % R)];
         int lo, hi;
         bool present;
-        if (s == 0) {
-            lo = hi = 0;
+        if (s == 0) {  // the free starts (diagonal 0 alone in global alignment)
+            lo = -pb;
+            hi = tb;
             present = true;
         } else {
             lo = 1 << 30;
@@ -972,7 +975,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                 int mval;
                 int ival = NUL32, dval = NUL32, rec = 0;
                 if (s == 0) {
-                    mval = 0;
+                    mval = max(k, 0);
                 } else {
                     // candidates as unsigned distances t = L - c below the
                     // diagonal's limit L = min(m, n + k): admissible offsets
@@ -1011,7 +1014,12 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     const int hi4 = (tid & 1) ? rec : other;
                     histF[(k - lo) >> 1] = (uint8_t)(lo4 | (hi4 << 4));
                 }
-                if (k == kt && mval == m) sh_flag = 1;
+                // an end cell: the last text column with at most pe pattern
+                // bases left, or the last pattern row with at most te text
+                // bases left (global: the corner cell on diagonal m - n)
+                if (mval >= 0 && ((mval == m && mval - k >= n - pe) ||
+                                  (mval - k == n && mval >= m - te)))
+                    atomicMin(&sh_end, k);
             };
             // two cells per thread and pass: both cells' sources are read
             // before either is computed, so their latencies overlap
@@ -1031,7 +1039,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             if (a.cigar) table[-s] = RowMeta{lo, hi, hoff};
         }
         __syncthreads();
-        if (sh_flag) {
+        if (sh_end != INT_MAX) {
             S = (int)s;
             break;
         }
@@ -1097,15 +1105,20 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         return (f[(kk - mm.lo) >> 1] >> (((kk - mm.lo) & 1) << 2)) & 15;
     };
     long long s = S;
-    int k = kt, h = m;
+    int k = sh_end, h = getM(S, k);
+    // the free suffix (runs are emitted last to first)
+    emit(OP_D, n - (h - k));
+    emit(OP_I, m - h);
     bool bad = false;
     for (;;) {
         if (s < 0 || h < 0) {
             bad = true;
             break;
         }
-        if (s == 0) {
-            emit(OP_M, h);
+        if (s == 0) {  // M_0[k] = max(k, 0) before extension, after the free prefix
+            emit(OP_M, h - max(k, 0));
+            emit(OP_I, k);
+            emit(OP_D, -k);
             break;
         }
         const int f = getF(s, k);

@@ -1,0 +1,120 @@
+"""GPU parity of ends-free alignment (free pattern / text prefixes and
+suffixes, semi-global read-in-reference alignment) against the CPU oracle:
+scores and CIGAR runs byte for byte, through the C ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_same, say
+
+pytestmark = pytest.mark.gpu
+
+PEN = (4, 6, 2)
+
+
+@pytest.fixture(scope="module")
+def wfa():
+    import paper_2204_02085_amd as w
+
+    return w
+
+
+@pytest.fixture(scope="module")
+def aligner(wfa):
+    al = wfa.Aligner(0)
+    yield al
+    al.close()
+
+
+@pytest.fixture(autouse=True)
+def _defaults(aligner):
+    aligner.set_options()
+    aligner.set_ends_free()
+    yield
+    aligner.set_options()
+    aligner.set_ends_free()
+
+
+def oracle_of(oracle_lib, batch, ends, pen=PEN, cigar=True):
+    return oracle_lib.align_batch(batch, pen, cigar=cigar, threads=8, ends=ends)
+
+
+def flanked(synth_lib, batch, seed, lo, hi):
+    """The batch with random flanks of lo..hi bases added to both ends of
+    every text (a read inside a stretch of reference)."""
+    rng = np.random.default_rng(seed)
+    pairs = []
+    for i in range(len(batch)):
+        p, t = batch.pair(i)
+        a = rng.choice(list(b"ACGT"), int(rng.integers(lo, hi + 1))).astype(np.uint8).tobytes()
+        b = rng.choice(list(b"ACGT"), int(rng.integers(lo, hi + 1))).astype(np.uint8).tobytes()
+        pairs.append((p, a + t + b))
+    return synth_lib.from_pairs(pairs)
+
+
+ENDS = [(5, 0, 0, 5), (0, 10, 10, 0), (20, 20, 20, 20), (3, 7, 2, 9), (100, 100, 0, 0)]
+
+
+@pytest.mark.parametrize("ends", ENDS)
+def test_pairs100_e4(aligner, oracle_lib, synth_lib, ends):
+    say(f"case: ends-free {ends}, pairs100_e4 3000 pairs, CIGAR")
+    b = synth_lib.workload("pairs100_e4_5m", 3000, first=901)
+    aligner.set_ends_free(*ends)
+    got = aligner.align(b, PEN)
+    assert_same(got, oracle_of(oracle_lib, b, ends), b, f"ends {ends}")
+
+
+@pytest.mark.parametrize("ends", [(0, 0, 10_000, 10_000), (0, 0, 30, 30)])
+def test_semi_global_read_in_reference(aligner, oracle_lib, synth_lib, ends):
+    """100 bp reads with 4 % edits inside 110-200 bp of reference."""
+    say(f"case: semi-global {ends}, reads in flanked references")
+    b = flanked(synth_lib, synth_lib.workload("pairs100_e4_5m", 2000, first=55), 7, 5, 50)
+    aligner.set_ends_free(*ends)
+    got = aligner.align(b, PEN)
+    ref = oracle_of(oracle_lib, b, ends)
+    assert_same(got, ref, b, f"semi-global {ends}")
+    if ends[2] >= 50:  # fully free text ends: the read's own edits only
+        assert int(np.median(ref.scores)) <= 40
+
+
+def test_uneven_score_only_and_penalties(aligner, oracle_lib, synth_lib):
+    say("case: ends-free (8, 4, 6, 12), uneven 50-300 bp, score only and (1, 0, 1)")
+    b = synth_lib.workload("uneven50_300_2m", 2000, first=3)
+    ends = (8, 4, 6, 12)
+    aligner.set_ends_free(*ends)
+    sc, _, _ = aligner.align(b, PEN, cigar=False)
+    assert np.array_equal(sc, oracle_of(oracle_lib, b, ends, cigar=False).scores)
+    got = aligner.align(b, (1, 0, 1))
+    assert_same(got, oracle_of(oracle_lib, b, ends, pen=(1, 0, 1)), b, "edit distance ends-free")
+
+
+def test_host_memory_chunks(aligner, oracle_lib, synth_lib):
+    say("case: ends-free (0, 0, 40, 40) through the host-memory pipeline, chunks of 500")
+    b = flanked(synth_lib, synth_lib.workload("pairs100_e2_5m", 2500, first=11), 3, 0, 40)
+    ends = (0, 0, 40, 40)
+    aligner.set_ends_free(*ends)
+    aligner.set_options(host_chunk_pairs=500)
+    got = aligner.align_host(b, PEN)
+    assert_same(got, oracle_of(oracle_lib, b, ends), b, "ends-free host")
+
+
+def test_edge_cases(aligner, oracle_lib, synth_lib):
+    say("case: ends-free edge cases (empty sides, all free, equal sequences)")
+    pairs = [(b"", b""), (b"", b"ACGT"), (b"ACGT", b""), (b"ACGT", b"ACGT"), (b"A", b"C"),
+             (b"ACGTACGT", b"TTTTACGTACGTTTTT"), (b"GGGGACGT", b"ACGTCCCC"),
+             (b"ACGT" * 10, b"TGCA" * 10)]
+    b = synth_lib.from_pairs(pairs)
+    for ends in [(0, 0, 4, 4), (2, 2, 2, 2), (50, 50, 50, 50), (0, 4, 4, 0)]:
+        aligner.set_ends_free(*ends)
+        got = aligner.align(b, PEN)
+        assert_same(got, oracle_of(oracle_lib, b, ends), b, f"edges {ends}")
+
+
+def test_back_to_global(aligner, oracle_lib, synth_lib):
+    """Clearing the free ends restores global alignment on the same context."""
+    say("case: ends-free then global on one context")
+    b = synth_lib.workload("pairs100_e4_5m", 2000, first=5)
+    aligner.set_ends_free(10, 10, 10, 10)
+    aligner.align(b, PEN)
+    aligner.set_ends_free()
+    got = aligner.align(b, PEN)
+    assert_same(got, oracle_lib.align_batch(b, PEN, cigar=True, threads=8), b, "global again")

@@ -55,7 +55,8 @@ def test_pair_descriptor_layout(tmp_path):
     import paper_2204_02085_amd as wfa
 
     structs = {"wfa_pair": None, "wfa_penalties": wfa.wfa_penalties,
-               "wfa_options": wfa.wfa_options, "wfa_stats": wfa.wfa_stats}
+               "wfa_options": wfa.wfa_options, "wfa_stats": wfa.wfa_stats,
+               "wfa_ends_free": wfa.wfa_ends_free}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "wfa.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
