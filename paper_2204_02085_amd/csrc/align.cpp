@@ -354,10 +354,17 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     // ---- plan ------------------------------------------------------------
     int schedule = e->opt.schedule ? e->opt.schedule : WFA_SCHED_AUTO;
     int window = e->opt.window ? e->opt.window : auto_window(max_len);
-    ShortPlan sp;
     const bool global = e->ends.pb == 0 && e->ends.pe == 0 && e->ends.tb == 0 && e->ends.te == 0;
-    bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN &&
-                     global;
+    if (!global && !e->opt.window && window) {
+        // ends-free: the window must hold the free start diagonals -pb .. tb
+        // with room to spare (it is centred between 0 and m - n)
+        const uint32_t reach = std::max(std::min<uint32_t>((uint32_t)e->ends.pb, st.max_p),
+                                        std::min<uint32_t>((uint32_t)e->ends.tb, st.max_t));
+        while (window < 256 && (uint32_t)window < 2 * reach + 16) window *= 2;
+        if ((uint32_t)window < 2 * reach + 16) window = 0;
+    }
+    ShortPlan sp;
+    bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN;
     int lanes = 0;
     if (use_short) {
         const int cap = e->opt.step_cap ? e->opt.step_cap : default_cap(pen, window);
@@ -467,6 +474,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             a.tw = d.tw;
             a.order = bucket ? ws.order.as<uint32_t>() : nullptr;
             a.num = (uint32_t)N;
+            a.ends = e->ends;
             a.queue = &flags->queue;
             a.queue_chunk = queue_chunk;
             a.pen = pen;

@@ -287,6 +287,8 @@ int short_plan(Engine* ctx, const Pen& pen, bool cigar, int window, int lanes, i
     // runs: every non-match op costs at least min(x, e) (in units of g)
     const int minc = std::min(pen.x, pen.e);
     sp->slot_cap = 2 * ((cap / minc) + 1) + 2;
+    // ends-free: a free prefix and a free suffix run
+    if (ctx->ends.pb || ctx->ends.pe || ctx->ends.tb || ctx->ends.te) sp->slot_cap += 2;
     // the I/D rings are free during the backtrace, which stages the runs
     // there (two spare words take the stores of a walk that overflows)
     sp->id_off = (sp->ring * RW * sp->row_bytes + 15) & ~15;

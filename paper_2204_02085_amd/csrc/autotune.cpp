@@ -27,13 +27,17 @@ struct Candidate {
 };
 
 std::string class_key(const char* arch, const wfa_penalties& pen, int mode, uint32_t max_len,
-                      uint32_t max_diff, size_t n) {
+                      uint32_t max_diff, size_t n, const wfa::Ends& ends) {
     // length and length-difference classes on a log2 scale
     auto lg = [](uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; };
     std::ostringstream k;
     k << arch << "/x" << pen.mismatch << "o" << pen.gap_open << "e" << pen.gap_extend << "/"
       << (mode == WFA_CIGAR ? "cigar" : "score") << "/len" << lg(max_len) << "/diff" << lg(max_diff)
       << "/n" << lg((uint32_t)std::min<size_t>(n, 1u << 30));
+    if (ends.pb || ends.pe || ends.tb || ends.te)  // ends-free: the free ends' classes
+        k << "/ends" << lg(std::min<uint32_t>(ends.pb, max_len)) << "."
+          << lg(std::min<uint32_t>(ends.pe, max_len)) << "." << lg(std::min<uint32_t>(ends.tb, max_len))
+          << "." << lg(std::min<uint32_t>(ends.te, max_len));
     return k.str();
 }
 
@@ -131,7 +135,7 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
     std::string a(arch);
     a = a.substr(0, a.find(':'));
-    const std::string key = class_key(a.c_str(), pen, mode, max_len, max_diff, num_pairs);
+    const std::string key = class_key(a.c_str(), pen, mode, max_len, max_diff, num_pairs, ctx->ends);
     if (!force && load_entry(cache_path, key, chosen)) {
         ctx->opt = *chosen;
         return WFA_OK;

@@ -53,6 +53,7 @@ struct ShortArgs {
     const uint64_t* tw;         // packed text words
     const uint32_t* order;      // queue position -> pair index (NULL: identity)
     uint32_t num;               // pairs in the queue
+    Ends ends;                  // free ends (all zero: global alignment)
     uint32_t* queue;            // persistent: next queue position (device counter)
     int queue_chunk;            // rounds of 64/G pairs a wave claims per atomic
     Pen pen;

@@ -430,7 +430,7 @@ struct RowNull<int16_t> {
     static constexpr int value = -16384;
 };
 
-template <int G, int DPL, bool CIGAR, class RowT>
+template <int G, int DPL, bool CIGAR, class RowT, bool ENDS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_short(
     ShortArgs a, int persistent) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -520,11 +520,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const int kt = m - n;
         const int kmin = (kt >> 1) - W / 2;
         const int nwp = (n + 31) >> 5, nwt = (m + 31) >> 5;
+        // ends-free: the pair's free ends (the start diagonals -pbc .. tbc)
+        const int pbc = ENDS ? min(a.ends.pb, n) : 0, pec = ENDS ? min(a.ends.pe, n) : 0;
+        const int tbc = ENDS ? min(a.ends.tb, m) : 0, tec = ENDS ? min(a.ends.te, m) : 0;
         // 0 running, 1 finished or idle, 2 overflow
         int st = active_ok ? 0 : 1;
-        if (active_ok && !(kmin <= 0 && 0 < kmin + W && kmin <= kt && kt < kmin + W &&
-                           nwp + 1 <= a.seq_words && nwt + 1 <= a.seq_words))
-            st = 2;
+        const bool fits = ENDS ? (kmin <= -pbc && tbc < kmin + W)
+                               : (kmin <= 0 && 0 < kmin + W && kmin <= kt && kt < kmin + W);
+        if (active_ok && !(fits && nwp + 1 <= a.seq_words && nwt + 1 <= a.seq_words)) st = 2;
 
         // stage both sequences (zero past their ends)
         for (int w = gl; w < a.seq_words; w += G) {
@@ -557,11 +560,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         // layers this group computes: at first the fewest that hold diagonal 0
         int lay = 1;
         {
-            const int j0 = -kmin;
+            const int j0 = -pbc - kmin, j1 = tbc - kmin;  // the start diagonals
             while (lay < DPL && (j0 < W / 2 - G / 2 - (lay - 1) * (G / 2) ||
-                                 j0 > W / 2 + G / 2 - 1 + (lay - 1) * (G / 2)))
+                                 j1 > W / 2 + G / 2 - 1 + (lay - 1) * (G / 2)))
                 lay++;
         }
+        int endj = W;  // ends-free CIGAR: lowest window index of an end cell
         // Offsets (in cells, + 1 for the pad) of the current M and I/D rows,
         // kept as running sums (scalar adds, no multiplies): M row of step 0
         // after the NULL rows, I/D row of step 0 last in its ring.
@@ -601,6 +605,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             // extend them, store the row and the decision records, and note
             // termination, window-edge and layer-growth conditions.
             bool term = false, edge = false, grow = false;
+            int tj = W;  // lowest window index of this lane's end cells this step
 #pragma unroll
             for (int d = 0; d < DPL; d++) {
                 if (d >= nlay) break;
@@ -608,7 +613,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 const int L = lim[d];
                 int Mv, Iv = NUL, Dv = NUL, rec = 0;
                 if (s == 0) {
-                    Mv = (kmin + j == 0) ? 0 : NUL;
+                    if (ENDS)  // the free starts: M_0[k] = max(k, 0) for -pbc <= k <= tbc
+                        Mv = (kd[d] >= -pbc && kd[d] <= tbc) ? max(kd[d], 0) : NUL;
+                    else
+                        Mv = (kmin + j == 0) ? 0 : NUL;
                 } else {
                     // Candidates as distances t = L - c below the diagonal's limit
                     // L: an admissible offset has 0 <= t <= L, a NULL source
@@ -669,7 +677,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     FL[(s * W + j) >> 1] = (uint8_t)(lo | (hi << 4));  // s <= cap here
                 }
                 const bool live = Mv >= 0;  // M is at least I and D
-                term |= (j == jt) & (Mv == m);
+                if (ENDS) {
+                    // an end cell: the last text column with at most pec
+                    // pattern bases left, or the last pattern row with at
+                    // most tec text bases left
+                    const int vv = Mv - kd[d];
+                    const bool tc = live && ((Mv == m && vv >= n - pec) || (vv == n && Mv >= m - tec));
+                    term |= tc;
+                    if (CIGAR) tj = tc ? min(tj, j) : tj;
+                } else {
+                    term |= (j == jt) & (Mv == m);
+                }
                 if (d == DPL - 1) edge |= bnd & live;
                 if (d < DPL - 1) grow |= (d == lay - 1) & bnd & live;
             }
@@ -680,11 +698,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             if (nlay == DPL) gedge = group_any<G>(__ballot(edge), gshift);
             if (DPL > 1 && growable) ggrow = group_any<G>(__ballot(grow), gshift);
             S = (run && gterm) ? s : S;
+            if (ENDS && CIGAR) endj = (run && gterm) ? tj : endj;
             st = run ? (gterm ? 1 : ((gedge || s >= a.cap) ? 2 : 0)) : st;
             lay += (run && ggrow) ? 1 : 0;
             wave_sync();
         }
 
+        // ends-free CIGAR: the end cell on the group's lowest diagonal
+        if (ENDS && CIGAR) {
+#pragma unroll
+            for (int off = G / 2; off >= 1; off >>= 1) endj = min(endj, __shfl_xor(endj, off));
+        }
         // results: the group leader walks the backtrace
         int cnt = 0;  // runs the group copies out (CIGAR, pair finished here)
         if (active_ok && gl == 0) {
@@ -693,6 +717,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 const int cap_runs = a.slot_cap;
                 int nr = 0, cop = -1, clen = 0;
                 int s = S, k = kt, h = m;  // an M cell and its offset after extension
+                if (ENDS) {
+                    const int je = min(endj, W - 1);
+                    k = kmin + je;
+                    h = RM[(S + 1) * RW + 1 + je];
+                    // the free suffix opens the run list (runs are last to first)
+                    if (n - (h - k) > 0) {
+                        cop = OP_D;
+                        clen = n - (h - k);
+                    } else if (m - h > 0) {
+                        cop = OP_I;
+                        clen = m - h;
+                    }
+                }
                 // Replays the decisions recorded in the forward pass, one event
                 // per iteration: at M cell (s, k) it finds where M came from
                 // (a mismatch from M at s - x, or the end of a gap whose chain
@@ -742,18 +779,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         }
                         op = ms + 1;  // op codes: X=1 I=2 D=3
                     }
+                    const bool last = s == 0;
+                    // ends-free: M_0[k] = max(k, 0) before extension, after a
+                    // free prefix of k text (k > 0) or -k pattern (k < 0) bases
+                    int fop = -1, flen = 0;
+                    if (ENDS && last) {
+                        h0 = max(k, 0);
+                        fop = k > 0 ? OP_I : (k < 0 ? OP_D : -1);
+                        flen = k > 0 ? k : -k;
+                    }
                     const int mlen = h - h0;
                     if (mlen < 0 || hn < 0) {
                         overflow = true;
                         break;
                     }
                     const bool hasM = mlen > 0;
-                    const bool last = s == 0;
+                    if (ENDS && !hasM && fop >= 0 && cop == fop) {  // one run with the prefix
+                        clen += flen;
+                        fop = -1;
+                    }
                     const bool flush = cop >= 0 && (hasM || last || cop != op);
                     STAGE[min(nr, cap_runs + 1)] = ((uint32_t)clen << 4) | (uint32_t)cop;
                     nr += flush ? 1 : 0;
                     STAGE[min(nr, cap_runs + 1)] = ((uint32_t)mlen << 4) | (uint32_t)OP_M;
                     nr += hasM ? 1 : 0;
+                    if (ENDS && fop >= 0) {
+                        STAGE[min(nr, cap_runs + 1)] = ((uint32_t)flen << 4) | (uint32_t)fop;
+                        nr++;
+                    }
                     if (last) break;
                     clen = (flush || hasM) ? L : clen + L;
                     cop = op;
@@ -1392,22 +1445,27 @@ template <int G, int DPL, class RowT>
 static hipError_t launch_short_t(const ShortArgs& a, bool cigar, bool persistent, int bt, int grid,
                                  hipStream_t s) {
     const size_t lds = (size_t)short_groups_per_block(G, bt) * a.group_bytes;
-    if (cigar)
-        hipLaunchKernelGGL((k_short<G, DPL, true, RowT>), dim3(grid), dim3(bt), lds, s, a,
-                           persistent ? 1 : 0);
+    const bool ends = a.ends.pb || a.ends.pe || a.ends.tb || a.ends.te;
+    const int pers = persistent ? 1 : 0;
+    if (cigar && ends)
+        hipLaunchKernelGGL((k_short<G, DPL, true, RowT, true>), dim3(grid), dim3(bt), lds, s, a, pers);
+    else if (cigar)
+        hipLaunchKernelGGL((k_short<G, DPL, true, RowT, false>), dim3(grid), dim3(bt), lds, s, a, pers);
+    else if (ends)
+        hipLaunchKernelGGL((k_short<G, DPL, false, RowT, true>), dim3(grid), dim3(bt), lds, s, a, pers);
     else
-        hipLaunchKernelGGL((k_short<G, DPL, false, RowT>), dim3(grid), dim3(bt), lds, s, a,
-                           persistent ? 1 : 0);
+        hipLaunchKernelGGL((k_short<G, DPL, false, RowT, false>), dim3(grid), dim3(bt), lds, s, a, pers);
     return hipGetLastError();
 }
 
 template <int G, int DPL, class RowT>
 static int occ_t(bool cigar, int bt, int lds) {
+    // the ends-free variants hold the same LDS and launch bounds
     int blocks = 0;
     hipError_t e = cigar ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &blocks, (const void*)k_short<G, DPL, true, RowT>, bt, lds)
+                               &blocks, (const void*)k_short<G, DPL, true, RowT, false>, bt, lds)
                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &blocks, (const void*)k_short<G, DPL, false, RowT>, bt, lds);
+                               &blocks, (const void*)k_short<G, DPL, false, RowT, false>, bt, lds);
     return e == hipSuccess ? blocks : 0;
 }
 

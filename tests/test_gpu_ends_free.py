@@ -118,3 +118,43 @@ def test_back_to_global(aligner, oracle_lib, synth_lib):
     aligner.set_ends_free()
     got = aligner.align(b, PEN)
     assert_same(got, oracle_lib.align_batch(b, PEN, cigar=True, threads=8), b, "global again")
+
+
+SHAPES = [(32, 8), (48, 16), (64, 16), (64, 32), (128, 64), (256, 64)]
+
+
+@pytest.mark.parametrize("window,lanes", SHAPES)
+def test_short_kernel_shapes(aligner, oracle_lib, synth_lib, wfa, window, lanes):
+    """Free ends inside the short kernel's window, for each of several
+    shapes, int8 (100 bp) and int16 (50-300 bp) offsets, score and CIGAR:
+    the short kernel finishes most pairs (windows up to 128) and every
+    result is the oracle's."""
+    ends = (6, 3, 4, 9)
+    aligner.set_ends_free(*ends)
+    for name, count in (("pairs100_e4_5m", 3000), ("uneven50_300_2m", 1500)):
+        say(f"case: ends-free {ends}, short kernel W{window} G{lanes}, {name}")
+        b = synth_lib.workload(name, count, first=77)
+        aligner.set_options(window=window, lanes_per_pair=lanes,
+                            schedule=wfa.WFA_SCHED_PERSISTENT)
+        got = aligner.align(b, PEN)
+        st = aligner.stats()
+        assert_same(got, oracle_of(oracle_lib, b, ends), b, f"W{window} G{lanes} {name}")
+        if name == "pairs100_e4_5m" and window <= 128:  # (a 256-wide CIGAR plan needs more LDS)
+            assert st["short_pairs"] > count // 2, st
+        sc, _, _ = aligner.align(b, PEN, cigar=False)
+        assert np.array_equal(sc, oracle_of(oracle_lib, b, ends, cigar=False).scores)
+
+
+def test_short_kernel_semi_global(aligner, oracle_lib, synth_lib, wfa):
+    """Reads inside references a few bases longer, text ends free: the short
+    kernel holds the free start diagonals; plain and persistent launches."""
+    b = flanked(synth_lib, synth_lib.workload("pairs100_e4_5m", 3000, first=2024), 9, 0, 8)
+    ends = (0, 0, 16, 16)
+    aligner.set_ends_free(*ends)
+    ref = oracle_of(oracle_lib, b, ends)
+    for sched in ("PLAIN", "PERSISTENT", "AUTO"):
+        say(f"case: semi-global short kernel, schedule {sched}")
+        aligner.set_options(schedule=getattr(wfa, "WFA_SCHED_" + sched))
+        got = aligner.align(b, PEN)
+        assert aligner.stats()["short_pairs"] > 1500
+        assert_same(got, ref, b, f"semi-global {sched}")
