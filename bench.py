@@ -415,14 +415,20 @@ def main():
         del p2, t2, d2, o2
 
     # the other configurations, for the record: 2 M uneven pairs (one
-    # persistent bucketed graph-replayed launch, autotuned) and 100 k long
-    # pairs (general kernel), timed after one warm-up call
+    # persistent bucketed graph-replayed launch, autotuned), 100 k long
+    # pairs (general kernel), and the main workload aligned ends-free (up to
+    # 10 bases of either sequence free at either end, autotuned), timed after
+    # one warm-up call
     others = None
     if args.other_configs:
         others = {}
-        for name, count, tune, modes in [("uneven50_300_2m", 2_000_000, True, ("cigar",)),
-                                         ("long1k_10k_100k", 100_000, False, ("score", "cigar"))]:
-            log(f"configuration {name}: {count} pairs")
+        for name, count, tune, modes, ends in [
+                ("uneven50_300_2m", 2_000_000, True, ("cigar",), None),
+                ("long1k_10k_100k", 100_000, False, ("score", "cigar"), None),
+                (args.workload, args.pairs, True, ("cigar",), (10, 10, 10, 10))]:
+            label = name if ends is None else name + "_ends_free_" + "_".join(map(str, ends))
+            log(f"configuration {label}: {count} pairs")
+            al.set_ends_free(*(ends or ()))
             bo = synth.workload(name, count)
             no = len(bo)
             if enc == wfa.WFA_PACKED2:
@@ -455,8 +461,11 @@ def main():
                              "ms_short_kernel": st["ms_align"], "ms_general": st["ms_general"],
                              "options": opts or "defaults"}
                 del oo
-            others[name] = rec
+            if ends is not None:
+                rec["ends_free"] = list(ends)
+            others[label] = rec
             del po, to, do_, bo
+        al.set_ends_free()
 
     serving = None
     if args.serving_requests > 0:
