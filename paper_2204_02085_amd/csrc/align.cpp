@@ -141,7 +141,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult) -> uint64_t {
         const uint64_t nm1 = (uint64_t)n + m + 1;
         uint64_t sl;
-        sl = R * 3 * 4 * nm1;  // the ring of full-width rows
+        sl = (R + 1) * 3 * 4 * (nm1 + 2);  // the ring of full-width rows and a NULL slot
         if (cigar) {
             // history, first guess: a pair at 10 % divergence (score about
             // 0.1 * L times the mean edit cost) keeps ~s'^2 / e' cells of 4.5

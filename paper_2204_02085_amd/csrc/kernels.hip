@@ -914,6 +914,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int MAXR = GENERAL_MAX_RING;  // metadata ring (pre + 1 <= MAXR)
     __shared__ RowMeta meta[MAXR];
+    __shared__ int wr_lo[MAXR], wr_hi[MAXR];  // range of diagonals each ring slot holds
     __shared__ int sh_end;  // lowest diagonal whose M cell ends the alignment
     __shared__ int sh_fail;
 
@@ -946,18 +947,29 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     }
     sv.np32 = 2 * nwp;
     sv.nt32 = 2 * nwt;
-    for (int r = tid; r < MAXR; r += BT) meta[r] = RowMeta{0, -1, -1};
+    for (int r = tid; r < MAXR; r += BT) {
+        meta[r] = RowMeta{0, -1, -1};
+        wr_lo[r] = 0;
+        wr_hi[r] = -1;
+    }
     if (tid == 0) {
         sh_end = INT_MAX;
         sh_fail = 0;
     }
-    __syncthreads();
 
     // step table (CIGAR mode) lives at the end of the slice, entry s at
     // slice_bytes - 16 * (s + 1)
     RowMeta* table = (RowMeta*)(slice + slice_bytes) - 1;
-    const long long full_row = 3LL * 4 * (n + m + 1);
-    long long bump = R * full_row;  // CIGAR history starts after the ring
+    // Ring slots of M, I and D rows indexed by diagonal: FW entries each,
+    // diagonal k at k + n + 1 (one pad on each side), then one slot of NULL
+    // rows that stands for steps without a wavefront.  Every slot starts
+    // NULL, and a step that takes over a slot writes its range [lo, hi] and
+    // NULLs whatever the slot's previous step wrote outside it, so every
+    // entry outside a source step's range reads NULL and the cells read
+    // their sources without range checks.
+    const int FW = n + m + 3;
+    const long long full_row = 3LL * 4 * FW;
+    long long bump = (R + 1) * full_row;  // CIGAR history starts after the ring
     if (bump > slice_bytes) {
         if (tid == 0) {
             const uint32_t at = atomicAdd(a.fail_count, 1u);
@@ -965,20 +977,28 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         }
         return;
     }
+    {
+        int* ring = (int*)slice;
+        const long long cnt = (R + 1) * 3LL * FW;
+        for (long long i = tid; i < cnt; i += BT) ring[i] = NUL32;
+    }
+    __syncthreads();
+    const int* nullrow = (const int*)(slice + R * full_row) + n + 1;
     // a hard bound on steps: deleting all of P and inserting all of T
     const long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
 
     int S = -1;
-    for (long long s = 0;; s++) {
+    int rs = 0;  // s % R
+    for (long long s = 0;; s++, rs = rs + 1 == R ? 0 : rs + 1) {
         if (s > max_score_g) {
             if (tid == 0) sh_fail = 2;
             break;
         }
         // the source rows of this step (metadata ring entry of step t: t % R)
         RowMeta sx{0, -1, -1}, so{0, -1, -1}, se{0, -1, -1};
-        if (s >= X) sx = meta[(int)((s - X) % R)];
-        if (s >= OE) so = meta[(int)((s - OE) % R)];
-        if (s >= E) se = meta[(int)((s - E) % R)];
+        if (s >= X) sx = meta[rs - X + (rs < X ? R : 0)];
+        if (s >= OE) so = meta[rs - OE + (rs < OE ? R : 0)];
+        if (s >= E) se = meta[rs - E + (rs < E ? R : 0)];
         int lo, hi;
         bool present;
         if (s == 0) {  // the free starts (diagonal 0 alone in global alignment)
@@ -1000,7 +1020,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         long long off = -1, hoff = -1;
         if (present) {
             const int w = hi - lo + 1;
-            off = (s % R) * full_row;
+            off = rs * full_row;
             if (a.cigar) {
                 hoff = bump;
                 bump += (4LL * w + (w + 1) / 2 + 15) & ~15LL;
@@ -1009,20 +1029,24 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     break;
                 }
             }
-            int* rowM = (int*)(slice + off);
-            int* rowI = rowM + w;
-            int* rowD = rowI + w;
+            int* rowM = (int*)(slice + off) + n + 1;
+            int* rowI = rowM + FW;
+            int* rowD = rowI + FW;
+            {  // the slot's previous values outside [lo, hi] become NULL
+                const int plo = wr_lo[rs], phi = wr_hi[rs];
+                for (int k = plo + tid; k <= phi && k < lo; k += BT)
+                    rowM[k] = rowI[k] = rowD[k] = NUL32;
+                for (int k = max(hi + 1, plo) + tid; k <= phi; k += BT)
+                    rowM[k] = rowI[k] = rowD[k] = NUL32;
+            }
             int* histM = a.cigar ? (int*)(slice + hoff) : nullptr;
             uint8_t* histF = a.cigar ? (uint8_t*)(histM + w) : nullptr;
-            // source components (M of s - x and s - o - e, I and D of s - e);
-            // a diagonal outside a source row's range reads NULL
-            const int* MX = sx.off >= 0 ? (const int*)(slice + sx.off) : nullptr;
-            const int* MO = so.off >= 0 ? (const int*)(slice + so.off) : nullptr;
-            const int* IE = se.off >= 0 ? (const int*)(slice + se.off) + (se.hi - se.lo + 1) : nullptr;
-            const int* DE = IE ? IE + (se.hi - se.lo + 1) : nullptr;
-            auto rd = [](const int* base, const RowMeta& mm, int kk) -> int {
-                return (base && kk >= mm.lo && kk <= mm.hi) ? base[kk - mm.lo] : NUL32;
-            };
+            // source components (M of s - x and s - o - e, I and D of s - e),
+            // indexed by diagonal; an absent step reads the NULL slot
+            const int* MX = sx.off >= 0 ? (const int*)(slice + sx.off) + n + 1 : nullrow;
+            const int* MO = so.off >= 0 ? (const int*)(slice + so.off) + n + 1 : nullrow;
+            const int* IE = (se.off >= 0 ? (const int*)(slice + se.off) + n + 1 : nullrow) + FW;
+            const int* DE = IE + FW;
             // one cell from its five source offsets
             auto cell = [&](int k, int va, int vb, int vc, int ve, int vx) {
                 int mval;
@@ -1054,9 +1078,9 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     rec = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
                 }
                 if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
-                rowM[k - lo] = mval;
-                rowI[k - lo] = ival;
-                rowD[k - lo] = dval;
+                rowM[k] = mval;
+                rowI[k] = ival;
+                rowD[k] = dval;
                 if (a.cigar) {
                     histM[k - lo] = mval;
                     // lanes hold neighbouring diagonals (k - lo has the lane's
@@ -1075,23 +1099,32 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     atomicMin(&sh_end, k);
             };
             // two cells per thread and pass: both cells' sources are read
-            // before either is computed, so their latencies overlap
+            // before either is computed, so their latencies overlap (a second
+            // cell past hi reads in-range sources and is dropped)
             for (int k0 = lo + tid; k0 <= hi; k0 += 2 * BT) {
                 const int k1 = k0 + BT;
-                const int a0 = rd(MO, so, k0 - 1), b0 = rd(IE, se, k0 - 1), c0 = rd(MO, so, k0 + 1),
-                          e0 = rd(DE, se, k0 + 1), x0 = rd(MX, sx, k0);
-                const int a1 = rd(MO, so, k1 - 1), b1 = rd(IE, se, k1 - 1), c1 = rd(MO, so, k1 + 1),
-                          e1 = rd(DE, se, k1 + 1), x1 = rd(MX, sx, k1);
+                const int k1r = min(k1, hi);
+                const int a0 = MO[k0 - 1], b0 = IE[k0 - 1], c0 = MO[k0 + 1], e0 = DE[k0 + 1],
+                          x0 = MX[k0];
+                const int a1 = MO[k1r - 1], b1 = IE[k1r - 1], c1 = MO[k1r + 1], e1 = DE[k1r + 1],
+                          x1 = MX[k1r];
                 cell(k0, a0, b0, c0, e0, x0);
                 if (k1 <= hi) cell(k1, a1, b1, c1, e1, x1);
             }
         }
-        __syncthreads();
+        // this step's metadata (sources of this step are other entries, so
+        // no thread still reading them can see it change)
         if (tid == 0) {
-            meta[s % R] = RowMeta{lo, hi, off};
+            meta[rs] = RowMeta{lo, hi, off};
             if (a.cigar) table[-s] = RowMeta{lo, hi, hoff};
         }
         __syncthreads();
+        // the slot's range, read by the next step that takes it over (every
+        // thread has read this step's entry before the barrier)
+        if (tid == 0 && present) {
+            wr_lo[rs] = lo;
+            wr_hi[rs] = hi;
+        }
         if (sh_end != INT_MAX) {
             S = (int)s;
             break;

@@ -96,7 +96,7 @@ size_t pair_bytes(const wfa_server_cfg& cfg, uint32_t n, uint32_t m) {
     // CIGAR mode the history: an offset and a 4-bit record per cell (about
     // s'^2 / e' cells) and a 16-byte table entry per step, plus the runs
     const double pre = std::max(x, o + e) / g;
-    double wf = 12.0 * (pre + 1) * ((double)n + m + 1);
+    double wf = 12.0 * (pre + 2) * ((double)n + m + 3);
     if (cfg.mode == WFA_CIGAR) {
         wf += 4.5 * s * s / (g * e) + 16.0 * (s / g + 1);
         io += (size_t)(4.0 * 2 * (s / std::min(x, e) + 1));

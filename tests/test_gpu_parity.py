@@ -118,6 +118,20 @@ def test_penalty_sets(aligner, oracle_lib, synth_lib, pen):
     assert_same(got, oracle_of(oracle_lib, b, pen), b, f"pen {pen}")
 
 
+@pytest.mark.parametrize("pen", [(4, 6, 4), (3, 1, 4), (1, 0, 1), (2, 3, 1), (5, 2, 3)])
+def test_general_kernel_penalty_sets(aligner, oracle_lib, synth_lib, wfa, pen):
+    """Every pair on the general kernel under penalty sets whose scaled gap
+    extension exceeds one step (steps without a wavefront between steps with
+    one, so the wavefront's range can narrow from one step to the next)."""
+    say(f"case: general kernel, penalties {pen}")
+    b = synth_lib.workload("uneven50_300_2m", 1500, first=4321)
+    aligner.set_options(schedule=wfa.WFA_SCHED_GENERAL)
+    got = aligner.align(b, pen)
+    assert_same(got, oracle_of(oracle_lib, b, pen), b, f"general pen {pen}")
+    sc, _, _ = aligner.align(b, pen, cigar=False)
+    assert np.array_equal(sc, oracle_of(oracle_lib, b, pen, cigar=False).scores)
+
+
 def test_host_memory_path(aligner, oracle_lib, synth_lib):
     say("case: host-memory staging path")
     b = synth_lib.workload("pairs100_e4_5m", 5000, first=1000)
