@@ -132,6 +132,12 @@ typedef struct {
     int32_t host_chunk_pairs; /* pairs per chunk of the host-memory pipeline
                                  (at least 1/1024 of the batch); 0: a quarter
                                  of the batch, within [262144, 2097152] */
+    int32_t cascade_window;   /* largest window of the cascade: further
+                                 short-kernel passes, each over the pairs the
+                                 previous pass handed over, with windows 64,
+                                 128, 256 above the first; only what the last
+                                 pass hands over goes to the general kernel.
+                                 0: up to 256; -1: no cascade */
 } wfa_options;
 
 /* Ends-free alignment.  Up to pattern_begin_free leading pattern bases OR
@@ -171,6 +177,8 @@ typedef struct {
     double ms_general;
     double ms_compact;
     double ms_total;             /* host wall time of the call                       */
+    int32_t cascade_window;      /* window of the cascade's last pass, 0: none       */
+    int32_t pad_;
 } wfa_stats;
 
 enum {

@@ -53,7 +53,7 @@ class wfa_options(ctypes.Structure):
                 ("step_cap", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("bucket", ctypes.c_int32), ("general_pairs", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32),
-                ("host_chunk_pairs", ctypes.c_int32)]
+                ("host_chunk_pairs", ctypes.c_int32), ("cascade_window", ctypes.c_int32)]
 
 
 class wfa_ends_free(ctypes.Structure):
@@ -69,7 +69,8 @@ class wfa_stats(ctypes.Structure):
                 ("step_cap", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("graph_replayed", ctypes.c_int32), ("ms_pack", ctypes.c_double),
                 ("ms_align", ctypes.c_double), ("ms_general", ctypes.c_double),
-                ("ms_compact", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_compact", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("cascade_window", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -474,6 +474,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             a.tw = d.tw;
             a.order = bucket ? ws.order.as<uint32_t>() : nullptr;
             a.num = (uint32_t)N;
+            a.npairs = (uint32_t)N;
             a.ends = e->ends;
             a.queue = &flags->queue;
             a.queue_chunk = queue_chunk;
@@ -502,7 +503,8 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         if (cigar && use_short) {
             HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, q));
             HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
-                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), d.offsets,
+                                  ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
+                                  ws.gen_runs.as<uint32_t>(), d.offsets,
                                   N, d.runs, d.capacity, q));
         }
         return WFA_OK;
@@ -561,17 +563,93 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         return WFA_E_ALPHABET;
     }
 
-    // ---- general kernel for the rest ---------------------------------------
+    // ---- the cascade: wider short-kernel passes (windows 64, 128, 256 above
+    // the first, up to the cascade's largest), each over the pairs the
+    // previous pass handed over, before anything goes to the general kernel ---
     uint64_t general_done = 0, requeued = 0, gen_used = 0;
+    uint32_t ovf_final = use_short ? fl.ovf_count : 0;
+    const Buf* ovf_buf = &ws.ovf_list;
+    int window2 = 0;
+    double ms_cascade = 0.0;
+    if (use_short) requeued += fl.ovf_count;
+    if (use_short && fl.ovf_count > 0 && e->opt.cascade_window >= 0) {
+        const int wmax = e->opt.cascade_window > 0 ? e->opt.cascade_window : 256;
+        RCCHK(ws.ensure(ws.ovf_list2, (size_t)fl.ovf_count * 4));
+        Buf* lists[2] = {&ws.ovf_list, &ws.ovf_list2};
+        int in_list = 0;
+        uint64_t slots2_used = 0;  // words of slots2 taken by earlier passes
+        // the cascade's windows: 64, 128, 256 above the first window
+        for (int w2 = 64; w2 <= wmax && ovf_final > 0; w2 *= 2) {
+            if (w2 <= window) continue;
+            const int l2 = default_lanes(w2);
+            ShortPlan sp2;
+            if (!short_shape_supported(w2, l2) ||
+                short_plan(e, pen, cigar, w2, l2, default_cap(pen, w2), max_len, &sp2) != WFA_OK)
+                break;
+            const uint32_t n2 = ovf_final;
+            if (cigar)
+                RCCHK(ws.grow_keep(ws.slots2, (slots2_used + (uint64_t)n2 * sp2.slot_cap) * 4,
+                                   slots2_used * 4, s));
+            const int gpb2 = short_groups_per_block(l2, sp2.block_threads);
+            int bpc2 = short_max_blocks_per_cu(w2, l2, cigar, sp2.block_threads,
+                                               sp2.lds_per_block, sp2.row_bytes);
+            if (bpc2 < 1) bpc2 = 1;
+            int grid2 = e->num_cus * bpc2;
+            const size_t need2 = (n2 + gpb2 - 1) / gpb2;
+            if ((size_t)grid2 > need2) grid2 = (int)need2;
+            ShortArgs a{};
+            a.pairs = d.pairs;
+            a.pw = d.pw;
+            a.tw = d.tw;
+            a.order = lists[in_list]->as<uint32_t>();  // the previous pass's hand-overs
+            a.num = n2;
+            a.npairs = (uint32_t)N;
+            a.ends = e->ends;
+            a.queue = &flags->queue2;
+            a.queue_chunk = 1;
+            a.pen = pen;
+            a.cap = sp2.cap;
+            a.ring = sp2.ring;
+            a.ring2 = sp2.ring2;
+            a.id_off = sp2.id_off;
+            a.seq_words = sp2.seq_words;
+            a.group_bytes = sp2.group_bytes;
+            a.rows_bytes = sp2.rows_bytes;
+            a.slot_cap = sp2.slot_cap;
+            a.row_bytes = sp2.row_bytes;
+            a.scores = d.scores;
+            a.nruns = ws.nruns.as<uint32_t>();
+            a.run_src = ws.run_src.as<uint64_t>();
+            a.run_src_add = SLOTS2_BIT + slots2_used;
+            a.slots = cigar ? ws.slots2.as<uint32_t>() + slots2_used : nullptr;
+            a.ovf_list = lists[1 - in_list]->as<uint32_t>();
+            a.ovf_count = &flags->ovf_count2;
+            HIPCHK(launch_fill_u32(&flags->ovf_count2, 0u, 2, s));  // ovf_count2, queue2
+            HIPCHK(hipEventRecord(e->ev[10], s));
+            HIPCHK(launch_short(a, w2, l2, cigar, true, sp2.block_threads, grid2, s));
+            HIPCHK(hipEventRecord(e->ev[11], s));
+            uint32_t n_out = 0;
+            HIPCHK(hipMemcpyAsync(&n_out, &flags->ovf_count2, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ms_cascade += ev_ms(e->ev[10], e->ev[11]);
+            if (cigar) slots2_used += (uint64_t)n2 * sp2.slot_cap;
+            ovf_final = n_out;
+            in_list = 1 - in_list;
+            ovf_buf = lists[in_list];
+            window2 = w2;
+            requeued += n_out;
+        }
+    }
+
+    // ---- general kernel for the rest ---------------------------------------
     std::vector<uint32_t> pending;
     if (!use_short) {
         pending.resize(N);
         for (size_t i = 0; i < N; i++) pending[i] = (uint32_t)i;
-    } else if (fl.ovf_count) {
-        pending.resize(fl.ovf_count);
-        HIPCHK(hipMemcpy(pending.data(), ws.ovf_list.ptr, fl.ovf_count * 4ull, hipMemcpyDeviceToHost));
+    } else if (ovf_final) {
+        pending.resize(ovf_final);
+        HIPCHK(hipMemcpy(pending.data(), ovf_buf->ptr, ovf_final * 4ull, hipMemcpyDeviceToHost));
         std::sort(pending.begin(), pending.end());
-        requeued += fl.ovf_count;
     }
     HIPCHK(hipEventRecord(e->ev[2], s));
     if (!pending.empty()) {
@@ -583,7 +661,8 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     // ---- CIGAR offsets and compaction ------------------------------------------
     uint64_t total = 0;
     if (cigar) {
-        const bool rescan = !use_short || !pending.empty();
+        // any hand-over changes run counts after the first pass's scan
+        const bool rescan = !use_short || fl.ovf_count > 0;
         if (rescan) {
             RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(N + 1) + 64));
             HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, s));
@@ -594,7 +673,8 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         }
         if (rescan && total <= d.capacity)
             HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
-                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), d.offsets, N,
+                                  ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
+                                  ws.gen_runs.as<uint32_t>(), d.offsets, N,
                                   d.runs, d.capacity, s));
         if (cigar_needed) *cigar_needed = (size_t)total;
     }
@@ -604,7 +684,8 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     wfa_stats& L = e->last;
     L.pairs = N;
     L.general_pairs = general_done;
-    L.short_pairs = use_short ? N - (fl.ovf_count) : 0;
+    L.short_pairs = use_short ? N - ovf_final : 0;
+    L.cascade_window = window2;
     L.requeued = requeued;
     L.cigar_runs = total;
     L.window = use_short ? window : 0;
@@ -613,7 +694,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     L.schedule = !use_short ? WFA_SCHED_GENERAL : (persistent ? WFA_SCHED_PERSISTENT : WFA_SCHED_PLAIN);
     L.graph_replayed = replayed ? 1 : 0;
     L.ms_pack = use_short ? ev_ms(e->ev[0], e->ev[4]) : 0.0;
-    L.ms_align = use_short ? ev_ms(e->ev[4], e->ev[5]) : 0.0;
+    L.ms_align = (use_short ? ev_ms(e->ev[4], e->ev[5]) : 0.0) + ms_cascade;
     L.ms_general = ev_ms(e->ev[2], e->ev[3]);
     L.ms_compact = (use_short ? ev_ms(e->ev[5], e->ev[1]) : 0.0) + ev_ms(e->ev[3], e->ev[8]);
     L.ms_total = now_ms() - t_start;

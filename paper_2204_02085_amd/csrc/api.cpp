@@ -198,6 +198,10 @@ extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
         return WFA_E_INVAL;
     if (opt->general_pairs < 0) return WFA_E_INVAL;
     if (opt->host_chunk_pairs < 0) return WFA_E_INVAL;
+    if (opt->cascade_window < -1 ||
+        (opt->cascade_window > 0 &&
+         !short_shape_supported(opt->cascade_window, default_lanes(opt->cascade_window))))
+        return WFA_E_INVAL;
     ctx->opt = *opt;
     return WFA_OK;
 }
@@ -347,7 +351,8 @@ extern "C" int wfa_copy_last_cigars(wfa_ctx* ctx, uint32_t* runs, size_t capacit
         uint64_t* off = ws.out_offsets.as<uint64_t>();
         API_HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, off, ws.scan_tmp.ptr, s));
         API_HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
-                                  ws.slots.as<uint32_t>(), ws.gen_runs.as<uint32_t>(), off, N, runs,
+                                  ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
+                                  ws.gen_runs.as<uint32_t>(), off, N, runs,
                                   capacity, s));
         if (offsets)
             API_HIPCHK(hipMemcpyAsync(offsets, off, (N + 1) * 8, hipMemcpyDeviceToDevice, s));

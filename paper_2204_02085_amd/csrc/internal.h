@@ -28,19 +28,20 @@ struct Workspace {
     // host-memory pipeline: device copies of the whole batch's inputs and
     // outputs (host_off: offsets of the batch, host_loff: of one chunk)
     Buf in_pairs, in_p, in_t, out_scores, out_runs, out_offsets, host_off, host_loff;
-    // short kernel
-    Buf nruns, run_src, slots, ovf_list, order, keys, hist;
+    // short kernel (slots2 / ovf_list2: the wider second pass)
+    Buf nruns, run_src, slots, ovf_list, order, keys, hist, slots2, ovf_list2;
     // general kernel
     Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
 
-    std::array<Buf*, 30> all() {
+    std::array<Buf*, 32> all() {
         return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,
                 &words_t, &packed_pairs, &in_pairs, &in_p,      &in_t,      &out_scores,
                 &out_runs, &out_offsets, &host_off, &host_loff, &nruns,   &run_src,
-                &slots,   &ovf_list,   &order,    &keys,        &hist,      &jobs,
-                &job_nruns, &job_offsets, &fail_list, &arena,   &gen_runs,  &gen_tmp};
+                &slots,   &ovf_list,   &order,    &keys,        &hist,      &slots2,
+                &ovf_list2, &jobs,     &job_nruns, &job_offsets, &fail_list, &arena,
+                &gen_runs, &gen_tmp};
     }
     int ensure(Buf& b, size_t bytes);
     // grow to at least `bytes`, keeping the first `keep` bytes (copied on `s`,
@@ -57,6 +58,8 @@ struct DevFlags {
     uint32_t ovf_count;           // pairs the short kernel handed over
     uint32_t queue;               // persistent queue head
     uint32_t fail_count;          // general jobs whose slice was too small
+    uint32_t ovf_count2;          // pairs a cascade pass (a wider short pass) handed over
+    uint32_t queue2;              // queue head of a cascade pass
     uint32_t pad;
     uint64_t total_runs;          // exclusive-scan total of per-pair runs
 };
@@ -90,7 +93,7 @@ struct Engine {
     hipStream_t stream = nullptr;
     hipStream_t h2d = nullptr, d2h = nullptr;  // copy streams of the host-memory pipeline
     Workspace ws;
-    hipEvent_t ev[10] = {};
+    hipEvent_t ev[12] = {};
     wfa_options opt{};
     wfa::Ends ends{};  // free ends of later calls (all zero: global alignment)
     wfa_stats last{};

@@ -53,6 +53,7 @@ struct ShortArgs {
     const uint64_t* tw;         // packed text words
     const uint32_t* order;      // queue position -> pair index (NULL: identity)
     uint32_t num;               // pairs in the queue
+    uint32_t npairs;            // pairs of the batch (bound of the indices in `order`)
     Ends ends;                  // free ends (all zero: global alignment)
     uint32_t* queue;            // persistent: next queue position (device counter)
     int queue_chunk;            // rounds of 64/G pairs a wave claims per atomic
@@ -69,6 +70,7 @@ struct ShortArgs {
     int32_t* scores;            // [pairs]
     uint32_t* nruns;            // [pairs] runs written
     uint64_t* run_src;          // [pairs] where the reversed runs live
+    uint64_t run_src_add;       // added to run_src (a cascade pass: SLOTS2_BIT + its offset in slots2)
     uint32_t* slots;            // [pairs * slot_cap] reversed runs, packed per wave
     uint32_t* ovf_list;         // pairs the kernel could not hold
     uint32_t* ovf_count;
@@ -141,9 +143,14 @@ hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_l
 
 // Copy reversed runs from their staging places into the caller's buffer.
 // Nothing is written if offsets[n] exceeds `capacity`.
+// run_src of a pair: a word offset into `slots`, into `slots2` with
+// SLOTS2_BIT set, or into `gen_runs` with GEN_BIT set
+constexpr uint64_t GEN_BIT = 1ULL << 63;
+constexpr uint64_t SLOTS2_BIT = 1ULL << 62;
 hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const uint32_t* slots,
-                          const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
-                          uint32_t* out, uint64_t capacity, hipStream_t s);
+                          const uint32_t* slots2, const uint32_t* gen_runs,
+                          const uint64_t* offsets, size_t n, uint32_t* out, uint64_t capacity,
+                          hipStream_t s);
 
 // Counting sort of pairs by expected work: keys + histogram, then (after an
 // exclusive scan of the histogram into `cursor`) the scatter into `order`.

@@ -31,7 +31,6 @@ namespace {
 
 constexpr int NUL16 = -16384;          // NULL offset in int16 rows
 constexpr int NUL32 = -(1 << 30);      // NULL offset in int32 rows
-constexpr uint64_t GEN_BIT = 1ULL << 63;
 enum { OP_M = 0, OP_X = 1, OP_I = 2, OP_D = 3 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -505,7 +504,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         bool active_ok = q < a.num;
         if (active_ok) {
             pair = a.order ? a.order[q] : q;
-            if (pair >= a.num) {  // a corrupt permutation must not fault: skip the entry
+            if (pair >= a.npairs) {  // a corrupt permutation must not fault: skip the entry
                 active_ok = false;
                 pair = 0;
             }
@@ -843,7 +842,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             for (int r = gl; r < mine; r += G) a.slots[base + r] = STAGE[r];
             if (done) {
                 a.nruns[pair] = (uint32_t)cnt;
-                a.run_src[pair] = base;
+                a.run_src[pair] = base + a.run_src_add;
             }
             wbump += (uint64_t)tot;
         }
@@ -1308,6 +1307,7 @@ constexpr int COMPACT_UNROLL = 8;
 __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ nruns,
                                                  const uint64_t* __restrict__ run_src,
                                                  const uint32_t* __restrict__ slots,
+                                                 const uint32_t* __restrict__ slots2,
                                                  const uint32_t* __restrict__ gen_runs,
                                                  const uint64_t* __restrict__ offsets, size_t n,
                                                  uint32_t* __restrict__ out, uint64_t capacity) {
@@ -1317,7 +1317,8 @@ __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ nr
         const uint32_t cnt = nruns[i];
         const uint64_t src = run_src[i];
         const uint64_t dst = offsets[i];
-        const uint32_t* sp = (src & GEN_BIT) ? gen_runs + (src & ~GEN_BIT) : slots + src;
+        const uint64_t off = src & ~(GEN_BIT | SLOTS2_BIT);
+        const uint32_t* sp = (src & GEN_BIT) ? gen_runs + off : ((src & SLOTS2_BIT) ? slots2 : slots) + off;
         uint32_t* o = out + dst + cnt - 1;
         for (uint32_t r0 = 0; r0 < cnt; r0 += COMPACT_UNROLL) {
             uint32_t v[COMPACT_UNROLL];
@@ -1586,11 +1587,12 @@ hipError_t launch_pair_lengths(const PairDesc* pairs, const uint32_t* idx, size_
 }
 
 hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const uint32_t* slots,
-                          const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
-                          uint32_t* out, uint64_t capacity, hipStream_t s) {
+                          const uint32_t* slots2, const uint32_t* gen_runs,
+                          const uint64_t* offsets, size_t n, uint32_t* out, uint64_t capacity,
+                          hipStream_t s) {
     if (n)
         hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s,
-                           nruns, run_src, slots, gen_runs, offsets, n, out, capacity);
+                           nruns, run_src, slots, slots2, gen_runs, offsets, n, out, capacity);
     return hipGetLastError();
 }
 
