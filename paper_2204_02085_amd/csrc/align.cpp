@@ -145,11 +145,13 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         if (cigar) {
             // history, first guess: a pair at 10 % divergence (score about
             // 0.1 * L times the mean edit cost) keeps ~s'^2 / e' cells of 4.5
-            // bytes (offset and record) plus a 16-byte step-table entry per
-            // step, and its runs; pairs that need more are re-run with 4x
+            // bytes (offset and record; 2.5 with 16-bit offsets) plus a 16-byte
+            // step-table entry per step, and its runs; pairs that need more
+            // are re-run with 4x
             const double L = std::max(n, m);
             const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
-            const double est = 4.5 * sg * sg / pen.e + 32.0 * sg + 4.0 * (double)nm1 + 4096.0;
+            const double cellb = m < 0xFFFF ? 2.5 : 4.5;
+            const double est = cellb * sg * sg / pen.e + 32.0 * sg + 4.0 * (double)nm1 + 4096.0;
             sl += (uint64_t)std::min(std::max(est, 16.0 * 1024), 64.0 * 1024 * 1024) * mult;
         }
         return (sl + 255) & ~(uint64_t)255;

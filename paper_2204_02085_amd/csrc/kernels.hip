@@ -853,12 +853,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // ---------------------------------------------------------------------------
 // General kernel: one workgroup per pair, any length, any score.
 //
-// Slice layout (bytes): a ring of pre + 1 full-width rows of M, I and D
-// (int32, diagonals [-n, m]) that the score steps work in.  CIGAR mode adds,
-// after the ring, one history row per step that grows towards the end of
-// the slice: the step's M offsets (int32) and a 4-bit decision record per
-// diagonal (as in the short kernel); the step table {lo, hi, offset} grows
-// down from the end, and the backtrace writes reversed runs into the gap.
+// Slice layout (bytes): a ring of pre + 1 full-width slots of M, I and D
+// rows (int32, diagonals [-n - 1, m + 1]) that the score steps work in, and
+// a slot of NULL rows.  CIGAR mode adds, after the ring, one history row per
+// step that grows towards the end of the slice: the step's M offsets (16-bit
+// while the text is shorter than 65535 bases, else 32-bit) and a 4-bit
+// decision record per diagonal (as in the short kernel); the step table
+// {lo, hi, offset} grows down from the end, and the backtrace writes
+// reversed runs into the gap.
 // ---------------------------------------------------------------------------
 struct RowMeta {
     int lo, hi;
@@ -968,6 +970,10 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     // their sources without range checks.
     const int FW = n + m + 3;
     const long long full_row = 3LL * 4 * FW;
+    // CIGAR history offsets: 16-bit (0xFFFF for NULL) while every offset
+    // fits, else 32-bit
+    const bool h16 = m < 0xFFFF;
+    const int hbytes = h16 ? 2 : 4;
     long long bump = (R + 1) * full_row;  // CIGAR history starts after the ring
     if (bump > slice_bytes) {
         if (tid == 0) {
@@ -1022,7 +1028,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             off = rs * full_row;
             if (a.cigar) {
                 hoff = bump;
-                bump += (4LL * w + (w + 1) / 2 + 15) & ~15LL;
+                bump += ((long long)hbytes * w + (w + 1) / 2 + 15) & ~15LL;
                 if (bump > slice_bytes - 16LL * (s + 2)) {
                     if (tid == 0) sh_fail = 1;
                     break;
@@ -1038,8 +1044,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                 for (int k = max(hi + 1, plo) + tid; k <= phi; k += BT)
                     rowM[k] = rowI[k] = rowD[k] = NUL32;
             }
-            int* histM = a.cigar ? (int*)(slice + hoff) : nullptr;
-            uint8_t* histF = a.cigar ? (uint8_t*)(histM + w) : nullptr;
+            unsigned char* histM = a.cigar ? slice + hoff : nullptr;
+            uint8_t* histF = a.cigar ? histM + (long long)hbytes * w : nullptr;
             // source components (M of s - x and s - o - e, I and D of s - e),
             // indexed by diagonal; an absent step reads the NULL slot
             const int* MX = sx.off >= 0 ? (const int*)(slice + sx.off) + n + 1 : nullrow;
@@ -1081,7 +1087,10 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                 rowI[k] = ival;
                 rowD[k] = dval;
                 if (a.cigar) {
-                    histM[k - lo] = mval;
+                    if (h16)
+                        ((uint16_t*)histM)[k - lo] = mval < 0 ? (uint16_t)0xFFFF : (uint16_t)mval;
+                    else
+                        ((int*)histM)[k - lo] = mval;
                     // lanes hold neighbouring diagonals (k - lo has the lane's
                     // parity): both write the byte of the pair of cells; a
                     // partner past hi reads 0
@@ -1178,6 +1187,10 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         if (ss < 0) return NUL32;
         const RowMeta mm = table[-ss];
         if (mm.off < 0 || kk < mm.lo || kk > mm.hi) return NUL32;
+        if (h16) {
+            const uint16_t v = ((const uint16_t*)(slice + mm.off))[kk - mm.lo];
+            return v == 0xFFFF ? NUL32 : (int)v;
+        }
         return ((const int*)(slice + mm.off))[kk - mm.lo];
     };
     // decision record of (ss, kk); -1 outside the step's range
@@ -1186,7 +1199,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         const RowMeta mm = table[-ss];
         if (mm.off < 0 || kk < mm.lo || kk > mm.hi) return -1;
         const int w = mm.hi - mm.lo + 1;
-        const uint8_t* f = (const uint8_t*)((const int*)(slice + mm.off) + w);
+        const uint8_t* f = (const uint8_t*)(slice + mm.off) + (long long)hbytes * w;
         return (f[(kk - mm.lo) >> 1] >> (((kk - mm.lo) & 1) << 2)) & 15;
     };
     long long s = S;

@@ -98,7 +98,8 @@ size_t pair_bytes(const wfa_server_cfg& cfg, uint32_t n, uint32_t m) {
     const double pre = std::max(x, o + e) / g;
     double wf = 12.0 * (pre + 2) * ((double)n + m + 3);
     if (cfg.mode == WFA_CIGAR) {
-        wf += 4.5 * s * s / (g * e) + 16.0 * (s / g + 1);
+        const double cellb = m < 0xFFFF ? 2.5 : 4.5;  // 16-bit history offsets below 64 K
+        wf += cellb * s * s / (g * e) + 16.0 * (s / g + 1);
         io += (size_t)(4.0 * 2 * (s / std::min(x, e) + 1));
     }
     return io + (size_t)wf;
