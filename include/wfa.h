@@ -208,9 +208,10 @@ void wfa_ctx_destroy(wfa_ctx *ctx);
 int wfa_set_options(wfa_ctx *ctx, const wfa_options *opt);
 
 /* Select ends-free alignment (wfa_ends_free) for later wfa_align_batch and
- * wfa_autotune calls on the context; NULL or all zero selects global
- * alignment (the default).  Bounds above WFA_MAX_LENGTH are WFA_E_INVAL.
- * The server (wfa_server_*) always aligns globally. */
+ * wfa_autotune calls on the context, and for servers opened on it later
+ * (a server keeps the setting it opened with); NULL or all zero selects
+ * global alignment (the default).  Bounds above WFA_MAX_LENGTH are
+ * WFA_E_INVAL. */
 int wfa_set_ends_free(wfa_ctx *ctx, const wfa_ends_free *ends);
 
 /* Align num_pairs pairs.

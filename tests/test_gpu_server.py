@@ -56,3 +56,25 @@ def test_server_mix_equals_alone(oracle_lib, synth_lib):
         assert_same((results[i]["scores"], results[i]["runs"], results[i]["offsets"]), ref, reqs[i],
                     f"request {i}")
     al.close()
+
+
+def test_server_ends_free(oracle_lib, synth_lib):
+    """A server opened on a context with free ends aligns every request with
+    them (and keeps them after the context returns to global alignment)."""
+    import paper_2204_02085_amd as wfa
+
+    say("case: server with free ends (5, 5, 20, 20), 12 requests")
+    ends = (5, 5, 20, 20)
+    al = wfa.Aligner(0)
+    al.set_ends_free(*ends)
+    srv = wfa.Server(al, hbm_budget_bytes=4 << 30, streams=2, max_chunk_pairs=2048)
+    al.set_ends_free()
+    reqs = [synth_lib.workload("uneven50_300_2m", 50 + 40 * i, first=1000 * i) for i in range(12)]
+    tickets = [srv.submit(r) for r in reqs]
+    results = [srv.poll(t) for t in tickets]
+    srv.close()
+    for i, (req, res) in enumerate(zip(reqs, results)):
+        assert res["status"] == 0
+        ref = oracle_lib.align_batch(req, PEN, threads=8, ends=ends)
+        assert_same((res["scores"], res["runs"], res["offsets"]), ref, req, f"request {i}")
+    al.close()
