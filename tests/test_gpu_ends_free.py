@@ -158,3 +158,46 @@ def test_short_kernel_semi_global(aligner, oracle_lib, synth_lib, wfa):
         got = aligner.align(b, PEN)
         assert aligner.stats()["short_pairs"] > 1500
         assert_same(got, ref, b, f"semi-global {sched}")
+
+
+def test_full_size_ends_free(aligner, oracle_lib, synth_lib):
+    """5,000,000 pairs of 100 bp at E = 4 % aligned with 10 free bases at
+    each end of either sequence, default launch: every pair's runs spell
+    both sequences; a sample (random pairs, the 500 highest scores, the
+    first and last pair) is byte-exact against the oracle and its CIGARs
+    re-score to the ends-free score."""
+    import brute
+
+    ends = (10, 10, 10, 10)
+    b = synth_lib.workload("pairs100_e4_5m")
+    say(f"case: pairs100_e4_5m full size, ends-free {ends}")
+    aligner.set_ends_free(*ends)
+    sc, runs, off = aligner.align(b, PEN, capacity=len(b) * 40 + 1024)
+    st = aligner.stats()
+    say(f"  stats: {st}")
+    assert st["short_pairs"] > 0.99 * len(b)
+    # spelling: the runs consume exactly n pattern and m text bases
+    counts = np.diff(off.astype(np.int64))
+    ops = (runs & 15).astype(np.int64)
+    lens = (runs >> 4).astype(np.int64)
+    pid = np.repeat(np.arange(len(b)), counts)
+    assert not ((pid[1:] == pid[:-1]) & (ops[1:] == ops[:-1])).any()
+    used_p = np.bincount(pid, weights=lens * (ops != 2), minlength=len(b)).astype(np.int64)
+    used_t = np.bincount(pid, weights=lens * (ops != 3), minlength=len(b)).astype(np.int64)
+    assert np.array_equal(used_p, b.p_len.astype(np.int64))
+    assert np.array_equal(used_t, b.t_len.astype(np.int64))
+    rng = np.random.default_rng(3)
+    top = np.argsort(sc, kind="stable")[-500:]
+    idx = np.unique(np.concatenate([rng.choice(len(b), 20_000, replace=False), top,
+                                    [0, len(b) - 1]]))
+    sub = b.subset(idx)
+    ref = oracle_of(oracle_lib, sub, ends)
+    sub_off = np.zeros(len(idx) + 1, np.uint64)
+    pieces = [runs[int(off[i]):int(off[i + 1])] for i in idx]
+    np.cumsum([len(p) for p in pieces], out=sub_off[1:])
+    got = (sc[idx], np.concatenate(pieces).astype(np.uint32), sub_off)
+    assert_same(got, ref, sub, "full-size ends-free sample")
+    for j in range(0, len(idx), 40):
+        p, t = sub.pair(j)
+        r = got[1][int(sub_off[j]):int(sub_off[j + 1])]
+        assert brute.check_cigar_ends(p, t, r, *PEN, ends) == int(got[0][j])
