@@ -138,22 +138,28 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
         return (uint64_t)a.n + a.m > (uint64_t)b.n + b.m;
     });
+    // CIGAR history, first guess: a pair at 10 % divergence (score about
+    // 0.1 * L times the mean edit cost) keeps ~s'^2 / e' cells of 4.5 bytes
+    // (offset and record; 2.5 with 16-bit offsets) plus a 16-byte step-table
+    // entry per step, and its runs
+    auto hist_est = [&](uint32_t n, uint32_t m) -> double {
+        const double L = std::max(n, m);
+        const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
+        const double cellb = m < 0xFFFF ? 2.5 : 4.5;
+        return cellb * sg * sg / pen.e + 32.0 * sg + 4.0 * ((double)n + m + 1) + 4096.0;
+    };
+    // After each launch the guess is scaled by 1.25x the largest ratio of
+    // used to guessed bytes seen so far (never above the guess itself), so
+    // batches less divergent than the guess run more pairs at a time; pairs
+    // whose slice is still too small are re-run with 4x
+    double scale_seen = 0.0, hist_scale = 1.0;
     auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult) -> uint64_t {
         const uint64_t nm1 = (uint64_t)n + m + 1;
         uint64_t sl;
         sl = (R + 1) * 3 * 4 * (nm1 + 2);  // the ring of full-width rows and a NULL slot
-        if (cigar) {
-            // history, first guess: a pair at 10 % divergence (score about
-            // 0.1 * L times the mean edit cost) keeps ~s'^2 / e' cells of 4.5
-            // bytes (offset and record; 2.5 with 16-bit offsets) plus a 16-byte
-            // step-table entry per step, and its runs; pairs that need more
-            // are re-run with 4x
-            const double L = std::max(n, m);
-            const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
-            const double cellb = m < 0xFFFF ? 2.5 : 4.5;
-            const double est = cellb * sg * sg / pen.e + 32.0 * sg + 4.0 * (double)nm1 + 4096.0;
-            sl += (uint64_t)std::min(std::max(est, 16.0 * 1024), 64.0 * 1024 * 1024) * mult;
-        }
+        if (cigar)
+            sl += (uint64_t)std::min(std::max(hist_est(n, m) * hist_scale, 16.0 * 1024),
+                                     64.0 * 1024 * 1024) * mult;
         return (sl + 255) & ~(uint64_t)255;
     };
 
@@ -211,6 +217,10 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             RCCHK(ws.ensure(ws.job_nruns, nj * 4));
             RCCHK(ws.ensure(ws.job_offsets, (nj + 1) * 8));
             RCCHK(ws.ensure(ws.fail_list, nj * 4));
+            if (cigar) {
+                RCCHK(ws.ensure(ws.job_used, nj * 8));
+                HIPCHK(launch_fill_u64(ws.job_used.as<uint64_t>(), 0ull, nj, s));
+            }
             RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(nj) + 64));
             HIPCHK(hipMemcpyAsync(ws.jobs.ptr, ids.data(), nj * 4, hipMemcpyHostToDevice, s));
             HIPCHK(launch_fill_u32(ws.job_nruns.as<uint32_t>(), 0u, nj, s));
@@ -230,12 +240,23 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.nruns = ws.nruns.as<uint32_t>();
             g.run_src = ws.run_src.as<uint64_t>();
             g.job_nruns = ws.job_nruns.as<uint32_t>();
+            g.job_used = cigar ? ws.job_used.as<uint64_t>() : nullptr;
             g.fail_list = ws.fail_list.as<uint32_t>();
             g.fail_count = &flags->fail_count;
             HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, s));
             uint32_t nfail = 0;
             HIPCHK(hipMemcpyAsync(&nfail, &flags->fail_count, 4, hipMemcpyDeviceToHost, s));
+            std::vector<uint64_t> used(cigar ? nj : 0);
+            if (cigar)
+                HIPCHK(hipMemcpyAsync(used.data(), ws.job_used.ptr, nj * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            if (cigar) {
+                for (size_t i = 0; i < nj; i++)
+                    if (used[i])
+                        scale_seen = std::max(scale_seen, (double)used[i] /
+                                                              hist_est(jobs[off + i].n, jobs[off + i].m));
+                if (scale_seen > 0) hist_scale = std::min(1.0, std::max(1.0 / 16, 1.25 * scale_seen));
+            }
             if (nfail) {
                 std::vector<uint32_t> f(nfail);
                 HIPCHK(hipMemcpy(f.data(), ws.fail_list.ptr, nfail * 4ull, hipMemcpyDeviceToHost));

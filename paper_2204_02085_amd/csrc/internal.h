@@ -31,17 +31,17 @@ struct Workspace {
     // short kernel (slots2 / ovf_list2: the wider second pass)
     Buf nruns, run_src, slots, ovf_list, order, keys, hist, slots2, ovf_list2;
     // general kernel
-    Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp;
+    Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp, job_used;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
 
-    std::array<Buf*, 32> all() {
+    std::array<Buf*, 33> all() {
         return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,
                 &words_t, &packed_pairs, &in_pairs, &in_p,      &in_t,      &out_scores,
                 &out_runs, &out_offsets, &host_off, &host_loff, &nruns,   &run_src,
                 &slots,   &ovf_list,   &order,    &keys,        &hist,      &slots2,
                 &ovf_list2, &jobs,     &job_nruns, &job_offsets, &fail_list, &arena,
-                &gen_runs, &gen_tmp};
+                &gen_runs, &gen_tmp, &job_used};
     }
     int ensure(Buf& b, size_t bytes);
     // grow to at least `bytes`, keeping the first `keep` bytes (copied on `s`,

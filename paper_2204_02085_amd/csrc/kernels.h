@@ -92,6 +92,8 @@ struct GeneralArgs {
     uint32_t* nruns;
     uint64_t* run_src;          // offset (in uint32 words) of the job's runs in the arena
     uint32_t* job_nruns;        // [num_jobs] runs of each finished job (0 if it failed)
+    uint64_t* job_used;         // [num_jobs] CIGAR mode: slice bytes past the ring a
+                                // finished job used (history, step table, runs)
     uint32_t* fail_list;        // jobs whose slice was too small
     uint32_t* fail_count;
 };

@@ -1279,6 +1279,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     a.scores[pair] = S * a.pen.g;
     a.nruns[pair] = (uint32_t)nr;
     a.job_nruns[job] = (uint32_t)nr;
+    a.job_used[job] = (uint64_t)(bump - (R + 1) * full_row) + 16ull * (S + 1) + 4ull * nr;
     a.run_src[pair] = ((uint64_t)job * a.slice_bytes + (uint64_t)bump) / 4;  // arena words
 }
 
