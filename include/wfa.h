@@ -198,7 +198,9 @@ enum { WFA_OP_MATCH = 0, WFA_OP_MISMATCH = 1, WFA_OP_INS = 2, WFA_OP_DEL = 3 };
 #define WFA_MAX_LENGTH ((uint32_t)1 << 26) /* bases per sequence */
 
 /* Create a context on HIP device `device` whose device workspace may grow to
- * `hbm_budget_bytes` (0: 64 GiB).  *out receives the context. */
+ * `hbm_budget_bytes` (0: three quarters of the device's memory; the
+ * workspace only grows as far as the batches need).  *out receives the
+ * context. */
 int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx **out);
 
 /* Free the context and all device memory it owns.  NULL is ignored. */

@@ -122,7 +122,15 @@ int engine_init(Engine* e, int device, size_t budget) {
         return WFA_E_DEVICE;
     }
     e->device = device;
-    e->ws.budget = budget ? budget : ((size_t)64 << 30);
+    // default budget: three quarters of the device's memory (the workspace
+    // grows only as far as the batches need)
+    size_t total_mem = 0;
+    {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, device) == hipSuccess) total_mem = p.totalGlobalMem;
+        else (void)hipGetLastError();
+    }
+    e->ws.budget = budget ? budget : (total_mem ? total_mem / 4 * 3 : ((size_t)64 << 30));
     // default priority: every stream of the library runs at the same priority
     he = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking);
     if (he != hipSuccess) {
