@@ -880,6 +880,15 @@ struct SeqView {
         if (SEQ_LDS) return t[q];
         return q < nt32 ? t[q] : 0u;
     }
+    // 16 bases from base `pos` on (one 32-bit funnel shift)
+    __device__ __forceinline__ uint32_t win16P(int pos) const {
+        const int q = pos >> 4;
+        return __builtin_amdgcn_alignbit(P(q + 1), P(q), (uint32_t)(pos & 15) << 1);
+    }
+    __device__ __forceinline__ uint32_t win16T(int pos) const {
+        const int q = pos >> 4;
+        return __builtin_amdgcn_alignbit(T(q + 1), T(q), (uint32_t)(pos & 15) << 1);
+    }
     __device__ __forceinline__ uint64_t winP(int pos) const {
         const int q = pos >> 4;
         const uint32_t b = (uint32_t)(pos & 15) << 1;
@@ -900,6 +909,17 @@ template <bool SEQ_LDS>
 __device__ __forceinline__ int extend_general(const SeqView<SEQ_LDS>& sv, int n, int m, int k,
                                               int h) {
     int v = h - k;
+    // a 16-base compare first: most cells of a long, divergent pair stop
+    // within it, and a wave runs on to the 32-base compares only while one
+    // of its lanes still matches
+    if (v < n && h < m) {
+        const uint32_t d = sv.win16P(v) ^ sv.win16T(h);
+        int r = d ? (int)(__builtin_ctz(d) >> 1) : 16;
+        r = min(r, min(n - v, m - h));
+        v += r;
+        h += r;
+        if (r < 16) return h;
+    }
     while (v < n && h < m) {
         int r = common_prefix(sv.winP(v), sv.winT(h));
         r = min(r, min(n - v, m - h));
