@@ -49,8 +49,9 @@
  * while chunk i aligns, one library thread copies chunk i+1's descriptors
  * and sequence bytes to the device and another copies chunk i-1's scores,
  * offsets and runs back, each on a stream of its own.  Host buffers from
- * wfa_host_alloc (page-locked) move at the full link rate; ordinary
- * pageable buffers work too, through the HIP runtime's staging.
+ * wfa_host_alloc (page-locked) move by DMA at the full link rate; ordinary
+ * pageable buffers go through page-locked staging slots that library
+ * threads fill and empty while the DMA engine moves the previous slot.
  *
  * Ownership.  The caller owns every input and output buffer; the library
  * keeps no caller pointer after a call returns.  The library owns its

@@ -15,6 +15,7 @@
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -51,6 +52,94 @@ namespace {
 constexpr size_t MIN_CHUNK = 262144;
 constexpr size_t MAX_CHUNK = 2097152;
 constexpr size_t MAX_CHUNKS = 1024;  // bounds the host-side bookkeeping
+
+// A pool of host threads that copy one buffer into another in equal parts
+// (the caller copies one part itself); used to move pageable caller memory
+// through page-locked staging slots at several times one thread's rate.
+class CopyPool {
+  public:
+    explicit CopyPool(unsigned workers) {
+        try {
+            for (unsigned i = 0; i < workers; i++) th_.emplace_back([this, i] { run(i + 1); });
+        } catch (...) {
+            // fewer workers: the caller covers the missing parts
+        }
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    void copy(void* dst, const void* src, size_t bytes) {
+        const unsigned parts = (unsigned)th_.size() + 1;
+        if (parts == 1 || bytes < ((size_t)1 << 20)) {
+            std::memcpy(dst, src, bytes);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            dst_ = (unsigned char*)dst;
+            src_ = (const unsigned char*)src;
+            bytes_ = bytes;
+            parts_ = parts;
+            left_ = parts - 1;
+            gen_++;
+        }
+        cv_.notify_all();
+        part(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [&] { return left_ == 0; });
+    }
+
+  private:
+    void part(unsigned i) {
+        const size_t per = ((bytes_ / parts_) + 63) & ~(size_t)63;
+        const size_t a = std::min(bytes_, per * i), b = std::min(bytes_, per * (i + 1));
+        if (b > a) std::memcpy(dst_ + a, src_ + a, b - a);
+    }
+    void run(unsigned i) {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+            }
+            part(i);
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                left_--;
+            }
+            done_.notify_one();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    uint64_t gen_ = 0;
+    unsigned parts_ = 1, left_ = 0;
+    bool stop_ = false;
+    unsigned char* dst_ = nullptr;
+    const unsigned char* src_ = nullptr;
+    size_t bytes_ = 0;
+};
+
+// Whether `p` is page-locked host memory the DMA engines can read directly.
+bool page_locked(const void* p) {
+    if (!p) return true;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeHost;
+}
+
+constexpr size_t STAGE_SLOT = (size_t)32 << 20;  // bytes per staging slot (two per direction)
 
 double wall_ms() {
     using namespace std::chrono;
@@ -241,6 +330,90 @@ int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, siz
         HIPCHK(hipStreamWaitEvent(e->h2d, e->ev[7], 0));
     }
 
+    // Caller memory that is not page-locked moves through page-locked
+    // staging: two slots per direction, filled (inputs) or emptied (results)
+    // by a pool of host threads while the DMA engine works on the other slot.
+    const bool locked_in = page_locked(io.pairs) && page_locked(io.patterns) &&
+                           page_locked(io.texts);
+    const bool locked_out = page_locked(io.scores) &&
+                            (!cigar || (page_locked(io.offsets) && page_locked(io.runs)));
+    unsigned char* stage_in = nullptr;
+    unsigned char* stage_out = nullptr;
+    hipEvent_t sev[4] = {};
+    auto destroy_stage_events = [&]() {
+        for (auto& v : sev)
+            if (v) (void)hipEventDestroy(v);
+    };
+    if (!locked_in || !locked_out) {
+        RCCHK(ws.ensure_pinned(4 * STAGE_SLOT));
+        stage_in = (unsigned char*)ws.pinned;
+        stage_out = stage_in + 2 * STAGE_SLOT;
+        for (auto& v : sev) {
+            if (hipEventCreateWithFlags(&v, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                destroy_stage_events();
+                destroy_events();
+                return WFA_E_DEVICE;
+            }
+        }
+    }
+    const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
+    std::unique_ptr<CopyPool> pool_in, pool_out;
+    if (!locked_in) pool_in.reset(new CopyPool(std::min(7u, std::max(1u, hc / 2)) - 1));
+    if (!locked_out) pool_out.reset(new CopyPool(std::min(3u, std::max(1u, hc / 4)) - 1));
+    bool in_used[2] = {false, false};
+    int in_next = 0;
+    // host -> device, on h2d (returns once the caller's bytes are read or staged)
+    auto to_device = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (locked_in) {
+            HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, e->h2d));
+            return WFA_OK;
+        }
+        for (size_t off = 0; off < bytes; off += STAGE_SLOT) {
+            const size_t len = std::min(STAGE_SLOT, bytes - off);
+            const int sl = in_next;
+            in_next ^= 1;
+            if (in_used[sl]) HIPCHK(hipEventSynchronize(sev[sl]));
+            unsigned char* slot = stage_in + sl * STAGE_SLOT;
+            pool_in->copy(slot, (const unsigned char*)src + off, len);
+            HIPCHK(hipMemcpyAsync((unsigned char*)dst + off, slot, len, hipMemcpyHostToDevice,
+                                  e->h2d));
+            HIPCHK(hipEventRecord(sev[sl], e->h2d));
+            in_used[sl] = true;
+        }
+        return WFA_OK;
+    };
+    // device -> host, on d2h, after what d2h already waits for (returns with
+    // the bytes in caller memory when staged, else with the copy enqueued)
+    auto to_host = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (locked_out) {
+            HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, e->d2h));
+            return WFA_OK;
+        }
+        // piece i + 1 moves into one slot while piece i leaves the other
+        size_t prev_off = 0, prev_len = 0;
+        int prev_sl = -1, sl = 0;
+        for (size_t off = 0;; off += STAGE_SLOT) {
+            const size_t len = off < bytes ? std::min(STAGE_SLOT, bytes - off) : 0;
+            if (len) {
+                HIPCHK(hipMemcpyAsync(stage_out + sl * STAGE_SLOT, (const unsigned char*)src + off,
+                                      len, hipMemcpyDeviceToHost, e->d2h));
+                HIPCHK(hipEventRecord(sev[2 + sl], e->d2h));
+            }
+            if (prev_sl >= 0) {
+                HIPCHK(hipEventSynchronize(sev[2 + prev_sl]));
+                pool_out->copy((unsigned char*)dst + prev_off, stage_out + prev_sl * STAGE_SLOT,
+                               prev_len);
+            }
+            if (!len) break;
+            prev_sl = sl;
+            prev_off = off;
+            prev_len = len;
+            sl ^= 1;
+        }
+        return WFA_OK;
+    };
+
     Progress pr;
     // stage 1: inputs of every chunk, in order, on h2d
     auto copy_in = [&]() -> int {
@@ -248,16 +421,15 @@ int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, siz
         for (size_t k = 0; k < K; k++) {
             if (pr.failed()) return WFA_OK;
             const Chunk& c = ch[k];
-            HIPCHK(hipMemcpyAsync(ws.in_pairs.as<wfa_pair>() + c.first, io.pairs + c.first,
-                                  c.n * sizeof(wfa_pair), hipMemcpyHostToDevice, e->h2d));
+            RCCHK(to_device(ws.in_pairs.as<wfa_pair>() + c.first, io.pairs + c.first,
+                            c.n * sizeof(wfa_pair)));
             if (c.p_hi > c.p_lo)
-                HIPCHK(hipMemcpyAsync(ws.in_p.as<uint8_t>() + c.p_lo * unit,
-                                      (const uint8_t*)io.patterns + c.p_lo * unit,
-                                      (c.p_hi - c.p_lo) * unit, hipMemcpyHostToDevice, e->h2d));
+                RCCHK(to_device(ws.in_p.as<uint8_t>() + c.p_lo * unit,
+                                (const uint8_t*)io.patterns + c.p_lo * unit,
+                                (c.p_hi - c.p_lo) * unit));
             if (c.t_hi > c.t_lo)
-                HIPCHK(hipMemcpyAsync(ws.in_t.as<uint8_t>() + c.t_lo * unit,
-                                      (const uint8_t*)io.texts + c.t_lo * unit,
-                                      (c.t_hi - c.t_lo) * unit, hipMemcpyHostToDevice, e->h2d));
+                RCCHK(to_device(ws.in_t.as<uint8_t>() + c.t_lo * unit,
+                                (const uint8_t*)io.texts + c.t_lo * unit, (c.t_hi - c.t_lo) * unit));
             HIPCHK(hipEventRecord(ev_in[k], e->h2d));
             pr.publish(&pr.in_issued, k + 1);
         }
@@ -270,15 +442,13 @@ int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, siz
             if (!pr.wait(&pr.aligned, k + 1)) return WFA_OK;
             const Chunk& c = ch[k];
             HIPCHK(hipStreamWaitEvent(e->d2h, ev_al[k], 0));
-            HIPCHK(hipMemcpyAsync(io.scores + c.first, ws.out_scores.as<int32_t>() + c.first,
-                                  c.n * 4, hipMemcpyDeviceToHost, e->d2h));
+            RCCHK(to_host(io.scores + c.first, ws.out_scores.as<int32_t>() + c.first, c.n * 4));
             if (cigar) {
-                HIPCHK(hipMemcpyAsync(io.offsets + c.first, ws.host_off.as<uint64_t>() + c.first,
-                                      (c.n + 1) * 8, hipMemcpyDeviceToHost, e->d2h));
+                RCCHK(to_host(io.offsets + c.first, ws.host_off.as<uint64_t>() + c.first,
+                              (c.n + 1) * 8));
                 if (c.runs && c.run_base + c.runs <= io.capacity)
-                    HIPCHK(hipMemcpyAsync(io.runs + c.run_base,
-                                          ws.out_runs.as<uint32_t>() + c.run_base, c.runs * 4,
-                                          hipMemcpyDeviceToHost, e->d2h));
+                    RCCHK(to_host(io.runs + c.run_base, ws.out_runs.as<uint32_t>() + c.run_base,
+                                  c.runs * 4));
             }
             HIPCHK(hipStreamSynchronize(e->d2h));
             pr.publish(&pr.out_done, k + 1);
@@ -398,6 +568,7 @@ int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, siz
                         hipStreamSynchronize(e->d2h) == hipSuccess;
     if (!synced) (void)hipGetLastError();
     destroy_events();
+    destroy_stage_events();
     for (int rc : {rc_al, rc_in, rc_out}) {
         if (rc != WFA_OK) {
             if (bad_pair && chunk_bad >= 0) *bad_pair = chunk_bad;
