@@ -8,6 +8,10 @@
 // at the caller's own offsets (so the descriptors need no rewriting), the
 // scores, the offsets counted from the batch's first run, and every run, so
 // wfa_copy_last_cigars can serve a call that ran out of run capacity.
+//
+// Page-locked caller buffers move by DMA directly; pageable ones pass
+// through two page-locked staging slots per direction that a pool of host
+// threads fills or empties while the DMA engine works on the other slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
