@@ -123,7 +123,9 @@ typedef struct {
     int32_t window;         /* diagonals held per pair by the short kernel:
                                16, 24, 32, 48, 64, 128, 256 */
     int32_t step_cap;       /* score steps (in units of gcd(x,o,e)) held in LDS  */
-    int32_t use_graph;      /* 1: replay a captured hipGraph; -1: never; 0: auto */
+    int32_t use_graph;      /* 1: replay captured hipGraphs of the work before and
+                               after the short kernel; -1: never; 0: for the
+                               persistent and automatic schedules */
     int32_t bucket;         /* 1: sort pairs by (length, length difference); -1: off */
     int32_t general_pairs;  /* concurrent pairs of the general kernel; 0: by budget */
     int32_t block_threads;  /* threads per workgroup of the short kernel: 64..256 */

@@ -397,8 +397,8 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     }
     const bool persistent = use_short && schedule != WFA_SCHED_PLAIN;
     const bool bucket = persistent && e->opt.bucket >= 0;
+    // graphs: by default for the persistent schedule; the plain one only on request
     const bool graph = use_short && !io.no_graph && e->opt.use_graph >= 0 &&
-                       schedule != WFA_SCHED_PLAIN &&
                        (e->opt.use_graph > 0 || schedule == WFA_SCHED_AUTO ||
                         schedule == WFA_SCHED_PERSISTENT);
 

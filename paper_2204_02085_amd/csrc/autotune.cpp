@@ -298,7 +298,7 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
                     c.opt.step_cap = capx;
                     c.opt.block_threads = bt;
                     c.opt.bucket = form == 1 ? 1 : -1;
-                    c.opt.use_graph = form == 0 ? -1 : 1;
+                    c.opt.use_graph = 1;  // pre/post phases replayed in every form
                     const int r = evaluate(c, 5);
                     if (r != WFA_OK && r != WFA_E_NOMEM) {
                         status = r;
