@@ -363,8 +363,11 @@ int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, siz
     }
     const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
     std::unique_ptr<CopyPool> pool_in, pool_out;
-    if (!locked_in) pool_in.reset(new CopyPool(std::min(7u, std::max(1u, hc / 2)) - 1));
-    if (!locked_out) pool_out.reset(new CopyPool(std::min(3u, std::max(1u, hc / 4)) - 1));
+    // helper threads only for batches large enough to repay starting them
+    const uint64_t in_bytes = N * sizeof(wfa_pair) + (hp + ht) * unit;
+    const bool big = in_bytes >= ((uint64_t)64 << 20);
+    if (!locked_in) pool_in.reset(new CopyPool(big ? std::min(7u, std::max(1u, hc / 2)) - 1 : 0));
+    if (!locked_out) pool_out.reset(new CopyPool(big ? std::min(3u, std::max(1u, hc / 4)) - 1 : 0));
     bool in_used[2] = {false, false};
     int in_next = 0;
     // host -> device, on h2d (returns once the caller's bytes are read or staged)
