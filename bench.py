@@ -62,7 +62,8 @@ def parse():
                          "the main workload; 'none' or empty: skip")
     ap.add_argument("--other-configs", type=int, default=1,
                     help="also time the uneven (2M pairs, autotuned) and long-read (100k pairs, "
-                         "score-only and CIGAR) configurations once each (0: skip)")
+                         "score-only and CIGAR) configurations, and the main workload score-only "
+                         "and ends-free (0: skip)")
     ap.add_argument("--host-steps", type=int, default=2,
                     help="calls timed with host ASCII inputs and host outputs (PCIe "
                          "included; 0: skip)")
@@ -416,17 +417,20 @@ def main():
 
     # the other configurations, for the record: 2 M uneven pairs (one
     # persistent bucketed graph-replayed launch, autotuned), 100 k long
-    # pairs (general kernel), and the main workload aligned ends-free (up to
-    # 10 bases of either sequence free at either end, autotuned), timed after
-    # one warm-up call
+    # pairs (general kernel), the main workload in score-only mode, and the
+    # main workload aligned ends-free (up to 10 bases of either sequence free
+    # at either end, autotuned), timed after one warm-up call
     others = None
     if args.other_configs:
         others = {}
         for name, count, tune, modes, ends in [
                 ("uneven50_300_2m", 2_000_000, True, ("cigar",), None),
                 ("long1k_10k_100k", 100_000, False, ("score", "cigar"), None),
+                (args.workload, args.pairs, True, ("score",), None),
                 (args.workload, args.pairs, True, ("cigar",), (10, 10, 10, 10))]:
             label = name if ends is None else name + "_ends_free_" + "_".join(map(str, ends))
+            if name == args.workload and ends is None:
+                label = name + "_score_only"
             log(f"configuration {label}: {count} pairs")
             al.set_ends_free(*(ends or ()))
             bo = synth.workload(name, count)
