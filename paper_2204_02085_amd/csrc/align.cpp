@@ -525,7 +525,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     auto phase_post = [&](hipStream_t q) -> int {
         if (cigar && use_short) {
             HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, d.offsets, ws.scan_tmp.ptr, q));
-            HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+            HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                   ws.gen_runs.as<uint32_t>(), d.offsets,
                                   N, d.runs, d.capacity, q));
@@ -695,7 +695,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             total = short_total;
         }
         if (rescan && total <= d.capacity)
-            HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+            HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                   ws.gen_runs.as<uint32_t>(), d.offsets, N,
                                   d.runs, d.capacity, s));

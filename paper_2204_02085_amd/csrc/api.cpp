@@ -358,7 +358,7 @@ extern "C" int wfa_copy_last_cigars(wfa_ctx* ctx, uint32_t* runs, size_t capacit
         if (rc != WFA_OK) return rc;
         uint64_t* off = ws.out_offsets.as<uint64_t>();
         API_HIPCHK(launch_scan(SCAN_U32, ws.nruns.ptr, N, off, ws.scan_tmp.ptr, s));
-        API_HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+        API_HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                   ws.gen_runs.as<uint32_t>(), off, N, runs,
                                   capacity, s));

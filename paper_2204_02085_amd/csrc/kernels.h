@@ -149,10 +149,9 @@ hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_l
 // SLOTS2_BIT set, or into `gen_runs` with GEN_BIT set
 constexpr uint64_t GEN_BIT = 1ULL << 63;
 constexpr uint64_t SLOTS2_BIT = 1ULL << 62;
-hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const uint32_t* slots,
-                          const uint32_t* slots2, const uint32_t* gen_runs,
-                          const uint64_t* offsets, size_t n, uint32_t* out, uint64_t capacity,
-                          hipStream_t s);
+hipError_t launch_compact(const uint64_t* run_src, const uint32_t* slots, const uint32_t* slots2,
+                          const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
+                          uint32_t* out, uint64_t capacity, hipStream_t s);
 
 // Counting sort of pairs by expected work: keys + histogram, then (after an
 // exclusive scan of the histogram into `cursor`) the scatter into `order`.

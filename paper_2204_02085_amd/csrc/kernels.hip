@@ -1332,36 +1332,62 @@ __global__ void k_pair_lengths(const PairDesc* __restrict__ pairs, const uint32_
 }
 
 // reversed runs -> caller buffer in alignment order (nothing is written if
-// the total exceeds the capacity).  One thread per pair: its counters load
-// together and its runs move COMPACT_UNROLL at a time, so a wave keeps many
-// independent loads in flight (neighbouring pairs' runs are neighbours in
-// the slots and in the output).
-constexpr int COMPACT_UNROLL = 8;
+// the total exceeds the capacity).  A block takes COMPACT_PAIRS consecutive
+// pairs and fills their whole output range [offsets[first], offsets[first +
+// COMPACT_PAIRS]) with consecutive threads on consecutive runs, so every
+// store is coalesced.  A thread finds the pair of output position q by a
+// binary search over the tile's run ends in LDS; the pair's runs sit in its
+// slot in backtrace order, so position q takes slot entry end - 1 - q.
+// Reads stay scattered across pairs (slots follow the bucketed order), but
+// a wave's 64 positions touch only the few pairs they belong to.
+constexpr int COMPACT_PAIRS = 256;
+constexpr int COMPACT_UNROLL = 4;
 
-__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ nruns,
-                                                 const uint64_t* __restrict__ run_src,
-                                                 const uint32_t* __restrict__ slots,
-                                                 const uint32_t* __restrict__ slots2,
-                                                 const uint32_t* __restrict__ gen_runs,
-                                                 const uint64_t* __restrict__ offsets, size_t n,
-                                                 uint32_t* __restrict__ out, uint64_t capacity) {
+__global__ __launch_bounds__(COMPACT_PAIRS) void k_compact(const uint64_t* __restrict__ run_src,
+                                                           const uint32_t* __restrict__ slots,
+                                                           const uint32_t* __restrict__ slots2,
+                                                           const uint32_t* __restrict__ gen_runs,
+                                                           const uint64_t* __restrict__ offsets,
+                                                           size_t n, uint32_t* __restrict__ out,
+                                                           uint64_t capacity) {
+    __shared__ uint64_t end[COMPACT_PAIRS];
+    __shared__ const uint32_t* src_of[COMPACT_PAIRS];
     if (offsets[n] > capacity) return;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t cnt = nruns[i];
-        const uint64_t src = run_src[i];
-        const uint64_t dst = offsets[i];
-        const uint64_t off = src & ~(GEN_BIT | SLOTS2_BIT);
-        const uint32_t* sp = (src & GEN_BIT) ? gen_runs + off : ((src & SLOTS2_BIT) ? slots2 : slots) + off;
-        uint32_t* o = out + dst + cnt - 1;
-        for (uint32_t r0 = 0; r0 < cnt; r0 += COMPACT_UNROLL) {
+    const int t = threadIdx.x;
+    const size_t tiles = (n + COMPACT_PAIRS - 1) / COMPACT_PAIRS;
+    for (size_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const size_t first = tile * COMPACT_PAIRS;
+        const int np = (int)min((size_t)COMPACT_PAIRS, n - first);
+        if (t < np) {
+            const uint64_t src = run_src[first + t];
+            const uint64_t off = src & ~(GEN_BIT | SLOTS2_BIT);
+            src_of[t] = (src & GEN_BIT) ? gen_runs + off : ((src & SLOTS2_BIT) ? slots2 : slots) + off;
+            end[t] = offsets[first + t + 1];
+        }
+        __syncthreads();
+        const uint64_t lo = offsets[first], hi = end[np - 1];
+        for (uint64_t q0 = lo + t; q0 < hi; q0 += COMPACT_PAIRS * COMPACT_UNROLL) {
             uint32_t v[COMPACT_UNROLL];
 #pragma unroll
-            for (int u = 0; u < COMPACT_UNROLL; u++) v[u] = r0 + u < cnt ? sp[r0 + u] : 0u;
+            for (int u = 0; u < COMPACT_UNROLL; u++) {
+                const uint64_t q = q0 + (uint64_t)u * COMPACT_PAIRS;
+                if (q < hi) {
+                    // p = number of tile pairs whose runs end at or before q
+                    // (ends never decrease); q < hi keeps p below np
+                    int p = 0;
 #pragma unroll
-            for (int u = 0; u < COMPACT_UNROLL; u++)
-                if (r0 + u < cnt) o[-(int64_t)(r0 + u)] = v[u];
+                    for (int step = COMPACT_PAIRS / 2; step; step >>= 1)
+                        if (p + step <= np && end[p + step - 1] <= q) p += step;
+                    v[u] = src_of[p][end[p] - 1 - q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < COMPACT_UNROLL; u++) {
+                const uint64_t q = q0 + (uint64_t)u * COMPACT_PAIRS;
+                if (q < hi) out[q] = v[u];
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -1620,13 +1646,12 @@ hipError_t launch_pair_lengths(const PairDesc* pairs, const uint32_t* idx, size_
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const uint32_t* nruns, const uint64_t* run_src, const uint32_t* slots,
-                          const uint32_t* slots2, const uint32_t* gen_runs,
-                          const uint64_t* offsets, size_t n, uint32_t* out, uint64_t capacity,
-                          hipStream_t s) {
+hipError_t launch_compact(const uint64_t* run_src, const uint32_t* slots, const uint32_t* slots2,
+                          const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
+                          uint32_t* out, uint64_t capacity, hipStream_t s) {
     if (n)
-        hipLaunchKernelGGL(k_compact, dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s,
-                           nruns, run_src, slots, slots2, gen_runs, offsets, n, out, capacity);
+        hipLaunchKernelGGL(k_compact, dim3(grid_for(n, COMPACT_PAIRS, 1 << 20)), dim3(COMPACT_PAIRS),
+                           0, s, run_src, slots, slots2, gen_runs, offsets, n, out, capacity);
     return hipGetLastError();
 }
 

@@ -508,7 +508,7 @@ int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, siz
                 // the buffer has grown
                 if (!pr.wait(&pr.out_done, k)) return WFA_OK;
                 RCCHK(ws.grow_keep(ws.out_runs, (base + needed + 1) * 4, base * 4, e->stream));
-                HIPCHK(launch_compact(ws.nruns.as<uint32_t>(), ws.run_src.as<uint64_t>(),
+                HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                       ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                       ws.gen_runs.as<uint32_t>(), ws.host_loff.as<uint64_t>(), c.n,
                                       ws.out_runs.as<uint32_t>() + base, needed, e->stream));
