@@ -298,6 +298,43 @@ def test_very_long_pair_sequences_outside_lds(aligner, oracle_lib, synth_lib):
     check_invariants_vectorized(b, *got, PEN)
 
 
+def test_history_offset_width_boundary(aligner, oracle_lib, synth_lib):
+    """Texts of 65,532-65,537 bases, where the general kernel's CIGAR history
+    switches from 16-bit offsets (texts below 65,535 bases, 0xFFFF kept for
+    NULL) to 32-bit ones.  Edits sit next to both ends and in between, so the
+    backtrace reads history entries at the largest offsets; global and
+    ends-free, byte-exact against the oracle."""
+    rng = np.random.default_rng(65535)
+    pairs = []
+    for m in (65532, 65533, 65534, 65535, 65536, 65537):
+        t = bytearray(rng.choice(list(b"ACGT"), size=m).astype(np.uint8).tobytes())
+        p = bytearray(t)
+        spots = sorted({m - 1, m - 3, m - 9, 2, 0, *rng.integers(10, m - 20, 5).tolist()},
+                       reverse=True)
+        for j, pos in enumerate(spots):
+            kind = (j + m) % 3
+            if kind == 0:
+                p[pos] = b"ACGT"[(b"ACGT".index(p[pos]) + 1) % 4]
+            elif kind == 1:
+                p[pos:pos] = b"T"
+            else:
+                del p[pos]
+        pairs.append((bytes(p), bytes(t)))
+    b = synth_lib.from_pairs(pairs)
+    assert sorted(b.t_len.tolist()) == [65532, 65533, 65534, 65535, 65536, 65537]
+    for ends in ((0, 0, 0, 0), (3, 4, 5, 2)):
+        say(f"case: texts of 65532-65537 bases, ends {ends}, score + CIGAR")
+        aligner.set_ends_free(*ends)
+        try:
+            got = aligner.align(b, PEN, capacity=10_000)
+        finally:
+            aligner.set_ends_free()
+        ref = oracle_lib.align_batch(b, PEN, cigar=True, threads=8, ends=ends)
+        assert_same(got, ref, b, f"history width boundary, ends {ends}")
+        if ends == (0, 0, 0, 0):
+            check_invariants_vectorized(b, *got, PEN)
+
+
 def test_capacity_error_then_copy(aligner, oracle_lib, synth_lib, wfa):
     """A too-small CIGAR buffer returns WFA_E_CAPACITY with the needed size;
     wfa_copy_last_cigars then delivers the same runs."""
