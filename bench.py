@@ -77,10 +77,14 @@ def parse():
                     help="oracle sample size for the CPU baseline, about 15 s of CPU time "
                          "on 16 threads (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--serving-requests", type=int, default=120,
+    ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving run (0: skip)")
     ap.add_argument("--serving-load", type=float, default=0.75,
-                    help="offered load as a fraction of the measured saturation rate")
+                    help="offered load (fraction of the measured saturation rate) whose "
+                         "latencies are reported as the serving p50/p99")
+    ap.add_argument("--serving-sweep", default="0.25,0.5",
+                    help="further offered loads of the rate sweep, comma-separated ('none': "
+                         "only --serving-load)")
     return ap.parse_args()
 
 
@@ -205,11 +209,12 @@ def host_path_run(al, wfa, batch, steps, options):
     return out, scores
 
 
-def serving_run(al, wfa, synth, n_req, load, seed=11):
+def serving_run(al, wfa, synth, n_req, load, sweep=(), seed=11):
     """Poisson requests of 1-4096 pairs (log-uniform), 100-10,000 bp reads
     with 1-10 % edits, CIGAR mode, 64 GiB admission budget, 4 streams.
-    First all requests at once (saturation), then Poisson arrivals at
-    `load` x the saturation request rate; latency = done - submit."""
+    First all requests at once (saturation), then Poisson arrivals at each
+    offered load of the sweep (a fraction of the saturation request rate,
+    `load` among them); latency = done - submit."""
     import threading
 
     import numpy as np
@@ -259,14 +264,23 @@ def serving_run(al, wfa, synth, n_req, load, seed=11):
     sat = run(np.zeros(n_req))
     log(f"serving saturation: {sat}")
     sat_req_rate = n_req / (sat["wall_s"])
-    lam = load * sat_req_rate
-    gaps = rng.exponential(1.0 / lam, n_req)
-    loaded = run(gaps)
+    unit_gaps = rng.exponential(1.0, n_req)  # one arrival pattern, scaled per load
+    swept, loaded = [], None
+    for f in sorted(set(sweep) | {load}):
+        lam = f * sat_req_rate
+        r = run(unit_gaps / lam)
+        r.update({"offered_load": f, "offered_req_per_s": lam,
+                  "offered_pairs_per_s": f * sat_req_rate * total_pairs / n_req})
+        log(f"serving at load {f}: {r}")
+        swept.append(r)
+        if f == load:
+            loaded = r
     return {"workload": "serving_mix: Poisson requests of 1-4096 pairs (log-uniform), "
                         "100-10,000 bp log-uniform, 1-10 % edits, CIGAR",
             "requests": n_req, "pairs": total_pairs, "budget_gib": 64, "streams": 4,
-            "saturation": sat, "offered_load": load, "offered_req_per_s": lam,
-            "at_load": loaded, "p50_ms": loaded["p50_ms"], "p99_ms": loaded["p99_ms"]}
+            "saturation": sat, "offered_load": load, "offered_req_per_s": loaded["offered_req_per_s"],
+            "at_load": loaded, "sweep": swept,
+            "p50_ms": loaded["p50_ms"], "p99_ms": loaded["p99_ms"]}
 
 
 def main():
@@ -474,7 +488,9 @@ def main():
     serving = None
     if args.serving_requests > 0:
         log(f"serving run: {args.serving_requests} requests")
-        serving = serving_run(al, wfa, synth, args.serving_requests, args.serving_load)
+        sweep = () if args.serving_sweep == "none" else \
+            tuple(float(v) for v in args.serving_sweep.split(",") if v.strip())
+        serving = serving_run(al, wfa, synth, args.serving_requests, args.serving_load, sweep)
 
     roofline = None
     if cells_pp is not None and kernel_ms > 0:
