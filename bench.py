@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--serving-load", type=float, default=0.75,
                     help="offered load (fraction of the measured saturation rate) whose "
                          "latencies are reported as the serving p50/p99")
+    ap.add_argument("--serving-chunk", type=int, default=2048,
+                    help="most pairs per batch the server launches (max_chunk_pairs)")
     ap.add_argument("--serving-sweep", default="0.25,0.5",
                     help="further offered loads of the rate sweep, comma-separated ('none': "
                          "only --serving-load)")
@@ -209,7 +211,7 @@ def host_path_run(al, wfa, batch, steps, options):
     return out, scores
 
 
-def serving_run(al, wfa, synth, n_req, load, sweep=(), seed=11):
+def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=2048, seed=11):
     """Poisson requests of 1-4096 pairs (log-uniform), 100-10,000 bp reads
     with 1-10 % edits, CIGAR mode, 64 GiB admission budget, 4 streams.
     First all requests at once (saturation), then Poisson arrivals at each
@@ -228,7 +230,7 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), seed=11):
     total_pairs = int(sizes.sum())
 
     def run(gaps):
-        srv = wfa.Server(al, hbm_budget_bytes=64 << 30, streams=4, max_chunk_pairs=16384)
+        srv = wfa.Server(al, hbm_budget_bytes=64 << 30, streams=4, max_chunk_pairs=chunk)
         tickets = [None] * n_req
 
         def client():
@@ -278,6 +280,7 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), seed=11):
     return {"workload": "serving_mix: Poisson requests of 1-4096 pairs (log-uniform), "
                         "100-10,000 bp log-uniform, 1-10 % edits, CIGAR",
             "requests": n_req, "pairs": total_pairs, "budget_gib": 64, "streams": 4,
+            "max_chunk_pairs": chunk,
             "saturation": sat, "offered_load": load, "offered_req_per_s": loaded["offered_req_per_s"],
             "at_load": loaded, "sweep": swept,
             "p50_ms": loaded["p50_ms"], "p99_ms": loaded["p99_ms"]}
@@ -490,7 +493,8 @@ def main():
         log(f"serving run: {args.serving_requests} requests")
         sweep = () if args.serving_sweep == "none" else \
             tuple(float(v) for v in args.serving_sweep.split(",") if v.strip())
-        serving = serving_run(al, wfa, synth, args.serving_requests, args.serving_load, sweep)
+        serving = serving_run(al, wfa, synth, args.serving_requests, args.serving_load, sweep,
+                              args.serving_chunk)
 
     roofline = None
     if cells_pp is not None and kernel_ms > 0:
