@@ -82,7 +82,7 @@ def parse():
     ap.add_argument("--serving-load", type=float, default=0.75,
                     help="offered load (fraction of the measured saturation rate) whose "
                          "latencies are reported as the serving p50/p99")
-    ap.add_argument("--serving-chunk", type=int, default=2048,
+    ap.add_argument("--serving-chunk", type=int, default=16384,
                     help="most pairs per batch the server launches (max_chunk_pairs)")
     ap.add_argument("--serving-sweep", default="0.25,0.5",
                     help="further offered loads of the rate sweep, comma-separated ('none': "
@@ -211,7 +211,7 @@ def host_path_run(al, wfa, batch, steps, options):
     return out, scores
 
 
-def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=2048, seed=11):
+def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=16384, seed=11):
     """Poisson requests of 1-4096 pairs (log-uniform), 100-10,000 bp reads
     with 1-10 % edits, CIGAR mode, 64 GiB admission budget, 4 streams.
     First all requests at once (saturation), then Poisson arrivals at each
@@ -220,6 +220,7 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=2048, seed=11):
     import threading
 
     import numpy as np
+    import torch
 
     rng = np.random.default_rng(seed)
     sizes = np.round(2.0 ** rng.uniform(0, 12, n_req)).astype(int)
@@ -229,8 +230,11 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=2048, seed=11):
         first += int(k)
     total_pairs = int(sizes.sum())
 
+    # one long-lived server for the whole sweep, as a service would run
+    srv = wfa.Server(al, hbm_budget_bytes=64 << 30, streams=4, max_chunk_pairs=chunk)
+
     def run(gaps):
-        srv = wfa.Server(al, hbm_budget_bytes=64 << 30, streams=4, max_chunk_pairs=chunk)
+        st0 = srv.stats()
         tickets = [None] * n_req
 
         def client():
@@ -249,7 +253,8 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=2048, seed=11):
         res = [srv.poll(t) for t in tickets]
         t1 = time.perf_counter()
         st = srv.stats()
-        srv.close()
+        for t in tickets:
+            srv.release(t)
         bad = [r for r in res if r["status"] != 0]
         if bad:
             codes = sorted({int(r["status"]) for r in bad})
@@ -259,28 +264,37 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=2048, seed=11):
         span = max(r["done"] for r in res) - min(r["submit"] for r in res)
         return {"pairs_per_s": total_pairs / span, "wall_s": t1 - t0,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "admit_wait_p99_ms": float(np.percentile(wait, 99)), "batches": st["batches"],
-                "max_reserved_gib": st["max_reserved_bytes"] / 2**30}
+                "admit_wait_p99_ms": float(np.percentile(wait, 99)),
+                "batches": st["batches"] - st0["batches"],
+                "engine_busy_s": st["busy_s"] - st0["busy_s"]}
 
-    log(f"serving: {n_req} requests, {total_pairs} pairs; saturation run")
+    free_b, total_b = torch.cuda.mem_get_info()
+    log(f"serving: {n_req} requests, {total_pairs} pairs; device memory free "
+        f"{free_b / 2**30:.1f} of {total_b / 2**30:.1f} GiB; saturation run")
     sat = run(np.zeros(n_req))
     log(f"serving saturation: {sat}")
     sat_req_rate = n_req / (sat["wall_s"])
     unit_gaps = rng.exponential(1.0, n_req)  # one arrival pattern, scaled per load
     swept, loaded = [], None
-    for f in sorted(set(sweep) | {load}):
+    order = list(sweep) + ([] if load in sweep else [load])
+    for f in order:
         lam = f * sat_req_rate
+        free_b, _ = torch.cuda.mem_get_info()
+        log(f"serving at load {f}: device memory free {free_b / 2**30:.1f} GiB")
         r = run(unit_gaps / lam)
         r.update({"offered_load": f, "offered_req_per_s": lam,
                   "offered_pairs_per_s": f * sat_req_rate * total_pairs / n_req})
         log(f"serving at load {f}: {r}")
         swept.append(r)
-        if f == load:
+        if f == load and loaded is None:
             loaded = r
+    max_reserved = srv.stats()["max_reserved_bytes"] / 2**30
+    srv.close()
     return {"workload": "serving_mix: Poisson requests of 1-4096 pairs (log-uniform), "
                         "100-10,000 bp log-uniform, 1-10 % edits, CIGAR",
             "requests": n_req, "pairs": total_pairs, "budget_gib": 64, "streams": 4,
-            "max_chunk_pairs": chunk,
+            "max_chunk_pairs": chunk, "options": "defaults (chosen per batch)",
+            "max_reserved_gib": max_reserved,
             "saturation": sat, "offered_load": load, "offered_req_per_s": loaded["offered_req_per_s"],
             "at_load": loaded, "sweep": swept,
             "p50_ms": loaded["p50_ms"], "p99_ms": loaded["p99_ms"]}
@@ -491,6 +505,10 @@ def main():
     serving = None
     if args.serving_requests > 0:
         log(f"serving run: {args.serving_requests} requests")
+        # server engines start from the context's options: the library's own
+        # per-batch choice here, not a launch shape tuned for another workload
+        al.set_options()
+        al.set_ends_free()
         sweep = () if args.serving_sweep == "none" else \
             tuple(float(v) for v in args.serving_sweep.split(",") if v.strip())
         serving = serving_run(al, wfa, synth, args.serving_requests, args.serving_load, sweep,
