@@ -190,3 +190,33 @@ def test_empty_and_single_pair(aligner, oracle_lib, synth_lib):
     one = synth_lib.from_pairs([(b"ACGTTGCA", b"ACGTGCA")])
     got = aligner.align_host(one, PEN)
     assert_same(got, oracle_of(oracle_lib, one), one, "one")
+
+
+def test_large_pageable_batch_copy_threads(aligner, oracle_lib, synth_lib):
+    """Pageable buffers of about 100 MB in (the size from which helper
+    threads fill and empty the staging slots, each 32 MB piece split among
+    them): 450,000 pairs of 100 bp in one chunk and in the default chunks.
+    Every score, offset and run equals the device-memory path's on the same
+    batch, and a sample of pairs equals the oracle's."""
+    n = 450_000
+    b = synth_lib.workload("pairs100_e4_5m", n, first=123_457)
+    say(f"case: host pipeline, {n} pairs from pageable memory, device path for reference")
+    dev = aligner.align(b, PEN)
+    for chunk in (n, 0):
+        say(f"case: host pipeline, {n} pageable pairs, host_chunk_pairs={chunk}")
+        aligner.set_options(host_chunk_pairs=chunk)
+        sc, runs, off = aligner.align_host(b, PEN)
+        assert np.array_equal(sc, dev[0])
+        assert np.array_equal(off, dev[2])
+        assert np.array_equal(runs, dev[1])
+        say(f"case: host pipeline, {n} pageable pairs, score only, host_chunk_pairs={chunk}")
+        sc2, _, _ = aligner.align_host(b, PEN, cigar=False)
+        assert np.array_equal(sc2, dev[0])
+    rng = np.random.default_rng(8)
+    idx = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), [0, n - 1]]))
+    sub = b.subset(idx)
+    pieces = [dev[1][int(dev[2][i]):int(dev[2][i + 1])] for i in idx]
+    sub_off = np.zeros(len(idx) + 1, np.uint64)
+    np.cumsum([len(p) for p in pieces], out=sub_off[1:])
+    assert_same((dev[0][idx], np.concatenate(pieces).astype(np.uint32), sub_off),
+                oracle_of(oracle_lib, sub), sub, "large pageable sample")
