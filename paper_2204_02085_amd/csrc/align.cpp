@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -169,6 +170,8 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     // buffers, so staging and run buffers of later batches still fit.
     uint64_t mult = 1;
     int attempts = 0;
+    size_t launches = 0, min_conc = ~(size_t)0;
+    const size_t n_pending = jobs.size();
     while (!jobs.empty()) {
         if (++attempts > 40) {
             std::fprintf(stderr, "libwfa: %zu pairs still failing after 40 attempts\n", jobs.size());
@@ -205,6 +208,8 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
                 return WFA_E_NOMEM;
             }
             const size_t nj = conc;
+            launches++;
+            min_conc = std::min(min_conc, conc);
             const uint32_t max_len = std::max(head.n, head.m);
             const uint32_t lds_words = (head.n + 31) / 32 + 1 + (head.m + 31) / 32 + 1;
             const bool seq_lds = (uint64_t)lds_words * 8 <= 48 * 1024;
@@ -287,6 +292,12 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         jobs.swap(failed);
         mult *= 4;
     }
+    if (std::getenv("WFA_DEBUG"))
+        std::fprintf(stderr,
+                     "libwfa general: %zu pairs, %zu launches (fewest pairs in one: %zu), "
+                     "%d rounds, arena %.2f GiB, history scale %.3f\n",
+                     n_pending, launches, min_conc, attempts, ws.arena.bytes / 1073741824.0,
+                     hist_scale);
     return WFA_OK;
 }
 

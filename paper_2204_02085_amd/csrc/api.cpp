@@ -38,16 +38,16 @@ int Workspace::ensure(Buf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
     if (b.bytes >= bytes) return WFA_OK;
-    if (b.ptr) {
-        (void)hipFree(b.ptr);
-        total -= b.bytes;
-        b.ptr = nullptr;
-        b.bytes = 0;
-    }
+    release(b);
     generation++;
     if (total + bytes > budget) return WFA_E_NOMEM;
-    if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+    // stream-ordered on the engine's stream, which is then drained so the
+    // block is ready for any stream (a plain hipMalloc / hipFree would
+    // synchronise the whole device, stalling every other engine)
+    const hipError_t he = own[0] ? hipMallocAsync(&b.ptr, bytes, own[0]) : hipMalloc(&b.ptr, bytes);
+    if (he != hipSuccess || (own[0] && hipStreamSynchronize(own[0]) != hipSuccess)) {
         (void)hipGetLastError();
+        if (he == hipSuccess && b.ptr) (void)hipFree(b.ptr);
         b.ptr = nullptr;
         return WFA_E_NOMEM;
     }
@@ -75,7 +75,15 @@ int Workspace::grow_keep(Buf& b, size_t bytes, size_t keep, hipStream_t s) {
 
 void Workspace::release(Buf& b) {
     if (b.ptr) {
-        (void)hipFree(b.ptr);
+        if (own[0]) {
+            // nothing of this engine may still use the block
+            for (hipStream_t q : own)
+                if (q) (void)hipStreamSynchronize(q);
+            if (hipFreeAsync(b.ptr, own[0]) != hipSuccess || hipStreamSynchronize(own[0]) != hipSuccess)
+                (void)hipGetLastError();
+        } else {
+            (void)hipFree(b.ptr);
+        }
         total -= b.bytes;
     }
     b.ptr = nullptr;
@@ -144,6 +152,9 @@ int engine_init(Engine* e, int device, size_t budget) {
         (void)hipGetLastError();
         return WFA_E_DEVICE;
     }
+    e->ws.own[0] = e->stream;
+    e->ws.own[1] = e->h2d;
+    e->ws.own[2] = e->d2h;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) e->num_cus = prop.multiProcessorCount;
     if (e->num_cus <= 0) e->num_cus = 256;

@@ -34,6 +34,10 @@ struct Workspace {
     Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp, job_used;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
+    // the owning engine's streams: buffers are allocated and freed in stream
+    // order on the first one once all of them have drained, so growing one
+    // engine's buffers never waits for work of other engines on the device
+    hipStream_t own[3] = {nullptr, nullptr, nullptr};
 
     std::array<Buf*, 33> all() {
         return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -222,6 +223,17 @@ void worker_main(wfa_server* srv, Engine* eng) {
             std::fprintf(stderr, "libwfa server: batch of %zu pairs failed: %s\n", pairs.size(),
                          wfa_strerror(rc));
         const double t_end = srv->now();
+        if (eng && std::getenv("WFA_DEBUG")) {
+            const wfa_stats& L = eng->last;
+            std::fprintf(stderr,
+                         "libwfa server: batch %zu pairs, %.1f ms (engine: total %.1f, pack %.1f, "
+                         "short %.1f, general %.1f, compact %.1f ms; short %llu, general %llu, "
+                         "requeued %llu, chunks %d)\n",
+                         pairs.size(), (t_end - t_run) * 1e3, L.ms_total, L.ms_pack, L.ms_align,
+                         L.ms_general, L.ms_compact, (unsigned long long)L.short_pairs,
+                         (unsigned long long)L.general_pairs, (unsigned long long)L.requeued,
+                         L.host_chunks);
+        }
         {
             std::unique_lock<std::mutex> lk(srv->mu);
             srv->busy_s += t_end - t_run;
