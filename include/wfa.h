@@ -206,7 +206,9 @@ enum { WFA_OP_MATCH = 0, WFA_OP_MISMATCH = 1, WFA_OP_INS = 2, WFA_OP_DEL = 3 };
  * context. */
 int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx **out);
 
-/* Free the context and all device memory it owns.  NULL is ignored. */
+/* Free the context and all device memory it owns, including the engines
+ * that closed servers left with it.  Every server opened on it must be
+ * closed first.  NULL is ignored. */
 void wfa_ctx_destroy(wfa_ctx *ctx);
 
 /* Set tuning knobs for later calls (NULL restores the defaults). */
@@ -377,7 +379,10 @@ int wfa_server_release(wfa_server *srv, uint64_t ticket);
  * its length would have at 6 % divergence. */
 size_t wfa_server_estimate_bytes(const wfa_server *srv, const wfa_request *req);
 int wfa_server_get_stats(const wfa_server *srv, wfa_server_stats *out);
-/* Finish all submitted work, stop the workers and free the server. */
+/* Finish all submitted work, stop the workers and free the server.  Its
+ * per-stream engines (streams and device workspaces, up to 16 of them) stay
+ * with the context and are taken over by the next server opened on it;
+ * wfa_ctx_destroy frees them. */
 int wfa_server_close(wfa_server *srv);
 
 #ifdef __cplusplus

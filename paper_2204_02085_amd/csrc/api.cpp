@@ -192,6 +192,9 @@ extern "C" int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx** out
 
 extern "C" void wfa_ctx_destroy(wfa_ctx* ctx) {
     if (!ctx) return;
+    for (auto& e : ctx->idle)
+        if (e) engine_destroy(e.get());
+    ctx->idle.clear();
     engine_destroy(ctx);
     delete ctx;
 }

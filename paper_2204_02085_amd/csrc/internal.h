@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/wfa.h"
@@ -109,7 +111,13 @@ struct Engine {
     uint64_t last_total = 0;
 };
 
-struct wfa_ctx : Engine {};
+// The context's own engine, plus the engines of closed servers: a server
+// opened later takes them over with their streams and device buffers
+// instead of allocating its own again.
+struct wfa_ctx : Engine {
+    std::mutex idle_mu;
+    std::vector<std::unique_ptr<Engine>> idle;
+};
 
 // Batch inputs/outputs as given by the caller.
 struct BatchIO {

@@ -305,13 +305,30 @@ extern "C" int wfa_server_open(wfa_ctx* ctx, const wfa_server_cfg* cfg, wfa_serv
             srv->engines.emplace_back(nullptr);
             continue;
         }
-        auto e = std::make_unique<Engine>();
-        const int rc = engine_init(e.get(), ctx->device, srv->cfg.hbm_budget_bytes / S);
-        if (rc != WFA_OK) {
-            for (auto& x : srv->engines)
-                if (x) engine_destroy(x.get());
-            delete srv;
-            return rc;
+        std::unique_ptr<Engine> e;
+        {
+            std::lock_guard<std::mutex> lk(ctx->idle_mu);
+            if (!ctx->idle.empty()) {
+                e = std::move(ctx->idle.back());
+                ctx->idle.pop_back();
+            }
+        }
+        if (e) {
+            // an engine of a closed server: its buffers stay unless they
+            // exceed this server's share of the budget
+            e->ws.budget = srv->cfg.hbm_budget_bytes / S;
+            if (e->ws.total > e->ws.budget) e->ws.release_all();
+            e->last_valid = false;
+        } else {
+            e = std::make_unique<Engine>();
+            const int rc = engine_init(e.get(), ctx->device, srv->cfg.hbm_budget_bytes / S);
+            if (rc != WFA_OK) {
+                engine_destroy(e.get());
+                for (auto& x : srv->engines)
+                    if (x) engine_destroy(x.get());
+                delete srv;
+                return rc;
+            }
         }
         e->opt = ctx->opt;
         e->opt.use_graph = -1;  // batch sizes vary from launch to launch
@@ -438,8 +455,17 @@ extern "C" int wfa_server_close(wfa_server* srv) {
     }
     srv->cv_work.notify_all();
     for (auto& t : srv->workers) t.join();
-    for (auto& e : srv->engines)
-        if (e) engine_destroy(e.get());
+    // engines go back to the context for the next server (up to 16 kept)
+    for (auto& e : srv->engines) {
+        if (!e) continue;
+        if (e->stream) (void)hipStreamSynchronize(e->stream);
+        std::lock_guard<std::mutex> lk(srv->ctx->idle_mu);
+        if (srv->ctx->idle.size() < 16) {
+            srv->ctx->idle.push_back(std::move(e));
+        } else {
+            engine_destroy(e.get());
+        }
+    }
     delete srv;
     return WFA_OK;
 }
