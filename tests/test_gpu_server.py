@@ -78,3 +78,32 @@ def test_server_ends_free(oracle_lib, synth_lib):
         ref = oracle_lib.align_batch(req, PEN, threads=8, ends=ends)
         assert_same((res["scores"], res["runs"], res["offsets"]), ref, req, f"request {i}")
     al.close()
+
+
+def test_servers_in_a_row_take_over_engines(oracle_lib, synth_lib):
+    """Servers opened one after another on one context take over the engines
+    of closed ones: free ends, budgets and stream counts of the new server
+    hold (ends-free, then global with a smaller budget and more streams,
+    then global with fewer streams), and every result equals the oracle."""
+    import paper_2204_02085_amd as wfa
+
+    al = wfa.Aligner(0)
+    reqs = [synth_lib.workload("uneven50_300_2m", 40 + 30 * i, first=500 * i) for i in range(8)]
+    reqs.append(synth_lib.workload("serving_mix", 12, first=77))
+    plan = [((5, 5, 20, 20), 4 << 30, 2), ((0, 0, 0, 0), 1 << 30, 4), ((0, 0, 0, 0), 8 << 30, 3)]
+    for k, (ends, budget, streams) in enumerate(plan):
+        say(f"case: server {k} of a row, ends {ends}, budget {budget >> 30} GiB, {streams} streams")
+        al.set_ends_free(*ends)
+        srv = wfa.Server(al, hbm_budget_bytes=budget, streams=streams, max_chunk_pairs=1024)
+        al.set_ends_free()
+        tickets = [srv.submit(r) for r in reqs]
+        results = [srv.poll(t) for t in tickets]
+        st = srv.stats()
+        srv.close()
+        assert st["max_reserved_bytes"] <= budget
+        for i, (req, res) in enumerate(zip(reqs, results)):
+            assert res["status"] == 0
+            ref = oracle_lib.align_batch(req, PEN, threads=8, ends=ends)
+            assert_same((res["scores"], res["runs"], res["offsets"]), ref, req,
+                        f"server {k} request {i}")
+    al.close()
