@@ -243,9 +243,14 @@ class Aligner:
         if rc != WFA_OK:
             raise WFAError(rc, "wfa_ctx_create")
         self.ctx = ctx
+        self._servers = weakref.WeakSet()  # servers open on this context
 
     def close(self):
         if getattr(self, "ctx", None):
+            # a closing server hands its engines to the context, so every
+            # server goes before the context does
+            for srv in list(getattr(self, "_servers", ())):
+                srv.close()
             wfa_ctx_destroy(self.ctx)
             self.ctx = None
 
@@ -481,6 +486,10 @@ class Server:
         if rc != WFA_OK:
             raise WFAError(rc, "wfa_server_open")
         self.srv = srv
+        # the context must outlive the server: keep it, and let it close us first
+        self._aligner = aligner
+        if aligner is not None:
+            aligner._servers.add(self)
 
     def _request(self, batch):
         pairs = pairs_array(batch.p_off, batch.p_len, batch.t_off, batch.t_len)

@@ -107,3 +107,20 @@ def test_servers_in_a_row_take_over_engines(oracle_lib, synth_lib):
             assert_same((res["scores"], res["runs"], res["offsets"]), ref, req,
                         f"server {k} request {i}")
     al.close()
+
+
+def test_closing_the_context_closes_its_servers(synth_lib):
+    """Closing the Aligner first closes servers still open on it (they hand
+    their engines to the context), after their submitted work is done."""
+    import paper_2204_02085_amd as wfa
+
+    say("case: Aligner.close with a server still open")
+    al = wfa.Aligner(0)
+    srv = wfa.Server(al, hbm_budget_bytes=1 << 30, streams=2, max_chunk_pairs=512)
+    req = synth_lib.workload("pairs100_e4_5m", 300, first=9)
+    t = srv.submit(req)
+    res = srv.poll(t)
+    assert res["status"] == 0 and len(res["scores"]) == 300
+    al.close()
+    assert srv.srv is None and al.ctx is None
+    srv.close()  # a second close is a no-op
