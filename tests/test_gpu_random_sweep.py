@@ -63,7 +63,7 @@ def make_pairs(rng, count):
     return out
 
 
-@pytest.mark.parametrize("seed", range(40))
+@pytest.mark.parametrize("seed", range(100))
 def test_sweep(aligner, oracle_lib, synth_lib, wfa, seed):
     rng = np.random.default_rng(1000 + seed)
     pen = PENALTIES[seed % len(PENALTIES)]
