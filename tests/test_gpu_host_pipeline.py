@@ -8,6 +8,7 @@ sequence buffers, runs that outgrow the device run buffer mid-batch, and the
 error paths.
 """
 import ctypes
+import dataclasses
 
 import numpy as np
 import pytest
@@ -192,12 +193,13 @@ def test_empty_and_single_pair(aligner, oracle_lib, synth_lib):
     assert_same(got, oracle_of(oracle_lib, one), one, "one")
 
 
-def test_large_pageable_batch_copy_threads(aligner, oracle_lib, synth_lib):
+def test_large_pageable_batch_copy_threads(aligner, oracle_lib, synth_lib, wfa):
     """Pageable buffers of about 100 MB in (the size from which helper
     threads fill and empty the staging slots, each 32 MB piece split among
-    them): 450,000 pairs of 100 bp in one chunk and in the default chunks.
-    Every score, offset and run equals the device-memory path's on the same
-    batch, and a sample of pairs equals the oracle's."""
+    them): 450,000 pairs of 100 bp in one chunk and in the default chunks,
+    then the same sequences from page-locked memory (direct DMA).  Every
+    score, offset and run equals the device-memory path's on the same batch,
+    and a sample of pairs equals the oracle's."""
     n = 450_000
     b = synth_lib.workload("pairs100_e4_5m", n, first=123_457)
     say(f"case: host pipeline, {n} pairs from pageable memory, device path for reference")
@@ -212,6 +214,13 @@ def test_large_pageable_batch_copy_threads(aligner, oracle_lib, synth_lib):
         say(f"case: host pipeline, {n} pageable pairs, score only, host_chunk_pairs={chunk}")
         sc2, _, _ = aligner.align_host(b, PEN, cigar=False)
         assert np.array_equal(sc2, dev[0])
+    say(f"case: host pipeline, {n} pairs from page-locked memory (direct DMA)")
+    aligner.set_options()
+    pinned = dataclasses.replace(b, patterns=wfa.host_copy(b.patterns),
+                                 texts=wfa.host_copy(b.texts))
+    sc, runs, off = aligner.align_host(pinned, PEN, pinned=True)
+    assert np.array_equal(sc, dev[0]) and np.array_equal(off, dev[2])
+    assert np.array_equal(runs, dev[1])
     rng = np.random.default_rng(8)
     idx = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), [0, n - 1]]))
     sub = b.subset(idx)
