@@ -36,14 +36,15 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz -> 32-bit integer VALU lane-ops/s
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
-# Cost model of the algorithm (integer ops, independent of any kernel):
-#   one wavefront cell: 5 source reads, 3 candidate increments, 5 admissibility
-#   tests, 4 maxima, 3 stores                                      -> 20 ops
-#   one 32-base extension compare: offsets (2), two 2-word window extractions
-#   (6), xor (2), trailing-zero count (3), clamp to the ends (3), advance (2)
-#                                                                  -> 18 ops
-OPS_PER_CELL = 20
-OPS_PER_WINDOW = 18
+# Cost models of the algorithm (integer ops, independent of any kernel).
+# Primary (the scope table's): ~14 ops per wavefront cell (three state
+# updates with their admissibility tests) and ~25 per 32-base extension
+# word compare.  Second (itemised): a cell as 5 source reads, 3 candidate
+# increments, 5 admissibility tests, 4 maxima, 3 stores = 20 ops; a compare
+# as offsets (2), two 2-word window extractions (6), xor (2), trailing-zero
+# count (3), clamps to the ends (3), advance (2) = 18 ops.
+OPS_PER_CELL, OPS_PER_WINDOW = 14, 25
+OPS_PER_CELL_ITEMISED, OPS_PER_WINDOW_ITEMISED = 20, 18
 WORKLOAD = "pairs100_e4_5m"
 
 
@@ -67,8 +68,10 @@ def parse():
     ap.add_argument("--host-steps", type=int, default=2,
                     help="calls timed with host ASCII inputs and host outputs (PCIe "
                          "included; 0: skip)")
-    ap.add_argument("--tune-sample", type=int, default=0,
-                    help="pairs the autotuner times candidates on (0: the whole batch)")
+    ap.add_argument("--tune-sample", type=int, default=262_144,
+                    help="pairs the autotuner times candidates on: the pairs of the same seeded "
+                         "stream right after the timed batch, so tuning never sees the timed "
+                         "inputs")
     ap.add_argument("--options", default="",
                     help="JSON launch options instead of autotuning (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -95,6 +98,12 @@ def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_label(st: dict) -> str:
+    """Name of the kernel a call's first pass ran (from its statistics)."""
+    return (f"k_short<window {st['window']}, {st['lanes_per_pair']} lanes per pair, "
+            f"step cap {st['step_cap']}, cigar>")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2204_02085_amd", "csrc", "kernels.hip"), "rb") as f:
@@ -118,12 +127,30 @@ def read_profile(kernel_hash: str) -> dict:
     if vals.get("kernel_source_sha256_16") != kernel_hash:
         return {}
     out = {}
-    for k in ("hbm_bytes_per_launch", "valu_issue_per_cu_cycle"):
+    for k in ("hbm_bytes_per_launch", "valu_issue_per_cu_cycle", "traffic_over_algorithmic",
+              "valu_insts_per_pair"):
         try:
             out[k] = float(vals[k])
         except (KeyError, ValueError):
             pass
     return out
+
+
+def tune_on_disjoint_sample(al, wfa, synth, workload, n, count, enc, cigar=True):
+    """Autotune on `count` pairs of the same seeded stream that follow the
+    `n` pairs of the timed batch (never the timed inputs themselves)."""
+    import torch
+
+    sample = synth.workload(workload, count, first=n)
+    if enc == wfa.WFA_PACKED2:
+        sp, st_, sd = al.to_device_packed(sample)
+    else:
+        sp, st_, sd = al.to_device(sample)
+    chosen = al.autotune(sp, st_, sd, len(sample), (4, 6, 2), cigar, encoding=enc,
+                         sample_pairs=len(sample))
+    del sp, st_, sd
+    torch.cuda.synchronize()
+    return chosen
 
 
 def time_schedule(al, dev, n, steps, warmup, options, enc):
@@ -233,7 +260,14 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=16384, seed=11):
     # one long-lived server for the whole sweep, as a service would run
     srv = wfa.Server(al, hbm_budget_bytes=64 << 30, streams=4, max_chunk_pairs=chunk)
 
-    def run(gaps):
+    # requests whose results are compared with the CPU oracle (the six with
+    # the fewest bases, so the check stays within seconds)
+    import oracle
+
+    bases = [int(r.p_len.sum()) + int(r.t_len.sum()) for r in reqs]
+    checked = sorted(range(n_req), key=lambda i: bases[i])[:6]
+
+    def run(gaps, check=False):
         st0 = srv.stats()
         tickets = [None] * n_req
 
@@ -259,6 +293,16 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=16384, seed=11):
         if bad:
             codes = sorted({int(r["status"]) for r in bad})
             raise RuntimeError(f"{len(bad)} serving requests failed with status {codes}")
+        if check:
+            for i in checked:
+                ref = oracle.align_batch(reqs[i], (4, 6, 2), cigar=True, threads=8)
+                r = res[i]
+                if not (np.array_equal(r["scores"], ref.scores)
+                        and np.array_equal(r["offsets"], ref.offsets)
+                        and np.array_equal(r["runs"], ref.runs)):
+                    print(f"bench: serving request {i} differs from the oracle", file=sys.stderr)
+                    sys.exit(3)
+            log(f"serving parity: requests {checked} equal the oracle byte for byte")
         lat = np.array([r["done"] - r["submit"] for r in res]) * 1e3
         wait = np.array([r["admit"] - r["submit"] for r in res]) * 1e3
         span = max(r["done"] for r in res) - min(r["submit"] for r in res)
@@ -271,7 +315,7 @@ def serving_run(al, wfa, synth, n_req, load, sweep=(), chunk=16384, seed=11):
     free_b, total_b = torch.cuda.mem_get_info()
     log(f"serving: {n_req} requests, {total_pairs} pairs; device memory free "
         f"{free_b / 2**30:.1f} of {total_b / 2**30:.1f} GiB; saturation run")
-    sat = run(np.zeros(n_req))
+    sat = run(np.zeros(n_req), check=True)
     log(f"serving saturation: {sat}")
     sat_req_rate = n_req / (sat["wall_s"])
     unit_gaps = rng.exponential(1.0, n_req)  # one arrival pattern, scaled per load
@@ -346,8 +390,7 @@ def main():
     if args.options:
         tuned = {k: int(v) for k, v in json.loads(args.options).items()}
     else:
-        tuned = al.autotune(pat, txt, pairs, n, (4, 6, 2), True, encoding=enc,
-                            sample_pairs=args.tune_sample or n)
+        tuned = tune_on_disjoint_sample(al, wfa, synth, args.workload, n, args.tune_sample, enc)
     t_tune = time.perf_counter() - t_tune
 
     log(f"autotuned in {t_tune:.1f} s: {tuned}; timing {args.steps} steps")
@@ -355,10 +398,22 @@ def main():
     log(f"tuned: {n * args.steps / el / 1e6:.1f} M pairs/s")
     ms_step = el / args.steps * 1e3
     value = n * args.steps / el
-    kernel_ms = float(np.mean(kms))
     needed = al.last_needed()
     tuned_stats = st
     got_scores = scores.cpu().numpy().copy()
+    got_offsets = offsets.cpu().numpy().view(np.uint64).copy()
+
+    # the dominant kernel alone: the same launch with the work before and
+    # after it replayed as two graphs, so that events the library records
+    # around the kernel on its stream time it alone
+    kel, kms_k, kst = time_schedule(al, dev, n, args.steps, 1, {**tuned, "use_graph": 2}, enc)
+    kernel_ms = float(np.mean(kms_k))
+    log(f"kernel alone: {kernel_ms:.3f} ms per launch (whole call {ms_step:.3f} ms)")
+
+    # default knobs (the library's own per-batch choice, no tuning)
+    del_el, _, _ = time_schedule(al, dev, n, args.plain_steps or 5, 1, {}, enc)
+    default_value = n * (args.plain_steps or 5) / del_el
+    log(f"default knobs: {default_value / 1e6:.1f} M pairs/s")
 
     # the same launch shape (window, lanes, step cap, workgroup size) as one
     # persistent bucketed launch replayed through graphs, and as the plain
@@ -413,10 +468,18 @@ def main():
                          f"({(t1 - t0) * threads:.1f} thread-seconds)"}
         cells_pp = ref.stats["cells"] / len(sample)
         windows_pp = ref.stats["ext_windows"] / len(sample)
-        # parity spot check of the benchmarked batch against the sample
-        got = scores[: len(sample)].cpu().numpy()
-        if not np.array_equal(got, ref.scores):
-            print("WARNING: GPU scores differ from the oracle sample", file=sys.stderr)
+        # parity of the benchmarked batch: scores, CIGAR offsets and runs of
+        # the sample's pairs, byte for byte; any difference ends the run
+        k = len(sample)
+        got_runs = runs[: int(got_offsets[k])].cpu().numpy().view(np.uint32)
+        if not (np.array_equal(got_scores[:k], ref.scores)
+                and np.array_equal(got_offsets[: k + 1], ref.offsets)
+                and np.array_equal(got_runs, ref.runs)):
+            print(f"bench: the timed batch differs from the oracle on its first {k} pairs",
+                  file=sys.stderr)
+            sys.exit(3)
+        log(f"parity: the first {k} pairs of the timed batch equal the oracle byte for byte")
+        del got_runs
 
     host_path = None
     if args.host_steps > 0:
@@ -438,7 +501,7 @@ def main():
         else:
             p2, t2, d2 = al.to_device(b2)
         o2 = al.alloc_outputs(n2, n2 * 40 + 1024, True)
-        tuned2 = al.autotune(p2, t2, d2, n2, (4, 6, 2), True, encoding=enc, sample_pairs=n2)
+        tuned2 = tune_on_disjoint_sample(al, wfa, synth, args.second_set, n2, args.tune_sample, enc)
         el2, kms2, st2 = time_schedule(al, (p2, t2, d2, *o2), n2, args.steps, args.warmup, tuned2,
                                        enc)
         second = {"workload": args.second_set, "pairs": n2, "pairs_per_s": n2 * args.steps / el2,
@@ -476,8 +539,9 @@ def main():
                 runs_cap = no * (40 if no > 1_000_000 else 1500) + 1024
                 oo = al.alloc_outputs(no, runs_cap, cig)
                 if tune:
-                    opts = al.autotune(po, to, do_, no, (4, 6, 2), cig, encoding=enc,
-                                       sample_pairs=no)
+                    al.set_ends_free(*(ends or ()))
+                    opts = tune_on_disjoint_sample(al, wfa, synth, name, no,
+                                                   min(args.tune_sample, no // 4), enc, cig)
                 else:
                     opts = {}
                     al.set_options()
@@ -517,14 +581,20 @@ def main():
     roofline = None
     if cells_pp is not None and kernel_ms > 0:
         ops = n * (cells_pp * OPS_PER_CELL + windows_pp * OPS_PER_WINDOW)
+        ops_itemised = n * (cells_pp * OPS_PER_CELL_ITEMISED + windows_pp * OPS_PER_WINDOW_ITEMISED)
         achieved = ops / (kernel_ms * 1e-3)
         prof = read_profile(kernel_source_hash())
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / PEAK_INT_OPS,
                     "traffic": prof.get("hbm_bytes_per_launch"),
+                    "traffic_over_algorithmic": prof.get("traffic_over_algorithmic"),
                     "valu_issue_frac": prof.get("valu_issue_per_cu_cycle"),
-                    "kernel": f"k_short<window {tuned['window'] or 'auto'}, cigar>",
+                    "valu_insts_per_pair": prof.get("valu_insts_per_pair"),
+                    "kernel": kernel_label(kst),
                     "kernel_ms": kernel_ms, "ops_per_launch": ops,
+                    "cost_model": f"{OPS_PER_CELL} ops per cell + {OPS_PER_WINDOW} per 32-base "
+                                  "extension compare",
+                    "frac_itemised_model": ops_itemised / (kernel_ms * 1e-3) / PEAK_INT_OPS,
                     "cells_per_pair": cells_pp, "windows_per_pair": windows_pp}
 
     out = {
@@ -550,6 +620,8 @@ def main():
         "cigar_runs": needed,
         "autotuned_options": tuned,
         "autotune_seconds": t_tune,
+        "autotune_sample": f"{args.tune_sample} pairs of the same stream after the timed batch",
+        "default_knobs_pairs_per_s": default_value,
         "batched_vs_plain": batched,
         "phase_ms": {k: tuned_stats[k] for k in ("ms_pack", "ms_align", "ms_general", "ms_compact",
                                                  "ms_total")},

@@ -123,9 +123,15 @@ typedef struct {
     int32_t window;         /* diagonals held per pair by the short kernel:
                                16, 24, 32, 48, 64, 128, 256 */
     int32_t step_cap;       /* score steps (in units of gcd(x,o,e)) held in LDS  */
-    int32_t use_graph;      /* 1: replay captured hipGraphs of the work before and
-                               after the short kernel; -1: never; 0: for the
-                               persistent and automatic schedules */
+    int32_t use_graph;      /* 1: the whole first pass (counters, packing,
+                               bucketing, the short kernel, CIGAR offsets and
+                               compaction) is captured once as a hipGraph and
+                               replayed, one hipGraphLaunch per call;
+                               2: the work before and after the short kernel
+                               as two graphs, the kernel launched between them
+                               (wfa_stats.ms_align then times the kernel alone);
+                               -1: never; 0: form 1 for the persistent and
+                               automatic schedules */
     int32_t bucket;         /* 1: sort pairs by (length, length difference); -1: off */
     int32_t general_pairs;  /* concurrent pairs of the general kernel; 0: by budget */
     int32_t block_threads;  /* threads per workgroup of the short kernel: 64..256 */
@@ -141,6 +147,18 @@ typedef struct {
                                  128, 256 above the first; only what the last
                                  pass hands over goes to the general kernel.
                                  0: up to 256; -1: no cascade */
+    int32_t general_slice_kib; /* CIGAR mode: first guess of the history bytes
+                                 (KiB) per pair of the general kernel; a pair
+                                 whose history outgrows its slice is re-run
+                                 with a 4x slice.  0: estimated from the
+                                 lengths and the history seen so far */
+    int32_t general_step_limit; /* diagnostic: score steps (in units of
+                                 gcd(x,o,e)) after which the general kernel
+                                 gives up on a pair, which makes the call
+                                 return WFA_E_LIMIT.  0: no limit below the
+                                 bound that deleting all of P and inserting
+                                 all of T implies, so only an internal error
+                                 can give up */
 } wfa_options;
 
 /* Ends-free alignment.  Up to pattern_begin_free leading pattern bases OR
@@ -174,7 +192,10 @@ typedef struct {
     int32_t host_chunks;         /* chunks of the host-memory pipeline (0: device call) */
     int32_t step_cap;            /* short-kernel step cap used                       */
     int32_t schedule;            /* schedule used                                    */
-    int32_t graph_replayed;      /* 1 if a captured graph was replayed               */
+    int32_t graph_replayed;      /* graph form used (wfa_options.use_graph): 0 none,
+                                    1 one graph of the whole first pass, whose
+                                    duration ms_align then holds, 2 graphs
+                                    around a directly launched kernel        */
     double ms_pack;              /* device time of each phase, milliseconds          */
     double ms_align;
     double ms_general;
@@ -193,7 +214,12 @@ enum {
     WFA_E_DEVICE = -5,   /* a HIP call failed                                 */
     WFA_E_TOO_LONG = -6, /* a sequence longer than WFA_MAX_LENGTH             */
     WFA_E_BUSY = -7,     /* server queue full / ticket not finished          */
-    WFA_E_NOTFOUND = -8  /* unknown server ticket                             */
+    WFA_E_NOTFOUND = -8, /* unknown server ticket                             */
+    WFA_E_LIMIT = -9     /* the general kernel gave up on *bad_pair: more score
+                            steps than wfa_options.general_step_limit, or a
+                            history walk that did not lead back to the start
+                            (an internal error); that pair's score is -1 and
+                            the CIGAR outputs are not written               */
 };
 
 enum { WFA_OP_MATCH = 0, WFA_OP_MISMATCH = 1, WFA_OP_INS = 2, WFA_OP_DEL = 3 };

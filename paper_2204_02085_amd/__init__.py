@@ -28,6 +28,7 @@ WFA_HOST, WFA_DEVICE = 0, 1
 WFA_SCHED_AUTO, WFA_SCHED_PLAIN, WFA_SCHED_PERSISTENT, WFA_SCHED_GENERAL = 0, 1, 2, 3
 WFA_OK, WFA_E_INVAL, WFA_E_ALPHABET, WFA_E_NOMEM = 0, -1, -2, -3
 WFA_E_CAPACITY, WFA_E_DEVICE, WFA_E_TOO_LONG, WFA_E_BUSY, WFA_E_NOTFOUND = -4, -5, -6, -7, -8
+WFA_E_LIMIT = -9
 WFA_OP_MATCH, WFA_OP_MISMATCH, WFA_OP_INS, WFA_OP_DEL = 0, 1, 2, 3
 WFA_MAX_LENGTH = 1 << 26
 
@@ -53,7 +54,8 @@ class wfa_options(ctypes.Structure):
                 ("step_cap", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("bucket", ctypes.c_int32), ("general_pairs", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32),
-                ("host_chunk_pairs", ctypes.c_int32), ("cascade_window", ctypes.c_int32)]
+                ("host_chunk_pairs", ctypes.c_int32), ("cascade_window", ctypes.c_int32),
+                ("general_slice_kib", ctypes.c_int32), ("general_step_limit", ctypes.c_int32)]
 
 
 class wfa_ends_free(ctypes.Structure):

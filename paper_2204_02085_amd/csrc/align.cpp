@@ -102,9 +102,11 @@ struct Dev {
 
 // Pairs in `pending` on the workgroup-per-pair kernel, chunked by the budget;
 // pairs whose slice is too small are retried with a 4x slice.
+// A pair the kernel gives up on ends the call with WFA_E_LIMIT and its index
+// in *gave_up_pair.
 int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const BatchStats& st,
                 std::vector<uint32_t> pending, uint64_t& gen_used, hipStream_t s,
-                uint64_t* general_done, uint64_t* requeued) {
+                uint64_t* general_done, uint64_t* requeued, int64_t* gave_up_pair) {
     (void)st;
     Workspace& ws = e->ws;
     const uint64_t R = (uint64_t)pen.pre + 1;
@@ -158,7 +160,9 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         const uint64_t nm1 = (uint64_t)n + m + 1;
         uint64_t sl;
         sl = (R + 1) * 3 * 4 * (nm1 + 2);  // the ring of full-width rows and a NULL slot
-        if (cigar)
+        if (cigar && e->opt.general_slice_kib > 0)  // the caller's first guess
+            sl += (uint64_t)e->opt.general_slice_kib * 1024 * mult;
+        else if (cigar)
             sl += (uint64_t)std::min(std::max(hist_est(n, m) * hist_scale, 16.0 * 1024),
                                      64.0 * 1024 * 1024) * mult;
         return (sl + 255) & ~(uint64_t)255;
@@ -172,6 +176,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     int attempts = 0;
     size_t launches = 0, min_conc = ~(size_t)0;
     const size_t n_pending = jobs.size();
+    HIPCHK(launch_fill_u64((uint64_t*)&flags->gave_up, ~0ull, 1, s));
     while (!jobs.empty()) {
         if (++attempts > 40) {
             std::fprintf(stderr, "libwfa: %zu pairs still failing after 40 attempts\n", jobs.size());
@@ -248,13 +253,20 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.job_used = cigar ? ws.job_used.as<uint64_t>() : nullptr;
             g.fail_list = ws.fail_list.as<uint32_t>();
             g.fail_count = &flags->fail_count;
+            g.gave_up = &flags->gave_up;
+            g.step_limit = e->opt.general_step_limit;
             HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, s));
             uint32_t nfail = 0;
+            unsigned long long gave_up = ~0ull;
             HIPCHK(hipMemcpyAsync(&nfail, &flags->fail_count, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&gave_up, &flags->gave_up, 8, hipMemcpyDeviceToHost, s));
             std::vector<uint64_t> used(cigar ? nj : 0);
             if (cigar)
                 HIPCHK(hipMemcpyAsync(used.data(), ws.job_used.ptr, nj * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            // the flag is never reset within the call: after the last launch
+            // it holds the lowest pair index any launch gave up on
+            if (gave_up != ~0ull) *gave_up_pair = (int64_t)gave_up;
             if (cigar) {
                 for (size_t i = 0; i < nj; i++)
                     if (used[i])
@@ -292,6 +304,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         jobs.swap(failed);
         mult *= 4;
     }
+    if (*gave_up_pair >= 0) return WFA_E_LIMIT;
     if (std::getenv("WFA_DEBUG"))
         std::fprintf(stderr,
                      "libwfa general: %zu pairs, %zu launches (fewest pairs in one: %zu), "
@@ -308,10 +321,12 @@ bool GraphKey::operator==(const GraphKey& o) const {
         if (p[i] != o.p[i]) return false;
     for (int i = 0; i < 12; i++)
         if (ints[i] != o.ints[i]) return false;
-    return n == o.n;
+    return n == o.n && capacity == o.capacity && form == o.form;
 }
 
 void destroy_graph(GraphEntry& g) {
+    if (g.exec_all) (void)hipGraphExecDestroy(g.exec_all);
+    if (g.graph_all) (void)hipGraphDestroy(g.graph_all);
     if (g.exec_pre) (void)hipGraphExecDestroy(g.exec_pre);
     if (g.graph_pre) (void)hipGraphDestroy(g.graph_pre);
     if (g.exec_post) (void)hipGraphExecDestroy(g.exec_post);
@@ -544,7 +559,12 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         return WFA_OK;
     };
 
-    bool replayed = false;
+    // Graph forms: 1 (default) captures the whole device phase -- counters,
+    // packing, bucketing, the short-pair kernel, CIGAR offsets and
+    // compaction -- as one graph, so a call is one hipGraphLaunch; 2 captures
+    // the work before and after the kernel as two graphs and launches the
+    // kernel between them, so that events around it time the kernel alone.
+    const int form = graph ? (e->opt.use_graph == 2 ? 2 : 1) : 0;
     GraphEntry* hit = nullptr;
     if (graph) {
         GraphKey key;
@@ -552,19 +572,33 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
                                (const void*)(uintptr_t)ws.generation, nullptr};
         for (int i = 0; i < 8; i++) key.p[i] = ptrs[i];
         key.n = N;
+        key.capacity = d.capacity;
+        key.form = form;
         const int ints[12] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g,
                               window * 256 + lanes, sp.cap,
                               (int)st.max_p, (int)st.max_t, grid,
-                              (int)(bucket ? 1 : 0) | (int)(d.capacity > 0x7fffffff ? 2 : 0) |
-                                  (stride_p ? 4 : 0) | (stride_t ? 8 : 0)};
+                              (int)(bucket ? 1 : 0) | (stride_p ? 4 : 0) | (stride_t ? 8 : 0) |
+                                  (persistent ? 16 : 0) | (sp.block_threads << 8)};
         for (int i = 0; i < 12; i++) key.ints[i] = ints[i];
         for (auto& g : e->graphs)
             if (g.key == key) hit = &g;
         if (!hit) {
             GraphEntry g;
             g.key = key;
-            int rc = capture_graph(s, phase_pre, &g.graph_pre, &g.exec_pre);
-            if (rc == WFA_OK) rc = capture_graph(s, phase_post, &g.graph_post, &g.exec_post);
+            int rc;
+            if (form == 1) {
+                rc = capture_graph(
+                    s,
+                    [&](hipStream_t q) -> int {
+                        RCCHK(phase_pre(q));
+                        RCCHK(phase_kernel(q));
+                        return phase_post(q);
+                    },
+                    &g.graph_all, &g.exec_all);
+            } else {
+                rc = capture_graph(s, phase_pre, &g.graph_pre, &g.exec_pre);
+                if (rc == WFA_OK) rc = capture_graph(s, phase_post, &g.graph_post, &g.exec_post);
+            }
             if (rc != WFA_OK) {
                 destroy_graph(g);
                 return rc;
@@ -576,14 +610,19 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             e->graphs.push_back(g);
             hit = &e->graphs.back();
         }
-        replayed = true;
     }
+    // events: ev[0] start, ev[4] / ev[5] around the kernel (not in form 1,
+    // where the kernel runs inside the graph), ev[1] end
     HIPCHK(hipEventRecord(e->ev[0], s));
-    if (hit) HIPCHK(hipGraphLaunch(hit->exec_pre, s)); else RCCHK(phase_pre(s));
-    HIPCHK(hipEventRecord(e->ev[4], s));
-    RCCHK(phase_kernel(s));
-    HIPCHK(hipEventRecord(e->ev[5], s));
-    if (hit) HIPCHK(hipGraphLaunch(hit->exec_post, s)); else RCCHK(phase_post(s));
+    if (form == 1) {
+        HIPCHK(hipGraphLaunch(hit->exec_all, s));
+    } else {
+        if (hit) HIPCHK(hipGraphLaunch(hit->exec_pre, s)); else RCCHK(phase_pre(s));
+        HIPCHK(hipEventRecord(e->ev[4], s));
+        RCCHK(phase_kernel(s));
+        HIPCHK(hipEventRecord(e->ev[5], s));
+        if (hit) HIPCHK(hipGraphLaunch(hit->exec_post, s)); else RCCHK(phase_post(s));
+    }
     HIPCHK(hipEventRecord(e->ev[1], s));
     DevFlags fl;
     HIPCHK(hipMemcpyAsync(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
@@ -687,7 +726,14 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     }
     HIPCHK(hipEventRecord(e->ev[2], s));
     if (!pending.empty()) {
-        RCCHK(run_general(e, pen, cigar, d, st, pending, gen_used, s, &general_done, &requeued));
+        int64_t gave_up = -1;
+        const int rg = run_general(e, pen, cigar, d, st, pending, gen_used, s, &general_done,
+                                   &requeued, &gave_up);
+        if (rg == WFA_E_LIMIT && bad_pair) *bad_pair = gave_up;
+        if (rg != WFA_OK) {
+            (void)finish_user();
+            return rg;
+        }
         flags = ws.flags.as<DevFlags>();
     }
     HIPCHK(hipEventRecord(e->ev[3], s));
@@ -726,11 +772,17 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     L.lanes_per_pair = use_short ? lanes : 0;
     L.step_cap = use_short ? sp.cap : 0;
     L.schedule = !use_short ? WFA_SCHED_GENERAL : (persistent ? WFA_SCHED_PERSISTENT : WFA_SCHED_PLAIN);
-    L.graph_replayed = replayed ? 1 : 0;
-    L.ms_pack = use_short ? ev_ms(e->ev[0], e->ev[4]) : 0.0;
-    L.ms_align = (use_short ? ev_ms(e->ev[4], e->ev[5]) : 0.0) + ms_cascade;
+    L.graph_replayed = form;
+    if (form == 1) {  // the whole first pass ran as one graph
+        L.ms_pack = 0.0;
+        L.ms_align = ev_ms(e->ev[0], e->ev[1]) + ms_cascade;
+        L.ms_compact = ev_ms(e->ev[3], e->ev[8]);
+    } else {
+        L.ms_pack = use_short ? ev_ms(e->ev[0], e->ev[4]) : 0.0;
+        L.ms_align = (use_short ? ev_ms(e->ev[4], e->ev[5]) : 0.0) + ms_cascade;
+        L.ms_compact = (use_short ? ev_ms(e->ev[5], e->ev[1]) : 0.0) + ev_ms(e->ev[3], e->ev[8]);
+    }
     L.ms_general = ev_ms(e->ev[2], e->ev[3]);
-    L.ms_compact = (use_short ? ev_ms(e->ev[5], e->ev[1]) : 0.0) + ev_ms(e->ev[3], e->ev[8]);
     L.ms_total = now_ms() - t_start;
 
     e->last_valid = cigar;

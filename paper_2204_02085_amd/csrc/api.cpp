@@ -219,6 +219,10 @@ extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
                                opt->block_threads % 64))
         return WFA_E_INVAL;
     if (opt->general_pairs < 0) return WFA_E_INVAL;
+    if (opt->use_graph < -1 || opt->use_graph > 2) return WFA_E_INVAL;
+    if (opt->bucket < -1 || opt->bucket > 1) return WFA_E_INVAL;
+    if (opt->general_slice_kib < 0 || opt->general_slice_kib > (1 << 22)) return WFA_E_INVAL;
+    if (opt->general_step_limit < 0) return WFA_E_INVAL;
     if (opt->host_chunk_pairs < 0) return WFA_E_INVAL;
     if (opt->cascade_window < -1 ||
         (opt->cascade_window > 0 &&
@@ -259,6 +263,7 @@ extern "C" const char* wfa_strerror(int status) {
     case WFA_E_TOO_LONG: return "sequence longer than WFA_MAX_LENGTH";
     case WFA_E_BUSY: return "not finished / queue full";
     case WFA_E_NOTFOUND: return "unknown ticket";
+    case WFA_E_LIMIT: return "the general kernel gave up on a pair (step limit or internal error)";
     default: return "unknown status";
     }
 }

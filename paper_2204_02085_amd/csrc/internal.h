@@ -68,6 +68,7 @@ struct DevFlags {
     uint32_t queue2;              // queue head of a cascade pass
     uint32_t pad;
     uint64_t total_runs;          // exclusive-scan total of per-pair runs
+    unsigned long long gave_up;   // first pair the general kernel gave up on (~0: none)
 };
 
 struct ShortPlan {
@@ -77,19 +78,27 @@ struct ShortPlan {
     int block_threads = 256, lds_per_block = 0;
 };
 
+// Everything a captured graph bakes in: buffer addresses, sizes, the plan
+// and the caller's full CIGAR capacity (compaction writes nothing when the
+// runs exceed it, so a replay under another capacity would be wrong).
 struct GraphKey {
     const void* p[8] = {};
     size_t n = 0;
+    uint64_t capacity = 0;
+    int form = 0;  // 1: one graph of the whole device phase, 2: pre / post graphs
     int ints[12] = {};
     bool operator==(const GraphKey& o) const;
 };
 
-// Captured graphs of one plan: the work before the short-pair kernel
-// (counters, packing, bucketing) and after it (CIGAR offsets, compaction).
+// Captured graphs of one plan.  Form 1: one graph holding the work before
+// the short-pair kernel (counters, packing, bucketing), the kernel and the
+// work after it (CIGAR offsets, compaction).  Form 2: the work before and
+// after the kernel as two graphs, the kernel launched between them, so that
+// events recorded around it time the kernel alone.
 struct GraphEntry {
     GraphKey key;
-    hipGraph_t graph_pre = nullptr, graph_post = nullptr;
-    hipGraphExec_t exec_pre = nullptr, exec_post = nullptr;
+    hipGraph_t graph_all = nullptr, graph_pre = nullptr, graph_post = nullptr;
+    hipGraphExec_t exec_all = nullptr, exec_pre = nullptr, exec_post = nullptr;
 };
 
 // Everything one batch needs: a stream, a workspace, events and options.

@@ -96,6 +96,12 @@ struct GeneralArgs {
                                 // finished job used (history, step table, runs)
     uint32_t* fail_list;        // jobs whose slice was too small
     uint32_t* fail_count;
+    // A pair the kernel gives up on -- more score steps than `step_limit`
+    // (0: the bound n + m gap bases imply), or a history walk that does not
+    // lead back to the origin -- gets score -1 and no runs, and the lowest
+    // such pair index is kept here (atomicMin; the host starts it at ~0).
+    unsigned long long* gave_up;
+    long long step_limit;
 };
 
 // Kernel entry points (host-side launchers; all asynchronous on `s`).

@@ -1009,8 +1009,10 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     }
     __syncthreads();
     const int* nullrow = (const int*)(slice + R * full_row) + n + 1;
-    // a hard bound on steps: deleting all of P and inserting all of T
-    const long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
+    // a hard bound on steps: deleting all of P and inserting all of T (or a
+    // lower limit the host asks for)
+    long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
+    if (a.step_limit > 0 && a.step_limit < max_score_g) max_score_g = a.step_limit;
 
     int S = -1;
     int rs = 0;  // s % R
@@ -1159,10 +1161,11 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         }
     }
     __syncthreads();
-    if (sh_fail == 2) {  // step bound exceeded: report an invalid score, never loop
+    if (sh_fail == 2) {  // step bound exceeded: give up on the pair, never loop
         if (tid == 0) {
-            a.scores[pair] = -2;
+            a.scores[pair] = -1;
             a.nruns[pair] = 0;
+            atomicMin(a.gave_up, (unsigned long long)pair);
         }
         return;
     }
@@ -1282,9 +1285,10 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         k += dk;
         h = hn;
     }
-    if (bad) {  // inconsistent walk: invalid score, no loop
-        a.scores[pair] = -2;
+    if (bad) {  // inconsistent walk: give up on the pair, no loop
+        a.scores[pair] = -1;
         a.nruns[pair] = 0;
+        atomicMin(a.gave_up, (unsigned long long)pair);
         return;
     }
     if (cop >= 0) {

@@ -4,6 +4,8 @@ Scores and CIGAR runs must be byte-identical to the oracle's.  Inputs are
 the seeded synthetic workloads (pairs of 100 bp reads at 2 % and 4 % edits,
 uneven 50-300 bp pairs, long 1-10 kbp pairs) plus edge cases.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -40,11 +42,25 @@ def oracle_of(oracle_lib, batch, pen=PEN, cigar=True):
     return oracle_lib.align_batch(batch, pen, cigar=cigar, threads=8)
 
 
-def test_pairs100_e2_10k_all(aligner, oracle_lib, synth_lib):
-    """10,000 pairs of 100 bp at E = 2 %: every pair bit-exact."""
-    say("case: pairs100_e2_10k, all pairs, CIGAR, default schedule")
+def oracle_all(oracle_lib, batch, slot, pen=PEN):
+    """The oracle on every pair of a full-size batch, on all host threads
+    (at most 16); `slot` bounds the runs of one pair."""
+    threads = max(1, min(16, os.cpu_count() or 1))
+    return oracle_lib.align_batch(batch, pen, cigar=True, threads=threads, slot=slot)
+
+
+@pytest.mark.parametrize("schedule", ["PLAIN", "AUTO"])
+def test_pairs100_e2_10k_all(aligner, oracle_lib, synth_lib, wfa, schedule):
+    """10,000 pairs of 100 bp at E = 2 %: every pair bit-exact, with the plain
+    per-batch kernel and with the default (persistent) schedule."""
+    say(f"case: pairs100_e2_10k, all pairs, CIGAR, schedule {schedule}")
     b = synth_lib.workload("pairs100_e2_10k")
+    aligner.set_options(schedule=getattr(wfa, "WFA_SCHED_" + schedule))
     got = aligner.align(b, PEN)
+    st = aligner.stats()
+    assert st["short_pairs"] == len(b)
+    assert st["schedule"] == getattr(wfa, "WFA_SCHED_" + ("PLAIN" if schedule == "PLAIN"
+                                                          else "PERSISTENT"))
     assert_same(got, oracle_of(oracle_lib, b), b, "pairs100_e2_10k")
     check_sample_cigars(b, *got, PEN, range(0, len(b), 50))
 
@@ -191,65 +207,67 @@ def _subset_result(res, idx):
     return sc[idx], r, o
 
 
-def _full_size_check(aligner, oracle_lib, synth_lib, name, count, sample, seed):
-    b = synth_lib.workload(name, count)
-    say(f"case: {name} full size {len(b)} pairs, default schedule (the benchmarked launch)")
+def _full_size_check(aligner, oracle_lib, synth_lib, name, slot, options=None):
+    """A full-size batch in one call, compared with the oracle on every pair
+    (scores, offsets and runs byte for byte) and checked for the invariants
+    every optimal result has."""
+    b = synth_lib.workload(name)
+    say(f"case: {name} full size {len(b)} pairs, options {options or 'default'}")
+    if options:
+        aligner.set_options(**options)
     got = aligner.align(b, PEN, capacity=len(b) * 40 + 1024)
     st = aligner.stats()
     say(f"  stats: {st}")
     check_invariants_vectorized(b, *got, PEN)
-    rng = np.random.default_rng(seed)
-    top = np.argsort(got[0], kind="stable")[-500:]
-    idx = np.unique(np.concatenate([rng.choice(len(b), sample, replace=False), top,
-                                    [0, len(b) - 1]]))
-    sub = b.subset(idx)
-    ref = oracle_of(oracle_lib, sub)
-    assert_same(_subset_result(got, idx), ref, sub, f"{name} sample")
-    check_sample_cigars(sub, *_subset_result(got, idx), PEN, range(0, len(sub), 25))
-    return st
+    say(f"  oracle on all {len(b)} pairs")
+    ref = oracle_all(oracle_lib, b, slot)
+    assert_same(got, ref, b, f"{name} all pairs")
+    check_sample_cigars(b, *got, PEN, range(0, len(b), len(b) // 400))
+    return b, got, st
 
 
 def test_pairs100_e4_full_size(aligner, oracle_lib, synth_lib):
-    """5,000,000 pairs of 100 bp at E = 4 % (the benchmark workload)."""
-    st = _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e4_5m", None, 50_000, 1)
+    """5,000,000 pairs of 100 bp at E = 4 % (the benchmark workload), default
+    schedule: every pair against the oracle."""
+    _, _, st = _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e4_5m", 24)
     assert st["short_pairs"] == st["pairs"]
 
 
-def test_pairs100_e4_full_size_tuned_launch(aligner, oracle_lib, synth_lib, wfa):
-    """The same 5,000,000 pairs in the launch the autotuner picks for them
-    (one persistent bucketed launch between replayed graphs, 8 lanes per pair,
-    window 32, step cap 16, 128-thread workgroups) and in the plain launch of
-    that shape: both bit-exact against the oracle on a sample, and identical
-    to each other on every pair."""
-    b = synth_lib.workload("pairs100_e4_5m")
-    shape = dict(window=32, lanes_per_pair=8, step_cap=16, block_threads=128)
+def test_pairs100_e4_full_size_plain_vs_persistent(aligner, oracle_lib, synth_lib, wfa):
+    """The same 5,000,000 pairs in the benchmark's launch shape (8 lanes per
+    pair, window 32, step cap 16, 256-thread workgroups) as one persistent
+    bucketed graph-replayed launch and as the plain per-batch kernel: each
+    against the oracle on every pair."""
+    shape = dict(window=32, lanes_per_pair=8, step_cap=16, block_threads=256)
     res = {}
     for name, extra in [("persistent", dict(schedule=wfa.WFA_SCHED_PERSISTENT, bucket=1, use_graph=1)),
                         ("plain", dict(schedule=wfa.WFA_SCHED_PLAIN, bucket=-1, use_graph=-1))]:
-        say(f"case: pairs100_e4_5m full size, {name} launch {shape}")
-        aligner.set_options(**shape, **extra)
-        res[name] = aligner.align(b, PEN, capacity=len(b) * 40 + 1024)
-        st = aligner.stats()
+        _, res[name], st = _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e4_5m", 24,
+                                            {**shape, **extra})
         assert st["short_pairs"] == st["pairs"] and st["lanes_per_pair"] == 8
     for a_, b_ in zip(res["persistent"], res["plain"]):
         assert np.array_equal(a_, b_)
-    got = res["persistent"]
-    check_invariants_vectorized(b, *got, PEN)
-    rng = np.random.default_rng(11)
-    idx = np.unique(np.concatenate([rng.choice(len(b), 30_000, replace=False),
-                                    np.argsort(got[0], kind="stable")[-300:], [0, len(b) - 1]]))
-    sub = b.subset(idx)
-    assert_same(_subset_result(got, idx), oracle_of(oracle_lib, sub), sub, "tuned launch sample")
 
 
 def test_pairs100_e2_full_size(aligner, oracle_lib, synth_lib):
-    """5,000,000 pairs of 100 bp at E = 2 %."""
-    _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e2_5m", None, 50_000, 2)
+    """5,000,000 pairs of 100 bp at E = 2 %, default schedule: every pair."""
+    _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e2_5m", 16)
+
+
+def test_pairs100_e2_full_size_benchmarked_launch(aligner, oracle_lib, synth_lib, wfa):
+    """The E = 2 % set in the launch the benchmark's autotuner picks for it
+    (window 16, 8 lanes per pair, step cap 8, plain kernel, 128-thread
+    workgroups): every pair against the oracle; pairs needing more than 8
+    steps go through the cascade."""
+    _full_size_check(aligner, oracle_lib, synth_lib, "pairs100_e2_5m", 16,
+                     dict(schedule=wfa.WFA_SCHED_PLAIN, window=16, lanes_per_pair=8, step_cap=8,
+                          block_threads=128, bucket=-1, use_graph=-1))
 
 
 def test_uneven_full_size(aligner, oracle_lib, synth_lib):
-    """2,000,000 uneven pairs (50-300 bp, 0-5 % edits) in one batch."""
-    _full_size_check(aligner, oracle_lib, synth_lib, "uneven50_300_2m", None, 20_000, 3)
+    """2,000,000 uneven pairs (50-300 bp, 0-5 % edits) in one batch: every
+    pair against the oracle."""
+    _full_size_check(aligner, oracle_lib, synth_lib, "uneven50_300_2m", 80)
 
 
 def test_long_reads_sample(aligner, oracle_lib, synth_lib, wfa):

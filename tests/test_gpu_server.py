@@ -124,3 +124,55 @@ def test_closing_the_context_closes_its_servers(synth_lib):
     al.close()
     assert srv.srv is None and al.ctx is None
     srv.close()  # a second close is a no-op
+
+
+def test_server_large_long_requests(oracle_lib, synth_lib):
+    """Requests of the serving configuration's largest kind -- 2,048 to 4,096
+    pairs of 5-10 kbp reads at 10 % edits -- mixed with small requests of
+    100-10,000 bp: every request's results in the mix equal the same pairs
+    aligned alone, and an oracle sample (shortest and longest pair of each
+    large request, and the small requests whole) matches byte for byte."""
+    import paper_2204_02085_amd as wfa
+
+    big_spec = synth_lib.loguniform_single(5000, 10000, 0.10, 0.10)
+    sizes = [("small", 3), ("big", 2048), ("small", 40), ("big", 3000), ("small", 1),
+             ("big", 4096), ("small", 200)]
+    reqs, first = [], 0
+    for kind, k in sizes:
+        if kind == "big":
+            reqs.append(synth_lib.generate(big_spec, 606, k, first=first))
+        else:
+            reqs.append(synth_lib.workload("serving_mix", k, first=first))
+        first += k
+    say(f"case: server, {len(reqs)} requests, {sum(k for _, k in sizes)} pairs "
+        f"({sum(k for kind, k in sizes if kind == 'big')} of 5-10 kbp at 10 %), CIGAR")
+    al = wfa.Aligner(0)
+    srv = wfa.Server(al, hbm_budget_bytes=64 << 30, streams=4, max_chunk_pairs=16384)
+    tickets = [srv.submit(r) for r in reqs]
+    results = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    say(f"  server stats: {st}")
+    for i, (req, res) in enumerate(zip(reqs, results)):
+        assert res["status"] == 0, f"request {i} status {res['status']}"
+        say(f"  request {i}: {len(req)} pairs alone")
+        alone = al.align(req, PEN, capacity=len(req) * 1500 + 1024)
+        assert np.array_equal(res["scores"], alone[0]), f"request {i} scores"
+        assert np.array_equal(res["offsets"], alone[2]), f"request {i} offsets"
+        assert np.array_equal(res["runs"], alone[1]), f"request {i} runs"
+    for i, (kind, _) in enumerate(sizes):
+        req, res = reqs[i], results[i]
+        if kind == "big":
+            lens = np.maximum(req.p_len, req.t_len)
+            idx = [int(np.argmin(lens)), int(np.argmax(lens))]
+        else:
+            idx = list(range(len(req)))
+        say(f"  oracle on {len(idx)} pairs of request {i}")
+        sub = req.subset(idx)
+        ref = oracle_lib.align_batch(sub, PEN, threads=8)
+        parts = [res["runs"][int(res["offsets"][j]):int(res["offsets"][j + 1])] for j in idx]
+        off = np.zeros(len(idx) + 1, np.uint64)
+        np.cumsum([len(p) for p in parts], out=off[1:])
+        got = (res["scores"][idx], np.concatenate(parts).astype(np.uint32), off)
+        assert_same(got, ref, sub, f"request {i} oracle sample")
+    al.close()

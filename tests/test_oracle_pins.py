@@ -256,6 +256,73 @@ def test_ends_free_closed_forms(oracle_lib):
             assert a == b
 
 
+# ---- the oracle's work counters --------------------------------------------
+# The benchmark's algorithmic work per pair (cells, 32-base extension
+# windows) comes from the oracle's counters, so they are pinned too, by
+# closed forms that follow from the method's definitions:
+#  * a wavefront at score s spans one diagonal more on each side than the
+#    widest of its source wavefronts (s - x, s - o - e, s - e), clipped to
+#    [-n, m].  Under (4, 6, 2) every even score has a wavefront (s - 2 always
+#    does), so the span at s is [-s/2, s/2]: s + 1 cells, and a pair of score
+#    S (with S/2 <= min(n, m)) visits 1 + 3 + ... + (S + 1) = (S/2 + 1)^2
+#    cells in S/2 + 1 steps.  Under (1, 0, 1) every score has one, of 2s + 1
+#    cells: (S + 1)^2 cells in S + 1 steps.
+#  * identical sequences of length n: one cell, one extension of n matches,
+#    which a compare of 32 bases at a time covers in floor(n/32) + 1 windows
+#    (the last one finds the mismatch or the end).
+#  * one substitution at base j of n under (4, 6, 2): score 4 in steps
+#    s = 0, 2, 4 (1 + 3 + 5 = 9 cells; s = 2 holds only NULL cells), two
+#    extensions (from 0 over j matches, from j + 1 over n - j - 1 matches).
+def _counter_failures(align_fn):
+    """Counter closed forms that `align_fn(P, T, pen) -> (score, stats)`
+    violates (empty list: all hold)."""
+    bad = []
+    rng = np.random.default_rng(17)
+    for n in (0, 1, 5, 31, 32, 33, 63, 64, 65, 100, 200):
+        P = bytes(rng.choice(list(b"ACGT"), n).astype(np.uint8))
+        sc, st = align_fn(P, P, (4, 6, 2))
+        want = dict(cells=1, steps=1, ext_calls=1, ext_windows=n // 32 + 1, ext_matches=n)
+        if sc != 0 or any(st[k] != v for k, v in want.items()):
+            bad.append(("identical", n, sc, st))
+    for n, j in ((100, 50), (100, 0), (100, 99), (64, 31), (64, 32), (200, 131)):
+        P = bytearray(rng.choice(list(b"ACGT"), n).astype(np.uint8))
+        T = bytearray(P)
+        T[j] = b"ACGT"[(b"ACGT".index(T[j]) + 1) % 4]
+        sc, st = align_fn(bytes(P), bytes(T), (4, 6, 2))
+        want = dict(cells=9, steps=3, ext_calls=2,
+                    ext_windows=j // 32 + 1 + (n - j - 1) // 32 + 1, ext_matches=n - 1)
+        if sc != 4 or any(st[k] != v for k, v in want.items()):
+            bad.append(("substitution", n, j, sc, st))
+    pairs = [(bytes(rng.choice(list(b"ACGT"), int(rng.integers(20, 120))).astype(np.uint8)),)
+             for _ in range(60)]
+    for (P,) in pairs:
+        T = bytearray(P)
+        for _ in range(int(rng.integers(0, 6))):  # a few random edits
+            pos = int(rng.integers(0, max(len(T), 1)))
+            kind = int(rng.integers(0, 3))
+            if kind == 0 and T:
+                T[pos] = b"ACGT"[(b"ACGT".index(T[pos]) + 1) % 4]
+            elif kind == 1:
+                T[pos:pos] = bytes([b"ACGT"[int(rng.integers(0, 4))]])
+            elif T:
+                del T[pos]
+        T = bytes(T)
+        for pen, half in (((4, 6, 2), True), ((1, 0, 1), False)):
+            sc, st = align_fn(P, T, pen)
+            S = sc // 2 if half else sc
+            if S <= min(len(P), len(T)) and (st["cells"] != (S + 1) ** 2 or st["steps"] != S + 1):
+                bad.append(("span", pen, len(P), len(T), sc, st))
+    return bad
+
+
+def test_oracle_counters_closed_forms(oracle_lib):
+    def fn(P, T, pen):
+        sc, _, st = oracle_lib.align(P, T, pen, cigar=False, with_stats=True)
+        return sc, st
+
+    assert _counter_failures(fn) == []
+
+
 # ---- planted mistakes ------------------------------------------------------
 # Each mutant changes one line of the oracle's arithmetic the way a plausible
 # slip would; the pins must reject every one of them.
@@ -275,6 +342,9 @@ MUTANTS = {
     "mismatch_no_advance": ("xx = xx == OFF_NULL ? OFF_NULL : xx + 1;\n            int Mv",
                             "xx = xx == OFF_NULL ? OFF_NULL : xx;\n            int Mv"),
     "backtrace_D_moves_h": ("                k += 1;\n            }\n        }", "                k += 1;\n                h -= 1;\n            }\n        }"),
+    # counters the benchmark's algorithmic work comes from
+    "cells_width_short_by_one": ("st->cells += hi - lo + 1;", "st->cells += hi - lo;"),
+    "windows_rounded_up": ("st->ext_windows += run / 32 + 1;", "st->ext_windows += (run + 31) / 32;"),
 }
 
 
@@ -322,6 +392,28 @@ def _mutant_caught(so_path) -> bool:
                     return True
             except AssertionError:
                 return True
+    # the work counters
+    class _St(ctypes.Structure):
+        _fields_ = [(f, ctypes.c_int64) for f in
+                    ("cells", "steps", "ext_calls", "ext_windows", "ext_matches")]
+
+    def counted(P, T, pen):
+        n, m = len(P), len(T)
+        st = _St()
+        sc = ctypes.c_int32()
+        nr = ctypes.c_int64()
+        rc = lib.oracle_align(ctypes.create_string_buffer(P, n + 1), n,
+                              ctypes.create_string_buffer(T, m + 1), m, *pen, 0,
+                              ctypes.byref(sc), None, 0, ctypes.byref(nr), ctypes.byref(st))
+        if rc != 0:
+            raise RuntimeError("oracle_align failed")
+        return sc.value, {f: int(getattr(st, f)) for f, _ in st._fields_}
+
+    try:
+        if _counter_failures(counted):
+            return True
+    except RuntimeError:
+        return True
     # ends-free cases
     for pen in [(4, 6, 2), (1, 0, 1)]:
         for ends in ENDS_SHORT:
