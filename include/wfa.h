@@ -209,7 +209,9 @@ enum {
     WFA_OK = 0,
     WFA_E_INVAL = -1,    /* bad argument: penalties, NULL pointer, enum value */
     WFA_E_ALPHABET = -2, /* a byte outside ACGTacgt (ASCII input)             */
-    WFA_E_NOMEM = -3,    /* the HBM budget cannot hold the work               */
+    WFA_E_NOMEM = -3,    /* the HBM budget cannot hold the work; the context's
+                            device workspace is then released, so that a later
+                            batch that fits starts from nothing             */
     WFA_E_CAPACITY = -4, /* cigar_capacity is smaller than *cigar_needed      */
     WFA_E_DEVICE = -5,   /* a HIP call failed                                 */
     WFA_E_TOO_LONG = -6, /* a sequence longer than WFA_MAX_LENGTH             */
@@ -316,6 +318,37 @@ int wfa_autotune(wfa_ctx *ctx, const void *patterns, const void *texts, const wf
                  size_t num_pairs, wfa_encoding enc, wfa_memspace mem, wfa_penalties pen,
                  wfa_mode mode, size_t sample_pairs, const char *cache_path, int force,
                  wfa_options *chosen);
+
+/* ---------------------------------------------------------------------------
+ * Allocation-free alignment.
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and results as wfa_align_batch with mem = WFA_DEVICE (every
+ * buffer is device memory the caller owns), the context's options and free
+ * ends, but graphs are never captured, and the call allocates no device
+ * memory: its whole workspace (batch statistics, counters, packed sequences,
+ * CIGAR slots, bucketing, the cascade and the general kernel's arena) is
+ * carved from a static device array of WFA_NOALLOC_SCRATCH_BYTES that each
+ * GPU the library runs on holds until the process ends.  Limits and errors:
+ *   - num_pairs above WFA_NOALLOC_MAX_PAIRS: WFA_E_INVAL, nothing written;
+ *   - a workspace larger than the array (long or very divergent pairs whose
+ *     general-kernel slices do not fit): WFA_E_NOMEM;
+ *   - WFA_E_CAPACITY: scores, offsets and *cigar_needed are written, but the
+ *     runs are not kept for wfa_copy_last_cigars (call again with room).
+ * Every call on a GPU, from any context, uses that GPU's one array: calls
+ * that overlap in time on one GPU race and must be serialised by the caller.
+ * Each call clears whatever it relies on; nothing carries over between calls.
+ * ------------------------------------------------------------------------- */
+#define WFA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+#define WFA_NOALLOC_MAX_PAIRS ((uint32_t)1 << 18)
+
+int wfa_align_batch_noalloc(wfa_ctx *ctx, const void *patterns, const void *texts,
+                            const wfa_pair *pairs, size_t num_pairs, wfa_encoding enc,
+                            wfa_penalties pen, wfa_mode mode, int32_t *scores,
+                            uint32_t *cigar_runs, size_t cigar_capacity,
+                            uint64_t *cigar_offsets, size_t *cigar_needed, int64_t *bad_pair,
+                            void *stream);
 
 /* Counters of the last wfa_align_batch call. */
 int wfa_last_stats(const wfa_ctx *ctx, wfa_stats *out);

@@ -38,7 +38,10 @@ EXPORTED = [
     "wfa_last_stats", "wfa_strerror",
     "wfa_server_open", "wfa_server_submit", "wfa_server_poll", "wfa_server_release",
     "wfa_server_estimate_bytes", "wfa_server_get_stats", "wfa_server_close",
+    "wfa_align_batch_noalloc",
 ]
+WFA_NOALLOC_SCRATCH_BYTES = 128 << 20
+WFA_NOALLOC_MAX_PAIRS = 1 << 18
 
 PAIR_DTYPE = np.dtype([("p_start", "<u8"), ("t_start", "<u8"), ("p_len", "<u4"),
                        ("t_len", "<u4")])
@@ -132,6 +135,9 @@ def _load():
                              ctypes.c_int, p, p, sz, p, ctypes.POINTER(sz),
                              ctypes.POINTER(i64), p], ctypes.c_int),
         "wfa_copy_last_cigars": ([p, p, sz, p], ctypes.c_int),
+        "wfa_align_batch_noalloc": ([p, p, p, p, sz, ctypes.c_int, wfa_penalties, ctypes.c_int,
+                                     p, p, sz, p, ctypes.POINTER(sz), ctypes.POINTER(i64), p],
+                                    ctypes.c_int),
         "wfa_host_alloc": ([sz, ctypes.POINTER(p)], ctypes.c_int),
         "wfa_host_free": ([p], None),
         "wfa_pack2bit": ([p, p, p, p, sz, p, sz, p, ctypes.POINTER(sz), ctypes.POINTER(i64), p],
@@ -167,6 +173,7 @@ wfa_set_options = lib.wfa_set_options
 wfa_set_ends_free = lib.wfa_set_ends_free
 wfa_align_batch = lib.wfa_align_batch
 wfa_copy_last_cigars = lib.wfa_copy_last_cigars
+wfa_align_batch_noalloc = lib.wfa_align_batch_noalloc
 wfa_host_alloc = lib.wfa_host_alloc
 wfa_host_free = lib.wfa_host_free
 wfa_pack2bit = lib.wfa_pack2bit

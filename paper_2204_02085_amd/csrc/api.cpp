@@ -34,12 +34,30 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
+void Workspace::use_fixed(void* base, size_t size) {
+    for (Buf* b : all()) *b = Buf{};
+    fixed_base = (unsigned char*)base;
+    fixed_size = size;
+    fixed_top = 0;
+    total = 0;
+    budget = size;
+    generation++;
+}
+
 int Workspace::ensure(Buf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
     if (b.bytes >= bytes) return WFA_OK;
     release(b);
     generation++;
+    if (fixed_base) {  // carve from the region (256-byte aligned like its base)
+        if (fixed_top + bytes > fixed_size) return WFA_E_NOMEM;
+        b.ptr = fixed_base + fixed_top;
+        b.bytes = bytes;
+        fixed_top += bytes;
+        total = fixed_top;
+        return WFA_OK;
+    }
     if (total + bytes > budget) return WFA_E_NOMEM;
     // stream-ordered on the engine's stream, which is then drained so the
     // block is ready for any stream (a plain hipMalloc / hipFree would
@@ -74,6 +92,12 @@ int Workspace::grow_keep(Buf& b, size_t bytes, size_t keep, hipStream_t s) {
 }
 
 void Workspace::release(Buf& b) {
+    if (fixed_base) {
+        if (b.ptr && (unsigned char*)b.ptr + b.bytes == fixed_base + fixed_top) fixed_top -= b.bytes;
+        total = fixed_top;
+        b = Buf{};
+        return;
+    }
     if (b.ptr) {
         if (own[0]) {
             // nothing of this engine may still use the block
@@ -91,6 +115,10 @@ void Workspace::release(Buf& b) {
 }
 
 void Workspace::release_all() {
+    if (fixed_base) {
+        use_fixed(fixed_base, fixed_size);
+        return;
+    }
     for (Buf* b : all()) release(*b);
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
@@ -99,6 +127,7 @@ void Workspace::release_all() {
 
 int Workspace::ensure_pinned(size_t bytes) {
     if (pinned_bytes >= bytes) return WFA_OK;
+    if (fixed_base) return WFA_E_NOMEM;  // never allocates
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     pinned_bytes = 0;
@@ -181,8 +210,19 @@ extern "C" int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx** out
     if (!out) return WFA_E_INVAL;
     *out = nullptr;
     wfa_ctx* c = new wfa_ctx();
-    const int rc = engine_init(c, device, hbm_budget_bytes);
+    int rc = engine_init(c, device, hbm_budget_bytes);
+    // set-up of the allocation-free entry point: the scratch array's address
+    // on this device, and an engine (streams, events) whose workspace is
+    // carved from it
+    if (rc == WFA_OK) rc = noalloc_setup(device);
+    if (rc == WFA_OK) {
+        c->fixed.reset(new Engine());
+        rc = engine_init(c->fixed.get(), device, noalloc_scratch_bytes());
+        if (rc == WFA_OK) c->fixed->ws.use_fixed(noalloc_scratch(device), noalloc_scratch_bytes());
+    }
     if (rc != WFA_OK) {
+        if (c->fixed) engine_destroy(c->fixed.get());
+        engine_destroy(c);
         delete c;
         return rc;
     }
@@ -195,6 +235,8 @@ extern "C" void wfa_ctx_destroy(wfa_ctx* ctx) {
     for (auto& e : ctx->idle)
         if (e) engine_destroy(e.get());
     ctx->idle.clear();
+    if (ctx->fixed) engine_destroy(ctx->fixed.get());  // the scratch array itself stays
+    ctx->fixed.reset();
     engine_destroy(ctx);
     delete ctx;
 }

@@ -40,6 +40,13 @@ struct Workspace {
     // order on the first one once all of them have drained, so growing one
     // engine's buffers never waits for work of other engines on the device
     hipStream_t own[3] = {nullptr, nullptr, nullptr};
+    // Fixed mode (the allocation-free entry point): every buffer is carved
+    // from one caller-provided device region by a bump pointer and nothing is
+    // ever allocated; a buffer that does not fit is WFA_E_NOMEM.  Releasing
+    // the most recently carved buffer hands its bytes back.
+    unsigned char* fixed_base = nullptr;
+    size_t fixed_size = 0, fixed_top = 0;
+    void use_fixed(void* base, size_t size);  // start carving from an empty region
 
     std::array<Buf*, 33> all() {
         return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,
@@ -122,11 +129,19 @@ struct Engine {
 
 // The context's own engine, plus the engines of closed servers: a server
 // opened later takes them over with their streams and device buffers
-// instead of allocating its own again.
+// instead of allocating its own again.  `fixed` serves the allocation-free
+// entry point: its workspace lives in the device's static scratch array.
 struct wfa_ctx : Engine {
     std::mutex idle_mu;
     std::vector<std::unique_ptr<Engine>> idle;
+    std::unique_ptr<Engine> fixed;
 };
+
+// Allocation-free entry point: the device address of the static scratch
+// array (resolved once per device at context creation) and its size.
+int noalloc_setup(int device);
+void* noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
 
 // Batch inputs/outputs as given by the caller.
 struct BatchIO {

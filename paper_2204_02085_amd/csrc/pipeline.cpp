@@ -171,8 +171,16 @@ void scan_chunk_ends(const wfa_pair* pairs, size_t n, size_t chunk, bool ascii,
 
 int engine_align(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,
                  int64_t* bad_pair) {
-    if (io.mem == WFA_HOST) return engine_align_host(e, io, user_stream, cigar_needed, bad_pair);
-    return engine_align_device(e, io, user_stream, cigar_needed, bad_pair);
+    const int rc = io.mem == WFA_HOST
+                       ? engine_align_host(e, io, user_stream, cigar_needed, bad_pair)
+                       : engine_align_device(e, io, user_stream, cigar_needed, bad_pair);
+    if (rc == WFA_E_NOMEM) {
+        // the buffers a batch that did not fit left behind would count
+        // against every later batch: start the next one from nothing
+        graph_cache_clear(e);
+        e->ws.release_all();
+    }
+    return rc;
 }
 
 int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, size_t* cigar_needed,

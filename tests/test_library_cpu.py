@@ -77,3 +77,20 @@ def test_pair_descriptor_layout(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
+
+
+def test_noalloc_constants_and_null_context():
+    """The allocation-free entry point's limits in the binding match the
+    header, and it rejects a missing context before touching a device."""
+    import paper_2204_02085_amd as wfa
+
+    src = open(os.path.join(ROOT, "include", "wfa.h")).read()
+    assert "#define WFA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)" in src
+    assert "#define WFA_NOALLOC_MAX_PAIRS ((uint32_t)1 << 18)" in src
+    assert wfa.WFA_NOALLOC_SCRATCH_BYTES == 128 << 20 and wfa.WFA_NOALLOC_MAX_PAIRS == 1 << 18
+    needed = ctypes.c_size_t(7)
+    bad = ctypes.c_int64(7)
+    rc = wfa.wfa_align_batch_noalloc(None, None, None, None, 0, 0, wfa.wfa_penalties(4, 6, 2), 1,
+                                     None, None, 0, None, ctypes.byref(needed), ctypes.byref(bad),
+                                     None)
+    assert rc == wfa.WFA_E_INVAL and bad.value == -1 and needed.value == 0
