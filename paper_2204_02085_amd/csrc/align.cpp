@@ -319,7 +319,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
 bool GraphKey::operator==(const GraphKey& o) const {
     for (int i = 0; i < 8; i++)
         if (p[i] != o.p[i]) return false;
-    for (int i = 0; i < 12; i++)
+    for (int i = 0; i < 18; i++)
         if (ints[i] != o.ints[i]) return false;
     return n == o.n && capacity == o.capacity && form == o.form;
 }
@@ -574,12 +574,16 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         key.n = N;
         key.capacity = d.capacity;
         key.form = form;
-        const int ints[12] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g,
+        // every value the captured launches bake in besides the pointers:
+        // penalties, plan, lengths, grid, forms, free ends, queue claims
+        const int ints[18] = {(int)io.enc, (int)io.mode, pen.x, pen.oe, pen.e, pen.g,
                               window * 256 + lanes, sp.cap,
                               (int)st.max_p, (int)st.max_t, grid,
                               (int)(bucket ? 1 : 0) | (stride_p ? 4 : 0) | (stride_t ? 8 : 0) |
-                                  (persistent ? 16 : 0) | (sp.block_threads << 8)};
-        for (int i = 0; i < 12; i++) key.ints[i] = ints[i];
+                                  (persistent ? 16 : 0) | (sp.block_threads << 8),
+                              e->ends.pb, e->ends.pe, e->ends.tb, e->ends.te, queue_chunk,
+                              sp.slot_cap};
+        for (int i = 0; i < 18; i++) key.ints[i] = ints[i];
         for (auto& g : e->graphs)
             if (g.key == key) hit = &g;
         if (!hit) {

@@ -93,7 +93,7 @@ struct GraphKey {
     size_t n = 0;
     uint64_t capacity = 0;
     int form = 0;  // 1: one graph of the whole device phase, 2: pre / post graphs
-    int ints[12] = {};
+    int ints[18] = {};
     bool operator==(const GraphKey& o) const;
 };
 

@@ -61,10 +61,11 @@ def test_noalloc_equals_align_batch(oracle_lib, synth_lib, mode):
         # first call: 100 bp pairs at E = 4 % and uneven 50-300 bp pairs (some
         # go through the cascade) plus a few 1-2 kbp pairs (general kernel,
         # arena carved from the scratch array); second call: fewer pairs
-        big = synth_lib.from_pairs(
-            [synth_lib.workload("pairs100_e4_5m", 30_000).pair(i) for i in range(0, 30_000, 1)]
-            + [synth_lib.workload("uneven50_300_2m", 8000, first=50).pair(i) for i in range(8000)]
-            + _long_pairs(synth_lib, 6))
+        e4 = synth_lib.workload("pairs100_e4_5m", 30_000)
+        un = synth_lib.workload("uneven50_300_2m", 8000, first=50)
+        big = synth_lib.from_pairs([e4.pair(i) for i in range(len(e4))]
+                                   + [un.pair(i) for i in range(len(un))]
+                                   + _long_pairs(synth_lib, 6))
         small = synth_lib.workload("uneven50_300_2m", 3000, first=123_456)
         for label, b in (("first", big), ("second", small)):
             say(f"case: noalloc {mode}, {label} call, {len(b)} pairs")
