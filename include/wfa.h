@@ -152,6 +152,15 @@ typedef struct {
                                  whose history outgrows its slice is re-run
                                  with a 4x slice.  0: estimated from the
                                  lengths and the history seen so far */
+    int32_t lane_kernel;      /* 0 or 1: the first pass runs on the
+                                 one-pair-per-lane kernel, whose wavefront rows
+                                 live in registers, whenever it is built for the
+                                 penalties (x, o, e = 4, 6, 2 and multiples),
+                                 every sequence has at most 127 bases, the
+                                 alignment is global, no window or lanes per
+                                 pair are asked for and step_cap is at most 16
+                                 (it holds 8 steps if step_cap <= 8, else 16);
+                                 -1: never */
     int32_t general_step_limit; /* diagnostic: score steps (in units of
                                  gcd(x,o,e)) after which the general kernel
                                  gives up on a pair, which makes the call
@@ -202,7 +211,8 @@ typedef struct {
     double ms_compact;
     double ms_total;             /* host wall time of the call                       */
     int32_t cascade_window;      /* window of the cascade's last pass, 0: none       */
-    int32_t pad_;
+    int32_t lane_kernel;         /* 1 if the first pass ran one pair per lane
+                                    (window 0, lanes_per_pair 1)               */
 } wfa_stats;
 
 enum {

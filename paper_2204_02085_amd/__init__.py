@@ -58,7 +58,8 @@ class wfa_options(ctypes.Structure):
                 ("bucket", ctypes.c_int32), ("general_pairs", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32),
                 ("host_chunk_pairs", ctypes.c_int32), ("cascade_window", ctypes.c_int32),
-                ("general_slice_kib", ctypes.c_int32), ("general_step_limit", ctypes.c_int32)]
+                ("general_slice_kib", ctypes.c_int32), ("lane_kernel", ctypes.c_int32),
+                ("general_step_limit", ctypes.c_int32)]
 
 
 class wfa_ends_free(ctypes.Structure):
@@ -75,7 +76,7 @@ class wfa_stats(ctypes.Structure):
                 ("graph_replayed", ctypes.c_int32), ("ms_pack", ctypes.c_double),
                 ("ms_align", ctypes.c_double), ("ms_general", ctypes.c_double),
                 ("ms_compact", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("cascade_window", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("cascade_window", ctypes.c_int32), ("lane_kernel", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwfa.so")
 SOURCES = ["kernels.hip", "api.cpp", "align.cpp", "pipeline.cpp", "server.cpp", "autotune.cpp",
-           "noalloc.hip"]
+           "noalloc.hip", "k_lane.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -421,6 +421,32 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         if (!short_shape_supported(window, lanes)) lanes = default_lanes(window);
         if (short_plan(e, pen, cigar, window, lanes, cap, max_len, &sp) != WFA_OK) use_short = false;
     }
+    // The one-lane-per-pair kernel takes the first pass when it is built for
+    // the penalties, the batch's lengths and the step cap (8 if the caller
+    // asks for at most 8 steps, else 16), alignment is global, and no
+    // short-kernel shape was asked for.  Pairs it cannot hold go to the
+    // cascade from window 64 on, as from a 32-wide first pass.
+    bool lane = false;
+    if (use_short && global && e->opt.lane_kernel >= 0 && !e->opt.window && !e->opt.lanes_per_pair &&
+        e->opt.step_cap <= 16) {
+        const int lcap = (e->opt.step_cap > 0 && e->opt.step_cap <= 8) ? 8 : 16;
+        // a workgroup's LDS (both sequences and, with CIGAR, the history of
+        // every lane of its wavefronts) stays within 64 KiB
+        int lbt = e->opt.block_threads ? e->opt.block_threads : 256;
+        while (lbt > 64 && lane_lds_bytes(pen, lcap, cigar, lbt) > 64 * 1024) lbt -= 64;
+        if (lane_supported(pen, lcap, max_len) && lane_lds_bytes(pen, lcap, cigar, lbt) <= 64 * 1024) {
+            lane = true;
+            window = 32;
+            lanes = 1;
+            sp = ShortPlan{};
+            sp.window = 0;
+            sp.lanes = 1;
+            sp.cap = lcap;
+            sp.slot_cap = 2 * (lcap / std::min(pen.x, pen.e) + 1) + 2;
+            sp.block_threads = lbt;
+            sp.lds_per_block = lane_lds_bytes(pen, lcap, cigar, lbt);
+        }
+    }
     const bool persistent = use_short && schedule != WFA_SCHED_PLAIN;
     const bool bucket = persistent && e->opt.bucket >= 0;
     // graphs: by default for the persistent schedule; the plain one only on request
@@ -467,10 +493,12 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     int grid = 1;
     int queue_chunk = 1;
     if (use_short) {
-        const int gpb = short_groups_per_block(lanes, sp.block_threads);
+        // pairs per workgroup: lane groups of the short kernel, or one per lane
+        const int gpb = lane ? sp.block_threads : short_groups_per_block(lanes, sp.block_threads);
         if (persistent) {
-            int bpc = short_max_blocks_per_cu(window, lanes, cigar, sp.block_threads,
-                                              sp.lds_per_block, sp.row_bytes);
+            int bpc = lane ? lane_max_blocks_per_cu(pen, sp.cap, cigar, sp.block_threads)
+                           : short_max_blocks_per_cu(window, lanes, cigar, sp.block_threads,
+                                                     sp.lds_per_block, sp.row_bytes);
             if (bpc < 1) bpc = 1;
             grid = e->num_cus * bpc;
             const size_t needed = (N + gpb - 1) / gpb;
@@ -516,7 +544,26 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     };
     // the short-pair kernel itself
     auto phase_kernel = [&](hipStream_t q) -> int {
-        if (use_short) {
+        if (lane) {
+            LaneArgs a{};
+            a.pairs = d.pairs;
+            a.pw = d.pw;
+            a.tw = d.tw;
+            a.order = bucket ? ws.order.as<uint32_t>() : nullptr;
+            a.num = (uint32_t)N;
+            a.npairs = (uint32_t)N;
+            a.queue = &flags->queue;
+            a.queue_chunk = queue_chunk;
+            a.pen = pen;
+            a.slot_cap = sp.slot_cap;
+            a.scores = d.scores;
+            a.nruns = ws.nruns.as<uint32_t>();
+            a.run_src = ws.run_src.as<uint64_t>();
+            a.slots = ws.slots.as<uint32_t>();
+            a.ovf_list = ws.ovf_list.as<uint32_t>();
+            a.ovf_count = &flags->ovf_count;
+            HIPCHK(launch_lane(a, sp.cap, cigar, persistent, sp.block_threads, grid, q));
+        } else if (use_short) {
             ShortArgs a{};
             a.pairs = d.pairs;
             a.pw = d.pw;
@@ -772,8 +819,9 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     L.cascade_window = window2;
     L.requeued = requeued;
     L.cigar_runs = total;
-    L.window = use_short ? window : 0;
+    L.window = use_short && !lane ? window : 0;
     L.lanes_per_pair = use_short ? lanes : 0;
+    L.lane_kernel = lane ? 1 : 0;
     L.step_cap = use_short ? sp.cap : 0;
     L.schedule = !use_short ? WFA_SCHED_GENERAL : (persistent ? WFA_SCHED_PERSISTENT : WFA_SCHED_PLAIN);
     L.graph_replayed = form;

@@ -62,6 +62,7 @@ bool load_entry(const char* path, const std::string& key, wfa_options* out) {
         o.block_threads = get("block_threads");
         o.bucket = get("bucket");
         o.use_graph = get("use_graph");
+        o.lane_kernel = get("lane_kernel");
         *out = o;
         return true;
     }
@@ -84,6 +85,7 @@ void store_entry(const char* path, const std::string& key, const Candidate& c) {
       << ", \"lanes_per_pair\": " << c.opt.lanes_per_pair
       << ", \"step_cap\": " << c.opt.step_cap << ", \"block_threads\": " << c.opt.block_threads
       << ", \"bucket\": " << c.opt.bucket << ", \"use_graph\": " << c.opt.use_graph
+      << ", \"lane_kernel\": " << c.opt.lane_kernel
       << ", \"ms_per_million_pairs\": " << c.ms << "}";
     lines.push_back(e.str());
     std::ofstream f(path, std::ios::trunc);
@@ -251,6 +253,13 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         double ms;
     };
     std::vector<Shape> shapes;
+    // the one-pair-per-lane kernel (window 0 in the shape list): step cap 16,
+    // or 8 when the sample's largest score step allows
+    if (wfa::lane_supported(P, 16, max_len) && ctx->ends.pb == 0 && ctx->ends.pe == 0 &&
+        ctx->ends.tb == 0 && ctx->ends.te == 0) {
+        const int lc = (sample_steps >= 0 && sample_steps <= 8) ? 8 : 16;
+        shapes.push_back({0, 1, 16, lc, 1e30});
+    }
     const int windows[] = {16, 24, 32, 48, 64, 128, 256};
     for (int w : windows) {
         if (w < 2 * (int)max_diff + 4 && w != 256) continue;  // the target must fit the window
@@ -265,11 +274,12 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         Candidate c{};
         c.opt.schedule = WFA_SCHED_PLAIN;
         c.opt.window = sh.w;
-        c.opt.lanes_per_pair = sh.g;
+        c.opt.lanes_per_pair = sh.w ? sh.g : 0;
         c.opt.step_cap = sh.caps;
-        c.opt.block_threads = 128;
+        c.opt.block_threads = sh.w ? 128 : 256;
         c.opt.bucket = -1;
         c.opt.use_graph = -1;
+        c.opt.lane_kernel = sh.w ? -1 : 1;
         const int r = evaluate(c, 3);
         if (r == WFA_OK) sh.ms = c.ms;
         else if (r != WFA_E_NOMEM) { status = r; break; }
@@ -294,7 +304,8 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
                     Candidate c{};
                     c.opt.schedule = form == 0 ? WFA_SCHED_PLAIN : WFA_SCHED_PERSISTENT;
                     c.opt.window = sh.w;
-                    c.opt.lanes_per_pair = sh.g;
+                    c.opt.lanes_per_pair = sh.w ? sh.g : 0;
+                    c.opt.lane_kernel = sh.w ? -1 : 1;
                     c.opt.step_cap = capx;
                     c.opt.block_threads = bt;
                     c.opt.bucket = form == 1 ? 1 : -1;

@@ -1,0 +1,560 @@
+// One lane per pair: the wavefront algorithm with every wavefront row of a
+// pair in registers, for short reads under a fixed penalty set.
+//
+// The paper runs one pair per DPU thread (Introduction and Methods); on a
+// GPU the same independence puts one pair on each lane of a wavefront, 64
+// pairs stepping through the score steps together.  What makes this pay on
+// CDNA is that, for fixed scaled penalties (x', o'+e', e'), which (s, k)
+// cells of the WFA recurrences can hold an offset at all does not depend on
+// the sequences:
+//
+//   M_0[0] exists; I_s[k] exists if M_{s-o'-e'}[k-1] or I_{s-e'}[k-1] does;
+//   D_s[k] exists if M_{s-o'-e'}[k+1] or D_{s-e'}[k+1] does; M_s[k] exists
+//   if M_{s-x'}[k], I_s[k] or D_s[k] does.
+//
+// So the kernel is unrolled at compile time over exactly those cells (167
+// M cells for steps 0..16 under (4, 6, 2), against 289 in the full
+// triangle), every source index is a constant, the rows are plain
+// registers, and a cell whose source cannot exist drops that candidate at
+// compile time.  All lanes compute the same cells; each lane's own values
+// differ.  The recurrences, the admissibility rule (a candidate offset c on
+// diagonal k counts only if 0 <= c <= min(m, n + k), dropped before the
+// maximum), the extension along matches, the termination test
+// (M_s[m - n] == m) and the tie-break of the decision records are those of
+// the short-pair kernel, so the results are bit-identical to it and to the
+// oracle.
+//
+// LDS per wavefront, lane-interleaved (dword q of lane l at q * 64 + l, so
+// 64 lanes reading "their" dword q hit 64 different banks):
+//   - the pattern and the text in 2-bit little-endian words;
+//   - CIGAR mode: the history of every reachable M cell, its offset after
+//     extension (one byte, 0x80 for NULL) and its 4-bit decision record
+//     (source of M: mismatch / end of insertion / end of deletion; whether I
+//     and D opened from M), packed in the cells' compile-time order.
+// The backtrace is the short kernel's walk, run by every lane on its own
+// pair, with a per-block LDS table mapping (s, k) to the cell's index.
+//
+// A pair leaves through the overflow list (to the wider short-kernel passes
+// and the general kernel) when a sequence is longer than LMAX bases, when
+// its target diagonal lies outside the cells the kernel holds, when it needs
+// more than CAP steps, or when its walk or runs do not fit.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+#include "kernels.h"
+
+namespace wfa {
+
+namespace {
+
+constexpr int LNUL = -(1 << 20);  // NULL offset; drifts up by at most one per step
+
+// Which cells of steps 0..CAP can hold an offset (see above), and the
+// compact history index of each reachable M cell.
+template <int X, int OE, int E, int CAP, int KM>
+struct LaneReach {
+    static constexpr int W = 2 * KM + 1;
+    bool m[CAP + 1][W] = {};
+    bool i[CAP + 1][W] = {};
+    bool d[CAP + 1][W] = {};
+    short cidx[CAP + 1][W] = {};
+    int ncells = 0;
+    int kmax = 0;
+    constexpr LaneReach() {
+        for (int s = 0; s <= CAP; s++)
+            for (int j = 0; j < W; j++) cidx[s][j] = -1;
+        m[0][KM] = true;
+        for (int s = 1; s <= CAP; s++) {
+            for (int j = 0; j < W; j++) {
+                bool iv = false, dv = false, mv = false;
+                if (s >= OE && j >= 1 && m[s - OE][j - 1]) iv = true;
+                if (s >= E && j >= 1 && i[s - E][j - 1]) iv = true;
+                if (s >= OE && j + 1 < W && m[s - OE][j + 1]) dv = true;
+                if (s >= E && j + 1 < W && d[s - E][j + 1]) dv = true;
+                if (s >= X && m[s - X][j]) mv = true;
+                i[s][j] = iv;
+                d[s][j] = dv;
+                m[s][j] = mv || iv || dv;
+            }
+        }
+        int c = 0;
+        for (int s = 0; s <= CAP; s++)
+            for (int j = 0; j < W; j++)
+                if (m[s][j]) {
+                    cidx[s][j] = (short)c++;
+                    const int k = j - KM;
+                    kmax = (k > kmax) ? k : ((-k > kmax) ? -k : kmax);
+                }
+        ncells = c;
+    }
+};
+
+template <class P>
+__device__ __forceinline__ uint32_t lds_u32(P base, int dw) {
+    return base[dw];
+}
+
+// 32 bases from base `pos` of a lane's sequence column (dword q at q * 64).
+template <class P>
+__device__ __forceinline__ uint64_t col_window32(P col, int pos) {
+    const int q = pos >> 4;
+    const uint32_t b = (uint32_t)(pos & 15) << 1;
+    const uint32_t w0 = col[q * 64], w1 = col[q * 64 + 64], w2 = col[q * 64 + 128];
+    const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, b);
+    const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, b);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <class T>
+using lptr = __attribute__((address_space(3))) T*;
+
+template <int X, int OE, int E, int CAP, int LMAX, bool CIGAR>
+struct LaneKernel {
+    static constexpr int KM = CAP;  // array half-width; reachable |k| stays below it
+    using R = LaneReach<X, OE, E, CAP, KM>;
+    static constexpr R reach{};
+    static constexpr int W = R::W;
+    static_assert(reach.kmax < KM, "reachable cells must stay inside the arrays");
+    static constexpr int NC = reach.ncells;
+    static constexpr int RM = (X > OE ? X : OE) + 1;  // ring of M rows
+    static constexpr int RID = E + 1;                 // rings of I and D rows
+    static constexpr int SQ = (LMAX >> 4) + 3;        // dwords per sequence column
+    static constexpr int HMW = (NC + 3) / 4;          // history dwords: offsets
+    static constexpr int HRW = (NC + 7) / 8;          //                 records
+    // dwords per lane of LDS: both sequences, then the history
+    static constexpr int LANE_DW = 2 * SQ + (CIGAR ? HMW + HRW : 0);
+    static constexpr int WAVE_BYTES = LANE_DW * 64 * 4;
+    static constexpr int TABLE_BYTES = CIGAR ? ((CAP + 1) * W * 2 + 15) & ~15 : 0;
+
+    struct St {
+        int M[RM][W];
+        int I[RID][W];
+        int D[RID][W];
+        uint32_t pm, pr;  // history words being packed
+    };
+
+    struct Lane {
+        int n, m, kt;
+        bool run;  // holds a pair that has not finished
+        int S;
+        lptr<uint32_t> P, T, HM, HR;
+    };
+
+    template <int S, int J>
+    static __device__ __forceinline__ void cell(St& st, Lane& ln, bool& term) {
+        if constexpr (reach.m[S][J]) {
+            constexpr int k = J - KM;
+            const int L = min(ln.m, ln.n + k);  // largest admissible offset
+            int Mv, Iv = LNUL, Dv = LNUL;
+            uint32_t rec = 0;
+            if constexpr (S == 0) {
+                Mv = 0;
+            } else {
+                // candidates as unsigned distances t = L - c below the limit:
+                // admissible offsets 0 <= t <= L, NULL sources just below
+                // tn = L - NULL, offsets past L negative (huge); the largest
+                // admissible candidate is the smallest t, floored at tn
+                constexpr bool hA = S >= OE && J >= 1 && reach.m[S >= OE ? S - OE : 0][J >= 1 ? J - 1 : 0];
+                constexpr bool hB = S >= E && J >= 1 && reach.i[S >= E ? S - E : 0][J >= 1 ? J - 1 : 0];
+                constexpr bool hC = S >= OE && J + 1 < W && reach.m[S >= OE ? S - OE : 0][J + 1 < W ? J + 1 : 0];
+                constexpr bool hE = S >= E && J + 1 < W && reach.d[S >= E ? S - E : 0][J + 1 < W ? J + 1 : 0];
+                constexpr bool hX = S >= X && reach.m[S >= X ? S - X : 0][J];
+                const uint32_t tn = (uint32_t)(L - LNUL);
+                uint32_t ta = tn, tb = tn, tc = tn, te = tn, tx = tn;
+                if constexpr (hA) ta = (uint32_t)(L - 1 - st.M[(S - OE) % RM][J - 1]);
+                if constexpr (hB) tb = (uint32_t)(L - 1 - st.I[(S - E) % RID][J - 1]);
+                if constexpr (hC) tc = (uint32_t)(L - st.M[(S - OE) % RM][J + 1]);
+                if constexpr (hE) te = (uint32_t)(L - st.D[(S - E) % RID][J + 1]);
+                if constexpr (hX) tx = (uint32_t)(L - 1 - st.M[(S - X) % RM][J]);
+                const uint32_t ti = min(min(ta, tb), tn);
+                const uint32_t td = min(min(tc, te), tn);
+                const uint32_t tm = min(min(tx, ti), td);
+                Mv = L - (int)tm;
+                Iv = L - (int)ti;
+                Dv = L - (int)td;
+                if constexpr (CIGAR) {
+                    // tie-break: mismatch, then insertion, then deletion;
+                    // gap open before gap extension
+                    const uint32_t msrc = tx == tm ? 0u : (ti == tm ? 1u : 2u);
+                    rec = msrc | (ta == ti ? 4u : 0u) | (tc == td ? 8u : 0u);
+                }
+            }
+            // extend along matches, 32 bases per compare (wave-uniform loop;
+            // lanes with nothing to extend compare at offset 0 and add nothing)
+            {
+                const bool go = ln.run && Mv >= 0 && Mv < L;  // L < 0 off the matrix
+                int hp = go ? Mv : 0;
+                int vp = go ? Mv - k : 0;
+                int rem = go ? L - Mv : 0;
+                uint64_t gm = __ballot(go);
+                while (gm) {
+                    const uint64_t a = col_window32(ln.P, vp), b = col_window32(ln.T, hp);
+                    const uint64_t dx = a ^ b;
+                    const int cp = dx ? (int)(__builtin_ctzll(dx) >> 1) : 32;
+                    const int r = min(cp, rem);
+                    hp += r;
+                    vp += r;
+                    rem = r == 32 ? rem - 32 : 0;
+                    gm = __ballot(rem > 0);
+                }
+                Mv = go ? hp : Mv;
+            }
+            st.M[S % RM][J] = Mv;
+            if constexpr (reach.i[S][J]) st.I[S % RID][J] = Iv;
+            if constexpr (reach.d[S][J]) st.D[S % RID][J] = Dv;
+            if constexpr (CIGAR) {
+                constexpr int c = reach.cidx[S][J];
+                const uint32_t hb = Mv < 0 ? 0x80u : (uint32_t)Mv;
+                if constexpr ((c & 3) == 0) st.pm = hb;
+                else st.pm |= hb << (8 * (c & 3));
+                if constexpr ((c & 3) == 3 || c == NC - 1) ln.HM[(c >> 2) * 64] = st.pm;
+                if constexpr ((c & 7) == 0) st.pr = rec;
+                else st.pr |= rec << (4 * (c & 7));
+                if constexpr ((c & 7) == 7 || c == NC - 1) ln.HR[(c >> 3) * 64] = st.pr;
+            }
+            term |= (k == ln.kt) & (Mv == ln.m);
+        }
+    }
+
+    template <int S, int... Js>
+    static __device__ __forceinline__ bool step_cells(St& st, Lane& ln,
+                                                      std::integer_sequence<int, Js...>) {
+        bool term = false;
+        (cell<S, Js>(st, ln, term), ...);
+        return term;
+    }
+
+    // The history word being packed when the forward pass stops after step S
+    // (every lane finished): store it, so the walk never reads a stale word.
+    template <int S>
+    static __device__ __forceinline__ void flush(St& st, Lane& ln) {
+        if constexpr (CIGAR) {
+            constexpr int last = [] {
+                int c = -1;
+                for (int j = 0; j < W; j++)
+                    if (reach.m[S][j]) c = reach.cidx[S][j];
+                return c;
+            }();
+            if constexpr (last >= 0) {
+                if constexpr ((last & 3) != 3 && last != NC - 1) ln.HM[(last >> 2) * 64] = st.pm;
+                if constexpr ((last & 7) != 7 && last != NC - 1) ln.HR[(last >> 3) * 64] = st.pr;
+            }
+        }
+    }
+
+    // One score step; false once no lane of the wavefront is still running.
+    template <int S>
+    static __device__ __forceinline__ bool step(St& st, Lane& ln) {
+        // The lengths pass through an empty asm each step, so the per-diagonal
+        // limits min(m, n + k) are recomputed (two instructions per cell)
+        // instead of being kept in registers across the whole pass.
+        asm volatile("" : "+v"(ln.n), "+v"(ln.m));
+        const bool term = step_cells<S>(st, ln, std::make_integer_sequence<int, W>{});
+        const bool fin = ln.run && term;
+        ln.S = fin ? S : ln.S;
+        ln.run = ln.run && !term;
+        if (__ballot(ln.run) == 0) {
+            flush<S>(st, ln);
+            return false;
+        }
+        return true;
+    }
+
+    template <int... Ss>
+    static __device__ __forceinline__ void forward(St& st, Lane& ln,
+                                                   std::integer_sequence<int, Ss...>) {
+        (step<Ss>(st, ln) && ...);  // stops after the step where every lane finished
+    }
+};
+
+template <int X, int OE, int E, int CAP, int LMAX, bool CIGAR>
+__global__ __launch_bounds__(256) void k_lane(LaneArgs a, int persistent) {
+    using K = LaneKernel<X, OE, E, CAP, LMAX, CIGAR>;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    lptr<unsigned char> ldsb = (lptr<unsigned char>)lds;
+    // per block: the (s, k) -> history cell table (CIGAR), then one region
+    // per wavefront
+    lptr<short> table = (lptr<short>)ldsb;
+    if constexpr (CIGAR) {
+        for (int i = threadIdx.x; i < (CAP + 1) * K::W; i += blockDim.x)
+            table[i] = K::reach.cidx[i / K::W][i % K::W];
+        __syncthreads();
+    }
+    lptr<uint32_t> wbase = (lptr<uint32_t>)(ldsb + K::TABLE_BYTES + wave * K::WAVE_BYTES) + lane;
+    typename K::Lane ln;
+    ln.P = wbase;
+    ln.T = wbase + K::SQ * 64;
+    ln.HM = wbase + 2 * K::SQ * 64;
+    ln.HR = ln.HM + K::HMW * 64;
+
+    uint32_t claim = 0, claim_left = 0;
+    for (uint32_t iter = 0;; iter++) {
+        uint32_t qbase;
+        if (persistent) {
+            if (claim_left == 0) {
+                uint32_t t = 0;
+                if (lane == 0) t = atomicAdd(a.queue, (uint32_t)(64 * a.queue_chunk));
+                claim = __builtin_amdgcn_readfirstlane(t);
+                claim_left = (uint32_t)a.queue_chunk;
+            }
+            qbase = claim;
+            claim += 64;
+            claim_left--;
+        } else {
+            if (iter) break;
+            qbase = (blockIdx.x * wpb + wave) * 64;
+        }
+        if (qbase >= a.num) break;
+        const uint32_t q = qbase + lane;
+        uint32_t pair = 0;
+        bool active = q < a.num;
+        if (active) {
+            pair = a.order ? a.order[q] : q;
+            if (pair >= a.npairs) {  // a corrupt permutation must not fault: skip the entry
+                active = false;
+                pair = 0;
+            }
+        }
+        int n = 0, m = 0;
+        uint64_t ps = 0, ts = 0;
+        if (active) {
+            const PairDesc d = a.pairs[pair];
+            n = (int)d.p_len;
+            m = (int)d.t_len;
+            ps = d.p_start;
+            ts = d.t_start;
+        }
+        ln.n = n;
+        ln.m = m;
+        ln.kt = m - n;
+        // pairs this kernel cannot hold leave at once
+        bool fits = n <= LMAX && m <= LMAX && ln.kt >= -K::reach.kmax && ln.kt <= K::reach.kmax;
+        ln.run = active && fits;
+        ln.S = -1;
+        // stage both sequences in the lane's columns (zero past their ends)
+        {
+            const int nwp = ln.run ? (n + 31) >> 5 : 0, nwt = ln.run ? (m + 31) >> 5 : 0;
+#pragma unroll
+            for (int w = 0; w < (K::SQ + 1) / 2; w++) {
+                const uint64_t pv = w < nwp ? a.pw[ps + w] : 0ull;
+                const uint64_t tv = w < nwt ? a.tw[ts + w] : 0ull;
+                if (2 * w < K::SQ) {
+                    ln.P[(2 * w) * 64] = (uint32_t)pv;
+                    ln.T[(2 * w) * 64] = (uint32_t)tv;
+                }
+                if (2 * w + 1 < K::SQ) {
+                    ln.P[(2 * w + 1) * 64] = (uint32_t)(pv >> 32);
+                    ln.T[(2 * w + 1) * 64] = (uint32_t)(tv >> 32);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        typename K::St st;
+        if (__ballot(ln.run) != 0)
+            K::forward(st, ln, std::make_integer_sequence<int, CAP + 1>{});
+        // lanes still running after CAP steps leave through the overflow list
+        bool overflow = active && ln.S < 0;
+        int nr = 0;
+        if (CIGAR && active && !overflow) {
+            // The short kernel's walk, on this lane's pair: one event per
+            // iteration -- at M cell (s, k) the record names the source (a
+            // mismatch from M at s - x, or the end of a gap whose chain of I
+            // or D cells is followed back to the M cell it opened from); the
+            // iteration emits the cell's match run and the event's edit run
+            // (extending the open run when nothing matched in between and
+            // the op is the same) and moves to the source M cell.  Runs go
+            // to the pair's slot last to first.
+            const int cap_runs = a.slot_cap;
+            uint32_t* slot = a.slots + (uint64_t)pair * a.slot_cap;
+            auto cidx = [&](int s, int k) -> int {
+                if (s < 0 || s > CAP || k < -K::KM || k > K::KM) return -1;
+                return table[s * K::W + k + K::KM];
+            };
+            auto hm = [&](int c) -> int {
+                const uint32_t w = ln.HM[(c >> 2) * 64];
+                const int b = (int)((w >> (8 * (c & 3))) & 0xFFu);
+                return b & 0x80 ? -1 : b;
+            };
+            auto hr = [&](int c) -> int {
+                const uint32_t w = ln.HR[(c >> 3) * 64];
+                return (int)((w >> (4 * (c & 7))) & 15u);
+            };
+            int cop = -1, clen = 0;
+            int s = ln.S, k = ln.kt, h = m;
+            bool bad = false;
+            for (;;) {
+                const int c = cidx(s, k);
+                if (c < 0) {
+                    bad = true;
+                    break;
+                }
+                int h0 = 0, hn = 0, L = 1, op = 0, s2 = 0, dk = 0;
+                if (s > 0) {
+                    const int f = hr(c);
+                    const int ms = f & 3;
+                    if (ms == 0) {
+                        const int cs = cidx(s - X, k);
+                        if (cs < 0) {
+                            bad = true;
+                            break;
+                        }
+                        hn = hm(cs);
+                        h0 = hn + 1;
+                        s2 = s - X;
+                    } else {
+                        const int bit = ms == 1 ? 4 : 8;
+                        const int dj = ms == 1 ? -1 : 1;
+                        int sc = s, kc = k, fc = f;
+                        while (!(fc & bit)) {  // still extending: one step back
+                            sc -= E;
+                            kc += dj;
+                            const int cc = cidx(sc, kc);
+                            if (sc <= 0 || cc < 0) break;
+                            L++;
+                            fc = hr(cc);
+                        }
+                        const int co = cidx(sc - OE, kc + dj);
+                        if (!(fc & bit) || co < 0) {
+                            bad = true;  // a gap with no opening: inconsistent
+                            break;
+                        }
+                        hn = hm(co);
+                        h0 = ms == 1 ? hn + L : hn;  // insertions consume text
+                        s2 = sc - OE;
+                        dk = dj * L;
+                    }
+                    op = ms + 1;  // op codes: X=1 I=2 D=3
+                }
+                const bool last = s == 0;
+                const int mlen = h - h0;
+                if (mlen < 0 || hn < 0) {
+                    bad = true;
+                    break;
+                }
+                const bool hasM = mlen > 0;
+                const bool flushr = cop >= 0 && (hasM || last || cop != op);
+                if (flushr) {
+                    if (nr < cap_runs) slot[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    nr++;
+                }
+                if (hasM) {
+                    if (nr < cap_runs) slot[nr] = ((uint32_t)mlen << 4);
+                    nr++;
+                }
+                if (last) break;
+                clen = (flushr || hasM) ? L : clen + L;
+                cop = op;
+                s = s2;
+                k += dk;
+                h = hn;
+            }
+            if (bad || nr > cap_runs) overflow = true;
+        }
+        if (active) {
+            if (overflow) {
+                const uint32_t at = atomicAdd(a.ovf_count, 1u);
+                a.ovf_list[at] = pair;
+            } else {
+                a.scores[pair] = ln.S * a.pen.g;
+                a.nruns[pair] = CIGAR ? (uint32_t)nr : 0u;
+                if (CIGAR) a.run_src[pair] = (uint64_t)pair * a.slot_cap;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int X, int OE, int E, int CAP, int LMAX>
+struct LaneShape {
+    static int lds_bytes(bool cigar, int waves) {
+        return cigar ? LaneKernel<X, OE, E, CAP, LMAX, true>::TABLE_BYTES +
+                           waves * LaneKernel<X, OE, E, CAP, LMAX, true>::WAVE_BYTES
+                     : waves * LaneKernel<X, OE, E, CAP, LMAX, false>::WAVE_BYTES;
+    }
+    static hipError_t launch(const LaneArgs& a, bool cigar, bool persistent, int bt, int grid,
+                             hipStream_t s) {
+        const int lds = lds_bytes(cigar, bt / 64);
+        if (cigar)
+            hipLaunchKernelGGL((k_lane<X, OE, E, CAP, LMAX, true>), dim3(grid), dim3(bt), lds, s, a,
+                               persistent ? 1 : 0);
+        else
+            hipLaunchKernelGGL((k_lane<X, OE, E, CAP, LMAX, false>), dim3(grid), dim3(bt), lds, s, a,
+                               persistent ? 1 : 0);
+        return hipGetLastError();
+    }
+    static int occupancy(bool cigar, int bt) {
+        int blocks = 0;
+        const int lds = lds_bytes(cigar, bt / 64);
+        const hipError_t e =
+            cigar ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &blocks, (const void*)k_lane<X, OE, E, CAP, LMAX, true>, bt, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &blocks, (const void*)k_lane<X, OE, E, CAP, LMAX, false>, bt, lds);
+        return e == hipSuccess ? blocks : 0;
+    }
+    static int kmax() { return LaneKernel<X, OE, E, CAP, LMAX, false>::reach.kmax; }
+};
+
+// Shapes built: scaled penalties (2, 4, 1) -- x = 4, o = 6, e = 2 and their
+// multiples -- with 8 or 16 score steps, sequences up to 127 bases.
+#define WFA_LANE_SHAPES(F) \
+    F(2, 4, 1, 8, 127)     \
+    F(2, 4, 1, 16, 127)
+
+}  // namespace
+
+bool lane_supported(const Pen& pen, int cap, uint32_t max_len) {
+#define WFA_LANE_CASE(PX, POE, PE, PC, PLM) \
+    if (pen.x == PX && pen.oe == POE && pen.e == PE && cap == PC && max_len <= (uint32_t)PLM) return true;
+    WFA_LANE_SHAPES(WFA_LANE_CASE)
+#undef WFA_LANE_CASE
+    return false;
+}
+
+int lane_kmax(const Pen& pen, int cap) {
+#define WFA_LANE_CASE(PX, POE, PE, PC, PLM) \
+    if (pen.x == PX && pen.oe == POE && pen.e == PE && cap == PC) return LaneShape<PX, POE, PE, PC, PLM>::kmax();
+    WFA_LANE_SHAPES(WFA_LANE_CASE)
+#undef WFA_LANE_CASE
+    return -1;
+}
+
+int lane_lds_bytes(const Pen& pen, int cap, bool cigar, int block_threads) {
+#define WFA_LANE_CASE(PX, POE, PE, PC, PLM) \
+    if (pen.x == PX && pen.oe == POE && pen.e == PE && cap == PC) \
+        return LaneShape<PX, POE, PE, PC, PLM>::lds_bytes(cigar, block_threads / 64);
+    WFA_LANE_SHAPES(WFA_LANE_CASE)
+#undef WFA_LANE_CASE
+    return -1;
+}
+
+int lane_max_blocks_per_cu(const Pen& pen, int cap, bool cigar, int block_threads) {
+#define WFA_LANE_CASE(PX, POE, PE, PC, PLM) \
+    if (pen.x == PX && pen.oe == POE && pen.e == PE && cap == PC) \
+        return LaneShape<PX, POE, PE, PC, PLM>::occupancy(cigar, block_threads);
+    WFA_LANE_SHAPES(WFA_LANE_CASE)
+#undef WFA_LANE_CASE
+    return 0;
+}
+
+hipError_t launch_lane(const LaneArgs& a, int cap, bool cigar, bool persistent, int block_threads,
+                       int grid, hipStream_t s) {
+#define WFA_LANE_CASE(PX, POE, PE, PC, PLM) \
+    if (a.pen.x == PX && a.pen.oe == POE && a.pen.e == PE && cap == PC) \
+        return LaneShape<PX, POE, PE, PC, PLM>::launch(a, cigar, persistent, block_threads, grid, s);
+    WFA_LANE_SHAPES(WFA_LANE_CASE)
+#undef WFA_LANE_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace wfa

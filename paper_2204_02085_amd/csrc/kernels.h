@@ -76,6 +76,26 @@ struct ShortArgs {
     uint32_t* ovf_count;
 };
 
+// Arguments of the one-lane-per-pair kernel (all device pointers).
+struct LaneArgs {
+    const PairDesc* pairs;
+    const uint64_t* pw;         // packed pattern words
+    const uint64_t* tw;         // packed text words
+    const uint32_t* order;      // queue position -> pair index (NULL: identity)
+    uint32_t num;               // pairs in the queue
+    uint32_t npairs;            // pairs of the batch (bound of the indices in `order`)
+    uint32_t* queue;            // persistent: next queue position (device counter)
+    int queue_chunk;            // rounds of 64 pairs a wavefront claims per atomic
+    Pen pen;
+    int slot_cap;               // most runs a pair may have (CIGAR)
+    int32_t* scores;            // [pairs]
+    uint32_t* nruns;            // [pairs] runs written
+    uint64_t* run_src;          // [pairs] where the reversed runs live (slot of the pair)
+    uint32_t* slots;            // [pairs * slot_cap] reversed runs
+    uint32_t* ovf_list;         // pairs the kernel could not hold
+    uint32_t* ovf_count;
+};
+
 // Arguments of the general (workgroup-per-pair, HBM arena) kernel.
 struct GeneralArgs {
     const PairDesc* pairs;
@@ -145,6 +165,15 @@ hipError_t launch_short(const ShortArgs& a, int window, int lanes, bool cigar, b
 int short_groups_per_block(int lanes, int block_threads);
 int short_max_blocks_per_cu(int window, int lanes, bool cigar, int block_threads,
                             int lds_per_block, int row_bytes);
+
+// One-lane-per-pair kernel: built for some scaled penalty sets and step caps
+// (lane_supported); kmax is the largest |target diagonal| it can end on.
+bool lane_supported(const Pen& pen, int cap, uint32_t max_len);
+int lane_kmax(const Pen& pen, int cap);
+int lane_lds_bytes(const Pen& pen, int cap, bool cigar, int block_threads);
+int lane_max_blocks_per_cu(const Pen& pen, int cap, bool cigar, int block_threads);
+hipError_t launch_lane(const LaneArgs& a, int cap, bool cigar, bool persistent, int block_threads,
+                       int grid, hipStream_t s);
 
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds,
                           int lds_bytes, hipStream_t s);
