@@ -512,6 +512,11 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         }
     }
 
+    if (lane && cigar)  // one history region per wavefront of the launch
+        RCCHK(ws.ensure(ws.lane_hist, (size_t)grid * (sp.block_threads / 64) *
+                                          lane_hist_bytes_per_wave(pen, sp.cap, true)));
+    flags = ws.flags.as<DevFlags>();
+
     // ---- device phase (graph-capturable) ----------------------------------
     // Three phases; in graph mode the first and last are captured graphs and
     // the kernel between them is launched directly, so plain events around it
@@ -560,6 +565,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             a.nruns = ws.nruns.as<uint32_t>();
             a.run_src = ws.run_src.as<uint64_t>();
             a.slots = ws.slots.as<uint32_t>();
+            a.hist = cigar ? ws.lane_hist.as<uint32_t>() : nullptr;
             a.ovf_list = ws.ovf_list.as<uint32_t>();
             a.ovf_count = &flags->ovf_count;
             HIPCHK(launch_lane(a, sp.cap, cigar, persistent, sp.block_threads, grid, q));

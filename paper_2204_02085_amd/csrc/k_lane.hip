@@ -109,27 +109,54 @@ __device__ __forceinline__ uint64_t col_window32(P col, int pos) {
 
 template <class T>
 using lptr = __attribute__((address_space(3))) T*;
+template <class T>
+using gptr_t = __attribute__((address_space(1))) T*;
 
 template <int X, int OE, int E, int CAP, int LMAX, bool CIGAR>
 struct LaneKernel {
     static constexpr int KM = CAP;  // array half-width; reachable |k| stays below it
+    static constexpr int CAP1 = CAP + 1;
     using R = LaneReach<X, OE, E, CAP, KM>;
     static constexpr R reach{};
     static constexpr int W = R::W;
     static_assert(reach.kmax < KM, "reachable cells must stay inside the arrays");
     static constexpr int NC = reach.ncells;
-    static constexpr int RM = (X > OE ? X : OE) + 1;  // ring of M rows
-    static constexpr int RID = E + 1;                 // rings of I and D rows
+    static constexpr int RM = (X > OE ? X : OE) + 1;  // ring of M rows (registers)
+    static constexpr int RID = E + 1;                 // rings of I and D rows (registers)
     static constexpr int SQ = (LMAX >> 4) + 3;        // dwords per sequence column
-    static constexpr int HMW = (NC + 3) / 4;          // history dwords: offsets
-    static constexpr int HRW = (NC + 7) / 8;          //                 records
-    // dwords per lane of LDS: both sequences, then the history
-    static constexpr int LANE_DW = 2 * SQ + (CIGAR ? HMW + HRW : 0);
+
+    static constexpr int first_cell(int s) {
+        for (int j = 0; j < W; j++)
+            if (reach.m[s][j]) return reach.cidx[s][j];
+        return -1;
+    }
+    static constexpr int cells_of(int s) {
+        int c = 0;
+        for (int j = 0; j < W; j++) c += reach.m[s][j] ? 1 : 0;
+        return c;
+    }
+    static constexpr int max_cells() {
+        int mx = 0;
+        for (int s = 0; s <= CAP; s++) mx = cells_of(s) > mx ? cells_of(s) : mx;
+        return mx;
+    }
+    // LDS per lane: both sequences and the staging bytes of one step's cells
+    static constexpr int STW = (max_cells() + 3) / 4;
+    static constexpr int LANE_DW = 2 * SQ + STW;
     static constexpr int WAVE_BYTES = LANE_DW * 64 * 4;
-    static constexpr int TABLE_BYTES = CIGAR ? ((CAP + 1) * W * 2 + 15) & ~15 : 0;
+    // per block: the diagonal of each compact cell (int8), then (CIGAR) the
+    // (s, k) -> compact cell table (int16)
+    static constexpr int KOF_BYTES = (NC + 15) & ~15;
+    static constexpr int TABLE_BYTES = KOF_BYTES + (CIGAR ? (((CAP + 1) * W * 2 + 15) & ~15) : 0);
+    // CIGAR history per lane in global memory: the offset after extension of
+    // every reachable cell (a byte; 0x80 NULL) in compact order, then the
+    // cells' 4-bit decision records
+    static constexpr int HMW = (NC + 3) / 4;
+    static constexpr int HRW = (NC + 7) / 8;
+    static constexpr int HIST_DW = CIGAR ? HMW + HRW : 0;
 
     struct St {
-        int M[RM][W];
+        int M[RM][W];  // offsets after extension (0x80 stands for NULL)
         int I[RID][W];
         int D[RID][W];
         uint32_t pm, pr;  // history words being packed
@@ -139,23 +166,32 @@ struct LaneKernel {
         int n, m, kt;
         bool run;  // holds a pair that has not finished
         int S;
-        lptr<uint32_t> P, T, HM, HR;
+        lptr<uint32_t> P, T, G;  // sequence columns, staging column
+        gptr_t<uint32_t> H;      // history column (global), dword d at H[d * 64]
     };
 
+    static __device__ __forceinline__ lptr<uint8_t> gptr(const Lane& ln, int b) {
+        return (lptr<uint8_t>)(ln.G + (b >> 2) * 64) + (b & 3);
+    }
+
+    // Phase 1 of a step, one cell: the recurrences from the register rows,
+    // the decision record, and the offset before extension staged in LDS.
     template <int S, int J>
-    static __device__ __forceinline__ void cell(St& st, Lane& ln, bool& term) {
+    static __device__ __forceinline__ void cell(St& st, Lane& ln) {
         if constexpr (reach.m[S][J]) {
             constexpr int k = J - KM;
+            constexpr int g = reach.cidx[S][J] - first_cell(S);  // staging byte
             const int L = min(ln.m, ln.n + k);  // largest admissible offset
             int Mv, Iv = LNUL, Dv = LNUL;
-            uint32_t rec = 0;
+            [[maybe_unused]] uint32_t rec = 0;
             if constexpr (S == 0) {
                 Mv = 0;
             } else {
                 // candidates as unsigned distances t = L - c below the limit:
                 // admissible offsets 0 <= t <= L, NULL sources just below
                 // tn = L - NULL, offsets past L negative (huge); the largest
-                // admissible candidate is the smallest t, floored at tn
+                // admissible candidate is the smallest t, floored at tn.  An M
+                // source of 0x80 (NULL) is past every limit, so it drops out.
                 constexpr bool hA = S >= OE && J >= 1 && reach.m[S >= OE ? S - OE : 0][J >= 1 ? J - 1 : 0];
                 constexpr bool hB = S >= E && J >= 1 && reach.i[S >= E ? S - E : 0][J >= 1 ? J - 1 : 0];
                 constexpr bool hC = S >= OE && J + 1 < W && reach.m[S >= OE ? S - OE : 0][J + 1 < W ? J + 1 : 0];
@@ -179,19 +215,76 @@ struct LaneKernel {
                     // gap open before gap extension
                     const uint32_t msrc = tx == tm ? 0u : (ti == tm ? 1u : 2u);
                     rec = msrc | (ta == ti ? 4u : 0u) | (tc == td ? 8u : 0u);
+                    // materialise the record here: left to itself the compiler
+                    // sinks these compares to the record word's store, keeping
+                    // every candidate distance of eight cells live
+                    asm volatile("" : "+v"(rec));
                 }
             }
-            // extend along matches, 32 bases per compare (wave-uniform loop;
-            // lanes with nothing to extend compare at offset 0 and add nothing)
-            {
-                const bool go = ln.run && Mv >= 0 && Mv < L;  // L < 0 off the matrix
+            if constexpr (reach.i[S][J]) st.I[S % RID][J] = Iv;
+            if constexpr (reach.d[S][J]) st.D[S % RID][J] = Dv;
+            if constexpr (CIGAR) {
+                constexpr int c = reach.cidx[S][J];
+                if constexpr ((c & 7) == 0) st.pr = rec;
+                else st.pr |= rec << (4 * (c & 7));
+                if constexpr ((c & 7) == 7 || c == NC - 1) ln.H[(HMW + (c >> 3)) * 64] = st.pr;
+            }
+            // NULL (negative) becomes 0x80 (unsigned minimum)
+            *gptr(ln, g) = (uint8_t)min((uint32_t)Mv, 0x80u);
+        }
+    }
+
+    // Phase 3 of a step, one cell: the offset after extension into the
+    // register row and (CIGAR) the history.
+    template <int S, int J>
+    static __device__ __forceinline__ void cell_back(St& st, Lane& ln) {
+        if constexpr (reach.m[S][J]) {
+            constexpr int g = reach.cidx[S][J] - first_cell(S);
+            const int b = *gptr(ln, g);
+            st.M[S % RM][J] = b;
+            if constexpr (CIGAR) {
+                constexpr int c = reach.cidx[S][J];
+                if constexpr ((c & 3) == 0) st.pm = (uint32_t)b;
+                else st.pm |= (uint32_t)b << (8 * (c & 3));
+                if constexpr ((c & 3) == 3 || c == NC - 1) ln.H[(c >> 2) * 64] = st.pm;
+            }
+        }
+    }
+
+    template <int S, int... Js>
+    static __device__ __forceinline__ void step_cells(St& st, Lane& ln,
+                                                      std::integer_sequence<int, Js...>) {
+        (cell<S, Js>(st, ln), ...);
+    }
+    template <int S, int... Js>
+    static __device__ __forceinline__ void step_back(St& st, Lane& ln,
+                                                     std::integer_sequence<int, Js...>) {
+        (cell_back<S, Js>(st, ln), ...);
+    }
+
+    // Phase 2 of a step: extend every staged cell along matches, 32 bases
+    // per compare (a wave-uniform loop; lanes with nothing to extend compare
+    // at offset 0 and add nothing), stage the offset after extension, and
+    // test the target cell.  One rolled loop over the step's cells.
+    template <int S>
+    static __device__ __forceinline__ bool extend_step(Lane& ln, lptr<const int8_t> kof) {
+        constexpr int c0 = first_cell(S), ns = cells_of(S);
+        bool term = false;
+        if constexpr (ns > 0) {
+#pragma unroll 1
+            for (int j = 0; j < ns; j++) {
+                const int k = kof[c0 + j];
+                lptr<uint8_t> bp = gptr(ln, j);
+                const int Mv = *bp;  // 0x80 for NULL
+                const int L = min(ln.m, ln.n + k);
+                const bool go = ln.run && Mv < L;  // L <= LMAX < 0x80
                 int hp = go ? Mv : 0;
                 int vp = go ? Mv - k : 0;
                 int rem = go ? L - Mv : 0;
                 uint64_t gm = __ballot(go);
                 while (gm) {
-                    const uint64_t a = col_window32(ln.P, vp), b = col_window32(ln.T, hp);
-                    const uint64_t dx = a ^ b;
+                    const uint64_t a = col_window32(ln.P, vp), bb = col_window32(ln.T, hp);
+                    const uint64_t dx = a ^ bb;
                     const int cp = dx ? (int)(__builtin_ctzll(dx) >> 1) : 32;
                     const int r = min(cp, rem);
                     hp += r;
@@ -199,59 +292,38 @@ struct LaneKernel {
                     rem = r == 32 ? rem - 32 : 0;
                     gm = __ballot(rem > 0);
                 }
-                Mv = go ? hp : Mv;
+                if (go) *bp = (uint8_t)hp;
+                const int Mx = go ? hp : Mv;
+                term |= (k == ln.kt) & (Mx == ln.m);
             }
-            st.M[S % RM][J] = Mv;
-            if constexpr (reach.i[S][J]) st.I[S % RID][J] = Iv;
-            if constexpr (reach.d[S][J]) st.D[S % RID][J] = Dv;
-            if constexpr (CIGAR) {
-                constexpr int c = reach.cidx[S][J];
-                const uint32_t hb = Mv < 0 ? 0x80u : (uint32_t)Mv;
-                if constexpr ((c & 3) == 0) st.pm = hb;
-                else st.pm |= hb << (8 * (c & 3));
-                if constexpr ((c & 3) == 3 || c == NC - 1) ln.HM[(c >> 2) * 64] = st.pm;
-                if constexpr ((c & 7) == 0) st.pr = rec;
-                else st.pr |= rec << (4 * (c & 7));
-                if constexpr ((c & 7) == 7 || c == NC - 1) ln.HR[(c >> 3) * 64] = st.pr;
-            }
-            term |= (k == ln.kt) & (Mv == ln.m);
         }
-    }
-
-    template <int S, int... Js>
-    static __device__ __forceinline__ bool step_cells(St& st, Lane& ln,
-                                                      std::integer_sequence<int, Js...>) {
-        bool term = false;
-        (cell<S, Js>(st, ln, term), ...);
         return term;
     }
 
-    // The history word being packed when the forward pass stops after step S
-    // (every lane finished): store it, so the walk never reads a stale word.
+    // The history words being packed when the forward pass stops after step
+    // S (every lane finished): store them, so the walk never reads stale words.
     template <int S>
     static __device__ __forceinline__ void flush(St& st, Lane& ln) {
-        if constexpr (CIGAR) {
-            constexpr int last = [] {
-                int c = -1;
-                for (int j = 0; j < W; j++)
-                    if (reach.m[S][j]) c = reach.cidx[S][j];
-                return c;
-            }();
-            if constexpr (last >= 0) {
-                if constexpr ((last & 3) != 3 && last != NC - 1) ln.HM[(last >> 2) * 64] = st.pm;
-                if constexpr ((last & 7) != 7 && last != NC - 1) ln.HR[(last >> 3) * 64] = st.pr;
-            }
+        if constexpr (CIGAR && cells_of(S) > 0) {
+            constexpr int last = first_cell(S) + cells_of(S) - 1;
+            if constexpr ((last & 3) != 3 && last != NC - 1) ln.H[(last >> 2) * 64] = st.pm;
+            if constexpr ((last & 7) != 7 && last != NC - 1) ln.H[(HMW + (last >> 3)) * 64] = st.pr;
         }
     }
 
     // One score step; false once no lane of the wavefront is still running.
     template <int S>
-    static __device__ __forceinline__ bool step(St& st, Lane& ln) {
+    static __device__ __forceinline__ bool step(St& st, Lane& ln, lptr<const int8_t> kof) {
         // The lengths pass through an empty asm each step, so the per-diagonal
         // limits min(m, n + k) are recomputed (two instructions per cell)
         // instead of being kept in registers across the whole pass.
-        asm volatile("" : "+v"(ln.n), "+v"(ln.m));
-        const bool term = step_cells<S>(st, ln, std::make_integer_sequence<int, W>{});
+        // The history column's address passes through one too: otherwise the
+        // compiler hoists the address of every history word out of the pair
+        // loop and keeps them all in registers.
+        asm volatile("" : "+v"(ln.n), "+v"(ln.m), "+v"(ln.H));
+        step_cells<S>(st, ln, std::make_integer_sequence<int, W>{});
+        const bool term = extend_step<S>(ln, kof);
+        step_back<S>(st, ln, std::make_integer_sequence<int, W>{});
         const bool fin = ln.run && term;
         ln.S = fin ? S : ln.S;
         ln.run = ln.run && !term;
@@ -263,9 +335,9 @@ struct LaneKernel {
     }
 
     template <int... Ss>
-    static __device__ __forceinline__ void forward(St& st, Lane& ln,
+    static __device__ __forceinline__ void forward(St& st, Lane& ln, lptr<const int8_t> kof,
                                                    std::integer_sequence<int, Ss...>) {
-        (step<Ss>(st, ln) && ...);  // stops after the step where every lane finished
+        (step<Ss>(st, ln, kof) && ...);  // stops after the step where every lane finished
     }
 };
 
@@ -277,21 +349,24 @@ __global__ __launch_bounds__(256) void k_lane(LaneArgs a, int persistent) {
     const int wave = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     lptr<unsigned char> ldsb = (lptr<unsigned char>)lds;
-    // per block: the (s, k) -> history cell table (CIGAR), then one region
-    // per wavefront
-    lptr<short> table = (lptr<short>)ldsb;
-    if constexpr (CIGAR) {
-        for (int i = threadIdx.x; i < (CAP + 1) * K::W; i += blockDim.x)
-            table[i] = K::reach.cidx[i / K::W][i % K::W];
-        __syncthreads();
+    // per block: the diagonal of each compact cell, the (s, k) -> compact
+    // cell table (CIGAR), then one region per wavefront
+    lptr<int8_t> kof = (lptr<int8_t>)ldsb;
+    lptr<short> table = (lptr<short>)(ldsb + K::KOF_BYTES);
+    for (int i = threadIdx.x; i < (K::CAP1) * K::W; i += blockDim.x) {
+        const int s = i / K::W, j = i % K::W;
+        const int c = K::reach.cidx[s][j];
+        if (CIGAR) table[i] = (short)c;
+        if (c >= 0) kof[c] = (int8_t)(j - K::KM);
     }
+    __syncthreads();
     lptr<uint32_t> wbase = (lptr<uint32_t>)(ldsb + K::TABLE_BYTES + wave * K::WAVE_BYTES) + lane;
     typename K::Lane ln;
     ln.P = wbase;
     ln.T = wbase + K::SQ * 64;
-    ln.HM = wbase + 2 * K::SQ * 64;
-    ln.HR = ln.HM + K::HMW * 64;
-
+    ln.G = wbase + 2 * K::SQ * 64;
+    // this wavefront's history region (one per resident or launched wavefront)
+    ln.H = (gptr_t<uint32_t>)a.hist + ((uint64_t)(blockIdx.x * wpb + wave) * K::HIST_DW) * 64 + lane;
     uint32_t claim = 0, claim_left = 0;
     for (uint32_t iter = 0;; iter++) {
         uint32_t qbase;
@@ -359,7 +434,7 @@ __global__ __launch_bounds__(256) void k_lane(LaneArgs a, int persistent) {
 
         typename K::St st;
         if (__ballot(ln.run) != 0)
-            K::forward(st, ln, std::make_integer_sequence<int, CAP + 1>{});
+            K::forward(st, ln, (lptr<const int8_t>)kof, std::make_integer_sequence<int, CAP + 1>{});
         // lanes still running after CAP steps leave through the overflow list
         bool overflow = active && ln.S < 0;
         int nr = 0;
@@ -379,12 +454,12 @@ __global__ __launch_bounds__(256) void k_lane(LaneArgs a, int persistent) {
                 return table[s * K::W + k + K::KM];
             };
             auto hm = [&](int c) -> int {
-                const uint32_t w = ln.HM[(c >> 2) * 64];
+                const uint32_t w = ln.H[(c >> 2) * 64];
                 const int b = (int)((w >> (8 * (c & 3))) & 0xFFu);
                 return b & 0x80 ? -1 : b;
             };
             auto hr = [&](int c) -> int {
-                const uint32_t w = ln.HR[(c >> 3) * 64];
+                const uint32_t w = ln.H[(K::HMW + (c >> 3)) * 64];
                 return (int)((w >> (4 * (c & 7))) & 15u);
             };
             int cop = -1, clen = 0;
@@ -479,7 +554,11 @@ struct LaneShape {
     static int lds_bytes(bool cigar, int waves) {
         return cigar ? LaneKernel<X, OE, E, CAP, LMAX, true>::TABLE_BYTES +
                            waves * LaneKernel<X, OE, E, CAP, LMAX, true>::WAVE_BYTES
-                     : waves * LaneKernel<X, OE, E, CAP, LMAX, false>::WAVE_BYTES;
+                     : LaneKernel<X, OE, E, CAP, LMAX, false>::TABLE_BYTES +
+                           waves * LaneKernel<X, OE, E, CAP, LMAX, false>::WAVE_BYTES;
+    }
+    static int hist_dwords(bool cigar) {
+        return cigar ? LaneKernel<X, OE, E, CAP, LMAX, true>::HIST_DW * 64 : 0;
     }
     static hipError_t launch(const LaneArgs& a, bool cigar, bool persistent, int bt, int grid,
                              hipStream_t s) {
@@ -536,6 +615,15 @@ int lane_lds_bytes(const Pen& pen, int cap, bool cigar, int block_threads) {
     WFA_LANE_SHAPES(WFA_LANE_CASE)
 #undef WFA_LANE_CASE
     return -1;
+}
+
+size_t lane_hist_bytes_per_wave(const Pen& pen, int cap, bool cigar) {
+#define WFA_LANE_CASE(PX, POE, PE, PC, PLM) \
+    if (pen.x == PX && pen.oe == POE && pen.e == PE && cap == PC) \
+        return (size_t)LaneShape<PX, POE, PE, PC, PLM>::hist_dwords(cigar) * 4;
+    WFA_LANE_SHAPES(WFA_LANE_CASE)
+#undef WFA_LANE_CASE
+    return 0;
 }
 
 int lane_max_blocks_per_cu(const Pen& pen, int cap, bool cigar, int block_threads) {
