@@ -501,6 +501,10 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
                                                      sp.lds_per_block, sp.row_bytes);
             if (bpc < 1) bpc = 1;
             grid = e->num_cus * bpc;
+            if (std::getenv("WFA_DEBUG"))
+                std::fprintf(stderr, "libwfa plan: %s, %d threads per block, %d blocks per CU, "
+                                     "%d B LDS per block\n", lane ? "lane kernel" : "short kernel",
+                             sp.block_threads, bpc, sp.lds_per_block);
             const size_t needed = (N + gpb - 1) / gpb;
             if ((size_t)grid > needed) grid = (int)needed;
             // claims of several rounds keep the queue atomic off the critical
@@ -515,6 +519,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     if (lane && cigar)  // one history region per wavefront of the launch
         RCCHK(ws.ensure(ws.lane_hist, (size_t)grid * (sp.block_threads / 64) *
                                           lane_hist_bytes_per_wave(pen, sp.cap, true)));
+    if (lane && persistent) RCCHK(ws.ensure(ws.lane_queues, LANE_QUEUES * 32 * 4));
     flags = ws.flags.as<DevFlags>();
 
     // ---- device phase (graph-capturable) ----------------------------------
@@ -539,6 +544,8 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
                                      ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
         }
         HIPCHK(launch_fill_u32(ws.nruns.as<uint32_t>(), 0u, N, q));
+        if (lane && persistent)
+            HIPCHK(launch_fill_u32(ws.lane_queues.as<uint32_t>(), 0u, LANE_QUEUES * 32, q));
         if (use_short && bucket) {
             HIPCHK(launch_bucket_keys(d.pairs, N, ws.keys.as<uint32_t>(), ws.hist.as<uint32_t>(), q));
             HIPCHK(launch_scan(SCAN_U32, ws.hist.ptr, BUCKET_KEYS, cursor, ws.scan_tmp.ptr, q));
@@ -557,8 +564,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             a.order = bucket ? ws.order.as<uint32_t>() : nullptr;
             a.num = (uint32_t)N;
             a.npairs = (uint32_t)N;
-            a.queue = &flags->queue;
-            a.queue_chunk = queue_chunk;
+            a.queue = ws.lane_queues.as<uint32_t>();
             a.pen = pen;
             a.slot_cap = sp.slot_cap;
             a.scores = d.scores;

@@ -34,8 +34,9 @@ struct Workspace {
     Buf nruns, run_src, slots, ovf_list, order, keys, hist, slots2, ovf_list2;
     // general kernel
     Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp, job_used;
-    // one-pair-per-lane kernel: CIGAR history of every wavefront of a launch
-    Buf lane_hist;
+    // one-pair-per-lane kernel: CIGAR history of every wavefront of a launch,
+    // and the claim counters of its persistent form
+    Buf lane_hist, lane_queues;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
     // the owning engine's streams: buffers are allocated and freed in stream
@@ -50,13 +51,13 @@ struct Workspace {
     size_t fixed_size = 0, fixed_top = 0;
     void use_fixed(void* base, size_t size);  // start carving from an empty region
 
-    std::array<Buf*, 34> all() {
+    std::array<Buf*, 35> all() {
         return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,
                 &words_t, &packed_pairs, &in_pairs, &in_p,      &in_t,      &out_scores,
                 &out_runs, &out_offsets, &host_off, &host_loff, &nruns,   &run_src,
                 &slots,   &ovf_list,   &order,    &keys,        &hist,      &slots2,
                 &ovf_list2, &jobs,     &job_nruns, &job_offsets, &fail_list, &arena,
-                &gen_runs, &gen_tmp, &job_used, &lane_hist};
+                &gen_runs, &gen_tmp, &job_used, &lane_hist, &lane_queues};
     }
     int ensure(Buf& b, size_t bytes);
     // grow to at least `bytes`, keeping the first `keep` bytes (copied on `s`,

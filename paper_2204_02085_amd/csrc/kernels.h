@@ -84,8 +84,7 @@ struct LaneArgs {
     const uint32_t* order;      // queue position -> pair index (NULL: identity)
     uint32_t num;               // pairs in the queue
     uint32_t npairs;            // pairs of the batch (bound of the indices in `order`)
-    uint32_t* queue;            // persistent: next queue position (device counter)
-    int queue_chunk;            // rounds of 64 pairs a wavefront claims per atomic
+    uint32_t* queue;            // persistent: LANE_QUEUES claim counters, 32 words apart
     Pen pen;
     int slot_cap;               // most runs a pair may have (CIGAR)
     int32_t* scores;            // [pairs]
@@ -166,6 +165,10 @@ hipError_t launch_short(const ShortArgs& a, int window, int lanes, bool cigar, b
 int short_groups_per_block(int lanes, int block_threads);
 int short_max_blocks_per_cu(int window, int lanes, bool cigar, int block_threads,
                             int lds_per_block, int row_bytes);
+
+// Claim counters of the persistent one-lane-per-pair kernel (each on its own
+// 128-byte line: LANE_QUEUES * 32 words, zeroed before a launch).
+constexpr int LANE_QUEUES = 64;
 
 // One-lane-per-pair kernel: built for some scaled penalty sets and step caps
 // (lane_supported); kmax is the largest |target diagonal| it can end on.
