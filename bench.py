@@ -76,6 +76,9 @@ def parse():
                     help="JSON launch options instead of autotuning (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (PMC scale calibration)")
+    ap.add_argument("--calib-read-mib", type=int, default=0,
+                    help="first sum this many MiB of int32 (a read-only kernel of known bytes, "
+                         "PMC read-scale calibration)")
     ap.add_argument("--cpu-pairs", type=int, default=2_000_000,
                     help="oracle sample size for the CPU baseline, about 15 s of CPU time "
                          "on 16 threads (0: skip)")
@@ -100,6 +103,8 @@ def log(msg: str):
 
 def kernel_label(st: dict) -> str:
     """Name of the kernel a call's first pass ran (from its statistics)."""
+    if st.get("lane_kernel"):
+        return f"k_lane<one pair per lane, step cap {st['step_cap']}, cigar>"
     return (f"k_short<window {st['window']}, {st['lanes_per_pair']} lanes per pair, "
             f"step cap {st['step_cap']}, cigar>")
 
@@ -366,6 +371,14 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: 3 x {args.calib_copy_mib} MiB device to device")
         del src, dst
+    if args.calib_read_mib:
+        # a reduction reads its input once and writes a few bytes
+        x = torch.ones((args.calib_read_mib << 20) // 4, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            tot = int(x.sum().item())
+        torch.cuda.synchronize()
+        log(f"calibration read: 3 x {args.calib_read_mib} MiB summed ({tot} ones)")
+        del x
 
     t_gen = time.perf_counter()
     batch = synth.workload(args.workload, args.pairs)

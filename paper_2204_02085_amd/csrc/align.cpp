@@ -518,7 +518,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
 
     if (lane && cigar)  // one history region per wavefront of the launch
         RCCHK(ws.ensure(ws.lane_hist, (size_t)grid * (sp.block_threads / 64) *
-                                          lane_hist_bytes_per_wave(pen, sp.cap, true)));
+                                          lane_hist_bytes_per_wave(pen, sp.cap, true, sp.slot_cap)));
     if (lane && persistent) RCCHK(ws.ensure(ws.lane_queues, LANE_QUEUES * 32 * 4));
     flags = ws.flags.as<DevFlags>();
 

@@ -453,7 +453,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             // the op is the same) and moves to the source M cell.  Runs go
             // to the pair's slot last to first.
             const int cap_runs = a.slot_cap;
-            uint32_t* slot = a.slots + (uint64_t)pair * a.slot_cap;
+            // runs are staged lane-interleaved after the wavefront's history
+            // (run r of this lane at stage[r * 64]), so every store of the
+            // walk writes one contiguous 256-byte row
+            gptr_t<uint32_t> slot = ln.H + K::HIST_DW * 64;
             auto cidx = [&](int s, int k) -> int {
                 if (s < 0 || s > CAP || k < -K::KM || k > K::KM) return -1;
                 return table[s * K::W + k + K::KM];
@@ -522,11 +525,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 const bool hasM = mlen > 0;
                 const bool flushr = cop >= 0 && (hasM || last || cop != op);
                 if (flushr) {
-                    if (nr < cap_runs) slot[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    if (nr < cap_runs) slot[nr * 64] = ((uint32_t)clen << 4) | (uint32_t)cop;
                     nr++;
                 }
                 if (hasM) {
-                    if (nr < cap_runs) slot[nr] = ((uint32_t)mlen << 4);
+                    if (nr < cap_runs) slot[nr * 64] = ((uint32_t)mlen << 4);
                     nr++;
                 }
                 if (last) break;
@@ -538,6 +541,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             }
             if (bad || nr > cap_runs) overflow = true;
         }
+        // CIGAR: the 64 pairs' runs packed one after another at the start of
+        // the group's slot area (64 * slot_cap words from queue position
+        // qbase on), so the compaction reads dense data
+        uint64_t src = 0;
+        if (CIGAR) {
+            const int cnt = (active && !overflow) ? nr : 0;
+            int incl = cnt;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off);
+                incl += lane >= off ? t : 0;
+            }
+            src = (uint64_t)qbase * a.slot_cap + (uint64_t)(incl - cnt);
+            const gptr_t<uint32_t> stage = ln.H + K::HIST_DW * 64;
+            for (int r = 0; r < cnt; r++) a.slots[src + r] = stage[r * 64];
+        }
         if (active) {
             if (overflow) {
                 const uint32_t at = atomicAdd(a.ovf_count, 1u);
@@ -545,7 +564,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             } else {
                 a.scores[pair] = ln.S * a.pen.g;
                 a.nruns[pair] = CIGAR ? (uint32_t)nr : 0u;
-                if (CIGAR) a.run_src[pair] = (uint64_t)pair * a.slot_cap;
+                if (CIGAR) a.run_src[pair] = src;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -562,8 +581,9 @@ struct LaneShape {
                      : LaneKernel<X, OE, E, CAP, LMAX, false>::TABLE_BYTES +
                            waves * LaneKernel<X, OE, E, CAP, LMAX, false>::WAVE_BYTES;
     }
-    static int hist_dwords(bool cigar) {
-        return cigar ? LaneKernel<X, OE, E, CAP, LMAX, true>::HIST_DW * 64 : 0;
+    // history and run stage of one wavefront (slot_cap runs per lane)
+    static int hist_dwords(bool cigar, int slot_cap) {
+        return cigar ? (LaneKernel<X, OE, E, CAP, LMAX, true>::HIST_DW + slot_cap) * 64 : 0;
     }
     static hipError_t launch(const LaneArgs& a, bool cigar, bool persistent, int bt, int grid,
                              hipStream_t s) {
@@ -622,10 +642,10 @@ int lane_lds_bytes(const Pen& pen, int cap, bool cigar, int block_threads) {
     return -1;
 }
 
-size_t lane_hist_bytes_per_wave(const Pen& pen, int cap, bool cigar) {
+size_t lane_hist_bytes_per_wave(const Pen& pen, int cap, bool cigar, int slot_cap) {
 #define WFA_LANE_CASE(PX, POE, PE, PC, PLM) \
     if (pen.x == PX && pen.oe == POE && pen.e == PE && cap == PC) \
-        return (size_t)LaneShape<PX, POE, PE, PC, PLM>::hist_dwords(cigar) * 4;
+        return (size_t)LaneShape<PX, POE, PE, PC, PLM>::hist_dwords(cigar, slot_cap) * 4;
     WFA_LANE_SHAPES(WFA_LANE_CASE)
 #undef WFA_LANE_CASE
     return 0;

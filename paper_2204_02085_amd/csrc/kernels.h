@@ -89,9 +89,9 @@ struct LaneArgs {
     int slot_cap;               // most runs a pair may have (CIGAR)
     int32_t* scores;            // [pairs]
     uint32_t* nruns;            // [pairs] runs written
-    uint64_t* run_src;          // [pairs] where the reversed runs live (slot of the pair)
+    uint64_t* run_src;          // [pairs] where the reversed runs live (packed per group of 64)
     uint32_t* slots;            // [pairs * slot_cap] reversed runs
-    uint32_t* hist;             // CIGAR: one history region per launched wavefront
+    uint32_t* hist;             // CIGAR: one history and run-stage region per launched wavefront
     uint32_t* ovf_list;         // pairs the kernel could not hold
     uint32_t* ovf_count;
 };
@@ -176,9 +176,9 @@ bool lane_supported(const Pen& pen, int cap, uint32_t max_len);
 int lane_kmax(const Pen& pen, int cap);
 int lane_lds_bytes(const Pen& pen, int cap, bool cigar, int block_threads);
 int lane_max_blocks_per_cu(const Pen& pen, int cap, bool cigar, int block_threads);
-// CIGAR history bytes of one wavefront (global memory, one region per
-// wavefront of the launch)
-size_t lane_hist_bytes_per_wave(const Pen& pen, int cap, bool cigar);
+// CIGAR history and run stage bytes of one wavefront (global memory, one
+// region per wavefront of the launch)
+size_t lane_hist_bytes_per_wave(const Pen& pen, int cap, bool cigar, int slot_cap);
 hipError_t launch_lane(const LaneArgs& a, int cap, bool cigar, bool persistent, int block_threads,
                        int grid, hipStream_t s);
 
