@@ -369,8 +369,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     ln.P = wbase;
     ln.T = wbase + K::SQ * 64;
     ln.G = wbase + 2 * K::SQ * 64;
-    // this wavefront's history region (one per resident or launched wavefront)
-    ln.H = (gptr_t<uint32_t>)a.hist + ((uint64_t)(blockIdx.x * wpb + wave) * K::HIST_DW) * 64 + lane;
+    // this wavefront's history and run-stage region (HIST_DW + slot_cap rows
+    // of 64 dwords; one region per launched wavefront)
+    ln.H = (gptr_t<uint32_t>)a.hist +
+           ((uint64_t)(blockIdx.x * wpb + wave) * (CIGAR ? K::HIST_DW + a.slot_cap : 0)) * 64 + lane;
     // persistent: LANE_QUEUES counters (one per 128-byte line), wavefront w
     // drawing from counter w % LANE_QUEUES; the i-th claim from counter q is
     // the group of 64 queue entries number i * LANE_QUEUES + q, so every
