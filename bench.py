@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--encoding", choices=["packed2", "ascii"], default="packed2",
                     help="input encoding resident in HBM")
+    ap.add_argument("--mode", choices=["cigar", "score"], default="cigar",
+                    help="result mode of the timed workload")
     ap.add_argument("--second-set", default="pairs100_e2_5m",
                     help="the configuration's second set (E = 2 %%), timed the same way after "
                          "the main workload; 'none' or empty: skip")
@@ -68,7 +70,7 @@ def parse():
     ap.add_argument("--host-steps", type=int, default=2,
                     help="calls timed with host ASCII inputs and host outputs (PCIe "
                          "included; 0: skip)")
-    ap.add_argument("--tune-sample", type=int, default=262_144,
+    ap.add_argument("--tune-sample", type=int, default=1_048_576,
                     help="pairs the autotuner times candidates on: the pairs of the same seeded "
                          "stream right after the timed batch, so tuning never sees the timed "
                          "inputs")
@@ -158,19 +160,19 @@ def tune_on_disjoint_sample(al, wfa, synth, workload, n, count, enc, cigar=True)
     return chosen
 
 
-def time_schedule(al, dev, n, steps, warmup, options, enc):
+def time_schedule(al, dev, n, steps, warmup, options, enc, cigar=True):
     import torch
 
     al.set_options(**options)
     pat, txt, pairs, scores, runs, offsets = dev
     for _ in range(warmup):
-        al.align_device(pat, txt, pairs, n, scores, runs, offsets, (4, 6, 2), True, enc)
+        al.align_device(pat, txt, pairs, n, scores, runs, offsets, (4, 6, 2), cigar, enc)
     torch.cuda.synchronize()
     kernel_ms = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        al.align_device(pat, txt, pairs, n, scores, runs, offsets, (4, 6, 2), True, enc)
-        kernel_ms.append(al.stats()["ms_align"])
+        al.align_device(pat, txt, pairs, n, scores, runs, offsets, (4, 6, 2), cigar, enc)
+        kernel_ms.append(al.stats()["ms_align"] + al.stats()["ms_general"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = al.stats()
@@ -403,11 +405,13 @@ def main():
     if args.options:
         tuned = {k: int(v) for k, v in json.loads(args.options).items()}
     else:
-        tuned = tune_on_disjoint_sample(al, wfa, synth, args.workload, n, args.tune_sample, enc)
+        tuned = tune_on_disjoint_sample(al, wfa, synth, args.workload, n, args.tune_sample, enc,
+                                        args.mode == "cigar")
     t_tune = time.perf_counter() - t_tune
 
     log(f"autotuned in {t_tune:.1f} s: {tuned}; timing {args.steps} steps")
-    el, kms, st = time_schedule(al, dev, n, args.steps, args.warmup, tuned, enc)
+    cig = args.mode == "cigar"
+    el, kms, st = time_schedule(al, dev, n, args.steps, args.warmup, tuned, enc, cig)
     log(f"tuned: {n * args.steps / el / 1e6:.1f} M pairs/s")
     ms_step = el / args.steps * 1e3
     value = n * args.steps / el
@@ -419,14 +423,16 @@ def main():
     # the dominant kernel alone: the same launch with the work before and
     # after it replayed as two graphs, so that events the library records
     # around the kernel on its stream time it alone
-    kel, kms_k, kst = time_schedule(al, dev, n, args.steps, 1, {**tuned, "use_graph": 2}, enc)
+    kel, kms_k, kst = time_schedule(al, dev, n, args.steps, 1, {**tuned, "use_graph": 2}, enc, cig)
     kernel_ms = float(np.mean(kms_k))
     log(f"kernel alone: {kernel_ms:.3f} ms per launch (whole call {ms_step:.3f} ms)")
 
     # default knobs (the library's own per-batch choice, no tuning)
-    del_el, _, _ = time_schedule(al, dev, n, args.plain_steps or 5, 1, {}, enc)
-    default_value = n * (args.plain_steps or 5) / del_el
-    log(f"default knobs: {default_value / 1e6:.1f} M pairs/s")
+    default_value = None
+    if args.plain_steps > 0:
+        del_el, _, _ = time_schedule(al, dev, n, args.plain_steps, 1, {}, enc, cig)
+        default_value = n * args.plain_steps / del_el
+        log(f"default knobs: {default_value / 1e6:.1f} M pairs/s")
 
     # the same launch shape (window, lanes, step cap, workgroup size) as one
     # persistent bucketed launch replayed through graphs, and as the plain
@@ -436,13 +442,14 @@ def main():
         log("timing persistent and plain schedules")
         shape = {k: tuned.get(k, 0) for k in ("window", "lanes_per_pair", "step_cap",
                                               "block_threads")}
+        shape["lane_kernel"] = tuned.get("lane_kernel", 0)
         bel, bkms, bst = time_schedule(al, dev, n, args.plain_steps, 1,
                                        {**shape, "schedule": wfa.WFA_SCHED_PERSISTENT,
-                                        "bucket": 1, "use_graph": 1}, enc)
+                                        "bucket": 1, "use_graph": 1}, enc, cig)
         batched_value = n * args.plain_steps / bel
         pel, pkms, pst = time_schedule(al, dev, n, args.plain_steps, 1,
                                        {**shape, "schedule": wfa.WFA_SCHED_PLAIN,
-                                        "bucket": -1, "use_graph": -1}, enc)
+                                        "bucket": -1, "use_graph": -1}, enc, cig)
         plain_value = n * args.plain_steps / pel
         if not np.array_equal(scores.cpu().numpy(), got_scores):
             raise RuntimeError("plain and tuned schedules disagree")
@@ -472,7 +479,7 @@ def main():
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         sample = synth.workload(args.workload, min(args.cpu_pairs, n))
         t0 = time.perf_counter()
-        ref = oracle.align_batch(sample, (4, 6, 2), cigar=True, threads=threads)
+        ref = oracle.align_batch(sample, (4, 6, 2), cigar=args.mode == "cigar", threads=threads)
         t1 = time.perf_counter()
         cpu = {"value": len(sample) / (t1 - t0), "unit": "pairs/s", "cores": threads,
                "kind": "oracle",
@@ -484,15 +491,17 @@ def main():
         # parity of the benchmarked batch: scores, CIGAR offsets and runs of
         # the sample's pairs, byte for byte; any difference ends the run
         k = len(sample)
-        got_runs = runs[: int(got_offsets[k])].cpu().numpy().view(np.uint32)
-        if not (np.array_equal(got_scores[:k], ref.scores)
-                and np.array_equal(got_offsets[: k + 1], ref.offsets)
-                and np.array_equal(got_runs, ref.runs)):
+        cig_ok = True
+        if args.mode == "cigar":
+            got_runs = runs[: int(got_offsets[k])].cpu().numpy().view(np.uint32)
+            cig_ok = (np.array_equal(got_offsets[: k + 1], ref.offsets)
+                      and np.array_equal(got_runs, ref.runs))
+            del got_runs
+        if not (np.array_equal(got_scores[:k], ref.scores) and cig_ok):
             print(f"bench: the timed batch differs from the oracle on its first {k} pairs",
                   file=sys.stderr)
             sys.exit(3)
         log(f"parity: the first {k} pairs of the timed batch equal the oracle byte for byte")
-        del got_runs
 
     host_path = None
     if args.host_steps > 0:
@@ -625,7 +634,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "pairs": n, "read_length": 100,
                    "edits": 4 if "e4" in args.workload else 2, "penalties": [4, 6, 2],
-                   "mode": "cigar",
+                   "mode": args.mode,
                    "input": ("2-bit packed uint64 words in HBM" if enc == wfa.WFA_PACKED2
                              else "ASCII in HBM"),
                    "schedule": "autotuned (see autotuned_options)"},

@@ -238,28 +238,42 @@ enum { WFA_OP_MATCH = 0, WFA_OP_MISMATCH = 1, WFA_OP_INS = 2, WFA_OP_DEL = 3 };
 
 #define WFA_MAX_LENGTH ((uint32_t)1 << 26) /* bases per sequence */
 
-/* Create a context on HIP device `device` whose device workspace may grow to
+/* Source: the host side of the paper's system (Introduction and Methods:
+ * the host sets up the processing units that align the pairs); here one
+ * context per GPU.
+ * Create a context on HIP device `device` whose device workspace may grow to
  * `hbm_budget_bytes` (0: three quarters of the device's memory; the
  * workspace only grows as far as the batches need).  *out receives the
  * context. */
 int wfa_ctx_create(int device, size_t hbm_budget_bytes, wfa_ctx **out);
 
-/* Free the context and all device memory it owns, including the engines
+/* Source: as wfa_ctx_create.
+ * Free the context and all device memory it owns, including the engines
  * that closed servers left with it.  Every server opened on it must be
  * closed first.  NULL is ignored. */
 void wfa_ctx_destroy(wfa_ctx *ctx);
 
-/* Set tuning knobs for later calls (NULL restores the defaults). */
+/* Source: none in the paper (launch shape only; no result depends on it).
+ * Set tuning knobs for later calls (NULL restores the defaults); a value
+ * outside the documented ranges is WFA_E_INVAL and changes nothing. */
 int wfa_set_options(wfa_ctx *ctx, const wfa_options *opt);
 
-/* Select ends-free alignment (wfa_ends_free) for later wfa_align_batch and
+/* Source: a mode variant beyond the paper's global alignment (its Results
+ * close with other alignment algorithms as future work); the score is the least
+ * global score over the allowed clipped sub-pairs.
+ * Select ends-free alignment (wfa_ends_free) for later wfa_align_batch and
  * wfa_autotune calls on the context, and for servers opened on it later
  * (a server keeps the setting it opened with); NULL or all zero selects
  * global alignment (the default).  Bounds above WFA_MAX_LENGTH are
  * WFA_E_INVAL. */
 int wfa_set_ends_free(wfa_ctx *ctx, const wfa_ends_free *ends);
 
-/* Align num_pairs pairs.
+/* Source: Introduction and Methods -- every read pair is aligned on its own
+ * with the wavefront algorithm (gap-affine WFA, Marco-Sola et al. 2021:
+ * the I/D/M recurrences over diagonals, extension along matches, the end
+ * at M_s[m - n] = m, and the backtrace) and one result per pair is written
+ * back; Results -- 5 M pairs of 100 bp per batch.
+ * Align num_pairs pairs.
  *   patterns, texts   sequence buffers in `enc` and `mem`
  *   pairs             [num_pairs] descriptors, in `mem`
  *   pen, mode         penalties and result mode
@@ -281,22 +295,29 @@ int wfa_align_batch(wfa_ctx *ctx, const void *patterns, const void *texts,
                     uint32_t *cigar_runs, size_t cigar_capacity, uint64_t *cigar_offsets,
                     size_t *cigar_needed, int64_t *bad_pair, void *stream);
 
-/* After WFA_E_CAPACITY: copy the runs of the last call into `runs` (in the
+/* Source: as wfa_align_batch (the results written back).
+ * After WFA_E_CAPACITY: copy the runs of the last call into `runs` (in the
  * last call's memory space) if `capacity` suffices; offsets are those the
  * last call wrote and may be passed again (NULL: not rewritten). */
 int wfa_copy_last_cigars(wfa_ctx *ctx, uint32_t *runs, size_t capacity, uint64_t *offsets);
 
-/* Page-locked host memory for WFA_HOST batches (inputs and outputs), so
+/* Source: Results -- the paper's `Total` time includes moving pairs and
+ * results between the host and the processing units, which dominated it.
+ * Page-locked host memory for WFA_HOST batches (inputs and outputs), so
  * that the host-memory pipeline's copies run at the full link rate.
  * hipHostMalloc underneath: *out receives `bytes` bytes (0 is allowed and
  * gives a valid pointer) or NULL with WFA_E_NOMEM.  The caller owns the
  * block until wfa_host_free; it is not tied to a context.  */
 int wfa_host_alloc(size_t bytes, void **out);
 
-/* Free a block from wfa_host_alloc.  NULL is ignored. */
+/* Source: as wfa_host_alloc.  Free a block from wfa_host_alloc.  NULL is
+ * ignored. */
 void wfa_host_free(void *ptr);
 
-/* Encode ASCII sequences to the PACKED2 layout on the device.
+/* Source: Introduction and Methods -- the sequences of a pair are fetched
+ * into fast local memory before alignment; here they are read as 2-bit
+ * packed words.
+ * Encode ASCII sequences to the PACKED2 layout on the device.
  *   ascii        device bytes
  *   starts/lens  [count] device arrays: byte offset and length per sequence
  *   words        device output; sequence i starts at word word_starts[i]
@@ -310,20 +331,25 @@ int wfa_pack2bit(wfa_ctx *ctx, const uint8_t *ascii, const uint64_t *starts,
                  const uint32_t *lens, size_t count, uint64_t *words, size_t words_capacity,
                  uint64_t *word_starts, size_t *total_words, int64_t *bad_index, void *stream);
 
-/* Autotuner.  Times candidate options on the first `sample_pairs` pairs
- * (0: 262144) of the given batch, in two stages: first every short-kernel
- * shape (window, lanes per pair) whose window can hold the sample's length
- * differences, plain schedule, plus the general kernel; then, for the two
- * fastest shapes, every workgroup size (64, 128, 256), schedule form (plain;
- * persistent with and without bucketing) and step cap (the default, and the
- * largest score step of the sample, found by a score-only pass).  A
- * candidate's time is the fastest of several calls.  Every candidate must
- * return byte-identical results; the fastest is applied to the context and
- * cached in the JSON file `cache_path` (NULL: no cache) under a key of device
- * architecture, penalties, mode and the batch's length / length-difference /
- * size classes; a later call with the same key reuses it unless `force` is
- * set.  Arguments as wfa_align_batch; *chosen receives the options.
- * WFA_E_DEVICE if two candidates disagree. */
+/* Source: none in the paper (the launch shape is picked by measurement; no
+ * result depends on it).
+ * Autotuner.  Times candidate options on the
+ * first `sample_pairs` pairs (0: 262144) of the given batch, in two stages:
+ * first every first-pass shape -- the one-pair-per-lane kernel where it is
+ * built for the penalties and lengths (step cap 8 if the sample's largest
+ * score step allows, else 16), and every short-kernel shape (window, lanes
+ * per pair) whose window can hold the sample's length differences -- on the
+ * plain schedule, plus the general kernel; then, for the two fastest shapes,
+ * every workgroup size (64, 128, 256), schedule form (plain; persistent with
+ * and without bucketing) and step cap (the default, and the largest score
+ * step of the sample, found by a score-only pass); the library's own default
+ * choice is always a candidate.  A candidate's time is the fastest of several
+ * calls.  Every candidate must return byte-identical results; the fastest is
+ * applied to the context and cached in the JSON file `cache_path` (NULL: no
+ * cache) under a key of device architecture, penalties, mode and the batch's
+ * length / length-difference / size classes; a later call with the same key
+ * reuses it unless `force` is set.  Arguments as wfa_align_batch; *chosen
+ * receives the options.  WFA_E_DEVICE if two candidates disagree. */
 int wfa_autotune(wfa_ctx *ctx, const void *patterns, const void *texts, const wfa_pair *pairs,
                  size_t num_pairs, wfa_encoding enc, wfa_memspace mem, wfa_penalties pen,
                  wfa_mode mode, size_t sample_pairs, const char *cache_path, int force,
@@ -360,10 +386,12 @@ int wfa_align_batch_noalloc(wfa_ctx *ctx, const void *patterns, const void *text
                             uint64_t *cigar_offsets, size_t *cigar_needed, int64_t *bad_pair,
                             void *stream);
 
-/* Counters of the last wfa_align_batch call. */
+/* Source: Results -- the paper reports `Kernel` and `Total` time apart;
+ * these are the device time of each phase and the call's wall time.
+ * Counters of the last wfa_align_batch call. */
 int wfa_last_stats(const wfa_ctx *ctx, wfa_stats *out);
 
-/* Text of a status code (static storage). */
+/* Source: none in the paper.  Text of a status code (static storage). */
 const char *wfa_strerror(int status);
 
 /* ---------------------------------------------------------------------------
@@ -379,6 +407,9 @@ const char *wfa_strerror(int status);
  * join as soon as a worker and memory free up.  A request completes when its
  * last pair does.  Results equal those of wfa_align_batch on the same pairs
  * alone: every pair is aligned independently and deterministically.
+ * Source: the paper aligns one offline batch; serving many requests with
+ * continuous batching rests on the same per-pair independence (Introduction
+ * and Methods).
  * ------------------------------------------------------------------------- */
 typedef struct wfa_server wfa_server;
 

@@ -291,6 +291,11 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
         const int r = evaluate(g, 1);
         if (r != WFA_OK && r != WFA_E_NOMEM) status = r;
     }
+    if (status == WFA_OK) {  // the library's own per-batch choice is always a candidate
+        Candidate dflt{};
+        const int r = evaluate(dflt, 5);
+        if (r != WFA_OK && r != WFA_E_NOMEM) status = r;
+    }
     // Stage 2: the two fastest shapes, every workgroup size, schedule form
     // (plain; persistent with and without bucketing) and step cap.
     std::sort(shapes.begin(), shapes.end(), [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
