@@ -394,7 +394,8 @@ def main():
         enc = wfa.WFA_ASCII
         pat, txt, pairs = al.to_device(batch)
     torch.cuda.synchronize()
-    cap = n * 40 + 1024
+    # room for every run: ~40 per 100 bp pair, a quarter of the bases for long pairs
+    cap = int(max(n * 40, int(((batch.p_len.astype(np.int64) + batch.t_len) // 4 + 8).sum()))) + 1024
     scores, runs, offsets = al.alloc_outputs(n, cap, True)
     dev = (pat, txt, pairs, scores, runs, offsets)
 

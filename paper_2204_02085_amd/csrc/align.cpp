@@ -156,10 +156,10 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     // batches less divergent than the guess run more pairs at a time; pairs
     // whose slice is still too small are re-run with 4x
     double scale_seen = 0.0, hist_scale = 1.0;
-    auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult) -> uint64_t {
+    auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult, uint64_t rb) -> uint64_t {
         const uint64_t nm1 = (uint64_t)n + m + 1;
         uint64_t sl;
-        sl = (R + 1) * 3 * 4 * (nm1 + 2);  // the ring of full-width rows and a NULL slot
+        sl = (R + 1) * 3 * rb * (nm1 + 2);  // the ring of full-width rows and a NULL slot
         if (cigar && e->opt.general_slice_kib > 0)  // the caller's first guess
             sl += (uint64_t)e->opt.general_slice_kib * 1024 * mult;
         else if (cigar)
@@ -178,6 +178,10 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     const size_t n_pending = jobs.size();
     HIPCHK(launch_fill_u64((uint64_t*)&flags->gave_up, ~0ull, 1, s));
     while (!jobs.empty()) {
+        // 16-bit ring rows for a launch whose texts are all shorter than
+        // 32767 bases: the largest text length from each position on
+        std::vector<uint32_t> suffix_m(jobs.size() + 1, 0);
+        for (size_t i = jobs.size(); i-- > 0;) suffix_m[i] = std::max(suffix_m[i + 1], jobs[i].m);
         if (++attempts > 40) {
             std::fprintf(stderr, "libwfa: %zu pairs still failing after 40 attempts\n", jobs.size());
             return WFA_E_NOMEM;
@@ -185,7 +189,8 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         std::vector<Job> failed;
         for (size_t off = 0; off < jobs.size();) {
             const Job& head = jobs[off];  // the longest pair left
-            const uint64_t slice = slice_for(head.n, head.m, mult);
+            const bool rows16 = suffix_m[off] < 32767;
+            const uint64_t slice = slice_for(head.n, head.m, mult, rows16 ? 2 : 4);
             const size_t others = ws.total - ws.arena.bytes;
             const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
             const size_t want = std::min(jobs.size() - off, (size_t)1 << 20) * slice;
@@ -255,7 +260,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.fail_count = &flags->fail_count;
             g.gave_up = &flags->gave_up;
             g.step_limit = e->opt.general_step_limit;
-            HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, s));
+            HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, rows16, s));
             uint32_t nfail = 0;
             unsigned long long gave_up = ~0ull;
             HIPCHK(hipMemcpyAsync(&nfail, &flags->fail_count, 4, hipMemcpyDeviceToHost, s));

@@ -182,8 +182,9 @@ size_t lane_hist_bytes_per_wave(const Pen& pen, int cap, bool cigar, int slot_ca
 hipError_t launch_lane(const LaneArgs& a, int cap, bool cigar, bool persistent, int block_threads,
                        int grid, hipStream_t s);
 
+// rows16: 16-bit ring rows (every text of the launch shorter than 32767 bases)
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds,
-                          int lds_bytes, hipStream_t s);
+                          int lds_bytes, bool rows16, hipStream_t s);
 
 // Copy reversed runs from their staging places into the caller's buffer.
 // Nothing is written if offsets[n] exceeds `capacity`.

@@ -930,8 +930,12 @@ __device__ __forceinline__ int extend_general(const SeqView<SEQ_LDS>& sv, int n,
     return h;
 }
 
-template <bool SEQ_LDS>
+// RowT: int16_t ring rows while every offset fits (texts shorter than 32767
+// bases), halving the ring's memory traffic, else int32_t.  Stored NULLs are
+// normalised to RNUL, so no NULL drifts up over many steps.
+template <bool SEQ_LDS, class RowT>
 __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
+    constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int MAXR = GENERAL_MAX_RING;  // metadata ring (pre + 1 <= MAXR)
     __shared__ RowMeta meta[MAXR];
@@ -989,7 +993,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     // entry outside a source step's range reads NULL and the cells read
     // their sources without range checks.
     const int FW = n + m + 3;
-    const long long full_row = 3LL * 4 * FW;
+    const long long full_row = 3LL * (long long)sizeof(RowT) * FW;
     // CIGAR history offsets: 16-bit (0xFFFF for NULL) while every offset
     // fits, else 32-bit
     const bool h16 = m < 0xFFFF;
@@ -1003,12 +1007,12 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         return;
     }
     {
-        int* ring = (int*)slice;
+        RowT* ring = (RowT*)slice;
         const long long cnt = (R + 1) * 3LL * FW;
-        for (long long i = tid; i < cnt; i += BT) ring[i] = NUL32;
+        for (long long i = tid; i < cnt; i += BT) ring[i] = (RowT)RNUL;
     }
     __syncthreads();
-    const int* nullrow = (const int*)(slice + R * full_row) + n + 1;
+    const RowT* nullrow = (const RowT*)(slice + R * full_row) + n + 1;
     // a hard bound on steps: deleting all of P and inserting all of T (or a
     // lower limit the host asks for)
     long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
@@ -1056,24 +1060,24 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     break;
                 }
             }
-            int* rowM = (int*)(slice + off) + n + 1;
-            int* rowI = rowM + FW;
-            int* rowD = rowI + FW;
+            RowT* rowM = (RowT*)(slice + off) + n + 1;
+            RowT* rowI = rowM + FW;
+            RowT* rowD = rowI + FW;
             {  // the slot's previous values outside [lo, hi] become NULL
                 const int plo = wr_lo[rs], phi = wr_hi[rs];
                 for (int k = plo + tid; k <= phi && k < lo; k += BT)
-                    rowM[k] = rowI[k] = rowD[k] = NUL32;
+                    rowM[k] = rowI[k] = rowD[k] = (RowT)RNUL;
                 for (int k = max(hi + 1, plo) + tid; k <= phi; k += BT)
-                    rowM[k] = rowI[k] = rowD[k] = NUL32;
+                    rowM[k] = rowI[k] = rowD[k] = (RowT)RNUL;
             }
             unsigned char* histM = a.cigar ? slice + hoff : nullptr;
             uint8_t* histF = a.cigar ? histM + (long long)hbytes * w : nullptr;
             // source components (M of s - x and s - o - e, I and D of s - e),
             // indexed by diagonal; an absent step reads the NULL slot
-            const int* MX = sx.off >= 0 ? (const int*)(slice + sx.off) + n + 1 : nullrow;
-            const int* MO = so.off >= 0 ? (const int*)(slice + so.off) + n + 1 : nullrow;
-            const int* IE = (se.off >= 0 ? (const int*)(slice + se.off) + n + 1 : nullrow) + FW;
-            const int* DE = IE + FW;
+            const RowT* MX = sx.off >= 0 ? (const RowT*)(slice + sx.off) + n + 1 : nullrow;
+            const RowT* MO = so.off >= 0 ? (const RowT*)(slice + so.off) + n + 1 : nullrow;
+            const RowT* IE = (se.off >= 0 ? (const RowT*)(slice + se.off) + n + 1 : nullrow) + FW;
+            const RowT* DE = IE + FW;
             // one cell from its five source offsets
             auto cell = [&](int k, int va, int vb, int vc, int ve, int vx) {
                 int mval;
@@ -1105,9 +1109,9 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     rec = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
                 }
                 if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
-                rowM[k] = mval;
-                rowI[k] = ival;
-                rowD[k] = dval;
+                rowM[k] = (RowT)(mval < 0 ? RNUL : mval);
+                rowI[k] = (RowT)(ival < 0 ? RNUL : ival);
+                rowD[k] = (RowT)(dval < 0 ? RNUL : dval);
                 if (a.cigar) {
                     if (h16)
                         ((uint16_t*)histM)[k - lo] = mval < 0 ? (uint16_t)0xFFFF : (uint16_t)mval;
@@ -1624,12 +1628,18 @@ int short_max_blocks_per_cu(int window, int lanes, bool cigar, int bt, int lds_p
 }
 
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds, int lds_bytes,
-                          hipStream_t s) {
+                          bool rows16, hipStream_t s) {
     if (!a.num_jobs) return hipSuccess;
-    if (seq_in_lds)
-        hipLaunchKernelGGL(k_general<true>, dim3(a.num_jobs), dim3(block_threads), lds_bytes, s, a);
+    if (seq_in_lds && rows16)
+        hipLaunchKernelGGL((k_general<true, int16_t>), dim3(a.num_jobs), dim3(block_threads),
+                           lds_bytes, s, a);
+    else if (seq_in_lds)
+        hipLaunchKernelGGL((k_general<true, int32_t>), dim3(a.num_jobs), dim3(block_threads),
+                           lds_bytes, s, a);
+    else if (rows16)
+        hipLaunchKernelGGL((k_general<false, int16_t>), dim3(a.num_jobs), dim3(block_threads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_general<false>, dim3(a.num_jobs), dim3(block_threads), 0, s, a);
+        hipLaunchKernelGGL((k_general<false, int32_t>), dim3(a.num_jobs), dim3(block_threads), 0, s, a);
     return hipGetLastError();
 }
 
