@@ -159,7 +159,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult, uint64_t rb) -> uint64_t {
         const uint64_t nm1 = (uint64_t)n + m + 1;
         uint64_t sl;
-        sl = (R + 1) * 3 * rb * (nm1 + 2);  // the ring of full-width rows and a NULL slot
+        sl = (R + 1) * ((3 * rb * (nm1 + 2) + 15) & ~(uint64_t)15);  // ring slots, a NULL slot
         if (cigar && e->opt.general_slice_kib > 0)  // the caller's first guess
             sl += (uint64_t)e->opt.general_slice_kib * 1024 * mult;
         else if (cigar)

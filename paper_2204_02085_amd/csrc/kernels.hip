@@ -993,7 +993,9 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     // entry outside a source step's range reads NULL and the cells read
     // their sources without range checks.
     const int FW = n + m + 3;
-    const long long full_row = 3LL * (long long)sizeof(RowT) * FW;
+    // one ring slot: the M, I and D rows, padded to 16 bytes so that the
+    // history and the runs after the ring stay aligned
+    const long long full_row = (3LL * (long long)sizeof(RowT) * FW + 15) & ~15LL;
     // CIGAR history offsets: 16-bit (0xFFFF for NULL) while every offset
     // fits, else 32-bit
     const bool h16 = m < 0xFFFF;
