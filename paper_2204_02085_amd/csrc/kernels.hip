@@ -1009,8 +1009,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         return;
     }
     {
-        RowT* ring = (RowT*)slice;
-        const long long cnt = (R + 1) * 3LL * FW;
+        RowT* ring = (RowT*)slice;  // every slot, padding included
+        const long long cnt = (R + 1) * full_row / (long long)sizeof(RowT);
         for (long long i = tid; i < cnt; i += BT) ring[i] = (RowT)RNUL;
     }
     __syncthreads();
