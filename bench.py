@@ -112,17 +112,20 @@ def kernel_label(st: dict) -> str:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the source of the one-pair-per-lane kernel (the headline's
+    dominant kernel)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2204_02085_amd", "csrc", "kernels.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2204_02085_amd", "csrc", "k_lane.hip"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_profile(kernel_hash: str) -> dict:
-    """Figures of the committed PMC summary of the short-pair kernel (HBM
-    bytes per launch, VALU issue rate), if it was taken on the current kernel
-    source; empty otherwise."""
-    path = os.path.join(ROOT, "profiles", "k_short_pairs100_e4_5m_pmc.txt")
+def read_profile(kernel_hash: str, label: str) -> dict:
+    """Figures of the committed rocprofv3 summary of the headline kernel (HBM
+    bytes per launch, VALU issue rate, VALU instructions per pair), if it was
+    taken on the current kernel source and the same kernel launch; empty
+    otherwise."""
+    path = os.path.join(ROOT, "profiles", "k_lane_pairs100_e4_5m.txt")
     if not os.path.exists(path):
         return {}
     vals = {}
@@ -131,7 +134,7 @@ def read_profile(kernel_hash: str) -> dict:
             if " = " in line and not line.startswith("#"):
                 k, v = line.split(" = ", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_hash:
+    if vals.get("kernel_source_sha256_16") != kernel_hash or vals.get("kernel_label") != label:
         return {}
     out = {}
     for k in ("hbm_bytes_per_launch", "valu_issue_per_cu_cycle", "traffic_over_algorithmic",
@@ -606,7 +609,7 @@ def main():
         ops = n * (cells_pp * OPS_PER_CELL + windows_pp * OPS_PER_WINDOW)
         ops_itemised = n * (cells_pp * OPS_PER_CELL_ITEMISED + windows_pp * OPS_PER_WINDOW_ITEMISED)
         achieved = ops / (kernel_ms * 1e-3)
-        prof = read_profile(kernel_source_hash())
+        prof = read_profile(kernel_source_hash(), kernel_label(kst))
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / PEAK_INT_OPS,
                     "traffic": prof.get("hbm_bytes_per_launch"),
