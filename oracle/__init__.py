@@ -72,6 +72,11 @@ def _load():
         lib.oracle_align_batch_ends.argtypes = [p, p, p, p, p, p, i64, i, i, i, i, i, i, i, i, p,
                                                 p, i64, p, p, i, p]
         lib.oracle_align_batch_ends.restype = i
+        lib.oracle_align_adaptive.argtypes = [p, i, p, i, i, i, i, i, i, i, p, p, i64, p, p]
+        lib.oracle_align_adaptive.restype = i
+        lib.oracle_align_batch_adaptive.argtypes = [p, p, p, p, p, p, i64, i, i, i, i, i, i, p,
+                                                    p, i64, p, p, i, p]
+        lib.oracle_align_batch_adaptive.restype = i
         lib.oracle_pack2bit.argtypes = [p, i64, p, i64]
         lib.oracle_pack2bit.restype = i64
         _lib = lib
@@ -83,12 +88,14 @@ def _buf(b: bytes):
 
 
 def align(pattern: bytes, text: bytes, penalties=(4, 6, 2), cigar: bool = True,
-          with_stats: bool = False, ends=None):
+          with_stats: bool = False, ends=None, adaptive=None):
     """Align one pair.  Returns (score, runs) or (score, runs, stats).
 
     runs is a list of ``len << 4 | op`` words (empty in score-only mode).
     ends = (pattern_begin_free, pattern_end_free, text_begin_free,
     text_end_free) selects ends-free alignment (None: global).
+    adaptive = (min_wavefront_length, max_distance_threshold) selects the
+    WF-adaptive heuristic (global alignment only; None: exact).
     """
     lib = _load()
     x, o, e = penalties
@@ -99,9 +106,17 @@ def align(pattern: bytes, text: bytes, penalties=(4, 6, 2), cigar: bool = True,
     score = ctypes.c_int32(0)
     nr = ctypes.c_int64(0)
     st = Stats()
-    rc = lib.oracle_align_ends(_buf(pattern), n, _buf(text), m, x, o, e, pb, pe, tb, te,
-                               int(cigar), ctypes.byref(score), runs, cap, ctypes.byref(nr),
-                               ctypes.byref(st))
+    if adaptive is not None:
+        if ends is not None:
+            raise ValueError("the adaptive heuristic applies to global alignment only")
+        mwl, mdt = adaptive
+        rc = lib.oracle_align_adaptive(_buf(pattern), n, _buf(text), m, x, o, e, mwl, mdt,
+                                       int(cigar), ctypes.byref(score), runs, cap,
+                                       ctypes.byref(nr), ctypes.byref(st))
+    else:
+        rc = lib.oracle_align_ends(_buf(pattern), n, _buf(text), m, x, o, e, pb, pe, tb, te,
+                                   int(cigar), ctypes.byref(score), runs, cap, ctypes.byref(nr),
+                                   ctypes.byref(st))
     if rc != 0:
         raise ValueError(f"oracle_align failed with status {rc}")
     out = [int(runs[j]) for j in range(nr.value)]
@@ -119,9 +134,9 @@ class BatchResult:
 
 
 def align_batch(batch, penalties=(4, 6, 2), cigar: bool = True, threads: int = 1,
-                slot: int | None = None, ends=None) -> BatchResult:
+                slot: int | None = None, ends=None, adaptive=None) -> BatchResult:
     """Align every pair of a ``synth.Batch`` on `threads` host threads
-    (`ends` as in ``align``)."""
+    (`ends` and `adaptive` as in ``align``)."""
     lib = _load()
     x, o, e = penalties
     pb, pe, tb, te = (0, 0, 0, 0) if ends is None else ends
@@ -134,12 +149,22 @@ def align_batch(batch, penalties=(4, 6, 2), cigar: bool = True, threads: int = 1
     status = np.zeros(N, dtype=np.int32)
     runs = np.zeros(N * slot if cigar else 1, dtype=np.uint32)
     st = Stats()
-    rc = lib.oracle_align_batch_ends(batch.patterns.ctypes.data, batch.p_off.ctypes.data,
-                                batch.p_len.ctypes.data, batch.texts.ctypes.data,
-                                batch.t_off.ctypes.data, batch.t_len.ctypes.data, N, x, o, e,
-                                pb, pe, tb, te, int(cigar), scores.ctypes.data,
-                                runs.ctypes.data if cigar else None, slot, nruns.ctypes.data,
-                                status.ctypes.data, threads, ctypes.byref(st))
+    if adaptive is not None:
+        if ends is not None:
+            raise ValueError("the adaptive heuristic applies to global alignment only")
+        mwl, mdt = adaptive
+        rc = lib.oracle_align_batch_adaptive(
+            batch.patterns.ctypes.data, batch.p_off.ctypes.data, batch.p_len.ctypes.data,
+            batch.texts.ctypes.data, batch.t_off.ctypes.data, batch.t_len.ctypes.data, N, x, o,
+            e, mwl, mdt, int(cigar), scores.ctypes.data, runs.ctypes.data if cigar else None,
+            slot, nruns.ctypes.data, status.ctypes.data, threads, ctypes.byref(st))
+    else:
+        rc = lib.oracle_align_batch_ends(
+            batch.patterns.ctypes.data, batch.p_off.ctypes.data, batch.p_len.ctypes.data,
+            batch.texts.ctypes.data, batch.t_off.ctypes.data, batch.t_len.ctypes.data, N, x, o,
+            e, pb, pe, tb, te, int(cigar), scores.ctypes.data,
+            runs.ctypes.data if cigar else None, slot, nruns.ctypes.data, status.ctypes.data,
+            threads, ctypes.byref(st))
     if rc != 0:
         raise RuntimeError(f"oracle_align_batch failed with status {rc}")
     bad = np.nonzero(status)[0]

@@ -198,6 +198,53 @@ static int end_diagonal(const wavefront *w, int n, int m, int pe, int te) {
 
 static int clip(int v, int hi) { return v < hi ? v : hi; }
 
+/* Distance from the furthest point of diagonal k (offset h) to the end cell:
+ * the larger of the pattern and the text bases still to cover. */
+static int distance_to_end(int k, int h, int n, int m) {
+    int v = h - k;
+    return n - v > m - h ? n - v : m - h;
+}
+
+/* WF-adaptive reduction, the heuristic mode of the WFA paper that the
+ * method builds on (cited in section 1, Introduction and Methods): once
+ * a wavefront holds at least mwl diagonals, the distance of each diagonal's
+ * furthest point (v, h) to the end cell (n, m) is the larger of the pattern
+ * and the text bases it still has to cover, max(n - v, m - h); the diagonals
+ * at either end of the wavefront whose distance exceeds the smallest
+ * distance by more than mdt (or that hold no offset) are dropped, and the
+ * wavefront keeps the range between the outermost diagonals it keeps.
+ * Returns -1 when out of memory.  Readings: the width counts every diagonal
+ * of the wavefront's span, those without an offset included; a wavefront
+ * without any offset is left as it is; the reduction applies after the
+ * extension and the end test of the step, and not to a step that ends the
+ * alignment. */
+static int adaptive_reduce(wavefront *w, int n, int m, int mwl, int mdt) {
+    if (w->hi - w->lo + 1 < mwl) return 0;
+    int dmin = INT_MAX;
+    for (int k = w->lo; k <= w->hi; k++) {
+        int h = w->M[k - w->lo];
+        if (h != OFF_NULL && distance_to_end(k, h, n, m) < dmin) dmin = distance_to_end(k, h, n, m);
+    }
+    if (dmin == INT_MAX) return 0;
+    /* the kept range: from the outermost diagonals within dmin + mdt */
+    int lo2 = w->lo, hi2 = w->hi;
+    while (w->M[lo2 - w->lo] == OFF_NULL || distance_to_end(lo2, w->M[lo2 - w->lo], n, m) > dmin + mdt)
+        lo2++;
+    while (w->M[hi2 - w->lo] == OFF_NULL || distance_to_end(hi2, w->M[hi2 - w->lo], n, m) > dmin + mdt)
+        hi2--;
+    if (lo2 == w->lo && hi2 == w->hi) return 0;
+    wavefront nw = {0, 0, 0, NULL, NULL, NULL};
+    if (wf_alloc(&nw, lo2, hi2)) { wf_free(&nw); return -1; }
+    for (int k = lo2; k <= hi2; k++) {
+        nw.M[k - lo2] = w->M[k - w->lo];
+        nw.I[k - lo2] = w->I[k - w->lo];
+        nw.D[k - lo2] = w->D[k - w->lo];
+    }
+    wf_free(w);
+    *w = nw;
+    return 0;
+}
+
 int oracle_align(const uint8_t *P, int n, const uint8_t *T, int m,
                  int x, int o, int e, int want_cigar,
                  int32_t *score_out, uint32_t *runs, int64_t runs_cap, int64_t *nruns_out,
@@ -206,10 +253,34 @@ int oracle_align(const uint8_t *P, int n, const uint8_t *T, int m,
                              runs_cap, nruns_out, st);
 }
 
+/* The steps shared by every entry point: ends-free bounds (all zero for
+ * global alignment) and the WF-adaptive parameters (mwl = 0: exact). */
+static int align_core(const uint8_t *P, int n, const uint8_t *T, int m,
+                      int x, int o, int e, int pb, int pe, int tb, int te, int mwl, int mdt,
+                      int want_cigar, int32_t *score_out, uint32_t *runs, int64_t runs_cap,
+                      int64_t *nruns_out, oracle_stats *st);
+
 int oracle_align_ends(const uint8_t *P, int n, const uint8_t *T, int m,
                       int x, int o, int e, int pb, int pe, int tb, int te, int want_cigar,
                       int32_t *score_out, uint32_t *runs, int64_t runs_cap, int64_t *nruns_out,
                       oracle_stats *st) {
+    return align_core(P, n, T, m, x, o, e, pb, pe, tb, te, 0, 0, want_cigar, score_out, runs,
+                      runs_cap, nruns_out, st);
+}
+
+int oracle_align_adaptive(const uint8_t *P, int n, const uint8_t *T, int m, int x, int o, int e,
+                          int min_wavefront_length, int max_distance_threshold, int want_cigar,
+                          int32_t *score_out, uint32_t *runs, int64_t runs_cap, int64_t *nruns_out,
+                          oracle_stats *st) {
+    if (min_wavefront_length < 0 || max_distance_threshold < 0) return ORACLE_E_INVAL;
+    return align_core(P, n, T, m, x, o, e, 0, 0, 0, 0, min_wavefront_length,
+                      max_distance_threshold, want_cigar, score_out, runs, runs_cap, nruns_out, st);
+}
+
+static int align_core(const uint8_t *P, int n, const uint8_t *T, int m,
+                      int x, int o, int e, int pb, int pe, int tb, int te, int mwl, int mdt,
+                      int want_cigar, int32_t *score_out, uint32_t *runs, int64_t runs_cap,
+                      int64_t *nruns_out, oracle_stats *st) {
     if (x <= 0 || e <= 0 || o < 0 || n < 0 || m < 0) return ORACLE_E_INVAL;
     if (pb < 0 || pe < 0 || tb < 0 || te < 0) return ORACLE_E_INVAL;
     pb = clip(pb, n);
@@ -228,6 +299,7 @@ int oracle_align_ends(const uint8_t *P, int n, const uint8_t *T, int m,
     if (st) { st->cells += pb + tb + 1; st->steps += 1; }
     end_k = end_diagonal(&t.wf[0], n, m, pe, te);
     if (end_k != INT_MIN) S = 0;
+    if (S < 0 && mwl > 0 && adaptive_reduce(&t.wf[0], n, m, mwl, mdt)) { status = ORACLE_E_NOMEM; goto done; }
 
     for (int s = 1; S < 0; s++) {
         if (grow(&t, s)) { status = ORACLE_E_NOMEM; goto done; }
@@ -273,6 +345,7 @@ int oracle_align_ends(const uint8_t *P, int n, const uint8_t *T, int m,
         }
         end_k = end_diagonal(w, n, m, pe, te);
         if (end_k != INT_MIN) S = s;
+        if (S < 0 && mwl > 0 && adaptive_reduce(w, n, m, mwl, mdt)) { status = ORACLE_E_NOMEM; goto done; }
         if (!want_cigar && s - keep - 1 >= 0 && s - keep - 1 < t.cap) wf_free(&t.wf[s - keep - 1]);
     }
     *score_out = S;
@@ -374,6 +447,7 @@ typedef struct {
     const uint32_t *plen, *tlen;
     int x, o, e, want_cigar;
     int pb, pe, tb, te;
+    int mwl, mdt;
     int32_t *scores;
     uint32_t *runs;    /* slot-strided: pair i writes runs[i * slot ...] */
     int64_t slot;
@@ -387,10 +461,10 @@ static void *run_job(void *arg) {
     job_t *j = (job_t *)arg;
     for (int64_t i = j->begin; i < j->end; i++) {
         int64_t nr = 0;
-        int rc = oracle_align_ends(j->pbuf + j->poff[i], (int)j->plen[i], j->tbuf + j->toff[i],
-                                   (int)j->tlen[i], j->x, j->o, j->e, j->pb, j->pe, j->tb, j->te,
-                                   j->want_cigar, &j->scores[i],
-                                   j->runs ? j->runs + i * j->slot : NULL, j->slot, &nr, &j->st);
+        int rc = align_core(j->pbuf + j->poff[i], (int)j->plen[i], j->tbuf + j->toff[i],
+                            (int)j->tlen[i], j->x, j->o, j->e, j->pb, j->pe, j->tb, j->te, j->mwl,
+                            j->mdt, j->want_cigar, &j->scores[i],
+                            j->runs ? j->runs + i * j->slot : NULL, j->slot, &nr, &j->st);
         if (j->nruns) j->nruns[i] = nr;
         if (j->status) j->status[i] = rc;
     }
@@ -406,11 +480,40 @@ int oracle_align_batch(const uint8_t *pbuf, const uint64_t *poff, const uint32_t
                                    0, want_cigar, scores, runs, slot, nruns, status, threads, st);
 }
 
+static int batch_core(const uint8_t *pbuf, const uint64_t *poff, const uint32_t *plen,
+                      const uint8_t *tbuf, const uint64_t *toff, const uint32_t *tlen,
+                      int64_t count, int x, int o, int e, int pb, int pe, int tb, int te,
+                      int mwl, int mdt, int want_cigar, int32_t *scores, uint32_t *runs,
+                      int64_t slot, int64_t *nruns, int32_t *status, int threads,
+                      oracle_stats *st);
+
 int oracle_align_batch_ends(const uint8_t *pbuf, const uint64_t *poff, const uint32_t *plen,
                             const uint8_t *tbuf, const uint64_t *toff, const uint32_t *tlen,
                             int64_t count, int x, int o, int e, int pb, int pe, int tb, int te,
                             int want_cigar, int32_t *scores, uint32_t *runs, int64_t slot,
                             int64_t *nruns, int32_t *status, int threads, oracle_stats *st) {
+    return batch_core(pbuf, poff, plen, tbuf, toff, tlen, count, x, o, e, pb, pe, tb, te, 0, 0,
+                      want_cigar, scores, runs, slot, nruns, status, threads, st);
+}
+
+int oracle_align_batch_adaptive(const uint8_t *pbuf, const uint64_t *poff, const uint32_t *plen,
+                                const uint8_t *tbuf, const uint64_t *toff, const uint32_t *tlen,
+                                int64_t count, int x, int o, int e, int min_wavefront_length,
+                                int max_distance_threshold, int want_cigar, int32_t *scores,
+                                uint32_t *runs, int64_t slot, int64_t *nruns, int32_t *status,
+                                int threads, oracle_stats *st) {
+    if (min_wavefront_length < 0 || max_distance_threshold < 0) return ORACLE_E_INVAL;
+    return batch_core(pbuf, poff, plen, tbuf, toff, tlen, count, x, o, e, 0, 0, 0, 0,
+                      min_wavefront_length, max_distance_threshold, want_cigar, scores, runs, slot,
+                      nruns, status, threads, st);
+}
+
+static int batch_core(const uint8_t *pbuf, const uint64_t *poff, const uint32_t *plen,
+                      const uint8_t *tbuf, const uint64_t *toff, const uint32_t *tlen,
+                      int64_t count, int x, int o, int e, int pb, int pe, int tb, int te,
+                      int mwl, int mdt, int want_cigar, int32_t *scores, uint32_t *runs,
+                      int64_t slot, int64_t *nruns, int32_t *status, int threads,
+                      oracle_stats *st) {
     if (threads < 1) threads = 1;
     if (threads > 1024) threads = 1024;
     job_t *jobs = (job_t *)calloc((size_t)threads, sizeof(job_t));
@@ -421,6 +524,7 @@ int oracle_align_batch_ends(const uint8_t *pbuf, const uint64_t *poff, const uin
         j->pbuf = pbuf; j->tbuf = tbuf; j->poff = poff; j->toff = toff;
         j->plen = plen; j->tlen = tlen; j->x = x; j->o = o; j->e = e;
         j->pb = pb; j->pe = pe; j->tb = tb; j->te = te;
+        j->mwl = mwl; j->mdt = mdt;
         j->want_cigar = want_cigar; j->scores = scores; j->runs = runs; j->slot = slot;
         j->nruns = nruns; j->status = status;
         j->begin = count * t / threads;

@@ -25,6 +25,22 @@ int oracle_align_ends(const uint8_t *P, int n, const uint8_t *T, int m,
                       int32_t *score_out, uint32_t *runs, int64_t runs_cap, int64_t *nruns_out,
                       oracle_stats *st);
 
+/* WF-adaptive heuristic (global alignment): once a wavefront holds at least
+ * min_wavefront_length diagonals, diagonals at its ends farther from the end
+ * cell than the closest one by more than max_distance_threshold are dropped
+ * (min_wavefront_length 0: exact). */
+int oracle_align_adaptive(const uint8_t *P, int n, const uint8_t *T, int m, int x, int o, int e,
+                          int min_wavefront_length, int max_distance_threshold, int want_cigar,
+                          int32_t *score_out, uint32_t *runs, int64_t runs_cap, int64_t *nruns_out,
+                          oracle_stats *st);
+
+int oracle_align_batch_adaptive(const uint8_t *pbuf, const uint64_t *poff, const uint32_t *plen,
+                                const uint8_t *tbuf, const uint64_t *toff, const uint32_t *tlen,
+                                int64_t count, int x, int o, int e, int min_wavefront_length,
+                                int max_distance_threshold, int want_cigar, int32_t *scores,
+                                uint32_t *runs, int64_t slot, int64_t *nruns, int32_t *status,
+                                int threads, oracle_stats *st);
+
 int oracle_align_batch_ends(const uint8_t *pbuf, const uint64_t *poff, const uint32_t *plen,
                             const uint8_t *tbuf, const uint64_t *toff, const uint32_t *tlen,
                             int64_t count, int x, int o, int e, int pb, int pe, int tb, int te,

@@ -13,6 +13,10 @@
   clipped sub-pairs) by enumeration and by the pinned Gotoh DP, a Gotoh DP
   with free boundary cells, closed forms (semi-global, overlaps) and the
   symmetry of swapping the sequences,
+* the WF-adaptive heuristic: a worked example derived by hand from the
+  reduction's definition (both sides of the width and threshold
+  comparisons), exactness where no reduction can act, and that every result
+  is an alignment scoring at least the optimum,
 * planted mistakes: mutants of the oracle built on the CPU must fail the
   pins above.
 """
@@ -256,6 +260,100 @@ def test_ends_free_closed_forms(oracle_lib):
             assert a == b
 
 
+# ---- WF-adaptive heuristic ---------------------------------------------------
+# Worked by hand from the reduction's definition, penalties (4, 6, 2),
+# P = AA (n = 2), T = CCAA (m = 4); the optimum inserts CC (score 10, 2I2M).
+#  s=0  k=0 holds h=0 (A/C mismatch), distance max(2-0, 4-0) = 4.
+#  s=2  span [-1, 1], no offset (only gap extensions could reach it).
+#  s=4  X: k=0, h=1 (A/C mismatch again), distance 3; span [-2, 2] of width
+#       5; the reduction keeps [0, 0] once 5 >= min_wavefront_length.
+#  s=6  span [-2, 2] (from s=2 and s=4, one diagonal wider), no offset.
+#  s=8  span [-3, 3], width 7.  X: k=0, h=2 (v=2=n), distance max(0, 2) = 2;
+#       I opened from s=0: k=1, h=1, no match, distance max(2, 3) = 3;
+#       D opened from s=0: k=-1, h=0, distance max(1, 4) = 4.
+#       With the threshold 0 only k=0 stays, and the 2I path (which needs
+#       the I cell at k=1) is lost; threshold 1 keeps k=1 (3 <= 2 + 1).
+#  Threshold 0 then ends at s=14: I opened at s=12 from (v, h) = (1, 1),
+#  extended at s=14, one match: 1X2I1M, 4 + 6 + 2 + 2 = 14.  The reduction
+#  first bites at s=8 (width 7), unless s=4 (width 5) already trimmed: any
+#  min_wavefront_length up to 7 gives 14; from 8 on, no wavefront before the
+#  end reaches the width (s=10 spans [-2, 4] after clipping: 7) and the
+#  result is the exact one.  Swapping the sequences turns I into D.
+# Distances are taken after the extension: P = AC, T = CAC (optimum 1I2M, 8)
+# with (1, 0).  s=0: k=0, h=0, distance 3; s=4: X to k=0, h=1 (C/A), distance
+# 2, kept alone; s=8: X to k=0, h=2 (v = n), distance 1; I from s=0 to k=1,
+# h=1, which extends over AC to the end cell (h = 3): score 8.  Measured
+# before the extension that I cell would sit at distance 2 and be dropped.
+ADAPTIVE_WORKED = [
+    (b"AC", b"CAC", (1, 0), 8, "1I2M"),
+    (b"AA", b"CCAA", (1, 0), 14, "1X2I1M"),
+    (b"AA", b"CCAA", (5, 0), 14, "1X2I1M"),
+    (b"AA", b"CCAA", (7, 0), 14, "1X2I1M"),
+    (b"AA", b"CCAA", (8, 0), 10, "2I2M"),
+    (b"AA", b"CCAA", (1, 1), 10, "2I2M"),
+    (b"AA", b"CCAA", (0, 0), 10, "2I2M"),
+    (b"CCAA", b"AA", (1, 0), 14, "1X2D1M"),
+    (b"CCAA", b"AA", (1, 1), 10, "2D2M"),
+]
+
+
+def test_adaptive_worked_example(oracle_lib):
+    for P, T, ad, score, cigar in ADAPTIVE_WORKED:
+        s, runs = oracle_lib.align(P, T, (4, 6, 2), adaptive=ad)
+        assert (s, oracle_lib.cigar_string(runs)) == (score, cigar), (P, T, ad)
+        assert brute.check_cigar(P, T, runs, 4, 6, 2) == s
+
+
+def _adaptive_cases(synth_lib, seed):
+    rng = np.random.default_rng(seed)
+    pairs = synth_lib.random_pairs(rng, 40, 80) + synth_lib.random_pairs(rng, 10, 200)
+    pairs += synth_lib.random_pairs(rng, 10, 40, related=False)
+    pairs += [(b"", b""), (b"", b"ACG"), (b"GT", b""), (b"A", b"A")]
+    return pairs
+
+
+@pytest.mark.parametrize("pen", [(4, 6, 2), (1, 0, 1), (2, 3, 1)])
+def test_adaptive_without_reduction_is_exact(oracle_lib, synth_lib, pen):
+    """No reduction can happen when no wavefront reaches the minimum width
+    (longer than any span: n + m + 2), and none changes a result when the
+    threshold covers every distance (max(n, m)): both give the Gotoh
+    optimum."""
+    for P, T in _adaptive_cases(synth_lib, 31 + sum(pen)):
+        g = brute.gotoh_np(P, T, *pen)
+        n, m = len(P), len(T)
+        assert oracle_lib.align(P, T, pen, adaptive=(n + m + 2, 0)) == oracle_lib.align(P, T, pen)
+        s, runs = oracle_lib.align(P, T, pen, adaptive=(1, max(n, m)))
+        assert s == g, (P, T)
+        assert brute.check_cigar(P, T, runs, *pen) == s
+
+
+@pytest.mark.parametrize("ad", [(1, 0), (3, 1), (10, 5), (10, 50), (20, 2)])
+def test_adaptive_results_are_alignments(oracle_lib, synth_lib, ad):
+    """Whatever it drops, the heuristic reports an alignment: its CIGAR
+    spells both sequences and re-scores to the reported score, which is
+    never below the optimum; score-only mode agrees with CIGAR mode."""
+    below = 0
+    for P, T in _adaptive_cases(synth_lib, 7 + ad[0]):
+        for pen in [(4, 6, 2), (1, 0, 1)]:
+            s, runs = oracle_lib.align(P, T, pen, adaptive=ad)
+            g = brute.gotoh_np(P, T, *pen)
+            assert s >= g
+            below += s > g
+            assert brute.check_cigar(P, T, runs, *pen) == s, (P, T, pen)
+            assert oracle_lib.align(P, T, pen, cigar=False, adaptive=ad)[0] == s
+    if ad[1] <= 1:
+        assert below > 0  # tight thresholds do lose the optimum somewhere
+
+
+def test_adaptive_batch_equals_single(oracle_lib, synth_lib):
+    b = synth_lib.workload("uneven50_300_2m", 48)
+    r = oracle_lib.align_batch(b, (4, 6, 2), threads=3, adaptive=(5, 3))
+    for i in range(len(b)):
+        s, runs = oracle_lib.align(*b.pair(i), (4, 6, 2), adaptive=(5, 3))
+        assert s == int(r.scores[i])
+        assert list(r.runs[int(r.offsets[i]):int(r.offsets[i + 1])]) == runs
+
+
 # ---- the oracle's work counters --------------------------------------------
 # The benchmark's algorithmic work per pair (cells, 32-base extension
 # windows) comes from the oracle's counters, so they are pinned too, by
@@ -342,6 +440,16 @@ MUTANTS = {
     "mismatch_no_advance": ("xx = xx == OFF_NULL ? OFF_NULL : xx + 1;\n            int Mv",
                             "xx = xx == OFF_NULL ? OFF_NULL : xx;\n            int Mv"),
     "backtrace_D_moves_h": ("                k += 1;\n            }\n        }", "                k += 1;\n                h -= 1;\n            }\n        }"),
+    # the WF-adaptive reduction
+    "adaptive_distance_min": ("return n - v > m - h ? n - v : m - h;", "return n - v < m - h ? n - v : m - h;"),
+    "adaptive_distance_sum": ("return n - v > m - h ? n - v : m - h;", "return (n - v) + (m - h);"),
+    "adaptive_distance_k_sign": ("    int v = h - k;\n    return n - v", "    int v = h + k;\n    return n - v"),
+    "adaptive_width_strict": ("if (w->hi - w->lo + 1 < mwl) return 0;", "if (w->hi - w->lo + 1 <= mwl) return 0;"),
+    "adaptive_keep_strict": ("distance_to_end(lo2, w->M[lo2 - w->lo], n, m) > dmin + mdt", "distance_to_end(lo2, w->M[lo2 - w->lo], n, m) >= dmin + mdt"),
+    "adaptive_before_extension": (
+        "        for (int k = lo; k <= hi; k++) {\n            int i = k - lo;\n            if (w->M[i] != OFF_NULL) w->M[i] = extend(",
+        "        if (mwl > 0 && adaptive_reduce(w, n, m, mwl, mdt)) { status = ORACLE_E_NOMEM; goto done; }\n"
+        "        for (int k = w->lo; k <= w->hi; k++) {\n            int i = k - w->lo;\n            if (w->M[i] != OFF_NULL) w->M[i] = extend("),
     # counters the benchmark's algorithmic work comes from
     "cells_width_short_by_one": ("st->cells += hi - lo + 1;", "st->cells += hi - lo;"),
     "windows_rounded_up": ("st->ext_windows += run / 32 + 1;", "st->ext_windows += (run + 31) / 32;"),
@@ -413,6 +521,36 @@ def _mutant_caught(so_path) -> bool:
         if _counter_failures(counted):
             return True
     except RuntimeError:
+        return True
+    # the WF-adaptive heuristic
+    lib.oracle_align_adaptive.argtypes = [p, i, p, i, i, i, i, i, i, i, p, p, i64, p, p]
+
+    def adaptive(P, T, pen, ad):
+        n, m = len(P), len(T)
+        runs = (ctypes.c_uint32 * (n + m + 1))()
+        sc = ctypes.c_int32()
+        nr = ctypes.c_int64()
+        rc = lib.oracle_align_adaptive(ctypes.create_string_buffer(P, n + 1), n,
+                                       ctypes.create_string_buffer(T, m + 1), m, *pen, *ad, 1,
+                                       ctypes.byref(sc), runs, n + m + 1, ctypes.byref(nr), None)
+        if rc != 0:
+            raise AssertionError("oracle_align_adaptive failed")
+        return sc.value, list(runs)[:nr.value]
+
+    try:
+        for P, T, ad, score, cigar in ADAPTIVE_WORKED:
+            s, runs = adaptive(P, T, (4, 6, 2), ad)
+            if s != score or "".join(f"{r >> 4}{'MXID'[r & 15]}" for r in runs) != cigar:
+                return True
+        for P, T in cases[::5]:
+            s, runs = adaptive(P, T, (4, 6, 2), (1, max(len(P), len(T))))
+            if s != brute.gotoh(P, T, 4, 6, 2)[0]:
+                return True
+            for ad in [(1, 0), (3, 1)]:
+                s, runs = adaptive(P, T, (4, 6, 2), ad)
+                if s < brute.gotoh(P, T, 4, 6, 2)[0] or brute.check_cigar(P, T, runs, 4, 6, 2) != s:
+                    return True
+    except AssertionError:
         return True
     # ends-free cases
     for pen in [(4, 6, 2), (1, 0, 1)]:
