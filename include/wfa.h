@@ -188,6 +188,24 @@ typedef struct {
     uint32_t text_end_free;
 } wfa_ends_free;
 
+/* WF-adaptive heuristic: the wavefront reduction of the WFA paper that the
+ * method builds on (Marco-Sola et al. 2021).  After each score step's
+ * extension, a wavefront that spans at least min_wavefront_length diagonals
+ * (those without an offset included) drops the diagonals at either end
+ * whose furthest point (v, h) lies farther from the end cell than the
+ * closest one by more than max_distance_threshold, the distance being
+ * max(n - v, m - h), the bases still to cover (diagonals without an offset
+ * count as farthest).  The step that reaches the end cell is never reduced.
+ * The score is that of the path the search took, at least the optimum; the
+ * CIGAR spells that path and may cost less than the score where the path
+ * closes a gap and at once opens another of the same kind (one run in the
+ * CIGAR, one opening cheaper).  min_wavefront_length 0 selects exact
+ * alignment (the default). */
+typedef struct {
+    int32_t min_wavefront_length;
+    int32_t max_distance_threshold;
+} wfa_heuristic;
+
 /* Counters of the last wfa_align_batch call on a context. */
 typedef struct {
     uint64_t pairs;              /* pairs aligned                                    */
@@ -267,6 +285,17 @@ int wfa_set_options(wfa_ctx *ctx, const wfa_options *opt);
  * global alignment (the default).  Bounds above WFA_MAX_LENGTH are
  * WFA_E_INVAL. */
 int wfa_set_ends_free(wfa_ctx *ctx, const wfa_ends_free *ends);
+
+/* Source: the WF-adaptive heuristic of the WFA paper (Marco-Sola et al.
+ * 2021) that Introduction and Methods builds on; a faster, inexact mode.
+ * Select the heuristic (wfa_heuristic) for later wfa_align_batch,
+ * wfa_align_batch_noalloc and wfa_autotune calls on the context, and for
+ * servers opened on it later; NULL or min_wavefront_length 0 selects exact
+ * alignment.  Every pair then runs on the general kernel.  The heuristic
+ * applies to global alignment only: selecting it while free ends are set
+ * (or free ends while it is selected), or a negative field, is
+ * WFA_E_INVAL and changes nothing. */
+int wfa_set_heuristic(wfa_ctx *ctx, const wfa_heuristic *h);
 
 /* Source: Introduction and Methods -- every read pair is aligned on its own
  * with the wavefront algorithm (gap-affine WFA, Marco-Sola et al. 2021:

@@ -217,7 +217,9 @@ static int distance_to_end(int k, int h, int n, int m) {
  * of the wavefront's span, those without an offset included; a wavefront
  * without any offset is left as it is; the reduction applies after the
  * extension and the end test of the step, and not to a step that ends the
- * alignment. */
+ * alignment; the score is the step that reaches the end, whose path may
+ * close a gap and open another of the same kind at once (the CIGAR merges
+ * them into one run, one opening cheaper than the score). */
 static int adaptive_reduce(wavefront *w, int n, int m, int mwl, int mdt) {
     if (w->hi - w->lo + 1 < mwl) return 0;
     int dmin = INT_MAX;

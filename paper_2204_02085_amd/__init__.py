@@ -33,7 +33,8 @@ WFA_OP_MATCH, WFA_OP_MISMATCH, WFA_OP_INS, WFA_OP_DEL = 0, 1, 2, 3
 WFA_MAX_LENGTH = 1 << 26
 
 EXPORTED = [
-    "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_set_ends_free", "wfa_align_batch",
+    "wfa_ctx_create", "wfa_ctx_destroy", "wfa_set_options", "wfa_set_ends_free",
+    "wfa_set_heuristic", "wfa_align_batch",
     "wfa_copy_last_cigars", "wfa_host_alloc", "wfa_host_free", "wfa_pack2bit", "wfa_autotune",
     "wfa_last_stats", "wfa_strerror",
     "wfa_server_open", "wfa_server_submit", "wfa_server_poll", "wfa_server_release",
@@ -65,6 +66,10 @@ class wfa_options(ctypes.Structure):
 class wfa_ends_free(ctypes.Structure):
     _fields_ = [("pattern_begin_free", ctypes.c_uint32), ("pattern_end_free", ctypes.c_uint32),
                 ("text_begin_free", ctypes.c_uint32), ("text_end_free", ctypes.c_uint32)]
+
+
+class wfa_heuristic(ctypes.Structure):
+    _fields_ = [("min_wavefront_length", ctypes.c_int32), ("max_distance_threshold", ctypes.c_int32)]
 
 
 class wfa_stats(ctypes.Structure):
@@ -132,6 +137,7 @@ def _load():
         "wfa_ctx_destroy": ([p], None),
         "wfa_set_options": ([p, ctypes.POINTER(wfa_options)], ctypes.c_int),
         "wfa_set_ends_free": ([p, ctypes.POINTER(wfa_ends_free)], ctypes.c_int),
+        "wfa_set_heuristic": ([p, ctypes.POINTER(wfa_heuristic)], ctypes.c_int),
         "wfa_align_batch": ([p, p, p, p, sz, ctypes.c_int, ctypes.c_int, wfa_penalties,
                              ctypes.c_int, p, p, sz, p, ctypes.POINTER(sz),
                              ctypes.POINTER(i64), p], ctypes.c_int),
@@ -172,6 +178,7 @@ wfa_ctx_create = lib.wfa_ctx_create
 wfa_ctx_destroy = lib.wfa_ctx_destroy
 wfa_set_options = lib.wfa_set_options
 wfa_set_ends_free = lib.wfa_set_ends_free
+wfa_set_heuristic = lib.wfa_set_heuristic
 wfa_align_batch = lib.wfa_align_batch
 wfa_copy_last_cigars = lib.wfa_copy_last_cigars
 wfa_align_batch_noalloc = lib.wfa_align_batch_noalloc
@@ -282,6 +289,13 @@ class Aligner:
         rc = wfa_set_ends_free(self.ctx, ctypes.byref(ef))
         if rc != WFA_OK:
             raise WFAError(rc, "wfa_set_ends_free")
+
+    def set_heuristic(self, min_wavefront_length=0, max_distance_threshold=0):
+        """WF-adaptive heuristic for later calls (min_wavefront_length 0: exact)."""
+        h = wfa_heuristic(min_wavefront_length, max_distance_threshold)
+        rc = wfa_set_heuristic(self.ctx, ctypes.byref(h))
+        if rc != WFA_OK:
+            raise WFAError(rc, "wfa_set_heuristic")
 
     def autotune(self, patterns, texts, pairs, n, penalties=(4, 6, 2), cigar=True,
                  encoding=WFA_ASCII, sample_pairs=0, cache_path=None, force=False) -> dict:

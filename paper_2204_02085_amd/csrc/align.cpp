@@ -260,6 +260,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.fail_count = &flags->fail_count;
             g.gave_up = &flags->gave_up;
             g.step_limit = e->opt.general_step_limit;
+            g.heur = e->heur;
             HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, rows16, s));
             uint32_t nfail = 0;
             unsigned long long gave_up = ~0ull;
@@ -418,7 +419,10 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         if ((uint32_t)window < 2 * reach + 16) window = 0;
     }
     ShortPlan sp;
-    bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN;
+    // the WF-adaptive heuristic runs on the general kernel alone (the
+    // short-pair kernels are exact)
+    bool use_short = schedule != WFA_SCHED_GENERAL && window != 0 && max_len <= SHORT_MAX_LEN &&
+                     e->heur.mwl == 0;
     int lanes = 0;
     if (use_short) {
         const int cap = e->opt.step_cap ? e->opt.step_cap : default_cap(pen, window);

@@ -284,8 +284,24 @@ extern "C" int wfa_set_ends_free(wfa_ctx* ctx, const wfa_ends_free* ends) {
     if (ends->pattern_begin_free > WFA_MAX_LENGTH || ends->pattern_end_free > WFA_MAX_LENGTH ||
         ends->text_begin_free > WFA_MAX_LENGTH || ends->text_end_free > WFA_MAX_LENGTH)
         return WFA_E_INVAL;
+    const bool free_ends = ends->pattern_begin_free || ends->pattern_end_free ||
+                           ends->text_begin_free || ends->text_end_free;
+    if (free_ends && ctx->heur.mwl > 0) return WFA_E_INVAL;  // the heuristic is global-only
     ctx->ends = Ends{(int)ends->pattern_begin_free, (int)ends->pattern_end_free,
                      (int)ends->text_begin_free, (int)ends->text_end_free};
+    return WFA_OK;
+}
+
+extern "C" int wfa_set_heuristic(wfa_ctx* ctx, const wfa_heuristic* h) {
+    if (!ctx) return WFA_E_INVAL;
+    if (!h || h->min_wavefront_length == 0) {
+        if (h && h->max_distance_threshold < 0) return WFA_E_INVAL;
+        ctx->heur = Heuristic{0, 0};
+        return WFA_OK;
+    }
+    if (h->min_wavefront_length < 0 || h->max_distance_threshold < 0) return WFA_E_INVAL;
+    if (ctx->ends.pb || ctx->ends.pe || ctx->ends.tb || ctx->ends.te) return WFA_E_INVAL;
+    ctx->heur = Heuristic{h->min_wavefront_length, h->max_distance_threshold};
     return WFA_OK;
 }
 

@@ -27,7 +27,8 @@ struct Candidate {
 };
 
 std::string class_key(const char* arch, const wfa_penalties& pen, int mode, uint32_t max_len,
-                      uint32_t max_diff, size_t n, const wfa::Ends& ends) {
+                      uint32_t max_diff, size_t n, const wfa::Ends& ends,
+                      const wfa::Heuristic& heur) {
     // length and length-difference classes on a log2 scale
     auto lg = [](uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; };
     std::ostringstream k;
@@ -38,6 +39,7 @@ std::string class_key(const char* arch, const wfa_penalties& pen, int mode, uint
         k << "/ends" << lg(std::min<uint32_t>(ends.pb, max_len)) << "."
           << lg(std::min<uint32_t>(ends.pe, max_len)) << "." << lg(std::min<uint32_t>(ends.tb, max_len))
           << "." << lg(std::min<uint32_t>(ends.te, max_len));
+    if (heur.mwl > 0) k << "/adaptive" << heur.mwl << "." << heur.mdt;
     return k.str();
 }
 
@@ -137,7 +139,8 @@ extern "C" int wfa_autotune(wfa_ctx* ctx, const void* patterns, const void* text
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
     std::string a(arch);
     a = a.substr(0, a.find(':'));
-    const std::string key = class_key(a.c_str(), pen, mode, max_len, max_diff, num_pairs, ctx->ends);
+    const std::string key = class_key(a.c_str(), pen, mode, max_len, max_diff, num_pairs, ctx->ends,
+                                        ctx->heur);
     if (!force && load_entry(cache_path, key, chosen)) {
         ctx->opt = *chosen;
         return WFA_OK;

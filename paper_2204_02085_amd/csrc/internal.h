@@ -121,6 +121,7 @@ struct Engine {
     hipEvent_t ev[12] = {};
     wfa_options opt{};
     wfa::Ends ends{};  // free ends of later calls (all zero: global alignment)
+    wfa::Heuristic heur{};  // WF-adaptive heuristic of later calls (mwl 0: exact)
     wfa_stats last{};
     std::vector<GraphEntry> graphs;
     // state kept for wfa_copy_last_cigars

@@ -46,6 +46,15 @@ struct Ends {
     int pb, pe, tb, te;
 };
 
+// WF-adaptive heuristic (the WFA paper's wavefront reduction; global
+// alignment only): after a step's extension, a wavefront spanning at least
+// mwl diagonals drops the diagonals at either end whose distance to the end
+// cell, max(n - v, m - h), exceeds the least such distance by more than mdt.
+// mwl = 0: exact alignment.
+struct Heuristic {
+    int mwl, mdt;
+};
+
 // Arguments of the short-pair kernel (all device pointers).
 struct ShortArgs {
     const PairDesc* pairs;
@@ -122,6 +131,7 @@ struct GeneralArgs {
     // such pair index is kept here (atomicMin; the host starts it at ~0).
     unsigned long long* gave_up;
     long long step_limit;
+    Heuristic heur;             // mwl = 0: exact
 };
 
 // Kernel entry points (host-side launchers; all asynchronous on `s`).

@@ -942,6 +942,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     __shared__ int wr_lo[MAXR], wr_hi[MAXR];  // range of diagonals each ring slot holds
     __shared__ int sh_end;  // lowest diagonal whose M cell ends the alignment
     __shared__ int sh_fail;
+    __shared__ int sh_dmin, sh_klo, sh_khi;  // WF-adaptive: least distance, kept range
 
     const uint32_t job = blockIdx.x;
     if (job >= a.num_jobs) return;
@@ -980,7 +981,11 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     if (tid == 0) {
         sh_end = INT_MAX;
         sh_fail = 0;
+        sh_dmin = INT_MAX;
+        sh_klo = INT_MAX;
+        sh_khi = INT_MIN;
     }
+    const int MWL = a.heur.mwl, MDT = a.heur.mdt;
 
     // step table (CIGAR mode) lives at the end of the slice, entry s at
     // slice_bytes - 16 * (s + 1)
@@ -1018,6 +1023,9 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     // a hard bound on steps: deleting all of P and inserting all of T (or a
     // lower limit the host asks for)
     long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
+    // the heuristic may settle for a worse alignment; none costs more than
+    // its n + m bases at the dearest price each
+    if (MWL > 0) max_score_g = (long long)(n + m) * max(X, OE) + 2;
     if (a.step_limit > 0 && a.step_limit < max_score_g) max_score_g = a.step_limit;
 
     int S = -1;
@@ -1148,18 +1156,71 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                 if (k1 <= hi) cell(k1, a1, b1, c1, e1, x1);
             }
         }
+        // the range later steps read (the WF-adaptive reduction may narrow it;
+        // the step table keeps [lo, hi], by which the history row is indexed)
+        int klo = lo, khi = hi;
+        if (MWL > 0 && present && hi - lo + 1 >= MWL) {
+            __syncthreads();  // every cell written, sh_end final
+            if (sh_end == INT_MAX) {  // not for the step that ends the alignment
+                RowT* rowM = (RowT*)(slice + off) + n + 1;
+                // each thread reads back the cells it wrote (k = lo + tid mod BT)
+                int dl = INT_MAX;
+                for (int k = lo + tid; k <= hi; k += BT) {
+                    const int h = rowM[k];
+                    if (h >= 0) dl = min(dl, max(n - (h - k), m - h));
+                }
+                for (int o2 = 32; o2 >= 1; o2 >>= 1) dl = min(dl, __shfl_xor(dl, o2));
+                if ((tid & 63) == 0 && dl != INT_MAX) atomicMin(&sh_dmin, dl);
+                __syncthreads();
+                const int dmin = sh_dmin;
+                if (dmin != INT_MAX) {  // a wavefront without offsets stays as it is
+                    int kl = INT_MAX, kh = INT_MIN;
+                    for (int k = lo + tid; k <= hi; k += BT) {
+                        const int h = rowM[k];
+                        if (h >= 0 && max(n - (h - k), m - h) - dmin <= MDT) {
+                            kl = min(kl, k);
+                            kh = max(kh, k);
+                        }
+                    }
+                    for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+                        kl = min(kl, __shfl_xor(kl, o2));
+                        kh = max(kh, __shfl_xor(kh, o2));
+                    }
+                    if ((tid & 63) == 0 && kl != INT_MAX) {
+                        atomicMin(&sh_klo, kl);
+                        atomicMax(&sh_khi, kh);
+                    }
+                    __syncthreads();
+                    klo = sh_klo;
+                    khi = sh_khi;
+                    // the dropped diagonals read NULL from now on
+                    RowT* rowI = rowM + FW;
+                    RowT* rowD = rowI + FW;
+                    for (int k = lo + tid; k < klo; k += BT)
+                        rowM[k] = rowI[k] = rowD[k] = (RowT)RNUL;
+                    for (int k = khi + 1 + tid; k <= hi; k += BT)
+                        rowM[k] = rowI[k] = rowD[k] = (RowT)RNUL;
+                }
+            }
+        }
         // this step's metadata (sources of this step are other entries, so
         // no thread still reading them can see it change)
         if (tid == 0) {
-            meta[rs] = RowMeta{lo, hi, off};
+            meta[rs] = RowMeta{klo, khi, off};
             if (a.cigar) table[-s] = RowMeta{lo, hi, hoff};
         }
         __syncthreads();
         // the slot's range, read by the next step that takes it over (every
-        // thread has read this step's entry before the barrier)
+        // thread has read this step's entry before the barrier), and the
+        // reduction's accumulators, which every thread has read by now
         if (tid == 0 && present) {
-            wr_lo[rs] = lo;
-            wr_hi[rs] = hi;
+            wr_lo[rs] = klo;
+            wr_hi[rs] = khi;
+        }
+        if (tid == 0 && MWL > 0) {
+            sh_dmin = INT_MAX;
+            sh_klo = INT_MAX;
+            sh_khi = INT_MIN;
         }
         if (sh_end != INT_MAX) {
             S = (int)s;

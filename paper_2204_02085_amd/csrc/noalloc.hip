@@ -78,6 +78,7 @@ extern "C" int wfa_align_batch_noalloc(wfa_ctx* ctx, const void* patterns, const
     Engine* e = ctx->fixed.get();
     e->opt = ctx->opt;
     e->ends = ctx->ends;
+    e->heur = ctx->heur;
     // every call starts from an empty region; the kernels clear the flags,
     // counters and run counts they rely on before using them
     e->ws.use_fixed(base, WFA_NOALLOC_SCRATCH_BYTES);

@@ -333,6 +333,7 @@ extern "C" int wfa_server_open(wfa_ctx* ctx, const wfa_server_cfg* cfg, wfa_serv
         e->opt = ctx->opt;
         e->opt.use_graph = -1;  // batch sizes vary from launch to launch
         e->ends = ctx->ends;    // the context's free ends (global by default)
+        e->heur = ctx->heur;    // and its heuristic (exact by default)
         srv->engines.push_back(std::move(e));
     }
     for (int i = 0; i < S; i++) srv->workers.emplace_back(worker_main, srv, srv->engines[i].get());
