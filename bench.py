@@ -537,22 +537,32 @@ def main():
 
     # the other configurations, for the record: 2 M uneven pairs (one
     # persistent bucketed graph-replayed launch, autotuned), 100 k long
-    # pairs (general kernel), the main workload in score-only mode, and the
+    # pairs (general kernel), the main workload in score-only mode, the
     # main workload aligned ends-free (up to 10 bases of either sequence free
-    # at either end, autotuned), timed after one warm-up call
+    # at either end, autotuned), and the WF-adaptive heuristic (minimum
+    # wavefront length 10, distance threshold 50) on the long pairs and on
+    # 1 M pairs of the main workload, each timed after one warm-up call; the
+    # first pairs of each are checked against the oracle
     others = None
     if args.other_configs:
+        import oracle
+
         others = {}
-        for name, count, tune, modes, ends in [
-                ("uneven50_300_2m", 2_000_000, True, ("cigar",), None),
-                ("long1k_10k_100k", 100_000, False, ("score", "cigar"), None),
-                (args.workload, args.pairs, True, ("score",), None),
-                (args.workload, args.pairs, True, ("cigar",), (10, 10, 10, 10))]:
+        for name, count, tune, modes, ends, heur in [
+                ("uneven50_300_2m", 2_000_000, True, ("cigar",), None, None),
+                ("long1k_10k_100k", 100_000, False, ("score", "cigar"), None, None),
+                (args.workload, args.pairs, True, ("score",), None, None),
+                (args.workload, args.pairs, True, ("cigar",), (10, 10, 10, 10), None),
+                ("long1k_10k_100k", 100_000, False, ("score", "cigar"), None, (10, 50)),
+                (args.workload, min(args.pairs, 1_000_000), False, ("cigar",), None, (10, 50))]:
             label = name if ends is None else name + "_ends_free_" + "_".join(map(str, ends))
-            if name == args.workload and ends is None:
+            if name == args.workload and ends is None and heur is None:
                 label = name + "_score_only"
+            if heur is not None:
+                label = name + "_adaptive_" + "_".join(map(str, heur))
             log(f"configuration {label}: {count} pairs")
             al.set_ends_free(*(ends or ()))
+            al.set_heuristic(*(heur or ()))
             bo = synth.workload(name, count)
             no = len(bo)
             if enc == wfa.WFA_PACKED2:
@@ -585,12 +595,33 @@ def main():
                              "short_pairs": st["short_pairs"], "general_pairs": st["general_pairs"],
                              "ms_short_kernel": st["ms_align"], "ms_general": st["ms_general"],
                              "options": opts or "defaults"}
+                # the first pairs against the oracle (scores, and runs in CIGAR mode)
+                k = min(no, 200 if "long" in name else 2000)
+                sub = synth.workload(name, k)
+                ref = oracle.align_batch(sub, (4, 6, 2), cigar=cig,
+                                         threads=min(16, os.cpu_count() or 1), ends=ends,
+                                         adaptive=heur, slot=int((sub.p_len.astype(np.int64)
+                                                                  + sub.t_len).max()) + 1)
+                ok = np.array_equal(oo[0][:k].cpu().numpy(), ref.scores)
+                if cig and ok:
+                    off = oo[2][: k + 1].cpu().numpy().view(np.uint64)
+                    ok = (np.array_equal(off, ref.offsets) and np.array_equal(
+                        oo[1][: int(off[k])].cpu().numpy().view(np.uint32), ref.runs))
+                if not ok:
+                    print(f"bench: configuration {label} ({mode}) differs from the oracle on its "
+                          f"first {k} pairs", file=sys.stderr)
+                    sys.exit(3)
+                rec[mode]["oracle_checked_pairs"] = k
                 del oo
             if ends is not None:
                 rec["ends_free"] = list(ends)
+            if heur is not None:
+                rec["adaptive"] = {"min_wavefront_length": heur[0],
+                                   "max_distance_threshold": heur[1]}
             others[label] = rec
             del po, to, do_, bo
         al.set_ends_free()
+        al.set_heuristic()
 
     serving = None
     if args.serving_requests > 0:
@@ -599,6 +630,7 @@ def main():
         # per-batch choice here, not a launch shape tuned for another workload
         al.set_options()
         al.set_ends_free()
+        al.set_heuristic()
         sweep = () if args.serving_sweep == "none" else \
             tuple(float(v) for v in args.serving_sweep.split(",") if v.strip())
         serving = serving_run(al, wfa, synth, args.serving_requests, args.serving_load, sweep,

@@ -168,6 +168,17 @@ typedef struct {
                                  bound that deleting all of P and inserting
                                  all of T implies, so only an internal error
                                  can give up */
+    int32_t general_checkpoint; /* CIGAR mode of the general kernel: C in
+                                 [1, 256] (raised to pre + 1, pre = max(x,
+                                 o + e) in units of gcd(x, o, e)) keeps the
+                                 wavefront rows of pre + 1 consecutive steps
+                                 every C steps and
+                                 recomputes the steps in between during the
+                                 backtrace (far less memory per pair, the same
+                                 CIGAR); -1 keeps a history row of every step;
+                                 0: checkpoints every 128 steps for launches
+                                 whose longest sequence has 1500 bases or
+                                 more, full history below */
 } wfa_options;
 
 /* Ends-free alignment.  Up to pattern_begin_free leading pattern bases OR

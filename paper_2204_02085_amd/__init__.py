@@ -60,7 +60,7 @@ class wfa_options(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("lanes_per_pair", ctypes.c_int32),
                 ("host_chunk_pairs", ctypes.c_int32), ("cascade_window", ctypes.c_int32),
                 ("general_slice_kib", ctypes.c_int32), ("lane_kernel", ctypes.c_int32),
-                ("general_step_limit", ctypes.c_int32)]
+                ("general_step_limit", ctypes.c_int32), ("general_checkpoint", ctypes.c_int32)]
 
 
 class wfa_ends_free(ctypes.Structure):

@@ -145,26 +145,49 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     // 0.1 * L times the mean edit cost) keeps ~s'^2 / e' cells of 4.5 bytes
     // (offset and record; 2.5 with 16-bit offsets) plus a 16-byte step-table
     // entry per step, and its runs
-    auto hist_est = [&](uint32_t n, uint32_t m) -> double {
+    // Checkpoint mode (CIGAR): rows of R steps every ck steps, each of at most
+    // 2s + 1 diagonals at step s, so ~3 R rb sg^2 / ck bytes of checkpoints;
+    // a segment buffer of (ck + R) rows of 2 (ck + R - 1) / e + 1 columns
+    // (M, I, D and a record byte each); the step table and the runs.
+    auto ck_for = [&](uint32_t max_len) -> int {
+        if (!cigar) return 0;
+        int c = e->opt.general_checkpoint;
+        if (c < 0) return 0;
+        if (c == 0) c = max_len >= 1500 ? 128 : 0;
+        if (c == 0) return 0;
+        c = std::max<int>(c, (int)R);  // checkpoint windows never overlap
+        if (c + (int)R > GENERAL_SEG_ROWS || c > GENERAL_CKPT_MAX) return 0;
+        return c;
+    };
+    auto seg_bytes_for = [&](int ck, uint64_t rb) -> double {
+        if (!ck) return 0.0;
+        const uint64_t wc = 2 * ((ck + R - 1) / (uint64_t)pen.e) + 1;
+        return (double)((ck + R) * ((wc * (3 * rb + 1) + 15) & ~(uint64_t)15));
+    };
+    auto hist_est = [&](uint32_t n, uint32_t m, int ck, uint64_t rb) -> double {
         const double L = std::max(n, m);
         const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
+        if (ck)
+            return 3.0 * (double)R * (double)rb * sg * sg / ck + 64.0 * R * sg / ck +
+                   seg_bytes_for(ck, rb) + 16.0 * sg + 4.0 * ((double)n + m + 1) + 4096.0;
         const double cellb = m < 0xFFFF ? 2.5 : 4.5;
         return cellb * sg * sg / pen.e + 32.0 * sg + 4.0 * ((double)n + m + 1) + 4096.0;
     };
     // After each launch the guess is scaled by 1.25x the largest ratio of
-    // used to guessed bytes seen so far (never above the guess itself), so
-    // batches less divergent than the guess run more pairs at a time; pairs
-    // whose slice is still too small are re-run with 4x
-    double scale_seen = 0.0, hist_scale = 1.0;
-    auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult, uint64_t rb) -> uint64_t {
+    // used to guessed bytes seen so far (never above the guess itself; one
+    // scale per mode), so batches less divergent than the guess run more
+    // pairs at a time; pairs whose slice is still too small are re-run with 4x
+    double scale_seen[2] = {0.0, 0.0}, hist_scale[2] = {1.0, 1.0};
+    auto slice_for = [&](uint32_t n, uint32_t m, uint64_t mult, uint64_t rb, int ck) -> uint64_t {
         const uint64_t nm1 = (uint64_t)n + m + 1;
         uint64_t sl;
         sl = (R + 1) * ((3 * rb * (nm1 + 2) + 15) & ~(uint64_t)15);  // ring slots, a NULL slot
         if (cigar && e->opt.general_slice_kib > 0)  // the caller's first guess
-            sl += (uint64_t)e->opt.general_slice_kib * 1024 * mult;
+            sl += (uint64_t)e->opt.general_slice_kib * 1024 * mult + (uint64_t)seg_bytes_for(ck, rb);
         else if (cigar)
-            sl += (uint64_t)std::min(std::max(hist_est(n, m) * hist_scale, 16.0 * 1024),
-                                     64.0 * 1024 * 1024) * mult;
+            sl += (uint64_t)std::min(std::max(hist_est(n, m, ck, rb) * hist_scale[ck ? 1 : 0],
+                                              16.0 * 1024 + seg_bytes_for(ck, rb)),
+                                     64.0 * 1024 * 1024 + seg_bytes_for(ck, rb)) * mult;
         return (sl + 255) & ~(uint64_t)255;
     };
 
@@ -190,7 +213,8 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         for (size_t off = 0; off < jobs.size();) {
             const Job& head = jobs[off];  // the longest pair left
             const bool rows16 = suffix_m[off] < 32767;
-            const uint64_t slice = slice_for(head.n, head.m, mult, rows16 ? 2 : 4);
+            const int ck = ck_for(std::max(head.n, head.m));
+            const uint64_t slice = slice_for(head.n, head.m, mult, rows16 ? 2 : 4, ck);
             const size_t others = ws.total - ws.arena.bytes;
             const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
             const size_t want = std::min(jobs.size() - off, (size_t)1 << 20) * slice;
@@ -260,6 +284,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.fail_count = &flags->fail_count;
             g.gave_up = &flags->gave_up;
             g.step_limit = e->opt.general_step_limit;
+            g.ckpt = ck;
             g.heur = e->heur;
             HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, rows16, s));
             uint32_t nfail = 0;
@@ -274,11 +299,14 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             // it holds the lowest pair index any launch gave up on
             if (gave_up != ~0ull) *gave_up_pair = (int64_t)gave_up;
             if (cigar) {
+                const int mi = ck ? 1 : 0;
                 for (size_t i = 0; i < nj; i++)
                     if (used[i])
-                        scale_seen = std::max(scale_seen, (double)used[i] /
-                                                              hist_est(jobs[off + i].n, jobs[off + i].m));
-                if (scale_seen > 0) hist_scale = std::min(1.0, std::max(1.0 / 16, 1.25 * scale_seen));
+                        scale_seen[mi] = std::max(
+                            scale_seen[mi], (double)used[i] / hist_est(jobs[off + i].n, jobs[off + i].m,
+                                                                        ck, rows16 ? 2 : 4));
+                if (scale_seen[mi] > 0)
+                    hist_scale[mi] = std::min(1.0, std::max(1.0 / 16, 1.25 * scale_seen[mi]));
             }
             if (nfail) {
                 std::vector<uint32_t> f(nfail);
@@ -314,9 +342,9 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     if (std::getenv("WFA_DEBUG"))
         std::fprintf(stderr,
                      "libwfa general: %zu pairs, %zu launches (fewest pairs in one: %zu), "
-                     "%d rounds, arena %.2f GiB, history scale %.3f\n",
+                     "%d rounds, arena %.2f GiB, history scale %.3f (checkpoints %.3f)\n",
                      n_pending, launches, min_conc, attempts, ws.arena.bytes / 1073741824.0,
-                     hist_scale);
+                     hist_scale[0], hist_scale[1]);
     return WFA_OK;
 }
 

@@ -265,6 +265,8 @@ extern "C" int wfa_set_options(wfa_ctx* ctx, const wfa_options* opt) {
     if (opt->bucket < -1 || opt->bucket > 1) return WFA_E_INVAL;
     if (opt->general_slice_kib < 0 || opt->general_slice_kib > (1 << 22)) return WFA_E_INVAL;
     if (opt->general_step_limit < 0) return WFA_E_INVAL;
+    if (opt->general_checkpoint < -1 || opt->general_checkpoint > GENERAL_CKPT_MAX)
+        return WFA_E_INVAL;
     if (opt->lane_kernel < -1 || opt->lane_kernel > 1) return WFA_E_INVAL;
     if (opt->host_chunk_pairs < 0) return WFA_E_INVAL;
     if (opt->cascade_window < -1 ||

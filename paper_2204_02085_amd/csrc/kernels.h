@@ -30,6 +30,11 @@ constexpr int STATS_BLOCKS = 1024;
 
 // Largest pre + 1 (rows a step reads back, plus the current one) the kernels hold.
 constexpr int GENERAL_MAX_RING = 512;
+// Checkpoint CIGAR mode of the general kernel: at most this many steps
+// between checkpoints, and rows per recomputed segment (steps between two
+// checkpoints plus the pre + 1 rows of a checkpoint)
+constexpr int GENERAL_CKPT_MAX = 256;
+constexpr int GENERAL_SEG_ROWS = 768;
 
 // Penalties divided by their gcd g: every reachable score is a multiple of g,
 // so the kernels step s' = s / g and report g * s'.
@@ -132,6 +137,11 @@ struct GeneralArgs {
     unsigned long long* gave_up;
     long long step_limit;
     Heuristic heur;             // mwl = 0: exact
+    // CIGAR mode: 0 keeps a history row of every step; C > 0 keeps the rows
+    // of pre + 1 consecutive steps every C steps and recomputes the rest
+    // during the backtrace (C <= GENERAL_CKPT_MAX, C + pre + 1 <=
+    // GENERAL_SEG_ROWS)
+    int ckpt;
 };
 
 // Kernel entry points (host-side launchers; all asynchronous on `s`).

@@ -930,6 +930,41 @@ __device__ __forceinline__ int extend_general(const SeqView<SEQ_LDS>& sv, int n,
     return h;
 }
 
+// One cell of step s > 0 on diagonal k from its five source offsets: va = M
+// of s - o - e and vb = I of s - e on k - 1 (insertion), vc = M of s - o - e
+// and ve = D of s - e on k + 1 (deletion), vx = M of s - x on k (mismatch).
+// Candidates are compared as unsigned distances t = L - c below the
+// diagonal's limit L = min(m, n + k): admissible offsets 0 <= t <= L, NULL
+// sources L < t <= L - NULL, offsets past L negative (huge); the maximum
+// admissible candidate is the minimum t, floored at NULL.  Returns M before
+// extension, I and D (negative: NULL) and the decision record the backtrace
+// replays (tie-break: mismatch, then insertion, then deletion; gap open
+// before extend).
+struct GenCell {
+    int m, i, d, rec;
+};
+
+__device__ __forceinline__ GenCell general_cell(int n, int m, int k, int va, int vb, int vc, int ve,
+                                                int vx) {
+    const int L = min(m, n + k);
+    const uint32_t tn = (uint32_t)(L - NUL32);
+    const uint32_t ta = (uint32_t)(L - 1 - va);
+    const uint32_t tb = (uint32_t)(L - 1 - vb);
+    const uint32_t tc = (uint32_t)(L - vc);
+    const uint32_t te = (uint32_t)(L - ve);
+    const uint32_t tx = (uint32_t)(L - 1 - vx);
+    const uint32_t ti = min(min(ta, tb), tn);
+    const uint32_t td = min(min(tc, te), tn);
+    const uint32_t tm = min(min(tx, ti), td);
+    GenCell c;
+    c.m = L - (int)tm;
+    c.i = L - (int)ti;
+    c.d = L - (int)td;
+    const int msrc = tx == tm ? 0 : (ti == tm ? 1 : 2);
+    c.rec = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
+    return c;
+}
+
 // RowT: int16_t ring rows while every offset fits (texts shorter than 32767
 // bases), halving the ring's memory traffic, else int32_t.  Stored NULLs are
 // normalised to RNUL, so no NULL drifts up over many steps.
@@ -943,6 +978,11 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     __shared__ int sh_end;  // lowest diagonal whose M cell ends the alignment
     __shared__ int sh_fail;
     __shared__ int sh_dmin, sh_klo, sh_khi;  // WF-adaptive: least distance, kept range
+    // checkpoint CIGAR mode: per-row diagonal ranges of the segment being
+    // recomputed, and the walk's hand-over between segments
+    __shared__ int seg_a[GENERAL_SEG_ROWS], seg_b[GENERAL_SEG_ROWS];
+    __shared__ long long sh_ws;
+    __shared__ int sh_wk, sh_wstate;
 
     const uint32_t job = blockIdx.x;
     if (job >= a.num_jobs) return;
@@ -1006,6 +1046,17 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     const bool h16 = m < 0xFFFF;
     const int hbytes = h16 ? 2 : 4;
     long long bump = (R + 1) * full_row;  // CIGAR history starts after the ring
+    // Checkpoint CIGAR mode (CK > 0): instead of a history row per step, the
+    // ring rows of R consecutive steps are kept every CK steps, and the
+    // backtrace recomputes the steps between two checkpoints, in the cone of
+    // diagonals that can reach the walk's entry cell, into a segment buffer
+    // of fixed size placed after the checkpoints.
+    const int CK = a.cigar ? a.ckpt : 0;
+    const bool full_hist = a.cigar && CK == 0;
+    const int DMAX = CK ? (CK + R - 1) / E : 0;  // widest cone half-width
+    const int WC = 2 * DMAX + 1;                 // cone columns
+    const long long SEG_ROWB = ((long long)WC * (3 * (long long)sizeof(RowT) + 1) + 15) & ~15LL;
+    const long long seg_bytes = CK ? (long long)(CK + R) * SEG_ROWB : 0;
     if (bump > slice_bytes) {
         if (tid == 0) {
             const uint32_t at = atomicAdd(a.fail_count, 1u);
@@ -1029,10 +1080,17 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     if (a.step_limit > 0 && a.step_limit < max_score_g) max_score_g = a.step_limit;
 
     int S = -1;
+    long long end_off = -1;  // ring offset of the last step's rows
     int rs = 0;  // s % R
     for (long long s = 0;; s++, rs = rs + 1 == R ? 0 : rs + 1) {
         if (s > max_score_g) {
             if (tid == 0) sh_fail = 2;
+            break;
+        }
+        // checkpoint mode: the step table, the segment buffer and the
+        // checkpoints must stay apart
+        if (CK && bump + seg_bytes > slice_bytes - 16LL * (s + 2)) {
+            if (tid == 0) sh_fail = 1;
             break;
         }
         // the source rows of this step (metadata ring entry of step t: t % R)
@@ -1062,7 +1120,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         if (present) {
             const int w = hi - lo + 1;
             off = rs * full_row;
-            if (a.cigar) {
+            if (full_hist) {
                 hoff = bump;
                 bump += ((long long)hbytes * w + (w + 1) / 2 + 15) & ~15LL;
                 if (bump > slice_bytes - 16LL * (s + 2)) {
@@ -1080,8 +1138,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                 for (int k = max(hi + 1, plo) + tid; k <= phi; k += BT)
                     rowM[k] = rowI[k] = rowD[k] = (RowT)RNUL;
             }
-            unsigned char* histM = a.cigar ? slice + hoff : nullptr;
-            uint8_t* histF = a.cigar ? histM + (long long)hbytes * w : nullptr;
+            unsigned char* histM = full_hist ? slice + hoff : nullptr;
+            uint8_t* histF = full_hist ? histM + (long long)hbytes * w : nullptr;
             // source components (M of s - x and s - o - e, I and D of s - e),
             // indexed by diagonal; an absent step reads the NULL slot
             const RowT* MX = sx.off >= 0 ? (const RowT*)(slice + sx.off) + n + 1 : nullrow;
@@ -1095,34 +1153,17 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                 if (s == 0) {
                     mval = max(k, 0);
                 } else {
-                    // candidates as unsigned distances t = L - c below the
-                    // diagonal's limit L = min(m, n + k): admissible offsets
-                    // 0 <= t <= L, NULL sources L < t <= L - NULL, offsets past
-                    // L negative (huge); the maximum admissible candidate is
-                    // the minimum t, floored at NULL
-                    const int L = min(m, n + k);
-                    const uint32_t tn = (uint32_t)(L - NUL32);
-                    const uint32_t ta = (uint32_t)(L - 1 - va);
-                    const uint32_t tb = (uint32_t)(L - 1 - vb);
-                    const uint32_t tc = (uint32_t)(L - vc);
-                    const uint32_t te = (uint32_t)(L - ve);
-                    const uint32_t tx = (uint32_t)(L - 1 - vx);
-                    const uint32_t ti = min(min(ta, tb), tn);
-                    const uint32_t td = min(min(tc, te), tn);
-                    const uint32_t tm = min(min(tx, ti), td);
-                    mval = L - (int)tm;
-                    ival = L - (int)ti;
-                    dval = L - (int)td;
-                    // decisions the backtrace replays (tie-break: mismatch,
-                    // then insertion, then deletion; gap open before extend)
-                    const int msrc = tx == tm ? 0 : (ti == tm ? 1 : 2);
-                    rec = msrc | (ta == ti ? 4 : 0) | (tc == td ? 8 : 0);
+                    const GenCell c = general_cell(n, m, k, va, vb, vc, ve, vx);
+                    mval = c.m;
+                    ival = c.i;
+                    dval = c.d;
+                    rec = c.rec;
                 }
                 if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
                 rowM[k] = (RowT)(mval < 0 ? RNUL : mval);
                 rowI[k] = (RowT)(ival < 0 ? RNUL : ival);
                 rowD[k] = (RowT)(dval < 0 ? RNUL : dval);
-                if (a.cigar) {
+                if (full_hist) {
                     if (h16)
                         ((uint16_t*)histM)[k - lo] = mval < 0 ? (uint16_t)0xFFFF : (uint16_t)mval;
                     else
@@ -1207,7 +1248,11 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         // no thread still reading them can see it change)
         if (tid == 0) {
             meta[rs] = RowMeta{klo, khi, off};
-            if (a.cigar) table[-s] = RowMeta{lo, hi, hoff};
+            // full history: the row's range and place; checkpoint mode: the
+            // range later steps read, -1 for no wavefront, -2 for rows not
+            // (yet) kept
+            if (full_hist) table[-s] = RowMeta{lo, hi, hoff};
+            else if (CK) table[-s] = RowMeta{klo, khi, present ? -2LL : -1LL};
         }
         __syncthreads();
         // the slot's range, read by the next step that takes it over (every
@@ -1224,7 +1269,40 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         }
         if (sh_end != INT_MAX) {
             S = (int)s;
+            end_off = off;
             break;
+        }
+        if (CK && s > 0 && s % CK == 0) {
+            // checkpoint: the rows of steps s - R + 1 .. s (all in the ring
+            // now), each over the range later steps read, M then I then D
+            long long need = 0;
+            for (int j = 0; j < R; j++) {
+                const long long t = s - R + 1 + j;
+                if (t < 0) continue;
+                const RowMeta mm = meta[(int)(t % R)];
+                if (mm.off >= 0)
+                    need += (3LL * (long long)sizeof(RowT) * (mm.hi - mm.lo + 1) + 15) & ~15LL;
+            }
+            if (bump + need + seg_bytes > slice_bytes - 16LL * (s + 2)) {
+                if (tid == 0) sh_fail = 1;
+                break;
+            }
+            for (int j = 0; j < R; j++) {
+                const long long t = s - R + 1 + j;
+                if (t < 0) continue;
+                const RowMeta mm = meta[(int)(t % R)];
+                if (mm.off < 0) continue;
+                const int w = mm.hi - mm.lo + 1;
+                const RowT* src = (const RowT*)(slice + mm.off) + n + 1 + mm.lo;
+                RowT* dst = (RowT*)(slice + bump);
+                for (int i = tid; i < 3 * w; i += BT) {
+                    const int c = i / w, kk = i - c * w;
+                    dst[i] = src[(long long)c * FW + kk];
+                }
+                if (tid == 0) table[-t].off = bump;
+                bump += (3LL * (long long)sizeof(RowT) * w + 15) & ~15LL;
+            }
+            __syncthreads();  // copied before the next step takes over the oldest slot
         }
     }
     __syncthreads();
@@ -1248,6 +1326,218 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             a.scores[pair] = S * a.pen.g;
             a.nruns[pair] = 0;
         }
+        return;
+    }
+    if (CK) {
+        // ---- checkpoint mode: the backtrace, one segment at a time --------
+        // The walk starts at the end cell and runs back over a segment of
+        // steps (b, se], recomputed first from the checkpoint at step b (b a
+        // multiple of CK; b = 0: from the start) in the cone of diagonals
+        // that can reach the entry cell (se, ke): a step t's cells lie within
+        // (se - t) / e diagonals of ke, since every change of diagonal costs at
+        // least e.  The cone holds every source of its own cells, so each
+        // recomputed cell equals the forward pass's.  When the walk reaches a
+        // step at or below b, that cell is the entry of the next segment.
+        unsigned char* segbuf = slice + bump;
+        const long long runs_at = bump + seg_bytes;
+        uint32_t* out = (uint32_t*)(slice + runs_at);
+        const long long table_bottom = slice_bytes - 16LL * (S + 1);
+        const long long cap_runs = (table_bottom - runs_at) / 4;
+        long long nr = 0;
+        int cop = -1;
+        long long clen = 0;
+        auto emit = [&](int op, long long len) {
+            if (len <= 0) return;
+            if (op == cop) {
+                clen += len;
+            } else {
+                if (cop >= 0) {
+                    if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+                    nr++;
+                }
+                cop = op;
+                clen = len;
+            }
+        };
+        // the walk's state (thread 0): step, diagonal, offset, component
+        // (0 M, 1 I, 2 D)
+        long long ws = S;
+        int wk = sh_end, wh = 0, wc = 0;
+        if (tid == 0) {
+            wh = ((const RowT*)(slice + end_off) + n + 1)[wk];
+            emit(OP_D, n - (wh - wk));  // the free suffix (runs go last to first)
+            emit(OP_I, m - wh);
+            sh_ws = S;
+            sh_wk = sh_end;
+            sh_wstate = 0;
+        }
+        __syncthreads();
+        for (;;) {
+            const long long se = sh_ws;
+            const int ke = sh_wk, state = sh_wstate;
+            __syncthreads();  // read before thread 0 writes the next hand-over
+            if (state != 0) break;
+            const long long b = se > 0 ? ((se - 1) / CK) * CK : 0;
+            const long long t0 = b > 0 ? b - R + 1 : 0;
+            const int nrow = (int)(se - t0 + 1);
+            const int kb = ke - DMAX;  // diagonal of column 0
+            for (int r = tid; r < nrow; r += BT) {
+                const long long t = t0 + r;
+                const RowMeta mm = table[-t];
+                const int dl = (int)((se - t) / E);
+                seg_a[r] = mm.off == -1 ? 1 : max(ke - dl, mm.lo);
+                seg_b[r] = mm.off == -1 ? 0 : min(ke + dl, mm.hi);
+            }
+            __syncthreads();
+            // the segment buffer: per row M, I, D (WC columns each) and the
+            // decision records
+            auto rowp = [&](int r) -> RowT* { return (RowT*)(segbuf + (long long)r * SEG_ROWB); };
+            auto src = [&](long long ts, int comp, int kk) -> int {
+                if (ts < t0) return RNUL;
+                const int rr = (int)(ts - t0);
+                if (kk < seg_a[rr] || kk > seg_b[rr]) return RNUL;
+                return rowp(rr)[comp * WC + (kk - kb)];
+            };
+            if (b > 0) {  // the checkpoint's rows, within the cone
+                for (int r = 0; r < R; r++) {
+                    const int lo_ = seg_a[r], hi_ = seg_b[r];
+                    if (lo_ > hi_) continue;
+                    const RowMeta mm = table[-(t0 + r)];
+                    const int w = mm.hi - mm.lo + 1, cnt = hi_ - lo_ + 1;
+                    const RowT* from = (const RowT*)(slice + mm.off);
+                    RowT* to = rowp(r);
+                    for (int i = tid; i < 3 * cnt; i += BT) {
+                        const int c = i / cnt, kk = lo_ + (i - c * cnt);
+                        to[c * WC + (kk - kb)] = from[(long long)c * w + (kk - mm.lo)];
+                    }
+                }
+                __syncthreads();  // the first recomputed step reads these rows
+            }
+            for (long long t = b > 0 ? b + 1 : 0; t <= se; t++) {
+                const int r = (int)(t - t0);
+                RowT* dM = rowp(r);
+                uint8_t* dF = (uint8_t*)(dM + 3 * WC);
+                for (int k = seg_a[r] + tid; k <= seg_b[r]; k += BT) {
+                    int mval, ival = NUL32, dval = NUL32, rec = 0;
+                    if (t == 0) {
+                        mval = max(k, 0);
+                    } else {
+                        const GenCell c = general_cell(n, m, k, src(t - OE, 0, k - 1),
+                                                       src(t - E, 1, k - 1), src(t - OE, 0, k + 1),
+                                                       src(t - E, 2, k + 1), src(t - X, 0, k));
+                        mval = c.m;
+                        ival = c.i;
+                        dval = c.d;
+                        rec = c.rec;
+                    }
+                    if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
+                    dM[k - kb] = (RowT)(mval < 0 ? RNUL : mval);
+                    dM[WC + k - kb] = (RowT)(ival < 0 ? RNUL : ival);
+                    dM[2 * WC + k - kb] = (RowT)(dval < 0 ? RNUL : dval);
+                    dF[k - kb] = (uint8_t)rec;
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                auto val = [&](long long ts, int comp, int kk) -> int {
+                    const int v = src(ts, comp, kk);
+                    return v < 0 ? NUL32 : v;
+                };
+                int st = 0;  // 0: next segment, 1: done, 2: inconsistent
+                for (;;) {
+                    if (ws < 0 || wh < 0) {
+                        st = 2;
+                        break;
+                    }
+                    if (ws == 0) {  // M_0[k] = max(k, 0) before extension, after the free prefix
+                        if (wc != 0) {
+                            st = 2;
+                            break;
+                        }
+                        emit(OP_M, wh - max(wk, 0));
+                        emit(OP_I, wk);
+                        emit(OP_D, -wk);
+                        st = 1;
+                        break;
+                    }
+                    if (ws <= b) break;  // below this segment: hand over
+                    const int rr = (int)(ws - t0);
+                    if (wk < seg_a[rr] || wk > seg_b[rr]) {
+                        st = 2;
+                        break;
+                    }
+                    const int f = ((const uint8_t*)(rowp(rr) + 3 * WC))[wk - kb];
+                    if (wc == 0) {
+                        const int ms = f & 3;
+                        if (ms == 0) {
+                            const int hn = val(ws - X, 0, wk);
+                            if (hn < 0 || hn + 1 > wh) {
+                                st = 2;
+                                break;
+                            }
+                            emit(OP_M, wh - hn - 1);
+                            emit(OP_X, 1);
+                            ws -= X;
+                            wh = hn;
+                        } else {
+                            const int h0 = val(ws, ms, wk);  // I or D before the M cell
+                            if (h0 < 0 || h0 > wh) {
+                                st = 2;
+                                break;
+                            }
+                            emit(OP_M, wh - h0);
+                            wh = h0;
+                            wc = ms;
+                        }
+                    } else if (wc == 1) {  // insertion: from k - 1, one text base
+                        emit(OP_I, 1);
+                        wk -= 1;
+                        wh -= 1;
+                        if (f & 4) {
+                            ws -= OE;
+                            wc = 0;
+                        } else {
+                            ws -= E;
+                        }
+                    } else {  // deletion: from k + 1, one pattern base
+                        emit(OP_D, 1);
+                        wk += 1;
+                        if (f & 8) {
+                            ws -= OE;
+                            wc = 0;
+                        } else {
+                            ws -= E;
+                        }
+                    }
+                }
+                sh_ws = ws;
+                sh_wk = wk;
+                sh_wstate = st;
+            }
+            __syncthreads();
+        }
+        if (tid != 0) return;
+        if (sh_wstate == 2) {  // inconsistent walk: give up on the pair, no loop
+            a.scores[pair] = -1;
+            a.nruns[pair] = 0;
+            atomicMin(a.gave_up, (unsigned long long)pair);
+            return;
+        }
+        if (cop >= 0) {
+            if (nr < cap_runs) out[nr] = ((uint32_t)clen << 4) | (uint32_t)cop;
+            nr++;
+        }
+        if (nr > cap_runs) {
+            const uint32_t at = atomicAdd(a.fail_count, 1u);
+            a.fail_list[at] = pair;
+            return;
+        }
+        a.scores[pair] = S * a.pen.g;
+        a.nruns[pair] = (uint32_t)nr;
+        a.job_nruns[job] = (uint32_t)nr;
+        a.job_used[job] =
+            (uint64_t)(bump - (R + 1) * full_row + seg_bytes) + 16ull * (S + 1) + 4ull * nr;
+        a.run_src[pair] = ((uint64_t)job * a.slice_bytes + (uint64_t)runs_at) / 4;  // arena words
         return;
     }
     // backtrace by one thread over the step table and the history rows, one
