@@ -70,10 +70,10 @@ def parse():
     ap.add_argument("--host-steps", type=int, default=2,
                     help="calls timed with host ASCII inputs and host outputs (PCIe "
                          "included; 0: skip)")
-    ap.add_argument("--tune-sample", type=int, default=1_048_576,
-                    help="pairs the autotuner times candidates on: the pairs of the same seeded "
-                         "stream right after the timed batch, so tuning never sees the timed "
-                         "inputs")
+    ap.add_argument("--tune-sample", type=int, default=0,
+                    help="pairs the autotuner times candidates on (0: as many as the timed "
+                         "batch): the pairs of the same seeded stream right after the timed "
+                         "batch, so tuning never sees the timed inputs")
     ap.add_argument("--options", default="",
                     help="JSON launch options instead of autotuning (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -409,7 +409,7 @@ def main():
     if args.options:
         tuned = {k: int(v) for k, v in json.loads(args.options).items()}
     else:
-        tuned = tune_on_disjoint_sample(al, wfa, synth, args.workload, n, args.tune_sample, enc,
+        tuned = tune_on_disjoint_sample(al, wfa, synth, args.workload, n, args.tune_sample or n, enc,
                                         args.mode == "cigar")
     t_tune = time.perf_counter() - t_tune
 
@@ -527,7 +527,8 @@ def main():
         else:
             p2, t2, d2 = al.to_device(b2)
         o2 = al.alloc_outputs(n2, n2 * 40 + 1024, True)
-        tuned2 = tune_on_disjoint_sample(al, wfa, synth, args.second_set, n2, args.tune_sample, enc)
+        tuned2 = tune_on_disjoint_sample(al, wfa, synth, args.second_set, n2,
+                                         args.tune_sample or n2, enc)
         el2, kms2, st2 = time_schedule(al, (p2, t2, d2, *o2), n2, args.steps, args.warmup, tuned2,
                                        enc)
         second = {"workload": args.second_set, "pairs": n2, "pairs_per_s": n2 * args.steps / el2,
@@ -577,7 +578,7 @@ def main():
                 if tune:
                     al.set_ends_free(*(ends or ()))
                     opts = tune_on_disjoint_sample(al, wfa, synth, name, no,
-                                                   min(args.tune_sample, no // 4), enc, cig)
+                                                   min(args.tune_sample or no, no // 4), enc, cig)
                 else:
                     opts = {}
                     al.set_options()
@@ -678,7 +679,7 @@ def main():
         "cigar_runs": needed,
         "autotuned_options": tuned,
         "autotune_seconds": t_tune,
-        "autotune_sample": f"{args.tune_sample} pairs of the same stream after the timed batch",
+        "autotune_sample": f"{args.tune_sample or n} pairs of the same stream after the timed batch",
         "default_knobs_pairs_per_s": default_value,
         "batched_vs_plain": batched,
         "phase_ms": {k: tuned_stats[k] for k in ("ms_pack", "ms_align", "ms_general", "ms_compact",

@@ -176,9 +176,9 @@ typedef struct {
                                  recomputes the steps in between during the
                                  backtrace (far less memory per pair, the same
                                  CIGAR); -1 keeps a history row of every step;
-                                 0: checkpoints every 128 steps for launches
-                                 whose longest sequence has 1500 bases or
-                                 more, full history below */
+                                 0: full history while the device memory
+                                 holds it for two pairs per compute unit,
+                                 checkpoints every 128 steps beyond */
 } wfa_options;
 
 /* Ends-free alignment.  Up to pattern_begin_free leading pattern bases OR

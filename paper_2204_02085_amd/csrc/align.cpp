@@ -149,11 +149,14 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     // 2s + 1 diagonals at step s, so ~3 R rb sg^2 / ck bytes of checkpoints;
     // a segment buffer of (ck + R) rows of 2 (ck + R - 1) / e + 1 columns
     // (M, I, D and a record byte each); the step table and the runs.
-    auto ck_for = [&](uint32_t max_len) -> int {
+    // By default (general_checkpoint 0) a launch keeps the full history while
+    // the arena holds that for enough pairs to fill the device (two per
+    // compute unit); below that, checkpoints every 128 steps.
+    auto ck_for = [&](bool memory_bound) -> int {
         if (!cigar) return 0;
         int c = e->opt.general_checkpoint;
         if (c < 0) return 0;
-        if (c == 0) c = max_len >= 1500 ? 128 : 0;
+        if (c == 0) c = memory_bound ? 128 : 0;
         if (c == 0) return 0;
         c = std::max<int>(c, (int)R);  // checkpoint windows never overlap
         if (c + (int)R > GENERAL_SEG_ROWS || c > GENERAL_CKPT_MAX) return 0;
@@ -213,10 +216,14 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         for (size_t off = 0; off < jobs.size();) {
             const Job& head = jobs[off];  // the longest pair left
             const bool rows16 = suffix_m[off] < 32767;
-            const int ck = ck_for(std::max(head.n, head.m));
-            const uint64_t slice = slice_for(head.n, head.m, mult, rows16 ? 2 : 4, ck);
             const size_t others = ws.total - ws.arena.bytes;
             const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
+            const size_t fill = std::min(jobs.size() - off, (size_t)2 * e->num_cus);
+            const bool memory_bound =
+                (double)slice_for(head.n, head.m, mult, rows16 ? 2 : 4, 0) * (double)fill >
+                (double)std::max(arena_cap, ws.arena.bytes);
+            const int ck = ck_for(memory_bound);
+            const uint64_t slice = slice_for(head.n, head.m, mult, rows16 ? 2 : 4, ck);
             const size_t want = std::min(jobs.size() - off, (size_t)1 << 20) * slice;
             if (ws.arena.bytes < want && ws.arena.bytes < arena_cap) {
                 const size_t target = std::min(want, arena_cap);
@@ -257,6 +264,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             RCCHK(ws.ensure(ws.job_offsets, (nj + 1) * 8));
             RCCHK(ws.ensure(ws.fail_list, nj * 4));
             if (cigar) {
+                RCCHK(ws.ensure(ws.gen_state, nj * sizeof(GenJobState)));
                 RCCHK(ws.ensure(ws.job_used, nj * 8));
                 HIPCHK(launch_fill_u64(ws.job_used.as<uint64_t>(), 0ull, nj, s));
             }
@@ -285,6 +293,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.gave_up = &flags->gave_up;
             g.step_limit = e->opt.general_step_limit;
             g.ckpt = ck;
+            g.jstate = cigar ? ws.gen_state.as<GenJobState>() : nullptr;
             g.heur = e->heur;
             HIPCHK(launch_general(g, bt, seq_lds, lds_bytes, rows16, s));
             uint32_t nfail = 0;

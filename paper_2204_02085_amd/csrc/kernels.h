@@ -110,6 +110,14 @@ struct LaneArgs {
     uint32_t* ovf_count;
 };
 
+// What the general kernel's forward pass hands to its CIGAR walk, per job.
+struct GenJobState {
+    long long bump;     // end of the history rows (or checkpoints) in the slice
+    long long end_off;  // ring offset of the last step's rows
+    int S;              // score steps of the alignment (-1: no walk)
+    int end_k;          // diagonal of the end cell
+};
+
 // Arguments of the general (workgroup-per-pair, HBM arena) kernel.
 struct GeneralArgs {
     const PairDesc* pairs;
@@ -142,6 +150,7 @@ struct GeneralArgs {
     // during the backtrace (C <= GENERAL_CKPT_MAX, C + pre + 1 <=
     // GENERAL_SEG_ROWS)
     int ckpt;
+    GenJobState* jstate;        // CIGAR mode: [num_jobs] hand-over to the walk kernel
 };
 
 // Kernel entry points (host-side launchers; all asynchronous on `s`).

@@ -978,11 +978,6 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     __shared__ int sh_end;  // lowest diagonal whose M cell ends the alignment
     __shared__ int sh_fail;
     __shared__ int sh_dmin, sh_klo, sh_khi;  // WF-adaptive: least distance, kept range
-    // checkpoint CIGAR mode: per-row diagonal ranges of the segment being
-    // recomputed, and the walk's hand-over between segments
-    __shared__ int seg_a[GENERAL_SEG_ROWS], seg_b[GENERAL_SEG_ROWS];
-    __shared__ long long sh_ws;
-    __shared__ int sh_wk, sh_wstate;
 
     const uint32_t job = blockIdx.x;
     if (job >= a.num_jobs) return;
@@ -992,6 +987,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     const int tid = threadIdx.x, BT = blockDim.x;
     const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
     const int R = PRE + 1;
+    // no walk for this job unless the forward pass below succeeds
+    if (a.cigar && tid == 0) a.jstate[job].S = -1;
     // free ends of this pair (global alignment: all zero)
     const int pb = min(a.ends.pb, n), pe = min(a.ends.pe, n);
     const int tb = min(a.ends.tb, m), te = min(a.ends.te, m);
@@ -1328,6 +1325,68 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         }
         return;
     }
+    // CIGAR mode: the walk runs in its own kernel, one wavefront per pair
+    if (tid == 0) a.jstate[job] = GenJobState{bump, end_off, S, sh_end};
+}
+
+// The CIGAR backtrace of the general kernel's pairs, one wavefront per pair,
+// launched after k_general on the same stream: the forward pass hands over
+// the end cell, the score, the end of its history (or checkpoints) and the
+// ring offset of the last step.  The walk itself is serial; 64 lanes
+// recompute the segments of checkpoint mode.  The forward pass's workgroup
+// is free again while the walks run, many per compute unit.
+template <bool SEQ_LDS, class RowT>
+__global__ __launch_bounds__(64) void k_general_walk(GeneralArgs a) {
+    constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int seg_a[GENERAL_SEG_ROWS], seg_b[GENERAL_SEG_ROWS];
+    __shared__ long long sh_ws;
+    __shared__ int sh_wk, sh_wstate;
+
+    const uint32_t job = blockIdx.x;
+    if (job >= a.num_jobs) return;
+    const GenJobState js = a.jstate[job];
+    if (js.S < 0) return;  // the forward pass failed or gave up on this pair
+    const uint32_t pair = a.jobs[job];
+    const PairDesc desc = a.pairs[pair];
+    const int n = (int)desc.p_len, m = (int)desc.t_len;
+    const int tid = threadIdx.x, BT = blockDim.x;
+    const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
+    const int R = PRE + 1;
+    unsigned char* slice = a.arena + (uint64_t)job * a.slice_bytes;
+    const long long slice_bytes = (long long)a.slice_bytes;
+    const int FW = n + m + 3;
+    const long long full_row = (3LL * (long long)sizeof(RowT) * FW + 15) & ~15LL;
+    const bool h16 = m < 0xFFFF;
+    const int hbytes = h16 ? 2 : 4;
+    RowMeta* table = (RowMeta*)(slice + slice_bytes) - 1;
+    const int S = js.S, sh_end = js.end_k;
+    const long long bump = js.bump, end_off = js.end_off;
+    const int CK = a.ckpt;
+    const int DMAX = CK ? (CK + R - 1) / E : 0;
+    const int WC = 2 * DMAX + 1;
+    const long long SEG_ROWB = ((long long)WC * (3 * (long long)sizeof(RowT) + 1) + 15) & ~15LL;
+    const long long seg_bytes = CK ? (long long)(CK + R) * SEG_ROWB : 0;
+
+    SeqView<SEQ_LDS> sv;
+    const int nwp = (n + 31) >> 5, nwt = (m + 31) >> 5;
+    if (CK && SEQ_LDS) {
+        uint64_t* p64 = (uint64_t*)lds;
+        uint64_t* t64 = p64 + nwp + 1;
+        for (int w = tid; w <= nwp; w += BT) p64[w] = w < nwp ? a.pw[desc.p_start + w] : 0ULL;
+        for (int w = tid; w <= nwt; w += BT) t64[w] = w < nwt ? a.tw[desc.t_start + w] : 0ULL;
+        sv.p = (const uint32_t*)p64;
+        sv.t = (const uint32_t*)t64;
+        __syncthreads();
+    } else {
+        sv.p = (const uint32_t*)(a.pw + desc.p_start);
+        sv.t = (const uint32_t*)(a.tw + desc.t_start);
+    }
+    sv.np32 = 2 * nwp;
+    sv.nt32 = 2 * nwt;
+    (void)hbytes;
+    (void)full_row;
+
     if (CK) {
         // ---- checkpoint mode: the backtrace, one segment at a time --------
         // The walk starts at the end cell and runs back over a segment of
@@ -1983,16 +2042,27 @@ int short_max_blocks_per_cu(int window, int lanes, bool cigar, int bt, int lds_p
 hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_lds, int lds_bytes,
                           bool rows16, hipStream_t s) {
     if (!a.num_jobs) return hipSuccess;
+    const dim3 grid(a.num_jobs), walk(64);
     if (seq_in_lds && rows16)
-        hipLaunchKernelGGL((k_general<true, int16_t>), dim3(a.num_jobs), dim3(block_threads),
-                           lds_bytes, s, a);
+        hipLaunchKernelGGL((k_general<true, int16_t>), grid, dim3(block_threads), lds_bytes, s, a);
     else if (seq_in_lds)
-        hipLaunchKernelGGL((k_general<true, int32_t>), dim3(a.num_jobs), dim3(block_threads),
-                           lds_bytes, s, a);
+        hipLaunchKernelGGL((k_general<true, int32_t>), grid, dim3(block_threads), lds_bytes, s, a);
     else if (rows16)
-        hipLaunchKernelGGL((k_general<false, int16_t>), dim3(a.num_jobs), dim3(block_threads), 0, s, a);
+        hipLaunchKernelGGL((k_general<false, int16_t>), grid, dim3(block_threads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_general<false, int32_t>), dim3(a.num_jobs), dim3(block_threads), 0, s, a);
+        hipLaunchKernelGGL((k_general<false, int32_t>), grid, dim3(block_threads), 0, s, a);
+    if (!a.cigar) return hipGetLastError();
+    // the walks, one wavefront per pair (checkpoint mode stages the sequences
+    // in LDS as the forward pass did)
+    const bool walk_lds = seq_in_lds && a.ckpt > 0;
+    if (walk_lds && rows16)
+        hipLaunchKernelGGL((k_general_walk<true, int16_t>), grid, walk, lds_bytes, s, a);
+    else if (walk_lds)
+        hipLaunchKernelGGL((k_general_walk<true, int32_t>), grid, walk, lds_bytes, s, a);
+    else if (rows16)
+        hipLaunchKernelGGL((k_general_walk<false, int16_t>), grid, walk, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_general_walk<false, int32_t>), grid, walk, 0, s, a);
     return hipGetLastError();
 }
 
