@@ -25,14 +25,18 @@
 // oracle.
 //
 // LDS per wavefront, lane-interleaved (dword q of lane l at q * 64 + l, so
-// 64 lanes reading "their" dword q hit 64 different banks):
-//   - the pattern and the text in 2-bit little-endian words;
-//   - CIGAR mode: the history of every reachable M cell, its offset after
-//     extension (one byte, 0x80 for NULL) and its 4-bit decision record
-//     (source of M: mismatch / end of insertion / end of deletion; whether I
-//     and D opened from M), packed in the cells' compile-time order.
+// 64 lanes reading "their" dword q hit 64 different banks): the pattern and
+// the text in 2-bit little-endian words, and the bytes of one step's cells
+// on their way to the history.  Per block: the diagonal of each compact
+// cell and (CIGAR) the (s, k) -> compact cell table.
+// Global memory per wavefront, lane-interleaved the same way (CIGAR mode):
+// the history of every reachable M cell, its offset after extension (one
+// byte, 0x80 for NULL) and its 4-bit decision record (source of M:
+// mismatch / end of insertion / end of deletion; whether I and D opened
+// from M), packed in the cells' compile-time order, then a stage for the
+// runs.  Keeping it out of LDS leaves room for three wavefronts per SIMD.
 // The backtrace is the short kernel's walk, run by every lane on its own
-// pair, with a per-block LDS table mapping (s, k) to the cell's index.
+// pair.
 //
 // A pair leaves through the overflow list (to the wider short-kernel passes
 // and the general kernel) when a sequence is longer than LMAX bases, when
