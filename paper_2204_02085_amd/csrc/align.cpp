@@ -169,7 +169,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     };
     auto hist_est = [&](uint32_t n, uint32_t m, int ck, uint64_t rb) -> double {
         const double L = std::max(n, m);
-        const double sg = 0.1 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
+        const double sg = 0.14 * L * (pen.x + 2.0 * pen.oe) / 3.0 + pen.oe;
         if (ck)
             return 3.0 * (double)R * (double)rb * sg * sg / ck + 64.0 * R * sg / ck +
                    seg_bytes_for(ck, rb) + 16.0 * sg + 4.0 * ((double)n + m + 1) + 4096.0;
@@ -216,36 +216,45 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
         for (size_t off = 0; off < jobs.size();) {
             const Job& head = jobs[off];  // the longest pair left
             const bool rows16 = suffix_m[off] < 32767;
+            const uint64_t rb = rows16 ? 2 : 4;
             const size_t others = ws.total - ws.arena.bytes;
             const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
-            const size_t fill = std::min(jobs.size() - off, (size_t)2 * e->num_cus);
-            const bool memory_bound =
-                (double)slice_for(head.n, head.m, mult, rows16 ? 2 : 4, 0) * (double)fill >
-                (double)std::max(arena_cap, ws.arena.bytes);
+            // every pair gets a slice of its own size; full histories unless the
+            // arena cannot hold them for the longest pairs that fill the device
+            const size_t left = std::min(jobs.size() - off, (size_t)1 << 20);
+            const size_t fill = std::min(left, (size_t)2 * e->num_cus);
+            double fill_bytes = 0;
+            for (size_t i = 0; i < fill; i++)
+                fill_bytes += (double)slice_for(jobs[off + i].n, jobs[off + i].m, mult, rb, 0);
+            const bool memory_bound = fill_bytes > (double)std::max(arena_cap, ws.arena.bytes);
             const int ck = ck_for(memory_bound);
-            const uint64_t slice = slice_for(head.n, head.m, mult, rows16 ? 2 : 4, ck);
-            const size_t want = std::min(jobs.size() - off, (size_t)1 << 20) * slice;
+            std::vector<uint64_t> soff(left + 1, 0);
+            for (size_t i = 0; i < left; i++)
+                soff[i + 1] = soff[i] + slice_for(jobs[off + i].n, jobs[off + i].m, mult, rb, ck);
+            const uint64_t head_slice = soff[1];
+            const size_t want = soff[left];
             if (ws.arena.bytes < want && ws.arena.bytes < arena_cap) {
                 const size_t target = std::min(want, arena_cap);
-                if (target > ws.arena.bytes && target >= slice) {
+                if (target > ws.arena.bytes && target >= head_slice) {
                     ws.release(ws.arena);
                     // the device may hold less than the budget: halve until it fits
                     size_t t = target;
                     int rc = ws.ensure(ws.arena, t);
-                    while (rc != WFA_OK && t / 2 >= slice) {
+                    while (rc != WFA_OK && t / 2 >= head_slice) {
                         t /= 2;
                         rc = ws.ensure(ws.arena, t);
                     }
                     RCCHK(rc);
                 }
             }
-            size_t conc = ws.arena.bytes / slice;
+            // the pairs whose slices fit in the arena, in order
+            size_t conc = (size_t)(std::upper_bound(soff.begin(), soff.end(), (uint64_t)ws.arena.bytes) -
+                                   soff.begin()) - 1;
             if (e->opt.general_pairs > 0) conc = std::min(conc, (size_t)e->opt.general_pairs);
-            conc = std::min(conc, jobs.size() - off);
-            conc = std::min(conc, (size_t)1 << 20);
+            conc = std::min(conc, left);
             if (conc == 0) {
                 std::fprintf(stderr, "libwfa: general kernel slice %zu B exceeds the arena (%zu B, "
-                                     "budget %zu B)\n", (size_t)slice, ws.arena.bytes, ws.budget);
+                                     "budget %zu B)\n", (size_t)head_slice, ws.arena.bytes, ws.budget);
                 return WFA_E_NOMEM;
             }
             const size_t nj = conc;
@@ -269,7 +278,10 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
                 HIPCHK(launch_fill_u64(ws.job_used.as<uint64_t>(), 0ull, nj, s));
             }
             RCCHK(ws.ensure(ws.scan_tmp, scan_temp_bytes(nj) + 64));
+            RCCHK(ws.ensure(ws.gen_slices, (nj + 1) * 8));
             HIPCHK(hipMemcpyAsync(ws.jobs.ptr, ids.data(), nj * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(ws.gen_slices.ptr, soff.data(), (nj + 1) * 8, hipMemcpyHostToDevice,
+                                  s));
             HIPCHK(launch_fill_u32(ws.job_nruns.as<uint32_t>(), 0u, nj, s));
             HIPCHK(launch_fill_u32(&flags->fail_count, 0u, 1, s));
             GeneralArgs g{};
@@ -282,7 +294,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             g.ends = e->ends;
             g.cigar = cigar ? 1 : 0;
             g.arena = ws.arena.as<uint8_t>();
-            g.slice_bytes = slice;
+            g.slice_off = ws.gen_slices.as<uint64_t>();
             g.scores = d.scores;
             g.nruns = ws.nruns.as<uint32_t>();
             g.run_src = ws.run_src.as<uint64_t>();
@@ -336,7 +348,7 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
                 HIPCHK(hipStreamSynchronize(s));
                 RCCHK(ws.grow_keep(ws.gen_runs, (gen_used + chunk_runs + 1) * 4, gen_used * 4, s));
                 HIPCHK(launch_gather_general(ws.jobs.as<uint32_t>(), nj, ws.job_nruns.as<uint32_t>(),
-                                             ws.run_src.as<uint64_t>(), ws.arena.as<uint8_t>(), slice,
+                                             ws.run_src.as<uint64_t>(), ws.arena.as<uint8_t>(), 0,
                                              ws.job_offsets.as<uint64_t>(), gen_used,
                                              ws.gen_runs.as<uint32_t>(), s));
                 gen_used += chunk_runs;

@@ -33,7 +33,8 @@ struct Workspace {
     // short kernel (slots2 / ovf_list2: the wider second pass)
     Buf nruns, run_src, slots, ovf_list, order, keys, hist, slots2, ovf_list2;
     // general kernel
-    Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp, job_used, gen_state;
+    Buf jobs, job_nruns, job_offsets, fail_list, arena, gen_runs, gen_tmp, job_used, gen_state,
+        gen_slices;
     // one-pair-per-lane kernel: CIGAR history of every wavefront of a launch,
     // and the claim counters of its persistent form
     Buf lane_hist, lane_queues;
@@ -51,13 +52,14 @@ struct Workspace {
     size_t fixed_size = 0, fixed_top = 0;
     void use_fixed(void* base, size_t size);  // start carving from an empty region
 
-    std::array<Buf*, 36> all() {
+    std::array<Buf*, 37> all() {
         return {&stats,   &flags,      &scan_tmp, &ws_p,        &ws_t,      &words_p,
                 &words_t, &packed_pairs, &in_pairs, &in_p,      &in_t,      &out_scores,
                 &out_runs, &out_offsets, &host_off, &host_loff, &nruns,   &run_src,
                 &slots,   &ovf_list,   &order,    &keys,        &hist,      &slots2,
                 &ovf_list2, &jobs,     &job_nruns, &job_offsets, &fail_list, &arena,
-                &gen_runs, &gen_tmp, &job_used, &gen_state, &lane_hist, &lane_queues};
+                &gen_runs, &gen_tmp, &job_used, &gen_state, &gen_slices, &lane_hist,
+                &lane_queues};
     }
     int ensure(Buf& b, size_t bytes);
     // grow to at least `bytes`, keeping the first `keep` bytes (copied on `s`,

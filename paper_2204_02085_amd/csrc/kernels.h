@@ -128,8 +128,8 @@ struct GeneralArgs {
     Pen pen;
     Ends ends;
     int cigar;
-    uint8_t* arena;             // num_jobs slices of slice_bytes
-    uint64_t slice_bytes;
+    uint8_t* arena;             // num_jobs slices, job j's at [slice_off[j], slice_off[j + 1])
+    const uint64_t* slice_off;  // [num_jobs + 1] byte offsets of the slices
     int32_t* scores;
     uint32_t* nruns;
     uint64_t* run_src;          // offset (in uint32 words) of the job's runs in the arena

@@ -992,8 +992,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     // free ends of this pair (global alignment: all zero)
     const int pb = min(a.ends.pb, n), pe = min(a.ends.pe, n);
     const int tb = min(a.ends.tb, m), te = min(a.ends.te, m);
-    unsigned char* slice = a.arena + (uint64_t)job * a.slice_bytes;
-    const long long slice_bytes = (long long)a.slice_bytes;
+    unsigned char* slice = a.arena + a.slice_off[job];
+    const long long slice_bytes = (long long)(a.slice_off[job + 1] - a.slice_off[job]);
 
     SeqView<SEQ_LDS> sv;
     const int nwp = (n + 31) >> 5, nwt = (m + 31) >> 5;
@@ -1353,8 +1353,8 @@ __global__ __launch_bounds__(64) void k_general_walk(GeneralArgs a) {
     const int tid = threadIdx.x, BT = blockDim.x;
     const int X = a.pen.x, OE = a.pen.oe, E = a.pen.e, PRE = a.pen.pre;
     const int R = PRE + 1;
-    unsigned char* slice = a.arena + (uint64_t)job * a.slice_bytes;
-    const long long slice_bytes = (long long)a.slice_bytes;
+    unsigned char* slice = a.arena + a.slice_off[job];
+    const long long slice_bytes = (long long)(a.slice_off[job + 1] - a.slice_off[job]);
     const int FW = n + m + 3;
     const long long full_row = (3LL * (long long)sizeof(RowT) * FW + 15) & ~15LL;
     const bool h16 = m < 0xFFFF;
@@ -1596,7 +1596,7 @@ __global__ __launch_bounds__(64) void k_general_walk(GeneralArgs a) {
         a.job_nruns[job] = (uint32_t)nr;
         a.job_used[job] =
             (uint64_t)(bump - (R + 1) * full_row + seg_bytes) + 16ull * (S + 1) + 4ull * nr;
-        a.run_src[pair] = ((uint64_t)job * a.slice_bytes + (uint64_t)runs_at) / 4;  // arena words
+        a.run_src[pair] = (a.slice_off[job] + (uint64_t)runs_at) / 4;  // arena words
         return;
     }
     // backtrace by one thread over the step table and the history rows, one
@@ -1720,7 +1720,7 @@ __global__ __launch_bounds__(64) void k_general_walk(GeneralArgs a) {
     a.nruns[pair] = (uint32_t)nr;
     a.job_nruns[job] = (uint32_t)nr;
     a.job_used[job] = (uint64_t)(bump - (R + 1) * full_row) + 16ull * (S + 1) + 4ull * nr;
-    a.run_src[pair] = ((uint64_t)job * a.slice_bytes + (uint64_t)bump) / 4;  // arena words
+    a.run_src[pair] = (a.slice_off[job] + (uint64_t)bump) / 4;  // arena words
 }
 
 // Move the runs of finished general jobs out of the arena.
