@@ -1339,7 +1339,6 @@ template <bool SEQ_LDS, class RowT>
 __global__ __launch_bounds__(64) void k_general_walk(GeneralArgs a) {
     constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int seg_a[GENERAL_SEG_ROWS], seg_b[GENERAL_SEG_ROWS];
     __shared__ long long sh_ws;
     __shared__ int sh_wk, sh_wstate;
 
@@ -1386,6 +1385,10 @@ __global__ __launch_bounds__(64) void k_general_walk(GeneralArgs a) {
     sv.nt32 = 2 * nwt;
     (void)hbytes;
     (void)full_row;
+    // checkpoint mode: each segment row's diagonal range, in LDS after the
+    // staged sequences (the launch sizes the LDS for its longest pair)
+    int* seg_a = (int*)(lds + (CK && SEQ_LDS ? (((nwp + 1 + nwt + 1) * 8 + 15) & ~15) : 0));
+    int* seg_b = seg_a + (CK + R);
 
     if (CK) {
         // ---- checkpoint mode: the backtrace, one segment at a time --------
@@ -2052,17 +2055,19 @@ hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_l
     else
         hipLaunchKernelGGL((k_general<false, int32_t>), grid, dim3(block_threads), 0, s, a);
     if (!a.cigar) return hipGetLastError();
-    // the walks, one wavefront per pair (checkpoint mode stages the sequences
-    // in LDS as the forward pass did)
+    // the walks, one wavefront per pair; checkpoint mode stages the sequences
+    // in LDS as the forward pass did, followed by its segment rows' ranges
     const bool walk_lds = seq_in_lds && a.ckpt > 0;
+    const int segs = a.ckpt > 0 ? 8 * (a.ckpt + a.pen.pre + 1) : 0;
+    const int wl = (walk_lds ? ((lds_bytes + 15) & ~15) : 0) + segs;
     if (walk_lds && rows16)
-        hipLaunchKernelGGL((k_general_walk<true, int16_t>), grid, walk, lds_bytes, s, a);
+        hipLaunchKernelGGL((k_general_walk<true, int16_t>), grid, walk, wl, s, a);
     else if (walk_lds)
-        hipLaunchKernelGGL((k_general_walk<true, int32_t>), grid, walk, lds_bytes, s, a);
+        hipLaunchKernelGGL((k_general_walk<true, int32_t>), grid, walk, wl, s, a);
     else if (rows16)
-        hipLaunchKernelGGL((k_general_walk<false, int16_t>), grid, walk, 0, s, a);
+        hipLaunchKernelGGL((k_general_walk<false, int16_t>), grid, walk, wl, s, a);
     else
-        hipLaunchKernelGGL((k_general_walk<false, int32_t>), grid, walk, 0, s, a);
+        hipLaunchKernelGGL((k_general_walk<false, int32_t>), grid, walk, wl, s, a);
     return hipGetLastError();
 }
 
