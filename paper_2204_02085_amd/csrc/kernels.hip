@@ -1067,7 +1067,6 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
         for (long long i = tid; i < cnt; i += BT) ring[i] = (RowT)RNUL;
     }
     __syncthreads();
-    const RowT* nullrow = (const RowT*)(slice + R * full_row) + n + 1;
     // a hard bound on steps: deleting all of P and inserting all of T (or a
     // lower limit the host asks for)
     long long max_score_g = (2LL * (OE - E) + (long long)(n + m) * E) + 2;
@@ -1128,6 +1127,16 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             RowT* rowM = (RowT*)(slice + off) + n + 1;
             RowT* rowI = rowM + FW;
             RowT* rowD = rowI + FW;
+            // Ring cells are addressed from scalar slot bases with 32-bit byte
+            // offsets (diagonal k at (k + n + 1) * sizeof(RowT)), so each
+            // access is a global load or store with an SGPR base and a VGPR
+            // offset, not 64-bit vector address arithmetic.
+            unsigned char* wbase = slice + off;
+            auto rd = [](const unsigned char* base, uint32_t bo) -> int {
+                return *(const RowT*)(base + bo);
+            };
+            auto wr = [](unsigned char* base, uint32_t bo, RowT v) { *(RowT*)(base + bo) = v; };
+            const uint32_t rowb = (uint32_t)FW * (uint32_t)sizeof(RowT);  // bytes per row
             {  // the slot's previous values outside [lo, hi] become NULL
                 const int plo = wr_lo[rs], phi = wr_hi[rs];
                 for (int k = plo + tid; k <= phi && k < lo; k += BT)
@@ -1137,12 +1146,19 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             }
             unsigned char* histM = full_hist ? slice + hoff : nullptr;
             uint8_t* histF = full_hist ? histM + (long long)hbytes * w : nullptr;
-            // source components (M of s - x and s - o - e, I and D of s - e),
-            // indexed by diagonal; an absent step reads the NULL slot
-            const RowT* MX = sx.off >= 0 ? (const RowT*)(slice + sx.off) + n + 1 : nullrow;
-            const RowT* MO = so.off >= 0 ? (const RowT*)(slice + so.off) + n + 1 : nullrow;
-            const RowT* IE = (se.off >= 0 ? (const RowT*)(slice + se.off) + n + 1 : nullrow) + FW;
-            const RowT* DE = IE + FW;
+            // source components (M of s - x and s - o - e, I and D of s - e):
+            // the ring slot of step t is t mod R; an absent step reads the
+            // NULL slot R
+            const int slx = __builtin_amdgcn_readfirstlane(
+                sx.off >= 0 ? rs - X + (rs < X ? R : 0) : R);
+            const int slo = __builtin_amdgcn_readfirstlane(
+                so.off >= 0 ? rs - OE + (rs < OE ? R : 0) : R);
+            const int sle = __builtin_amdgcn_readfirstlane(
+                se.off >= 0 ? rs - E + (rs < E ? R : 0) : R);
+            const unsigned char* MXb = slice + (long long)slx * full_row;
+            const unsigned char* MOb = slice + (long long)slo * full_row;
+            const unsigned char* IEb = slice + (long long)sle * full_row + rowb;
+            const unsigned char* DEb = IEb + rowb;
             // one cell from its five source offsets
             auto cell = [&](int k, int va, int vb, int vc, int ve, int vx) {
                 int mval;
@@ -1157,9 +1173,10 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
                     rec = c.rec;
                 }
                 if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
-                rowM[k] = (RowT)(mval < 0 ? RNUL : mval);
-                rowI[k] = (RowT)(ival < 0 ? RNUL : ival);
-                rowD[k] = (RowT)(dval < 0 ? RNUL : dval);
+                const uint32_t bo = (uint32_t)(k + n + 1) * (uint32_t)sizeof(RowT);
+                wr(wbase, bo, (RowT)(mval < 0 ? RNUL : mval));
+                wr(wbase, bo + rowb, (RowT)(ival < 0 ? RNUL : ival));
+                wr(wbase, bo + 2 * rowb, (RowT)(dval < 0 ? RNUL : dval));
                 if (full_hist) {
                     if (h16)
                         ((uint16_t*)histM)[k - lo] = mval < 0 ? (uint16_t)0xFFFF : (uint16_t)mval;
@@ -1183,15 +1200,17 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
             // two cells per thread and pass: both cells' sources are read
             // before either is computed, so their latencies overlap (a second
             // cell past hi reads in-range sources and is dropped)
+            constexpr uint32_t RB = (uint32_t)sizeof(RowT);
             for (int k0 = lo + tid; k0 <= hi; k0 += 2 * BT) {
                 const int k1 = k0 + BT;
                 const int k1r = min(k1, hi);
-                const int a0 = MO[k0 - 1], b0 = IE[k0 - 1], c0 = MO[k0 + 1], e0 = DE[k0 + 1],
-                          x0 = MX[k0];
-                const int a1 = MO[k1r - 1], b1 = IE[k1r - 1], c1 = MO[k1r + 1], e1 = DE[k1r + 1],
-                          x1 = MX[k1r];
-                cell(k0, a0, b0, c0, e0, x0);
-                if (k1 <= hi) cell(k1, a1, b1, c1, e1, x1);
+                const uint32_t b0 = (uint32_t)(k0 + n + 1) * RB, b1 = (uint32_t)(k1r + n + 1) * RB;
+                const int a0 = rd(MOb, b0 - RB), c0 = rd(MOb, b0 + RB), x0 = rd(MXb, b0),
+                          i0 = rd(IEb, b0 - RB), e0 = rd(DEb, b0 + RB);
+                const int a1 = rd(MOb, b1 - RB), c1 = rd(MOb, b1 + RB), x1 = rd(MXb, b1),
+                          i1 = rd(IEb, b1 - RB), e1 = rd(DEb, b1 + RB);
+                cell(k0, a0, i0, c0, e0, x0);
+                if (k1 <= hi) cell(k1, a1, i1, c1, e1, x1);
             }
         }
         // the range later steps read (the WF-adaptive reduction may narrow it;
