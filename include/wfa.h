@@ -65,10 +65,17 @@
  * functions are thread-safe.
  *
  * Errors.  Every int-returning function returns WFA_OK (0) or a negative
- * WFA_E_* code; wfa_strerror gives its text.  On a validation error nothing
- * is written except *bad_pair, with one exception: a host-memory batch
- * checks its bytes chunk by chunk, so WFA_E_ALPHABET may leave the scores
- * and offsets of the chunks before the offending one written.
+ * WFA_E_* code; wfa_strerror gives its text.  On a validation error found on
+ * the host (WFA_E_INVAL, WFA_E_CAPACITY's size check aside) nothing is
+ * written except *bad_pair.  WFA_E_ALPHABET and WFA_E_TOO_LONG are found by
+ * kernels, which may already have written scores, offsets and runs; their
+ * contents are then unspecified.
+ *
+ * Plan reuse.  A call whose buffers (pointers), pair count, run capacity,
+ * 2-bit packed input and settings equal the previous call's on the context
+ * starts that call's launch before its batch facts are read back, and keeps
+ * the results if the facts lead to the same plan; otherwise it runs again as
+ * planned.  Results never depend on it.
  */
 #ifndef WFA_H
 #define WFA_H

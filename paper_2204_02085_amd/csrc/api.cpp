@@ -168,6 +168,12 @@ int engine_init(Engine* e, int device, size_t budget) {
         else (void)hipGetLastError();
     }
     e->ws.budget = budget ? budget : (total_mem ? total_mem / 4 * 3 : ((size_t)64 << 30));
+    he = hipHostMalloc(&e->readback, 256, hipHostMallocDefault);
+    if (he != hipSuccess) {
+        std::fprintf(stderr, "libwfa: hipHostMalloc -> %s\n", hipGetErrorString(he));
+        e->readback = nullptr;
+        return WFA_E_DEVICE;
+    }
     // default priority: every stream of the library runs at the same priority
     he = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking);
     if (he != hipSuccess) {
@@ -200,6 +206,8 @@ void engine_destroy(Engine* e) {
     e->ws.release_all();
     for (auto& ev : e->ev)
         if (ev) (void)hipEventDestroy(ev);
+    if (e->readback) (void)hipHostFree(e->readback);
+    e->readback = nullptr;
     if (e->stream) (void)hipStreamDestroy(e->stream);
     if (e->h2d) (void)hipStreamDestroy(e->h2d);
     if (e->d2h) (void)hipStreamDestroy(e->d2h);

@@ -2,8 +2,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <memory>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -124,6 +126,22 @@ struct Engine {
     wfa_options opt{};
     wfa::Ends ends{};  // free ends of later calls (all zero: global alignment)
     wfa::Heuristic heur{};  // WF-adaptive heuristic of later calls (mwl 0: exact)
+    // page-locked landing slots for the device path's small read-backs (batch
+    // facts, flags and run total), so those copies are asynchronous and one
+    // stream synchronisation ends each round trip
+    void* readback = nullptr;
+    // The last call's whole-pass graph and what it was planned under: a call
+    // with the same buffers, sizes, packed input and settings launches that
+    // graph right behind the batch-facts kernel, before the facts are back,
+    // and keeps its results when the facts lead to the same plan (any plan
+    // aligns any batch exactly; only its speed depends on the facts).
+    struct Spec {
+        bool valid = false;
+        GraphKey key;
+        wfa_options opt{};
+        wfa::Ends ends{};
+        wfa::Heuristic heur{};
+    } spec;
     wfa_stats last{};
     std::vector<GraphEntry> graphs;
     // state kept for wfa_copy_last_cigars
@@ -142,6 +160,16 @@ struct wfa_ctx : Engine {
     std::vector<std::unique_ptr<Engine>> idle;
     std::unique_ptr<Engine> fixed;
 };
+
+// Diagnostics level from WFA_DEBUG (unset or 0: none; 1: plans and passes;
+// 2: also host time per phase of every device-path call), read once.
+inline int debug_level() {
+    static const int level = [] {
+        const char* v = std::getenv("WFA_DEBUG");
+        return v ? std::max(1, std::atoi(v)) : 0;
+    }();
+    return level;
+}
 
 // Allocation-free entry point: the device address of the static scratch
 // array (resolved once per device at context creation) and its size.
