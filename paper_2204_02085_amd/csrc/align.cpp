@@ -472,8 +472,15 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     }
     GraphKey spec_key;
     BatchStats st;
-    HIPCHK(launch_batch_stats(in_pairs, N, ws.stats.as<BatchStats>(), WFA_MAX_LENGTH, s));
-    HIPCHK(hipMemcpyAsync(e->readback, ws.stats.ptr, sizeof(st), hipMemcpyDeviceToHost, s));
+    // with a speculative launch the batch facts run on the copy stream,
+    // beside the graph (both only read the inputs)
+    hipStream_t sf = spec_ent ? e->h2d : s;
+    if (spec_ent) {
+        HIPCHK(hipEventRecord(e->ev[9], s));  // after any wait on the caller's stream
+        HIPCHK(hipStreamWaitEvent(sf, e->ev[9], 0));
+    }
+    HIPCHK(launch_batch_stats(in_pairs, N, ws.stats.as<BatchStats>(), WFA_MAX_LENGTH, sf));
+    HIPCHK(hipMemcpyAsync(e->readback, ws.stats.ptr, sizeof(st), hipMemcpyDeviceToHost, sf));
     if (spec_ent) {
         spec_key = spec_ent->key;
         HIPCHK(hipEventRecord(e->ev[0], s));
@@ -483,6 +490,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         if (cigar)
             HIPCHK(hipMemcpyAsync(rb + sizeof(DevFlags), io.offsets + N, 8, hipMemcpyDeviceToHost,
                                   s));
+        HIPCHK(hipStreamSynchronize(sf));
     }
     e->spec.valid = false;  // set again once this call has planned and launched
     HIPCHK(hipStreamSynchronize(s));
