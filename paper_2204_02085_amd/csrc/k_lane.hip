@@ -34,7 +34,7 @@
 // byte, 0x80 for NULL) and its 4-bit decision record (source of M:
 // mismatch / end of insertion / end of deletion; whether I and D opened
 // from M), packed in the cells' compile-time order, then a stage for the
-// runs.  Keeping it out of LDS leaves room for three wavefronts per SIMD.
+// runs.  Keeping it out of LDS leaves room for four wavefronts per SIMD.
 // The backtrace is the short kernel's walk, run by every lane on its own
 // pair.
 //
@@ -345,11 +345,13 @@ struct LaneKernel {
     }
 };
 
-// At most 168 VGPRs (three wavefronts per SIMD): measured faster than the
-// compiler's own choice of up to 256 for the 16-step CIGAR form (2.0 against
-// 2.6 ms on 5 M pairs), the same for the smaller forms.
+// At most 128 VGPRs (four wavefronts per SIMD; the 16-step CIGAR form then
+// keeps 48 dwords per lane in scratch): on 5 M pairs at E = 4 % it took 1.85
+// ms against 1.91 ms at three wavefronts (168 VGPRs) and 2.08 ms at five,
+// in alternating runs on one device; the compiler's own choice of up to 256
+// VGPRs took 2.6 ms.
 template <int X, int OE, int E, int CAP, int LMAX, bool CIGAR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_lane(LaneArgs a,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_lane(LaneArgs a,
                                                                                     int persistent) {
     using K = LaneKernel<X, OE, E, CAP, LMAX, CIGAR>;
     extern __shared__ __align__(16) unsigned char lds[];
