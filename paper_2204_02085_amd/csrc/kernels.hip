@@ -234,6 +234,32 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_final(ScanKind kind, const void
     }
 }
 
+// A short scan (the bucket histogram): one block walks the tiles in order,
+// carrying the running total, and writes the total to out[n].
+constexpr size_t SCAN_SINGLE_MAX = 8 * (size_t)SCAN_TILE;
+__global__ __launch_bounds__(SCAN_T) void k_scan_single(ScanKind kind, const void* in, size_t n,
+                                                        uint64_t* out) {
+    uint64_t carry = 0;
+    for (size_t tile = 0; tile < n; tile += SCAN_TILE) {
+        const size_t base = tile + (size_t)threadIdx.x * SCAN_ITEMS;
+        uint64_t vals[SCAN_ITEMS];
+        uint64_t s = 0;
+        for (int j = 0; j < SCAN_ITEMS; j++) {
+            vals[j] = base + j < n ? scan_item(kind, in, base + j) : 0;
+            s += vals[j];
+        }
+        uint64_t incl = s;
+        const uint64_t total = block_inclusive_scan(incl);
+        uint64_t run = carry + incl - s;
+        for (int j = 0; j < SCAN_ITEMS; j++) {
+            if (base + j < n) out[base + j] = run;
+            run += vals[j];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 // ---------------------------------------------------------------------------
 // ASCII -> 2-bit packing.  One thread per output word (32 bases).
 // ---------------------------------------------------------------------------
@@ -1942,6 +1968,10 @@ hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, v
     uint64_t* bs = (uint64_t*)temp;
     if (nb == 0) {
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, out, 0ull, (size_t)1);
+        return hipGetLastError();
+    }
+    if (n <= SCAN_SINGLE_MAX) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN_T), 0, s, kind, in, n, out);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_partial, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs);
