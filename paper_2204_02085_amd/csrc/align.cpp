@@ -264,7 +264,11 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             const uint32_t lds_words = (head.n + 31) / 32 + 1 + (head.m + 31) / 32 + 1;
             const bool seq_lds = (uint64_t)lds_words * 8 <= 48 * 1024;
             const int lds_bytes = seq_lds ? (int)(lds_words * 8) : 0;
-            const int bt = max_len > 3000 ? 512 : (max_len > 600 ? 256 : 64);
+            // 256 threads per pair above 600 bases: a step's chain of ring reads,
+            // cells and barrier is latency-bound, so more pairs per CU beat more
+            // threads per pair (100 k pairs of 1-10 kbp: 446 ms against 568 ms
+            // with 512 threads and 1136 ms with 1024)
+            const int bt = max_len > 600 ? 256 : 64;
 
             std::vector<uint32_t> ids(nj);
             for (size_t i = 0; i < nj; i++) ids[i] = jobs[off + i].pair;
