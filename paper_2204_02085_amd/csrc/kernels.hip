@@ -991,6 +991,10 @@ __device__ __forceinline__ GenCell general_cell(int n, int m, int k, int va, int
     return c;
 }
 
+// LDS bytes of the general kernel's metadata ring and slot ranges for a ring
+// of R steps (16-byte aligned; the staged sequences follow)
+__host__ __device__ __forceinline__ int general_meta_lds(int R) { return (R * 24 + 15) & ~15; }
+
 // RowT: int16_t ring rows while every offset fits (texts shorter than 32767
 // bases), halving the ring's memory traffic, else int32_t.  Stored NULLs are
 // normalised to RNUL, so no NULL drifts up over many steps.
@@ -998,9 +1002,6 @@ template <bool SEQ_LDS, class RowT>
 __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr int MAXR = GENERAL_MAX_RING;  // metadata ring (pre + 1 <= MAXR)
-    __shared__ RowMeta meta[MAXR];
-    __shared__ int wr_lo[MAXR], wr_hi[MAXR];  // range of diagonals each ring slot holds
     __shared__ int sh_end;  // lowest diagonal whose M cell ends the alignment
     __shared__ int sh_fail;
     __shared__ int sh_dmin, sh_klo, sh_khi;  // WF-adaptive: least distance, kept range
@@ -1015,6 +1016,13 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     const int R = PRE + 1;
     // no walk for this job unless the forward pass below succeeds
     if (a.cigar && tid == 0) a.jstate[job].S = -1;
+    // dynamic LDS: the metadata ring (one entry per step of the ring), the
+    // range of diagonals each ring slot holds, then (SEQ_LDS) the sequences;
+    // sized to this penalty set's ring, so more workgroups fit on a CU
+    RowMeta* meta = (RowMeta*)lds;
+    int* wr_lo = (int*)(meta + R);
+    int* wr_hi = wr_lo + R;
+    unsigned char* seq_lds = lds + general_meta_lds(R);
     // free ends of this pair (global alignment: all zero)
     const int pb = min(a.ends.pb, n), pe = min(a.ends.pe, n);
     const int tb = min(a.ends.tb, m), te = min(a.ends.te, m);
@@ -1024,7 +1032,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     SeqView<SEQ_LDS> sv;
     const int nwp = (n + 31) >> 5, nwt = (m + 31) >> 5;
     if (SEQ_LDS) {
-        uint64_t* p64 = (uint64_t*)lds;
+        uint64_t* p64 = (uint64_t*)seq_lds;
         uint64_t* t64 = p64 + nwp + 1;
         for (int w = tid; w <= nwp; w += BT) p64[w] = w < nwp ? a.pw[desc.p_start + w] : 0ULL;
         for (int w = tid; w <= nwt; w += BT) t64[w] = w < nwt ? a.tw[desc.t_start + w] : 0ULL;
@@ -1036,7 +1044,7 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
     }
     sv.np32 = 2 * nwp;
     sv.nt32 = 2 * nwt;
-    for (int r = tid; r < MAXR; r += BT) {
+    for (int r = tid; r < R; r += BT) {
         meta[r] = RowMeta{0, -1, -1};
         wr_lo[r] = 0;
         wr_hi[r] = -1;
@@ -2095,14 +2103,15 @@ hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_l
                           bool rows16, hipStream_t s) {
     if (!a.num_jobs) return hipSuccess;
     const dim3 grid(a.num_jobs), walk(64);
+    const int ml = general_meta_lds(a.pen.pre + 1);
     if (seq_in_lds && rows16)
-        hipLaunchKernelGGL((k_general<true, int16_t>), grid, dim3(block_threads), lds_bytes, s, a);
+        hipLaunchKernelGGL((k_general<true, int16_t>), grid, dim3(block_threads), ml + lds_bytes, s, a);
     else if (seq_in_lds)
-        hipLaunchKernelGGL((k_general<true, int32_t>), grid, dim3(block_threads), lds_bytes, s, a);
+        hipLaunchKernelGGL((k_general<true, int32_t>), grid, dim3(block_threads), ml + lds_bytes, s, a);
     else if (rows16)
-        hipLaunchKernelGGL((k_general<false, int16_t>), grid, dim3(block_threads), 0, s, a);
+        hipLaunchKernelGGL((k_general<false, int16_t>), grid, dim3(block_threads), ml, s, a);
     else
-        hipLaunchKernelGGL((k_general<false, int32_t>), grid, dim3(block_threads), 0, s, a);
+        hipLaunchKernelGGL((k_general<false, int32_t>), grid, dim3(block_threads), ml, s, a);
     if (!a.cigar) return hipGetLastError();
     // the walks, one wavefront per pair; checkpoint mode stages the sequences
     // in LDS as the forward pass did, followed by its segment rows' ranges
