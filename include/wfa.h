@@ -183,9 +183,9 @@ typedef struct {
                                  recomputes the steps in between during the
                                  backtrace (far less memory per pair, the same
                                  CIGAR); -1 keeps a history row of every step;
-                                 0: full history while the device memory
-                                 holds it for two pairs per compute unit,
-                                 checkpoints every 128 steps beyond */
+                                 0: full history when the device memory holds
+                                 it for every pair of the launch, checkpoints
+                                 every 128 steps beyond */
 } wfa_options;
 
 /* Ends-free alignment.  Up to pattern_begin_free leading pattern bases OR

@@ -149,9 +149,9 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
     // 2s + 1 diagonals at step s, so ~3 R rb sg^2 / ck bytes of checkpoints;
     // a segment buffer of (ck + R) rows of 2 (ck + R - 1) / e + 1 columns
     // (M, I, D and a record byte each); the step table and the runs.
-    // By default (general_checkpoint 0) a launch keeps the full history while
-    // the arena holds that for enough pairs to fill the device (two per
-    // compute unit); below that, checkpoints every 128 steps.
+    // By default (general_checkpoint 0) a launch keeps the full history when
+    // the arena holds that for every pair left, else checkpoints every 128
+    // steps.
     auto ck_for = [&](bool memory_bound) -> int {
         if (!cigar) return 0;
         int c = e->opt.general_checkpoint;
@@ -219,14 +219,16 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             const uint64_t rb = rows16 ? 2 : 4;
             const size_t others = ws.total - ws.arena.bytes;
             const size_t arena_cap = ws.budget > others ? (ws.budget - others) / 4 * 3 : 0;
-            // every pair gets a slice of its own size; full histories unless the
-            // arena cannot hold them for the longest pairs that fill the device
+            // every pair gets a slice of its own size; full histories when the
+            // arena holds them for every pair left (one launch), else
+            // checkpoints: they let the pairs run in one launch, whose tail is
+            // shorter than several launches' tails (100 k pairs of 1-10 kbp:
+            // 580 ms in one launch against 611 ms in six)
             const size_t left = std::min(jobs.size() - off, (size_t)1 << 20);
-            const size_t fill = std::min(left, (size_t)2 * e->num_cus);
-            double fill_bytes = 0;
-            for (size_t i = 0; i < fill; i++)
-                fill_bytes += (double)slice_for(jobs[off + i].n, jobs[off + i].m, mult, rb, 0);
-            const bool memory_bound = fill_bytes > (double)std::max(arena_cap, ws.arena.bytes);
+            double full_bytes = 0;
+            for (size_t i = 0; i < left; i++)
+                full_bytes += (double)slice_for(jobs[off + i].n, jobs[off + i].m, mult, rb, 0);
+            const bool memory_bound = full_bytes > (double)std::max(arena_cap, ws.arena.bytes);
             const int ck = ck_for(memory_bound);
             std::vector<uint64_t> soff(left + 1, 0);
             for (size_t i = 0; i < left; i++)
