@@ -998,8 +998,13 @@ __host__ __device__ __forceinline__ int general_meta_lds(int R) { return (R * 24
 // RowT: int16_t ring rows while every offset fits (texts shorter than 32767
 // bases), halving the ring's memory traffic, else int32_t.  Stored NULLs are
 // normalised to RNUL, so no NULL drifts up over many steps.
+// Eight wavefronts per SIMD (the compiler holds the kernel to 78 SGPRs; 106
+// left it at seven): more pairs resident hide more of each step's latency
+// (100 k pairs of 1-10 kbp: 425 against 443 ms score-only, 564 against 581 ms
+// with checkpoint CIGARs).
 template <bool SEQ_LDS, class RowT>
-__global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_general(
+    GeneralArgs a) {
     constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int sh_end;  // lowest diagonal whose M cell ends the alignment
@@ -1389,7 +1394,8 @@ __global__ __launch_bounds__(1024) void k_general(GeneralArgs a) {
 // recompute the segments of checkpoint mode.  The forward pass's workgroup
 // is free again while the walks run, many per compute unit.
 template <bool SEQ_LDS, class RowT>
-__global__ __launch_bounds__(64) void k_general_walk(GeneralArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_general_walk(
+    GeneralArgs a) {
     constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ long long sh_ws;
