@@ -266,11 +266,17 @@ int run_general(Engine* e, const Pen& pen, bool cigar, const Dev& d, const Batch
             const uint32_t lds_words = (head.n + 31) / 32 + 1 + (head.m + 31) / 32 + 1;
             const bool seq_lds = (uint64_t)lds_words * 8 <= 48 * 1024;
             const int lds_bytes = seq_lds ? (int)(lds_words * 8) : 0;
-            // 256 threads per pair above 600 bases: a step's chain of ring reads,
-            // cells and barrier is latency-bound, so more pairs per CU beat more
-            // threads per pair (100 k pairs of 1-10 kbp: 446 ms against 568 ms
-            // with 512 threads and 1136 ms with 1024)
-            const int bt = max_len > 600 ? 256 : 64;
+            // Threads per pair above 600 bases, by the pairs in the launch: a
+            // step's chain of ring reads, cells and barrier is latency-bound,
+            // so a launch with many pairs runs faster with more pairs per CU
+            // (100 k pairs of 1-10 kbp: 446 ms with 256 threads against 568 ms
+            // with 512 and 1136 ms with 1024), while one with few pairs ends
+            // when its longest pair does, sooner with more threads on it (1-10
+            // kbp: 256 pairs 12.1 ms with 1024 threads against 24.2 ms with
+            // 256; 4096 pairs 23.5 ms with 512 against 32.4 ms; 8192 pairs
+            // 36.4 ms with 256 against 44.6 ms with 512)
+            const size_t per_cu = (nj + e->num_cus - 1) / e->num_cus;
+            const int bt = max_len <= 600 ? 64 : per_cu <= 8 ? 1024 : per_cu <= 24 ? 512 : 256;
 
             std::vector<uint32_t> ids(nj);
             for (size_t i = 0; i < nj; i++) ids[i] = jobs[off + i].pair;
