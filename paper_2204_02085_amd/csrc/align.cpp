@@ -601,10 +601,11 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     if (bucket) {
         RCCHK(ws.ensure(ws.order, N * 4));
         RCCHK(ws.ensure(ws.keys, N * 4));
-        RCCHK(ws.ensure(ws.hist, BUCKET_KEYS * 4 + (BUCKET_KEYS + 1) * 8));
+        RCCHK(ws.ensure(ws.hist, BUCKET_KEYS * 8));
     }
-    // exclusive scan of the bucket histogram, after its BUCKET_KEYS counters
-    uint64_t* cursor = bucket ? (uint64_t*)(ws.hist.as<uint8_t>() + BUCKET_KEYS * 4) : nullptr;
+    // the bucket histogram, then the pairs of each key placed so far
+    uint32_t* hist = bucket ? ws.hist.as<uint32_t>() : nullptr;
+    uint32_t* taken = bucket ? hist + BUCKET_KEYS : nullptr;
     DevFlags* flags = ws.flags.as<DevFlags>();
 
     int grid = 1;
@@ -646,8 +647,16 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     // kernel, ev[1] end).
     // pre: counters, packing, bucketing
     auto phase_pre = [&](hipStream_t q) -> int {
-        HIPCHK(launch_fill_u32((uint32_t*)flags, 0u, sizeof(DevFlags) / 4, q));
-        HIPCHK(launch_fill_u64((uint64_t*)&flags->err_pair, ~0ull, 1, q));
+        // the counters, err_pair = ~0 (its two words first), the run counts,
+        // the lane queues and the bucket histogram, in one launch
+        static_assert(offsetof(DevFlags, err_pair) == 0, "err_pair leads DevFlags");
+        FillOps fill{};
+        fill.add((uint32_t*)flags, 2, ~0u);
+        fill.add((uint32_t*)flags + 2, sizeof(DevFlags) / 4 - 2, 0u);
+        fill.add(ws.nruns.as<uint32_t>(), N, 0u);
+        if (lane && persistent) fill.add(ws.lane_queues.as<uint32_t>(), LANE_QUEUES * 32, 0u);
+        if (use_short && bucket) fill.add(hist, 2 * BUCKET_KEYS, 0u);
+        HIPCHK(launch_fill_multi(fill, q));
         if (ascii) {
             if (!stride_p)
                 HIPCHK(launch_scan(SCAN_WORDS_P, in_pairs, N, ws.ws_p.as<uint64_t>(), ws.scan_tmp.ptr, q));
@@ -660,14 +669,10 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
                                      ws.words_p.as<uint64_t>(), ws.words_t.as<uint64_t>(),
                                      ws.packed_pairs.as<PairDesc>(), &flags->err_pair, q));
         }
-        HIPCHK(launch_fill_u32(ws.nruns.as<uint32_t>(), 0u, N, q));
-        if (lane && persistent)
-            HIPCHK(launch_fill_u32(ws.lane_queues.as<uint32_t>(), 0u, LANE_QUEUES * 32, q));
         if (use_short && bucket) {
-            HIPCHK(launch_bucket_keys(d.pairs, N, ws.keys.as<uint32_t>(), ws.hist.as<uint32_t>(), q));
-            HIPCHK(launch_scan(SCAN_U32, ws.hist.ptr, BUCKET_KEYS, cursor, ws.scan_tmp.ptr, q));
-            HIPCHK(launch_bucket_scatter(ws.keys.as<uint32_t>(), N, cursor, ws.order.as<uint32_t>(),
-                                         q));
+            HIPCHK(launch_bucket_keys(d.pairs, N, ws.keys.as<uint32_t>(), hist, q));
+            HIPCHK(launch_bucket_scatter(ws.keys.as<uint32_t>(), N, hist, taken,
+                                         ws.order.as<uint32_t>(), q));
         }
         return WFA_OK;
     };

@@ -158,6 +158,24 @@ hipError_t launch_batch_stats(const PairDesc* pairs, size_t n, BatchStats* out, 
                               hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+// Several fills in one launch: p[0..n) = v for each of up to FILL_OPS ranges
+// (the ranges must not overlap).
+constexpr int FILL_OPS = 8;
+struct FillOp {
+    uint32_t* p;
+    uint64_t n;
+    uint32_t v;
+};
+struct FillOps {
+    FillOp op[FILL_OPS];
+    int count;
+    void add(uint32_t* p, uint64_t n, uint32_t v) {  // a count past FILL_OPS fails the launch
+        if (!n) return;
+        if (count < FILL_OPS) op[count] = FillOp{p, n, v};
+        count++;
+    }
+};
+hipError_t launch_fill_multi(const FillOps& ops, hipStream_t s);
 // dst[i] = src[i] + add for i < n
 hipError_t launch_add_u64(const uint64_t* src, uint64_t add, size_t n, uint64_t* dst,
                           hipStream_t s);
@@ -225,13 +243,15 @@ hipError_t launch_compact(const uint64_t* run_src, const uint32_t* slots, const 
                           const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
                           uint32_t* out, uint64_t capacity, hipStream_t s);
 
-// Counting sort of pairs by expected work: keys + histogram, then (after an
-// exclusive scan of the histogram into `cursor`) the scatter into `order`.
+// Counting sort of pairs by expected work: keys + histogram, then the
+// scatter into `order` (each block takes the exclusive scan of the histogram
+// itself and reserves its ranges through `taken`).  `hist` and `taken`
+// (BUCKET_KEYS words each) must be zero before the keys kernel.
 constexpr int BUCKET_KEYS = 4096;
 hipError_t launch_bucket_keys(const PairDesc* pairs, size_t n, uint32_t* keys, uint32_t* hist,
                               hipStream_t s);
-hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, uint64_t* cursor, uint32_t* order,
-                                 hipStream_t s);
+hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, const uint32_t* hist,
+                                 uint32_t* taken, uint32_t* order, hipStream_t s);
 // Gather runs of finished general jobs from the arena into gen_runs.
 // out[2i], out[2i+1] = lengths of pair idx[i] (pattern, text)
 hipError_t launch_pair_lengths(const PairDesc* pairs, const uint32_t* idx, size_t n, uint32_t* out,

@@ -155,6 +155,27 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
         p[i] = v;
 }
 
+// One launch for several fills.  Every thread walks the ranges in turn (the
+// loop over ranges is uniform), storing four words at a time where a range
+// starts on a 16-byte boundary.
+__global__ __launch_bounds__(256) void k_fill_multi(FillOps ops) {
+    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (int o = 0; o < ops.count; o++) {
+        uint32_t* p = ops.op[o].p;
+        const uint64_t n = ops.op[o].n;
+        const uint32_t v = ops.op[o].v;
+        uint64_t head = 0;
+        if (((uintptr_t)p & 15) == 0) {
+            const uint64_t n4 = n / 4;
+            const uint4 w = make_uint4(v, v, v, v);
+            for (uint64_t i = tid; i < n4; i += stride) ((uint4*)p)[i] = w;
+            head = n4 * 4;
+        }
+        for (uint64_t i = head + tid; i < n; i += stride) p[i] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // exclusive scan: tile of SCAN_T threads x SCAN_ITEMS items
 // ---------------------------------------------------------------------------
@@ -191,47 +212,40 @@ __device__ uint64_t block_inclusive_scan(uint64_t& v) {
     return total;
 }
 
+// Two passes over tiles of SCAN_TILE items.  Thread t of a tile takes items
+// t, t + SCAN_T, ... (each load and store of a wavefront is one contiguous
+// run); the first pass writes each tile's total, the second scans the tile
+// in SCAN_ITEMS block-wide rounds on top of the totals of the tiles before
+// it, which every block sums for itself.
 __global__ __launch_bounds__(SCAN_T) void k_scan_partial(ScanKind kind, const void* in, size_t n,
                                                          uint64_t* block_sums) {
-    const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + threadIdx.x;
     uint64_t s = 0;
-    for (int j = 0; j < SCAN_ITEMS; j++)
-        if (base + j < n) s += scan_item(kind, in, base + j);
-    uint64_t total = block_inclusive_scan(s);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(uint64_t* block_sums, size_t nb,
-                                                        uint64_t* out_total) {
-    uint64_t carry = 0;
-    for (size_t base = 0; base < nb; base += SCAN_T) {
-        const size_t i = base + threadIdx.x;
-        uint64_t v = i < nb ? block_sums[i] : 0;
-        const uint64_t mine = v;
-        uint64_t total = block_inclusive_scan(v);
-        if (i < nb) block_sums[i] = carry + v - mine;  // exclusive
-        carry += total;
-        __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        const size_t i = base + (size_t)j * SCAN_T;
+        if (i < n) s += scan_item(kind, in, i);
     }
-    if (threadIdx.x == 0) *out_total = carry;
+    const uint64_t total = block_inclusive_scan(s);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(SCAN_T) void k_scan_final(ScanKind kind, const void* in, size_t n,
                                                        const uint64_t* block_sums, uint64_t* out) {
-    const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
-    uint64_t vals[SCAN_ITEMS];
-    uint64_t s = 0;
+    uint64_t before = 0;
+    for (size_t b = threadIdx.x; b < blockIdx.x; b += SCAN_T) before += block_sums[b];
+    uint64_t carry = block_inclusive_scan(before);  // the block total: tiles before this one
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+#pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
-        vals[j] = base + j < n ? scan_item(kind, in, base + j) : 0;
-        s += vals[j];
+        const size_t i = base + (size_t)j * SCAN_T;
+        const uint64_t v = i < n ? scan_item(kind, in, i) : 0;
+        uint64_t incl = v;
+        const uint64_t total = block_inclusive_scan(incl);
+        if (i < n) out[i] = carry + incl - v;
+        carry += total;
     }
-    uint64_t incl = s;
-    block_inclusive_scan(incl);
-    uint64_t run = block_sums[blockIdx.x] + incl - s;
-    for (int j = 0; j < SCAN_ITEMS; j++) {
-        if (base + j < n) out[base + j] = run;
-        run += vals[j];
-    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = carry;
 }
 
 // A short scan (the bucket histogram): one block walks the tiles in order,
@@ -1906,25 +1920,47 @@ __global__ __launch_bounds__(256) void k_bucket_keys(const PairDesc* __restrict_
         if (local[i]) atomicAdd(&hist[i], local[i]);
 }
 
-// cursor[key] starts as the exclusive scan of the histogram; each block
-// reserves one range per key it holds and places its pairs inside it.
+// Each block takes the exclusive scan of the whole histogram (the first
+// pair of each key's range) into LDS, reserves one range per key it holds
+// by adding its count to `taken` (the pairs of that key placed so far), and
+// places its pairs inside those ranges.
+constexpr int BUCKET_PER_THREAD = BUCKET_KEYS / 256;
 __global__ __launch_bounds__(256) void k_bucket_scatter(const uint32_t* __restrict__ keys, size_t n,
-                                                        unsigned long long* __restrict__ cursor,
+                                                        const uint32_t* __restrict__ hist,
+                                                        uint32_t* __restrict__ taken,
                                                         uint32_t* __restrict__ order) {
     __shared__ uint32_t count[BUCKET_KEYS];
-    __shared__ unsigned long long start[BUCKET_KEYS];
-    for (int i = threadIdx.x; i < BUCKET_KEYS; i += blockDim.x) count[i] = 0;
+    __shared__ uint32_t start[BUCKET_KEYS];
+    const int t = threadIdx.x;
+    for (int i = t; i < BUCKET_KEYS; i += 256) count[i] = 0;
+    {
+        uint32_t h[BUCKET_PER_THREAD];
+        uint64_t own = 0;
+#pragma unroll
+        for (int j = 0; j < BUCKET_PER_THREAD; j++) {
+            h[j] = hist[t * BUCKET_PER_THREAD + j];
+            own += h[j];
+        }
+        uint64_t incl = own;
+        block_inclusive_scan(incl);
+        uint32_t run = (uint32_t)(incl - own);
+#pragma unroll
+        for (int j = 0; j < BUCKET_PER_THREAD; j++) {
+            start[t * BUCKET_PER_THREAD + j] = run;
+            run += h[j];
+        }
+    }
     __syncthreads();
     const size_t base = (size_t)blockIdx.x * BUCKET_CHUNK;
     const size_t end = min(n, base + BUCKET_CHUNK);
-    for (size_t i = base + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&count[keys[i]], 1u);
+    for (size_t i = base + t; i < end; i += 256) atomicAdd(&count[keys[i]], 1u);
     __syncthreads();
-    for (int i = threadIdx.x; i < BUCKET_KEYS; i += blockDim.x) {
-        start[i] = count[i] ? atomicAdd(&cursor[i], (unsigned long long)count[i]) : 0ull;
+    for (int i = t; i < BUCKET_KEYS; i += 256) {
+        if (count[i]) start[i] += atomicAdd(&taken[i], count[i]);
         count[i] = 0;
     }
     __syncthreads();
-    for (size_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+    for (size_t i = base + t; i < end; i += 256) {
         const uint32_t key = keys[i];
         const uint32_t r = atomicAdd(&count[key], 1u);
         order[start[key] + r] = (uint32_t)i;
@@ -1968,6 +2004,16 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_fill_multi(const FillOps& ops, hipStream_t s) {
+    if (ops.count < 0 || ops.count > FILL_OPS) return hipErrorInvalidValue;
+    uint64_t total = 0;
+    for (int o = 0; o < ops.count; o++) total += ops.op[o].n;
+    if (total)
+        hipLaunchKernelGGL(k_fill_multi, dim3(grid_for((total + 3) / 4, 256, 2048)), dim3(256), 0, s,
+                           ops);
+    return hipGetLastError();
+}
+
 hipError_t launch_add_u64(const uint64_t* src, uint64_t add, size_t n, uint64_t* dst,
                           hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_add_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, src, add, n, dst);
@@ -1989,7 +2035,6 @@ hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, v
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_partial, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, s, bs, nb, out + n);
     hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs, out);
     return hipGetLastError();
 }
@@ -2163,19 +2208,18 @@ hipError_t launch_compact(const uint64_t* run_src, const uint32_t* slots, const 
 
 hipError_t launch_bucket_keys(const PairDesc* pairs, size_t n, uint32_t* keys, uint32_t* hist,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, s, hist, 0u, (size_t)BUCKET_KEYS);
     const size_t blocks = (n + BUCKET_CHUNK - 1) / BUCKET_CHUNK;
     if (n)
         hipLaunchKernelGGL(k_bucket_keys, dim3(blocks), dim3(256), 0, s, pairs, n, keys, hist);
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, uint64_t* cursor, uint32_t* order,
-                                 hipStream_t s) {
+hipError_t launch_bucket_scatter(const uint32_t* keys, size_t n, const uint32_t* hist,
+                                 uint32_t* taken, uint32_t* order, hipStream_t s) {
     const size_t blocks = (n + BUCKET_CHUNK - 1) / BUCKET_CHUNK;
     if (n)
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, s, keys, n,
-                           (unsigned long long*)cursor, order);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, s, keys, n, hist, taken,
+                           order);
     return hipGetLastError();
 }
 
