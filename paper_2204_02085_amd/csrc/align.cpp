@@ -459,8 +459,8 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     // ---- batch facts -------------------------------------------------------
     RCCHK(ws.ensure(ws.stats, sizeof(BatchStats) * (1 + STATS_BLOCKS)));
     RCCHK(ws.ensure(ws.flags, sizeof(DevFlags)));
-    static_assert(sizeof(BatchStats) <= 128 && sizeof(DevFlags) + 8 <= 128, "read-back slots");
-    unsigned char* rb = (unsigned char*)e->readback + 128;  // flags, then the run total
+    static_assert(sizeof(BatchStats) <= 128 && sizeof(DevFlags) <= 128, "read-back slots");
+    unsigned char* rb = (unsigned char*)e->readback + 128;  // the flags (with the run total)
     // Speculative start: the previous call's whole-pass graph, if this call
     // matches everything that graph was planned under except the batch facts
     // (packed input, so no packing depends on them); kept below only if the
@@ -499,9 +499,6 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
         HIPCHK(hipGraphLaunch(spec_ent->exec_all, s));
         HIPCHK(hipEventRecord(e->ev[1], s));
         HIPCHK(hipMemcpyAsync(rb, ws.flags.ptr, sizeof(DevFlags), hipMemcpyDeviceToHost, s));
-        if (cigar)
-            HIPCHK(hipMemcpyAsync(rb + sizeof(DevFlags), io.offsets + N, 8, hipMemcpyDeviceToHost,
-                                  s));
         HIPCHK(hipStreamSynchronize(sf));
     }
     e->spec.valid = false;  // set again once this call has planned and launched
@@ -735,7 +732,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                   ws.gen_runs.as<uint32_t>(), d.offsets,
-                                  N, d.runs, d.capacity, q));
+                                  N, d.runs, d.capacity, &flags->total_runs, q));
         }
         return WFA_OK;
     };
@@ -815,11 +812,9 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             if (hit) HIPCHK(hipGraphLaunch(hit->exec_post, s)); else RCCHK(phase_post(s));
         }
         HIPCHK(hipEventRecord(e->ev[1], s));
+        // the run total of the short kernel's pairs (written by the
+        // compaction into total_runs) comes back with the flags
         HIPCHK(hipMemcpyAsync(rb, flags, sizeof(DevFlags), hipMemcpyDeviceToHost, s));
-        // the run total of the short kernel's pairs comes back with the flags
-        if (cigar && use_short)
-            HIPCHK(hipMemcpyAsync(rb + sizeof(DevFlags), d.offsets + N, 8, hipMemcpyDeviceToHost,
-                                  s));
         t_launched = now_ms();
         HIPCHK(hipStreamSynchronize(s));
     }
@@ -834,7 +829,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     DevFlags fl;
     uint64_t short_total = 0;
     std::memcpy(&fl, rb, sizeof(fl));
-    if (cigar && use_short) std::memcpy(&short_total, rb + sizeof(fl), 8);
+    if (cigar && use_short) short_total = fl.total_runs;
     if (fl.err_pair != ~0ull) {
         if (bad_pair) *bad_pair = (int64_t)fl.err_pair;
         return WFA_E_ALPHABET;
@@ -962,7 +957,7 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
             HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                   ws.gen_runs.as<uint32_t>(), d.offsets, N,
-                                  d.runs, d.capacity, s));
+                                  d.runs, d.capacity, nullptr, s));
         if (cigar_needed) *cigar_needed = (size_t)total;
     }
     if (tail) HIPCHK(hipEventRecord(e->ev[8], s));

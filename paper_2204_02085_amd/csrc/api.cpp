@@ -449,7 +449,7 @@ extern "C" int wfa_copy_last_cigars(wfa_ctx* ctx, uint32_t* runs, size_t capacit
         API_HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                   ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                   ws.gen_runs.as<uint32_t>(), off, N, runs,
-                                  capacity, s));
+                                  capacity, nullptr, s));
         if (offsets)
             API_HIPCHK(hipMemcpyAsync(offsets, off, (N + 1) * 8, hipMemcpyDeviceToDevice, s));
     } else {

@@ -81,7 +81,7 @@ struct DevFlags {
     uint32_t ovf_count2;          // pairs a cascade pass (a wider short pass) handed over
     uint32_t queue2;              // queue head of a cascade pass
     uint32_t pad;
-    uint64_t total_runs;          // exclusive-scan total of per-pair runs
+    uint64_t total_runs;          // run total of the first pass (written by the compaction)
     unsigned long long gave_up;   // first pair the general kernel gave up on (~0: none)
 };
 

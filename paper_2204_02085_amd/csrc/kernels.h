@@ -239,9 +239,11 @@ hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_l
 // SLOTS2_BIT set, or into `gen_runs` with GEN_BIT set
 constexpr uint64_t GEN_BIT = 1ULL << 63;
 constexpr uint64_t SLOTS2_BIT = 1ULL << 62;
+// total_out (may be null) receives offsets[n], the run total, whether or not
+// it fits the capacity.
 hipError_t launch_compact(const uint64_t* run_src, const uint32_t* slots, const uint32_t* slots2,
                           const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
-                          uint32_t* out, uint64_t capacity, hipStream_t s);
+                          uint32_t* out, uint64_t capacity, uint64_t* total_out, hipStream_t s);
 
 // Counting sort of pairs by expected work: keys + histogram, then the
 // scatter into `order` (each block takes the exclusive scan of the histogram

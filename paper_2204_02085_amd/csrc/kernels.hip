@@ -1831,13 +1831,16 @@ __global__ void k_pair_lengths(const PairDesc* __restrict__ pairs, const uint32_
 // the total exceeds the capacity).  A block takes COMPACT_PAIRS consecutive
 // pairs and fills their whole output range [offsets[first], offsets[first +
 // COMPACT_PAIRS]) with consecutive threads on consecutive runs, so every
-// store is coalesced.  A thread finds the pair of output position q by a
-// binary search over the tile's run ends in LDS; the pair's runs sit in its
-// slot in backtrace order, so position q takes slot entry end - 1 - q.
-// Reads stay scattered across pairs (slots follow the bucketed order), but
-// a wave's 64 positions touch only the few pairs they belong to.
+// store is coalesced.  The pair of each output position comes from an LDS
+// table that every pair's thread fills over its own range (one byte per run,
+// the pair's index in the tile); a tile with more runs than the table holds
+// finds it by a binary search over the run ends instead.  A pair's runs sit
+// in its slot in backtrace order, so position q takes slot entry end - 1 - q.
+// Reads stay scattered across pairs (slots follow the bucketed order), but a
+// wave's 64 positions touch only the few pairs they belong to.
 constexpr int COMPACT_PAIRS = 256;
 constexpr int COMPACT_UNROLL = 4;
+constexpr int COMPACT_OWNER = 16384;
 
 __global__ __launch_bounds__(COMPACT_PAIRS) void k_compact(const uint64_t* __restrict__ run_src,
                                                            const uint32_t* __restrict__ slots,
@@ -1845,42 +1848,70 @@ __global__ __launch_bounds__(COMPACT_PAIRS) void k_compact(const uint64_t* __res
                                                            const uint32_t* __restrict__ gen_runs,
                                                            const uint64_t* __restrict__ offsets,
                                                            size_t n, uint32_t* __restrict__ out,
-                                                           uint64_t capacity) {
+                                                           uint64_t capacity,
+                                                           uint64_t* __restrict__ total_out) {
     __shared__ uint64_t end[COMPACT_PAIRS];
     __shared__ const uint32_t* src_of[COMPACT_PAIRS];
+    __shared__ uint8_t owner[COMPACT_OWNER];
+    if (total_out && blockIdx.x == 0 && threadIdx.x == 0) *total_out = offsets[n];
     if (offsets[n] > capacity) return;
     const int t = threadIdx.x;
     const size_t tiles = (n + COMPACT_PAIRS - 1) / COMPACT_PAIRS;
     for (size_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const size_t first = tile * COMPACT_PAIRS;
         const int np = (int)min((size_t)COMPACT_PAIRS, n - first);
+        const uint64_t lo = offsets[first], hi = offsets[first + np];
+        const bool table = hi - lo <= (uint64_t)COMPACT_OWNER;
         if (t < np) {
             const uint64_t src = run_src[first + t];
             const uint64_t off = src & ~(GEN_BIT | SLOTS2_BIT);
             src_of[t] = (src & GEN_BIT) ? gen_runs + off : ((src & SLOTS2_BIT) ? slots2 : slots) + off;
-            end[t] = offsets[first + t + 1];
+            const uint64_t e = offsets[first + t + 1];
+            end[t] = e;
+            if (table)
+                for (uint32_t r = (uint32_t)(offsets[first + t] - lo); r < (uint32_t)(e - lo); r++)
+                    owner[r] = (uint8_t)t;
         }
         __syncthreads();
-        const uint64_t lo = offsets[first], hi = end[np - 1];
-        for (uint64_t q0 = lo + t; q0 < hi; q0 += COMPACT_PAIRS * COMPACT_UNROLL) {
-            uint32_t v[COMPACT_UNROLL];
+        if (table) {
+            const uint32_t total = (uint32_t)(hi - lo);
+            for (uint32_t q0 = t; q0 < total; q0 += COMPACT_PAIRS * COMPACT_UNROLL) {
+                uint32_t v[COMPACT_UNROLL];
 #pragma unroll
-            for (int u = 0; u < COMPACT_UNROLL; u++) {
-                const uint64_t q = q0 + (uint64_t)u * COMPACT_PAIRS;
-                if (q < hi) {
-                    // p = number of tile pairs whose runs end at or before q
-                    // (ends never decrease); q < hi keeps p below np
-                    int p = 0;
+                for (int u = 0; u < COMPACT_UNROLL; u++) {
+                    const uint32_t q = q0 + (uint32_t)u * COMPACT_PAIRS;
+                    if (q < total) {
+                        const int p = owner[q];
+                        v[u] = src_of[p][(uint32_t)(end[p] - lo) - 1 - q];
+                    }
+                }
 #pragma unroll
-                    for (int step = COMPACT_PAIRS / 2; step; step >>= 1)
-                        if (p + step <= np && end[p + step - 1] <= q) p += step;
-                    v[u] = src_of[p][end[p] - 1 - q];
+                for (int u = 0; u < COMPACT_UNROLL; u++) {
+                    const uint32_t q = q0 + (uint32_t)u * COMPACT_PAIRS;
+                    if (q < total) out[lo + q] = v[u];
                 }
             }
+        } else {
+            for (uint64_t q0 = lo + t; q0 < hi; q0 += COMPACT_PAIRS * COMPACT_UNROLL) {
+                uint32_t v[COMPACT_UNROLL];
 #pragma unroll
-            for (int u = 0; u < COMPACT_UNROLL; u++) {
-                const uint64_t q = q0 + (uint64_t)u * COMPACT_PAIRS;
-                if (q < hi) out[q] = v[u];
+                for (int u = 0; u < COMPACT_UNROLL; u++) {
+                    const uint64_t q = q0 + (uint64_t)u * COMPACT_PAIRS;
+                    if (q < hi) {
+                        // p = number of tile pairs whose runs end at or before q
+                        // (ends never decrease); q < hi keeps p below np
+                        int p = 0;
+#pragma unroll
+                        for (int step = COMPACT_PAIRS / 2; step; step >>= 1)
+                            if (p + step <= np && end[p + step - 1] <= q) p += step;
+                        v[u] = src_of[p][end[p] - 1 - q];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < COMPACT_UNROLL; u++) {
+                    const uint64_t q = q0 + (uint64_t)u * COMPACT_PAIRS;
+                    if (q < hi) out[q] = v[u];
+                }
             }
         }
         __syncthreads();
@@ -2199,10 +2230,11 @@ hipError_t launch_pair_lengths(const PairDesc* pairs, const uint32_t* idx, size_
 
 hipError_t launch_compact(const uint64_t* run_src, const uint32_t* slots, const uint32_t* slots2,
                           const uint32_t* gen_runs, const uint64_t* offsets, size_t n,
-                          uint32_t* out, uint64_t capacity, hipStream_t s) {
+                          uint32_t* out, uint64_t capacity, uint64_t* total_out, hipStream_t s) {
     if (n)
         hipLaunchKernelGGL(k_compact, dim3(grid_for(n, COMPACT_PAIRS, 1 << 20)), dim3(COMPACT_PAIRS),
-                           0, s, run_src, slots, slots2, gen_runs, offsets, n, out, capacity);
+                           0, s, run_src, slots, slots2, gen_runs, offsets, n, out, capacity,
+                           total_out);
     return hipGetLastError();
 }
 

@@ -445,7 +445,8 @@ int engine_align_host(Engine* e, const BatchIO& io, hipStream_t user_stream, siz
                 HIPCHK(launch_compact(ws.run_src.as<uint64_t>(),
                                       ws.slots.as<uint32_t>(), ws.slots2.as<uint32_t>(),
                                       ws.gen_runs.as<uint32_t>(), ws.host_loff.as<uint64_t>(), c.n,
-                                      ws.out_runs.as<uint32_t>() + base, needed, e->stream));
+                                      ws.out_runs.as<uint32_t>() + base, needed, nullptr,
+                                      e->stream));
                 rc = WFA_OK;
             }
             if (rc != WFA_OK) {
