@@ -12,7 +12,9 @@
 //
 // Kernels:
 //   k_batch_stats   lengths and word counts of a batch (planning)
-//   k_scan_*        exclusive scan (word starts, CIGAR offsets)
+//   k_fill_*        fills (one launch for several ranges: k_fill_multi)
+//   k_scan_*        exclusive scan (word starts, CIGAR offsets, job offsets)
+//   k_bucket_*      counting sort of pairs by expected work
 //   k_pack_*        ASCII -> 2-bit little-endian words, alphabet check
 //   k_short         short pairs: a lane group owns a fixed window of
 //                   diagonals (one or more per lane); all wavefront rows of a
