@@ -485,22 +485,21 @@ int engine_align_device(Engine* e, const BatchIO& io, hipStream_t user_stream,
     GraphKey spec_key;
     BatchStats st;
     // with a speculative launch the batch facts run on the copy stream,
-    // beside the graph (both only read the inputs)
+    // beside the graph (both only read the inputs); the graph is submitted
+    // first, so the device starts it before the host queues the facts
     hipStream_t sf = spec_ent ? e->h2d : s;
     if (spec_ent) {
         HIPCHK(hipEventRecord(e->ev[9], s));  // after any wait on the caller's stream
-        HIPCHK(hipStreamWaitEvent(sf, e->ev[9], 0));
-    }
-    HIPCHK(launch_batch_stats(in_pairs, N, ws.stats.as<BatchStats>(), WFA_MAX_LENGTH, sf));
-    HIPCHK(hipMemcpyAsync(e->readback, ws.stats.ptr, sizeof(st), hipMemcpyDeviceToHost, sf));
-    if (spec_ent) {
         spec_key = spec_ent->key;
         HIPCHK(hipEventRecord(e->ev[0], s));
         HIPCHK(hipGraphLaunch(spec_ent->exec_all, s));
         HIPCHK(hipEventRecord(e->ev[1], s));
         HIPCHK(hipMemcpyAsync(rb, ws.flags.ptr, sizeof(DevFlags), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(sf));
+        HIPCHK(hipStreamWaitEvent(sf, e->ev[9], 0));
     }
+    HIPCHK(launch_batch_stats(in_pairs, N, ws.stats.as<BatchStats>(), WFA_MAX_LENGTH, sf));
+    HIPCHK(hipMemcpyAsync(e->readback, ws.stats.ptr, sizeof(st), hipMemcpyDeviceToHost, sf));
+    if (spec_ent) HIPCHK(hipStreamSynchronize(sf));
     e->spec.valid = false;  // set again once this call has planned and launched
     HIPCHK(hipStreamSynchronize(s));
     std::memcpy(&st, e->readback, sizeof(st));
