@@ -1018,7 +1018,9 @@ __host__ __device__ __forceinline__ int general_meta_lds(int R) { return (R * 24
 // left it at seven): more pairs resident hide more of each step's latency
 // (100 k pairs of 1-10 kbp: 425 against 443 ms score-only, 564 against 581 ms
 // with checkpoint CIGARs).
-template <bool SEQ_LDS, class RowT>
+// HIST: the launch keeps a history row per step (CIGAR without checkpoints);
+// the other forms compute no decision records.
+template <bool SEQ_LDS, class RowT, bool HIST>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_general(
     GeneralArgs a) {
     constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
@@ -1104,7 +1106,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // diagonals that can reach the walk's entry cell, into a segment buffer
     // of fixed size placed after the checkpoints.
     const int CK = a.cigar ? a.ckpt : 0;
-    const bool full_hist = a.cigar && CK == 0;
+    constexpr bool full_hist = HIST;  // the launcher picks HIST = cigar && CK == 0
     const int DMAX = CK ? (CK + R - 1) / E : 0;  // widest cone half-width
     const int WC = 2 * DMAX + 1;                 // cone columns
     const long long SEG_ROWB = ((long long)WC * (3 * (long long)sizeof(RowT) + 1) + 15) & ~15LL;
@@ -1225,14 +1227,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                     mval = c.m;
                     ival = c.i;
                     dval = c.d;
-                    rec = c.rec;
+                    if constexpr (HIST) rec = c.rec;
                 }
                 if (mval >= 0) mval = extend_general(sv, n, m, k, mval);
                 const uint32_t bo = (uint32_t)(k + n + 1) * (uint32_t)sizeof(RowT);
                 wr(wbase, bo, (RowT)(mval < 0 ? RNUL : mval));
                 wr(wbase, bo + rowb, (RowT)(ival < 0 ? RNUL : ival));
                 wr(wbase, bo + 2 * rowb, (RowT)(dval < 0 ? RNUL : dval));
-                if (full_hist) {
+                if constexpr (full_hist) {
                     if (h16)
                         ((uint16_t*)histM)[k - lo] = mval < 0 ? (uint16_t)0xFFFF : (uint16_t)mval;
                     else
@@ -2188,14 +2190,20 @@ hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_l
     if (!a.num_jobs) return hipSuccess;
     const dim3 grid(a.num_jobs), walk(64);
     const int ml = general_meta_lds(a.pen.pre + 1);
-    if (seq_in_lds && rows16)
-        hipLaunchKernelGGL((k_general<true, int16_t>), grid, dim3(block_threads), ml + lds_bytes, s, a);
-    else if (seq_in_lds)
-        hipLaunchKernelGGL((k_general<true, int32_t>), grid, dim3(block_threads), ml + lds_bytes, s, a);
-    else if (rows16)
-        hipLaunchKernelGGL((k_general<false, int16_t>), grid, dim3(block_threads), ml, s, a);
-    else
-        hipLaunchKernelGGL((k_general<false, int32_t>), grid, dim3(block_threads), ml, s, a);
+    const int fl = seq_in_lds ? ml + lds_bytes : ml;
+    const bool hist = a.cigar && a.ckpt == 0;
+#define WFA_GEN_LAUNCH(SL, RT, H) \
+    hipLaunchKernelGGL((k_general<SL, RT, H>), grid, dim3(block_threads), fl, s, a)
+    if (seq_in_lds && rows16) {
+        if (hist) WFA_GEN_LAUNCH(true, int16_t, true); else WFA_GEN_LAUNCH(true, int16_t, false);
+    } else if (seq_in_lds) {
+        if (hist) WFA_GEN_LAUNCH(true, int32_t, true); else WFA_GEN_LAUNCH(true, int32_t, false);
+    } else if (rows16) {
+        if (hist) WFA_GEN_LAUNCH(false, int16_t, true); else WFA_GEN_LAUNCH(false, int16_t, false);
+    } else {
+        if (hist) WFA_GEN_LAUNCH(false, int32_t, true); else WFA_GEN_LAUNCH(false, int32_t, false);
+    }
+#undef WFA_GEN_LAUNCH
     if (!a.cigar) return hipGetLastError();
     // the walks, one wavefront per pair; checkpoint mode stages the sequences
     // in LDS as the forward pass did, followed by its segment rows' ranges
