@@ -1019,8 +1019,9 @@ __host__ __device__ __forceinline__ int general_meta_lds(int R) { return (R * 24
 // (100 k pairs of 1-10 kbp: 425 against 443 ms score-only, 564 against 581 ms
 // with checkpoint CIGARs).
 // HIST: the launch keeps a history row per step (CIGAR without checkpoints);
-// the other forms compute no decision records.
-template <bool SEQ_LDS, class RowT, bool HIST>
+// the other forms compute no decision records.  FREE: some end is free
+// (global alignment ends on the one corner cell).
+template <bool SEQ_LDS, class RowT, bool HIST, bool FREE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_general(
     GeneralArgs a) {
     constexpr int RNUL = sizeof(RowT) == 2 ? -16384 : NUL32;
@@ -1250,9 +1251,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 // an end cell: the last text column with at most pe pattern
                 // bases left, or the last pattern row with at most te text
                 // bases left (global: the corner cell on diagonal m - n)
-                if (mval >= 0 && ((mval == m && mval - k >= n - pe) ||
-                                  (mval - k == n && mval >= m - te)))
-                    atomicMin(&sh_end, k);
+                bool at_end;
+                if constexpr (FREE)
+                    at_end = mval >= 0 && ((mval == m && mval - k >= n - pe) ||
+                                           (mval - k == n && mval >= m - te));
+                else
+                    at_end = k == m - n && mval == m;
+                if (at_end) atomicMin(&sh_end, k);
             };
             // two cells per thread and pass: both cells' sources are read
             // before either is computed, so their latencies overlap (a second
@@ -2192,17 +2197,21 @@ hipError_t launch_general(const GeneralArgs& a, int block_threads, bool seq_in_l
     const int ml = general_meta_lds(a.pen.pre + 1);
     const int fl = seq_in_lds ? ml + lds_bytes : ml;
     const bool hist = a.cigar && a.ckpt == 0;
-#define WFA_GEN_LAUNCH(SL, RT, H) \
-    hipLaunchKernelGGL((k_general<SL, RT, H>), grid, dim3(block_threads), fl, s, a)
+    const bool free_ends = (a.ends.pb | a.ends.pe | a.ends.tb | a.ends.te) != 0;
+#define WFA_GEN_LAUNCH(SL, RT, H, F) \
+    hipLaunchKernelGGL((k_general<SL, RT, H, F>), grid, dim3(block_threads), fl, s, a)
+#define WFA_GEN_LAUNCH2(SL, RT, H) \
+    if (free_ends) WFA_GEN_LAUNCH(SL, RT, H, true); else WFA_GEN_LAUNCH(SL, RT, H, false)
     if (seq_in_lds && rows16) {
-        if (hist) WFA_GEN_LAUNCH(true, int16_t, true); else WFA_GEN_LAUNCH(true, int16_t, false);
+        if (hist) { WFA_GEN_LAUNCH2(true, int16_t, true); } else { WFA_GEN_LAUNCH2(true, int16_t, false); }
     } else if (seq_in_lds) {
-        if (hist) WFA_GEN_LAUNCH(true, int32_t, true); else WFA_GEN_LAUNCH(true, int32_t, false);
+        if (hist) { WFA_GEN_LAUNCH2(true, int32_t, true); } else { WFA_GEN_LAUNCH2(true, int32_t, false); }
     } else if (rows16) {
-        if (hist) WFA_GEN_LAUNCH(false, int16_t, true); else WFA_GEN_LAUNCH(false, int16_t, false);
+        if (hist) { WFA_GEN_LAUNCH2(false, int16_t, true); } else { WFA_GEN_LAUNCH2(false, int16_t, false); }
     } else {
-        if (hist) WFA_GEN_LAUNCH(false, int32_t, true); else WFA_GEN_LAUNCH(false, int32_t, false);
+        if (hist) { WFA_GEN_LAUNCH2(false, int32_t, true); } else { WFA_GEN_LAUNCH2(false, int32_t, false); }
     }
+#undef WFA_GEN_LAUNCH2
 #undef WFA_GEN_LAUNCH
     if (!a.cigar) return hipGetLastError();
     // the walks, one wavefront per pair; checkpoint mode stages the sequences
