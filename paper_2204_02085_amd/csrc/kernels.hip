@@ -1542,8 +1542,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
                 if (kk < seg_a[rr] || kk > seg_b[rr]) return RNUL;
                 return rowp(rr)[comp * WC + (kk - kb)];
             };
+            // Every row holds NULL on the cone's columns outside its cells, so
+            // the recomputed cells read their sources without range tests: a
+            // source of step t' lies in the cone of t' (one more diagonal per
+            // e steps back), within the row's WC columns.
+            auto pad_row = [&](int r) {
+                const int dl = (int)((se - (t0 + r)) / E);
+                const int ca = ke - dl, cb = ke + dl;
+                const int sa = seg_a[r], sb = seg_b[r];
+                RowT* row = rowp(r);
+                const int na = sa <= sb ? min(sa, cb + 1) : cb + 1;  // [ca, na) before the cells
+                for (int kk = ca + tid; kk < na; kk += BT)
+                    row[kk - kb] = row[WC + kk - kb] = row[2 * WC + kk - kb] = (RowT)RNUL;
+                for (int kk = (sa <= sb ? max(sb + 1, ca) : cb + 1) + tid; kk <= cb; kk += BT)
+                    row[kk - kb] = row[WC + kk - kb] = row[2 * WC + kk - kb] = (RowT)RNUL;
+            };
+            auto src_in_cone = [&](long long ts, int comp, int kk) -> int {
+                if (ts < t0) return RNUL;
+                return rowp((int)(ts - t0))[comp * WC + (kk - kb)];
+            };
             if (b > 0) {  // the checkpoint's rows, within the cone
                 for (int r = 0; r < R; r++) {
+                    pad_row(r);
                     const int lo_ = seg_a[r], hi_ = seg_b[r];
                     if (lo_ > hi_) continue;
                     const RowMeta mm = table[-(t0 + r)];
@@ -1561,14 +1581,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
                 const int r = (int)(t - t0);
                 RowT* dM = rowp(r);
                 uint8_t* dF = (uint8_t*)(dM + 3 * WC);
+                pad_row(r);
                 for (int k = seg_a[r] + tid; k <= seg_b[r]; k += BT) {
                     int mval, ival = NUL32, dval = NUL32, rec = 0;
                     if (t == 0) {
                         mval = max(k, 0);
                     } else {
-                        const GenCell c = general_cell(n, m, k, src(t - OE, 0, k - 1),
-                                                       src(t - E, 1, k - 1), src(t - OE, 0, k + 1),
-                                                       src(t - E, 2, k + 1), src(t - X, 0, k));
+                        const GenCell c = general_cell(
+                            n, m, k, src_in_cone(t - OE, 0, k - 1), src_in_cone(t - E, 1, k - 1),
+                            src_in_cone(t - OE, 0, k + 1), src_in_cone(t - E, 2, k + 1),
+                            src_in_cone(t - X, 0, k));
                         mval = c.m;
                         ival = c.i;
                         dval = c.d;
