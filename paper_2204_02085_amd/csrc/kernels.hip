@@ -1373,10 +1373,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 const int w = mm.hi - mm.lo + 1;
                 const RowT* src = (const RowT*)(slice + mm.off) + n + 1 + mm.lo;
                 RowT* dst = (RowT*)(slice + bump);
-                for (int i = tid; i < 3 * w; i += BT) {
-                    const int c = i / w, kk = i - c * w;
-                    dst[i] = src[(long long)c * FW + kk];
-                }
+                for (int c = 0; c < 3; c++)
+                    for (int kk = tid; kk < w; kk += BT) dst[c * w + kk] = src[(long long)c * FW + kk];
                 if (tid == 0) table[-t].off = bump;
                 bump += (3LL * (long long)sizeof(RowT) * w + 15) & ~15LL;
             }
@@ -1570,10 +1568,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
                     const int w = mm.hi - mm.lo + 1, cnt = hi_ - lo_ + 1;
                     const RowT* from = (const RowT*)(slice + mm.off);
                     RowT* to = rowp(r);
-                    for (int i = tid; i < 3 * cnt; i += BT) {
-                        const int c = i / cnt, kk = lo_ + (i - c * cnt);
-                        to[c * WC + (kk - kb)] = from[(long long)c * w + (kk - mm.lo)];
-                    }
+                    for (int c = 0; c < 3; c++)
+                        for (int kk = lo_ + tid; kk <= hi_; kk += BT)
+                            to[c * WC + (kk - kb)] = from[(long long)c * w + (kk - mm.lo)];
                 }
                 __syncthreads();  // the first recomputed step reads these rows
             }
