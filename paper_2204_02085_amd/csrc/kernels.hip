@@ -232,11 +232,34 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_partial(ScanKind kind, const vo
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
+// Up to SCAN_SELF_MAX tiles each block of the second pass sums the totals of
+// the tiles before it itself; beyond, a one-block pass turns the totals into
+// exclusive prefixes first (the sums would grow with the square of the tiles).
+constexpr size_t SCAN_SELF_MAX = 8192;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(uint64_t* block_sums, size_t nb) {
+    uint64_t carry = 0;
+    for (size_t base = 0; base < nb; base += SCAN_T) {
+        const size_t i = base + threadIdx.x;
+        uint64_t v = i < nb ? block_sums[i] : 0;
+        const uint64_t mine = v;
+        const uint64_t total = block_inclusive_scan(v);
+        if (i < nb) block_sums[i] = carry + v - mine;  // exclusive
+        carry += total;
+    }
+}
+
 __global__ __launch_bounds__(SCAN_T) void k_scan_final(ScanKind kind, const void* in, size_t n,
-                                                       const uint64_t* block_sums, uint64_t* out) {
-    uint64_t before = 0;
-    for (size_t b = threadIdx.x; b < blockIdx.x; b += SCAN_T) before += block_sums[b];
-    uint64_t carry = block_inclusive_scan(before);  // the block total: tiles before this one
+                                                       const uint64_t* block_sums, int prefixed,
+                                                       uint64_t* out) {
+    uint64_t carry;
+    if (prefixed) {
+        carry = block_sums[blockIdx.x];
+    } else {
+        uint64_t before = 0;
+        for (size_t b = threadIdx.x; b < blockIdx.x; b += SCAN_T) before += block_sums[b];
+        carry = block_inclusive_scan(before);  // the block total: tiles before this one
+    }
     const size_t base = (size_t)blockIdx.x * SCAN_TILE + threadIdx.x;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
@@ -2094,7 +2117,9 @@ hipError_t launch_scan(ScanKind kind, const void* in, size_t n, uint64_t* out, v
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_partial, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs);
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs, out);
+    const int prefixed = nb > SCAN_SELF_MAX ? 1 : 0;
+    if (prefixed) hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, s, bs, nb);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_T), 0, s, kind, in, n, bs, prefixed, out);
     return hipGetLastError();
 }
 

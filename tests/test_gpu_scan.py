@@ -2,7 +2,8 @@
 general kernel's job offsets, through wfa_pack2bit (whose word starts are
 the exclusive scan of ceil(length / 32)): every start and the total against
 numpy's cumulative sum, for counts on both sides of the one-block form's
-limit (8 tiles of 2048) and of tile edges, with a ragged last tile."""
+limit (8 tiles of 2048), of tile edges and of the 8192 tiles up to which
+each block sums the earlier tiles' totals itself, with a ragged last tile."""
 import numpy as np
 import pytest
 
@@ -20,13 +21,17 @@ def aligner():
     al.close()
 
 
-@pytest.mark.parametrize("n", [1, 2047, 2048, 2049, 16383, 16384, 16385, 18432, 20481, 300_001])
+@pytest.mark.parametrize("n", [1, 2047, 2048, 2049, 16383, 16384, 16385, 18432, 20481, 300_001,
+                               17_000_001])
 def test_word_starts(aligner, n):
     import torch
 
     say(f"case: scan of {n} word counts")
     rng = np.random.default_rng(n)
-    lens = rng.integers(0, 301, n).astype(np.int32)
+    if n > 1_000_000:  # past 8192 tiles (the tile totals scanned by a pass of their own)
+        lens = rng.choice(np.array([0, 1, 33, 70], np.int32), n, p=[0.8, 0.1, 0.06, 0.04])
+    else:
+        lens = rng.integers(0, 301, n).astype(np.int32)
     lens[rng.integers(0, n, max(1, n // 50))] = 0  # empty sequences scan as 0 words
     ascii = np.full(int(lens.sum()) + 1, ord("A"), np.uint8)
     starts = np.zeros(n, np.int64)
