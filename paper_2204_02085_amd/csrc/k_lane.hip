@@ -28,7 +28,7 @@
 // 64 lanes reading "their" dword q hit 64 different banks): the pattern and
 // the text in 2-bit little-endian words, and the bytes of one step's cells
 // on their way to the history.  Per block: the diagonal of each compact
-// cell and (CIGAR) the (s, k) -> compact cell table.
+// cell and the (s, k) -> compact cell table (the target test, the walk).
 // Global memory per wavefront, lane-interleaved the same way (CIGAR mode):
 // the history of every reachable M cell, its offset after extension (one
 // byte, 0x80 for NULL) and its 4-bit decision record (source of M:
@@ -148,10 +148,10 @@ struct LaneKernel {
     static constexpr int STW = (max_cells() + 3) / 4;
     static constexpr int LANE_DW = 2 * SQ + STW;
     static constexpr int WAVE_BYTES = LANE_DW * 64 * 4;
-    // per block: the diagonal of each compact cell (int8), then (CIGAR) the
-    // (s, k) -> compact cell table (int16)
+    // per block: the diagonal of each compact cell (int8), then the (s, k)
+    // -> compact cell table (int16)
     static constexpr int KOF_BYTES = (NC + 15) & ~15;
-    static constexpr int TABLE_BYTES = KOF_BYTES + (CIGAR ? (((CAP + 1) * W * 2 + 15) & ~15) : 0);
+    static constexpr int TABLE_BYTES = KOF_BYTES + (((CAP + 1) * W * 2 + 15) & ~15);
     // CIGAR history per lane in global memory: the offset after extension of
     // every reachable cell (a byte; 0x80 NULL) in compact order, then the
     // cells' 4-bit decision records
@@ -269,7 +269,9 @@ struct LaneKernel {
     // Phase 2 of a step: extend every staged cell along matches, 32 bases
     // per compare (a wave-uniform loop; lanes with nothing to extend compare
     // at offset 0 and add nothing), stage the offset after extension, and
-    // test the target cell.  One rolled loop over the step's cells.
+    // test the target cell.  One rolled loop over the step's cells; the
+    // target test afterwards reads the one staged byte of the lane's target
+    // diagonal through the (s, k) -> cell table.
     template <int S>
     static __device__ __forceinline__ bool extend_step(Lane& ln, lptr<const int8_t> kof) {
         constexpr int c0 = first_cell(S), ns = cells_of(S);
@@ -297,8 +299,13 @@ struct LaneKernel {
                     gm = __ballot(rem > 0);
                 }
                 if (go) *bp = (uint8_t)hp;
-                const int Mx = go ? hp : Mv;
-                term |= (k == ln.kt) & (Mx == ln.m);
+            }
+            // the (s, k) -> compact cell table follows the cells' diagonals
+            const lptr<const short> table = (lptr<const short>)((lptr<const unsigned char>)kof + KOF_BYTES);
+            const int jt = ln.kt + KM;
+            if (ln.run && jt >= 0 && jt < W) {
+                const int c = table[S * W + jt];
+                if (c >= 0) term = *gptr(ln, c - c0) == ln.m;  // 0x80 (NULL) never equals m
             }
         }
         return term;
@@ -360,13 +367,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int wpb = blockDim.x >> 6;
     lptr<unsigned char> ldsb = (lptr<unsigned char>)lds;
     // per block: the diagonal of each compact cell, the (s, k) -> compact
-    // cell table (CIGAR), then one region per wavefront
+    // cell table, then one region per wavefront
     lptr<int8_t> kof = (lptr<int8_t>)ldsb;
     lptr<short> table = (lptr<short>)(ldsb + K::KOF_BYTES);
     for (int i = threadIdx.x; i < (K::CAP1) * K::W; i += blockDim.x) {
         const int s = i / K::W, j = i % K::W;
         const int c = K::reach.cidx[s][j];
-        if (CIGAR) table[i] = (short)c;
+        table[i] = (short)c;
         if (c >= 0) kof[c] = (int8_t)(j - K::KM);
     }
     __syncthreads();
