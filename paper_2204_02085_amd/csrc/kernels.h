@@ -168,7 +168,7 @@ struct FillOp {
 };
 struct FillOps {
     FillOp op[FILL_OPS];
-    int count;
+    int count = 0;
     void add(uint32_t* p, uint64_t n, uint32_t v) {  // a count past FILL_OPS fails the launch
         if (!n) return;
         if (count < FILL_OPS) op[count] = FillOp{p, n, v};
