@@ -27,8 +27,9 @@
 // LDS per wavefront, lane-interleaved (dword q of lane l at q * 64 + l, so
 // 64 lanes reading "their" dword q hit 64 different banks): the pattern and
 // the text in 2-bit little-endian words, and the bytes of one step's cells
-// on their way to the history.  Per block: the diagonal of each compact
-// cell and the (s, k) -> compact cell table (the target test, the walk).
+// on their way to the history.  Per block: the (s, k) -> compact cell table
+// (the target test, the walk); the diagonal of each compact cell is a
+// constant table read with scalar loads.
 // Global memory per wavefront, lane-interleaved the same way (CIGAR mode):
 // the history of every reachable M cell, its offset after extension (one
 // byte, 0x80 for NULL) and its 4-bit decision record (source of M:
@@ -129,6 +130,18 @@ struct LaneKernel {
     static constexpr int RID = E + 1;                 // rings of I and D rows (registers)
     static constexpr int SQ = (LMAX >> 4) + 3;        // dwords per sequence column
 
+    // the diagonal of each compact cell, as a constant table the extension
+    // loop reads with scalar loads (its cell index is wave-uniform)
+    struct Kof {
+        int k[NC > 0 ? NC : 1] = {};
+        constexpr Kof() {
+            for (int s = 0; s <= CAP; s++)
+                for (int j = 0; j < W; j++)
+                    if (reach.cidx[s][j] >= 0) k[reach.cidx[s][j]] = j - KM;
+        }
+    };
+    static constexpr Kof kof_tab{};
+
     static constexpr int first_cell(int s) {
         for (int j = 0; j < W; j++)
             if (reach.m[s][j]) return reach.cidx[s][j];
@@ -148,10 +161,8 @@ struct LaneKernel {
     static constexpr int STW = (max_cells() + 3) / 4;
     static constexpr int LANE_DW = 2 * SQ + STW;
     static constexpr int WAVE_BYTES = LANE_DW * 64 * 4;
-    // per block: the diagonal of each compact cell (int8), then the (s, k)
-    // -> compact cell table (int16)
-    static constexpr int KOF_BYTES = (NC + 15) & ~15;
-    static constexpr int TABLE_BYTES = KOF_BYTES + (((CAP + 1) * W * 2 + 15) & ~15);
+    // per block: the (s, k) -> compact cell table (int16)
+    static constexpr int TABLE_BYTES = ((CAP + 1) * W * 2 + 15) & ~15;
     // CIGAR history per lane in global memory: the offset after extension of
     // every reachable cell (a byte; 0x80 NULL) in compact order, then the
     // cells' 4-bit decision records
@@ -273,13 +284,13 @@ struct LaneKernel {
     // target test afterwards reads the one staged byte of the lane's target
     // diagonal through the (s, k) -> cell table.
     template <int S>
-    static __device__ __forceinline__ bool extend_step(Lane& ln, lptr<const int8_t> kof) {
+    static __device__ __forceinline__ bool extend_step(Lane& ln, lptr<const short> table) {
         constexpr int c0 = first_cell(S), ns = cells_of(S);
         bool term = false;
         if constexpr (ns > 0) {
 #pragma unroll 1
             for (int j = 0; j < ns; j++) {
-                const int k = kof[c0 + j];
+                const int k = kof_tab.k[c0 + j];
                 lptr<uint8_t> bp = gptr(ln, j);
                 const int Mv = *bp;  // 0x80 for NULL
                 const int L = min(ln.m, ln.n + k);
@@ -300,8 +311,6 @@ struct LaneKernel {
                 }
                 if (go) *bp = (uint8_t)hp;
             }
-            // the (s, k) -> compact cell table follows the cells' diagonals
-            const lptr<const short> table = (lptr<const short>)((lptr<const unsigned char>)kof + KOF_BYTES);
             const int jt = ln.kt + KM;
             if (ln.run && jt >= 0 && jt < W) {
                 const int c = table[S * W + jt];
@@ -324,7 +333,7 @@ struct LaneKernel {
 
     // One score step; false once no lane of the wavefront is still running.
     template <int S>
-    static __device__ __forceinline__ bool step(St& st, Lane& ln, lptr<const int8_t> kof) {
+    static __device__ __forceinline__ bool step(St& st, Lane& ln, lptr<const short> table) {
         // The lengths pass through an empty asm each step, so the per-diagonal
         // limits min(m, n + k) are recomputed (two instructions per cell)
         // instead of being kept in registers across the whole pass.
@@ -333,7 +342,7 @@ struct LaneKernel {
         // loop and keeps them all in registers.
         asm volatile("" : "+v"(ln.n), "+v"(ln.m), "+v"(ln.H));
         step_cells<S>(st, ln, std::make_integer_sequence<int, W>{});
-        const bool term = extend_step<S>(ln, kof);
+        const bool term = extend_step<S>(ln, table);
         step_back<S>(st, ln, std::make_integer_sequence<int, W>{});
         const bool fin = ln.run && term;
         ln.S = fin ? S : ln.S;
@@ -346,9 +355,9 @@ struct LaneKernel {
     }
 
     template <int... Ss>
-    static __device__ __forceinline__ void forward(St& st, Lane& ln, lptr<const int8_t> kof,
+    static __device__ __forceinline__ void forward(St& st, Lane& ln, lptr<const short> table,
                                                    std::integer_sequence<int, Ss...>) {
-        (step<Ss>(st, ln, kof) && ...);  // stops after the step where every lane finished
+        (step<Ss>(st, ln, table) && ...);  // stops after the step where every lane finished
     }
 };
 
@@ -366,15 +375,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int wave = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     lptr<unsigned char> ldsb = (lptr<unsigned char>)lds;
-    // per block: the diagonal of each compact cell, the (s, k) -> compact
-    // cell table, then one region per wavefront
-    lptr<int8_t> kof = (lptr<int8_t>)ldsb;
-    lptr<short> table = (lptr<short>)(ldsb + K::KOF_BYTES);
+    // per block: the (s, k) -> compact cell table, then one region per
+    // wavefront
+    lptr<short> table = (lptr<short>)ldsb;
     for (int i = threadIdx.x; i < (K::CAP1) * K::W; i += blockDim.x) {
         const int s = i / K::W, j = i % K::W;
         const int c = K::reach.cidx[s][j];
         table[i] = (short)c;
-        if (c >= 0) kof[c] = (int8_t)(j - K::KM);
     }
     __syncthreads();
     lptr<uint32_t> wbase = (lptr<uint32_t>)(ldsb + K::TABLE_BYTES + wave * K::WAVE_BYTES) + lane;
@@ -454,7 +461,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
         typename K::St st;
         if (__ballot(ln.run) != 0)
-            K::forward(st, ln, (lptr<const int8_t>)kof, std::make_integer_sequence<int, CAP + 1>{});
+            K::forward(st, ln, (lptr<const short>)table, std::make_integer_sequence<int, CAP + 1>{});
         // lanes still running after CAP steps leave through the overflow list
         bool overflow = active && ln.S < 0;
         int nr = 0;
