@@ -170,12 +170,45 @@ struct LaneKernel {
     static constexpr int HRW = (NC + 7) / 8;
     static constexpr int HIST_DW = CIGAR ? HMW + HRW : 0;
 
+    // Register rows hold one byte per diagonal, four diagonals to a word
+    // (diagonal index J in byte J % 4 of word J / 4): every offset is at most
+    // LMAX < 0x80, and 0x80 stands for NULL.  A row word is rebuilt at each
+    // step from its reachable bytes only; bytes of unreachable diagonals are
+    // never read.  A finished word passes through an empty asm, so the
+    // compiler extracts each byte where a cell reads it instead of keeping
+    // the unpacked bytes in registers.
+    static constexpr int WP = (W + 3) / 4;
     struct St {
-        int M[RM][W];  // offsets after extension (0x80 stands for NULL)
-        int I[RID][W];
-        int D[RID][W];
+        uint32_t M[RM][WP];  // offsets after extension
+        uint32_t I[RID][WP];
+        uint32_t D[RID][WP];
         uint32_t pm, pr;  // history words being packed
     };
+    template <int J>
+    static __device__ __forceinline__ uint32_t byte_of(uint32_t w) {
+        return (w >> (8 * (J & 3))) & 0xffu;
+    }
+    static constexpr bool reaches(int T, int S, int j) {
+        return T == 0 ? reach.m[S][j] : (T == 1 ? reach.i[S][j] : reach.d[S][j]);
+    }
+    // whether J is the lowest / highest diagonal of its word that row type T
+    // (0: M, 1: I, 2: D) reaches at step S
+    static constexpr bool first_in_word(int T, int S, int J) {
+        for (int j = J & ~3; j < J; j++)
+            if (reaches(T, S, j)) return false;
+        return true;
+    }
+    static constexpr bool last_in_word(int T, int S, int J) {
+        for (int j = J + 1; j < ((J | 3) + 1) && j < W; j++)
+            if (reaches(T, S, j)) return false;
+        return true;
+    }
+    template <int T, int S, int J>
+    static __device__ __forceinline__ void put_byte(uint32_t& w, uint32_t v) {
+        if constexpr (first_in_word(T, S, J)) w = v << (8 * (J & 3));
+        else w |= v << (8 * (J & 3));
+        if constexpr (last_in_word(T, S, J)) asm volatile("" : "+v"(w));
+    }
 
     struct Lane {
         int n, m, kt;
@@ -203,10 +236,10 @@ struct LaneKernel {
                 Mv = 0;
             } else {
                 // candidates as unsigned distances t = L - c below the limit:
-                // admissible offsets 0 <= t <= L, NULL sources just below
-                // tn = L - NULL, offsets past L negative (huge); the largest
-                // admissible candidate is the smallest t, floored at tn.  An M
-                // source of 0x80 (NULL) is past every limit, so it drops out.
+                // admissible offsets 0 <= t <= L, offsets past L negative
+                // (huge); the largest admissible candidate is the smallest t,
+                // floored at tn = L - NULL.  A source byte of 0x80 (NULL) is
+                // past every limit, so it drops out.
                 constexpr bool hA = S >= OE && J >= 1 && reach.m[S >= OE ? S - OE : 0][J >= 1 ? J - 1 : 0];
                 constexpr bool hB = S >= E && J >= 1 && reach.i[S >= E ? S - E : 0][J >= 1 ? J - 1 : 0];
                 constexpr bool hC = S >= OE && J + 1 < W && reach.m[S >= OE ? S - OE : 0][J + 1 < W ? J + 1 : 0];
@@ -214,11 +247,11 @@ struct LaneKernel {
                 constexpr bool hX = S >= X && reach.m[S >= X ? S - X : 0][J];
                 const uint32_t tn = (uint32_t)(L - LNUL);
                 uint32_t ta = tn, tb = tn, tc = tn, te = tn, tx = tn;
-                if constexpr (hA) ta = (uint32_t)(L - 1 - st.M[(S - OE) % RM][J - 1]);
-                if constexpr (hB) tb = (uint32_t)(L - 1 - st.I[(S - E) % RID][J - 1]);
-                if constexpr (hC) tc = (uint32_t)(L - st.M[(S - OE) % RM][J + 1]);
-                if constexpr (hE) te = (uint32_t)(L - st.D[(S - E) % RID][J + 1]);
-                if constexpr (hX) tx = (uint32_t)(L - 1 - st.M[(S - X) % RM][J]);
+                if constexpr (hA) ta = (uint32_t)(L - 1) - byte_of<J - 1>(st.M[(S - OE) % RM][(J - 1) / 4]);
+                if constexpr (hB) tb = (uint32_t)(L - 1) - byte_of<J - 1>(st.I[(S - E) % RID][(J - 1) / 4]);
+                if constexpr (hC) tc = (uint32_t)L - byte_of<J + 1>(st.M[(S - OE) % RM][(J + 1) / 4]);
+                if constexpr (hE) te = (uint32_t)L - byte_of<J + 1>(st.D[(S - E) % RID][(J + 1) / 4]);
+                if constexpr (hX) tx = (uint32_t)(L - 1) - byte_of<J>(st.M[(S - X) % RM][J / 4]);
                 const uint32_t ti = min(min(ta, tb), tn);
                 const uint32_t td = min(min(tc, te), tn);
                 const uint32_t tm = min(min(tx, ti), td);
@@ -236,8 +269,9 @@ struct LaneKernel {
                     asm volatile("" : "+v"(rec));
                 }
             }
-            if constexpr (reach.i[S][J]) st.I[S % RID][J] = Iv;
-            if constexpr (reach.d[S][J]) st.D[S % RID][J] = Dv;
+            // NULL (negative) becomes 0x80 (unsigned minimum)
+            if constexpr (reach.i[S][J]) put_byte<1, S, J>(st.I[S % RID][J / 4], min((uint32_t)Iv, 0x80u));
+            if constexpr (reach.d[S][J]) put_byte<2, S, J>(st.D[S % RID][J / 4], min((uint32_t)Dv, 0x80u));
             if constexpr (CIGAR) {
                 constexpr int c = reach.cidx[S][J];
                 if constexpr ((c & 7) == 0) st.pr = rec;
@@ -256,7 +290,7 @@ struct LaneKernel {
         if constexpr (reach.m[S][J]) {
             constexpr int g = reach.cidx[S][J] - first_cell(S);
             const int b = *gptr(ln, g);
-            st.M[S % RM][J] = b;
+            put_byte<0, S, J>(st.M[S % RM][J / 4], (uint32_t)b);
             if constexpr (CIGAR) {
                 constexpr int c = reach.cidx[S][J];
                 if constexpr ((c & 3) == 0) st.pm = (uint32_t)b;
@@ -361,11 +395,11 @@ struct LaneKernel {
     }
 };
 
-// At most 128 VGPRs (four wavefronts per SIMD; the 16-step CIGAR form then
-// keeps 48 dwords per lane in scratch): on 5 M pairs at E = 4 % it took 1.85
-// ms against 1.91 ms at three wavefronts (168 VGPRs) and 2.08 ms at five,
-// in alternating runs on one device; the compiler's own choice of up to 256
-// VGPRs took 2.6 ms.
+// At most 128 VGPRs (four wavefronts per SIMD).  With the register rows as
+// packed bytes the 16-step CIGAR form needs 125 and no scratch: a 5 M-pair
+// call at E = 4 % took 1.87 ms against 2.02 ms with one register per
+// diagonal (128 VGPRs and 48 dwords per lane in scratch), and 1.88 ms at five
+// wavefronts (96 VGPRs, 30 spilled), in alternating runs on one device.
 template <int X, int OE, int E, int CAP, int LMAX, bool CIGAR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_lane(LaneArgs a,
                                                                                     int persistent) {
