@@ -54,7 +54,9 @@ namespace wfa {
 
 namespace {
 
-constexpr int LNUL = -(1 << 20);  // NULL offset; drifts up by at most one per step
+// NULL offset: far below every offset, and its low byte is 0x80, the NULL
+// byte of the packed rows, the staging and the history
+constexpr int LNUL = -(1 << 20) + 0x80;
 
 // Which cells of steps 0..CAP can hold an offset (see above), and the
 // compact history index of each reachable M cell.
@@ -203,10 +205,20 @@ struct LaneKernel {
             if (reaches(T, S, j)) return false;
         return true;
     }
+    // byte J % 4 of w = the low byte of v (its other bytes are ignored): the
+    // lowest reachable byte of a word starts it (bytes above it are left as
+    // they come, and are either written next or never read), the others go
+    // in by a byte permute that keeps the rest of the word
     template <int T, int S, int J>
     static __device__ __forceinline__ void put_byte(uint32_t& w, uint32_t v) {
-        if constexpr (first_in_word(T, S, J)) w = v << (8 * (J & 3));
-        else w |= v << (8 * (J & 3));
+        constexpr int p = J & 3;
+        if constexpr (first_in_word(T, S, J)) {
+            w = v << (8 * p);
+        } else {
+            constexpr uint32_t sel = (p == 0 ? 0x03020104u
+                                      : p == 1 ? 0x03020400u : p == 2 ? 0x03040100u : 0x04020100u);
+            w = __builtin_amdgcn_perm(v, w, sel);
+        }
         if constexpr (last_in_word(T, S, J)) asm volatile("" : "+v"(w));
     }
 
@@ -269,17 +281,18 @@ struct LaneKernel {
                     asm volatile("" : "+v"(rec));
                 }
             }
-            // NULL (negative) becomes 0x80 (unsigned minimum)
-            if constexpr (reach.i[S][J]) put_byte<1, S, J>(st.I[S % RID][J / 4], min((uint32_t)Iv, 0x80u));
-            if constexpr (reach.d[S][J]) put_byte<2, S, J>(st.D[S % RID][J / 4], min((uint32_t)Dv, 0x80u));
+            // an offset is in [0, L] or exactly NULL (the minimum is floored
+            // at tn), so its low byte is the offset or 0x80
+            if constexpr (reach.i[S][J]) put_byte<1, S, J>(st.I[S % RID][J / 4], (uint32_t)Iv);
+            if constexpr (reach.d[S][J]) put_byte<2, S, J>(st.D[S % RID][J / 4], (uint32_t)Dv);
             if constexpr (CIGAR) {
                 constexpr int c = reach.cidx[S][J];
                 if constexpr ((c & 7) == 0) st.pr = rec;
                 else st.pr |= rec << (4 * (c & 7));
                 if constexpr ((c & 7) == 7 || c == NC - 1) ln.H[(HMW + (c >> 3)) * 64] = st.pr;
             }
-            // NULL (negative) becomes 0x80 (unsigned minimum)
-            *gptr(ln, g) = (uint8_t)min((uint32_t)Mv, 0x80u);
+            // the low byte: the offset, or 0x80 for NULL
+            *gptr(ln, g) = (uint8_t)Mv;
         }
     }
 
