@@ -344,8 +344,11 @@ struct LaneKernel {
                 const int Mv = *bp;  // 0x80 for NULL
                 const int L = min(ln.m, ln.n + k);
                 const bool go = ln.run && Mv < L;  // L <= LMAX < 0x80
-                int hp = go ? Mv : 0;
-                int vp = go ? Mv - k : 0;
+                // a lane that does not extend keeps rem = 0, so it adds nothing
+                // and its compares read its own or a neighbouring column of
+                // this block's LDS (Mv - k within -16 .. 144), never stored
+                int hp = Mv;
+                int vp = Mv - k;
                 int rem = go ? L - Mv : 0;
                 uint64_t gm = __ballot(go);
                 while (gm) {
