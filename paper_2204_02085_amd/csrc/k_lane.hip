@@ -164,7 +164,9 @@ struct LaneKernel {
     static constexpr int LANE_DW = 2 * SQ + STW;
     static constexpr int WAVE_BYTES = LANE_DW * 64 * 4;
     // per block: the (s, k) -> compact cell table (int16)
-    static constexpr int TABLE_BYTES = ((CAP + 1) * W * 2 + 15) & ~15;
+    // (rounded to 256 bytes, so the lane columns that follow sit at whole
+    // multiples of 64 dwords and paired column reads need no base add)
+    static constexpr int TABLE_BYTES = ((CAP + 1) * W * 2 + 255) & ~255;
     // CIGAR history per lane in global memory: the offset after extension of
     // every reachable cell (a byte; 0x80 NULL) in compact order, then the
     // cells' 4-bit decision records
@@ -354,7 +356,14 @@ struct LaneKernel {
                 while (gm) {
                     const uint64_t a = col_window32(ln.P, vp), bb = col_window32(ln.T, hp);
                     const uint64_t dx = a ^ bb;
-                    const int cp = dx ? (int)(__builtin_ctzll(dx) >> 1) : 32;
+                    // matching bases before the first mismatch: trailing zero
+                    // bits of dx / 2, 32 when dx is 0 (v_ffbl gives ~0 for a zero
+                    // word; the saturating add keeps it ~0 for the high word)
+                    const uint32_t lo = (uint32_t)dx, hi = (uint32_t)(dx >> 32);
+                    uint32_t zl, zh;
+                    asm("v_ffbl_b32 %0, %1" : "=v"(zl) : "v"(lo));
+                    asm("v_ffbl_b32 %0, %1" : "=v"(zh) : "v"(hi));
+                    const int cp = (int)(min(min(zl, __builtin_elementwise_add_sat(zh, 32u)), 64u) >> 1);
                     const int r = min(cp, rem);
                     hp += r;
                     vp += r;
