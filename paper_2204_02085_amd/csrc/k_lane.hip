@@ -367,8 +367,10 @@ struct LaneKernel {
                     const int r = min(cp, rem);
                     hp += r;
                     vp += r;
-                    rem = r == 32 ? rem - 32 : 0;
-                    gm = __ballot(rem > 0);
+                    rem -= r;
+                    // a lane that stopped short (a mismatch, or the end) compares
+                    // at the same place again and adds 0 while others go on
+                    gm = __ballot(r == 32 && rem > 0);
                 }
                 if (go) *bp = (uint8_t)hp;
             }
