@@ -352,8 +352,10 @@ struct LaneKernel {
                 int hp = Mv;
                 int vp = Mv - k;
                 int rem = go ? L - Mv : 0;
-                uint64_t gm = __ballot(go);
-                while (gm) {
+                // at least one compare per cell: some lane of the wave almost
+                // always extends, and testing for none costs more than it saves
+                bool more;
+                do {
                     const uint64_t a = col_window32(ln.P, vp), bb = col_window32(ln.T, hp);
                     const uint64_t dx = a ^ bb;
                     // matching bases before the first mismatch: trailing zero
@@ -370,8 +372,8 @@ struct LaneKernel {
                     rem -= r;
                     // a lane that stopped short (a mismatch, or the end) compares
                     // at the same place again and adds 0 while others go on
-                    gm = __ballot(r == 32 && rem > 0);
-                }
+                    more = __ballot(r == 32 && rem > 0) != 0;
+                } while (more);
                 if (go) *bp = (uint8_t)hp;
             }
             const int jt = ln.kt + KM;
