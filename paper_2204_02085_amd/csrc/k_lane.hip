@@ -28,14 +28,14 @@
 // 64 lanes reading "their" dword q hit 64 different banks): the pattern and
 // the text in 2-bit little-endian words, and the bytes of one step's cells
 // on their way to the history.  Per block: the (s, k) -> compact cell table
-// (the target test, the walk); the diagonal of each compact cell is a
-// constant table read with scalar loads.
+// and the (s, k) -> history byte table (the target test, the walk); the
+// diagonal of each compact cell is a constant table read with scalar loads.
 // Global memory per wavefront, lane-interleaved the same way (CIGAR mode):
 // the history of every reachable M cell, its offset after extension (one
-// byte, 0x80 for NULL) and its 4-bit decision record (source of M:
-// mismatch / end of insertion / end of deletion; whether I and D opened
-// from M), packed in the cells' compile-time order, then a stage for the
-// runs.  Keeping it out of LDS leaves room for four wavefronts per SIMD.
+// byte, 0x80 for NULL; each step's staged dwords as they stand) and its
+// 4-bit decision record (source of M: mismatch / end of insertion / end of
+// deletion; whether I and D opened from M, packed in the cells' compile-time
+// order), then a stage for the runs.  Keeping it out of LDS leaves room for four wavefronts per SIMD.
 // The backtrace is the short kernel's walk, run by every lane on its own
 // pair.
 //
@@ -159,18 +159,56 @@ struct LaneKernel {
         for (int s = 0; s <= CAP; s++) mx = cells_of(s) > mx ? cells_of(s) : mx;
         return mx;
     }
+    // A step's staged offsets, its M row words and its history words share
+    // one layout: diagonal index J of step s at byte J - jbase(s), jbase(s)
+    // the lowest reachable J rounded down to a multiple of four, so each
+    // staged dword is a row word as it stands (bytes of unreachable diagonals
+    // are never read).
+    static constexpr int jlo(int s) {
+        for (int j = 0; j < W; j++)
+            if (reach.m[s][j]) return j;
+        return -1;
+    }
+    static constexpr int jhi(int s) {
+        for (int j = W - 1; j >= 0; j--)
+            if (reach.m[s][j]) return j;
+        return -1;
+    }
+    static constexpr int jbase(int s) { return jlo(s) < 0 ? 0 : (jlo(s) & ~3); }
+    static constexpr int nwords(int s) { return jlo(s) < 0 ? 0 : (jhi(s) - jbase(s)) / 4 + 1; }
+    static constexpr int hword(int s) {  // the history word of step s's first word
+        int t = 0;
+        for (int u = 0; u < s; u++) t += nwords(u);
+        return t;
+    }
+    static constexpr int max_words() {
+        int mx = 0;
+        for (int s = 0; s <= CAP; s++) mx = nwords(s) > mx ? nwords(s) : mx;
+        return mx;
+    }
+    // the history byte of each (s, k) cell (-1 where none), copied to LDS
+    struct HistByte {
+        short b[(CAP + 1) * W] = {};
+        constexpr HistByte() {
+            for (int s = 0; s <= CAP; s++)
+                for (int j = 0; j < W; j++)
+                    b[s * W + j] = reach.m[s][j] ? (short)(4 * hword(s) + j - jbase(s)) : (short)-1;
+        }
+    };
+    static constexpr HistByte hist_byte{};
     // LDS per lane: both sequences and the staging bytes of one step's cells
-    static constexpr int STW = (max_cells() + 3) / 4;
+    static constexpr int STW = max_words();
     static constexpr int LANE_DW = 2 * SQ + STW;
     static constexpr int WAVE_BYTES = LANE_DW * 64 * 4;
-    // per block: the (s, k) -> compact cell table (int16)
-    // (rounded to 256 bytes, so the lane columns that follow sit at whole
-    // multiples of 64 dwords and paired column reads need no base add)
-    static constexpr int TABLE_BYTES = ((CAP + 1) * W * 2 + 255) & ~255;
+    // per block: the (s, k) -> compact cell table and the (s, k) -> history
+    // byte table (int16 each), rounded to 256 bytes, so the lane columns that
+    // follow sit at whole multiples of 64 dwords and paired column reads need
+    // no base add
+    static constexpr int TABLE_BYTES = (2 * (CAP + 1) * W * 2 + 255) & ~255;
     // CIGAR history per lane in global memory: the offset after extension of
-    // every reachable cell (a byte; 0x80 NULL) in compact order, then the
-    // cells' 4-bit decision records
-    static constexpr int HMW = (NC + 3) / 4;
+    // every reachable cell (a byte; 0x80 NULL) in the staging layout, step
+    // after step, then the cells' 4-bit decision records in compact order
+    static constexpr int HMW = hword(CAP + 1);
     static constexpr int HRW = (NC + 7) / 8;
     static constexpr int HIST_DW = CIGAR ? HMW + HRW : 0;
 
@@ -186,7 +224,7 @@ struct LaneKernel {
         uint32_t M[RM][WP];  // offsets after extension
         uint32_t I[RID][WP];
         uint32_t D[RID][WP];
-        uint32_t pm, pr;  // history words being packed
+        uint32_t pr;  // the record word being packed
     };
     template <int J>
     static __device__ __forceinline__ uint32_t byte_of(uint32_t w) {
@@ -242,7 +280,7 @@ struct LaneKernel {
     static __device__ __forceinline__ void cell(St& st, Lane& ln) {
         if constexpr (reach.m[S][J]) {
             constexpr int k = J - KM;
-            constexpr int g = reach.cidx[S][J] - first_cell(S);  // staging byte
+            constexpr int g = J - jbase(S);  // staging byte
             const int L = min(ln.m, ln.n + k);  // largest admissible offset
             int Mv, Iv = LNUL, Dv = LNUL;
             [[maybe_unused]] uint32_t rec = 0;
@@ -298,21 +336,14 @@ struct LaneKernel {
         }
     }
 
-    // Phase 3 of a step, one cell: the offset after extension into the
-    // register row and (CIGAR) the history.
-    template <int S, int J>
-    static __device__ __forceinline__ void cell_back(St& st, Lane& ln) {
-        if constexpr (reach.m[S][J]) {
-            constexpr int g = reach.cidx[S][J] - first_cell(S);
-            const int b = *gptr(ln, g);
-            put_byte<0, S, J>(st.M[S % RM][J / 4], (uint32_t)b);
-            if constexpr (CIGAR) {
-                constexpr int c = reach.cidx[S][J];
-                if constexpr ((c & 3) == 0) st.pm = (uint32_t)b;
-                else st.pm |= (uint32_t)b << (8 * (c & 3));
-                if constexpr ((c & 3) == 3 || c == NC - 1) ln.H[(c >> 2) * 64] = st.pm;
-            }
-        }
+    // Phase 3 of a step, one staged dword (four diagonals): the offsets after
+    // extension as they stand into the register row and (CIGAR) the history.
+    template <int S, int Wi>
+    static __device__ __forceinline__ void word_back(St& st, Lane& ln) {
+        constexpr int rw = jbase(S) / 4 + Wi, hw = hword(S) + Wi;  // row word, history word
+        const uint32_t w = ln.G[Wi * 64];
+        st.M[S % RM][rw] = w;
+        if constexpr (CIGAR) ln.H[hw * 64] = w;
     }
 
     template <int S, int... Js>
@@ -320,10 +351,10 @@ struct LaneKernel {
                                                       std::integer_sequence<int, Js...>) {
         (cell<S, Js>(st, ln), ...);
     }
-    template <int S, int... Js>
+    template <int S, int... Ws>
     static __device__ __forceinline__ void step_back(St& st, Lane& ln,
-                                                     std::integer_sequence<int, Js...>) {
-        (cell_back<S, Js>(st, ln), ...);
+                                                     std::integer_sequence<int, Ws...>) {
+        (word_back<S, Ws>(st, ln), ...);
     }
 
     // Phase 2 of a step: extend every staged cell along matches, 32 bases
@@ -342,7 +373,8 @@ struct LaneKernel {
 #pragma unroll 4
             for (int j = 0; j < ns; j++) {
                 const int k = kof_tab.k[c0 + j];
-                lptr<uint8_t> bp = gptr(ln, j);
+                constexpr int jb = jbase(S);
+                lptr<uint8_t> bp = gptr(ln, k + KM - jb);
                 const int Mv = *bp;  // 0x80 for NULL
                 const int L = min(ln.m, ln.n + k);
                 const bool go = ln.run && Mv < L;  // L <= LMAX < 0x80
@@ -379,19 +411,19 @@ struct LaneKernel {
             const int jt = ln.kt + KM;
             if (ln.run && jt >= 0 && jt < W) {
                 const int c = table[S * W + jt];
-                if (c >= 0) term = *gptr(ln, c - c0) == ln.m;  // 0x80 (NULL) never equals m
+                constexpr int jb = jbase(S);
+                if (c >= 0) term = *gptr(ln, jt - jb) == ln.m;  // 0x80 (NULL) never equals m
             }
         }
         return term;
     }
 
-    // The history words being packed when the forward pass stops after step
-    // S (every lane finished): store them, so the walk never reads stale words.
+    // The record word being packed when the forward pass stops after step
+    // S (every lane finished): store it, so the walk never reads a stale word.
     template <int S>
     static __device__ __forceinline__ void flush(St& st, Lane& ln) {
         if constexpr (CIGAR && cells_of(S) > 0) {
             constexpr int last = first_cell(S) + cells_of(S) - 1;
-            if constexpr ((last & 3) != 3 && last != NC - 1) ln.H[(last >> 2) * 64] = st.pm;
             if constexpr ((last & 7) != 7 && last != NC - 1) ln.H[(HMW + (last >> 3)) * 64] = st.pr;
         }
     }
@@ -408,7 +440,7 @@ struct LaneKernel {
         asm volatile("" : "+v"(ln.n), "+v"(ln.m), "+v"(ln.H));
         step_cells<S>(st, ln, std::make_integer_sequence<int, W>{});
         const bool term = extend_step<S>(ln, table);
-        step_back<S>(st, ln, std::make_integer_sequence<int, W>{});
+        step_back<S>(st, ln, std::make_integer_sequence<int, nwords(S)>{});
         const bool fin = ln.run && term;
         ln.S = fin ? S : ln.S;
         ln.run = ln.run && !term;
@@ -427,8 +459,9 @@ struct LaneKernel {
 };
 
 // At most 128 VGPRs (four wavefronts per SIMD).  With the register rows as
-// packed bytes the 16-step CIGAR form needs 125 and no scratch (128 and 8
-// spilled dwords with the extension loop unrolled by four): a 5 M-pair call
+// packed bytes the 16-step CIGAR form needs 125 and no scratch (with the
+// extension loop unrolled by four and the row words taken from the staged
+// dwords as they stand): a 5 M-pair call
 // at E = 4 % took 1.87 ms (rolled) against 2.02 ms with one register per
 // diagonal (128 VGPRs and 48 dwords per lane in scratch), and 1.88 ms at five
 // wavefronts (96 VGPRs, 30 spilled), in alternating runs on one device.
@@ -441,13 +474,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int wave = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     lptr<unsigned char> ldsb = (lptr<unsigned char>)lds;
-    // per block: the (s, k) -> compact cell table, then one region per
-    // wavefront
+    // per block: the (s, k) -> compact cell table, the (s, k) -> history byte
+    // table, then one region per wavefront
     lptr<short> table = (lptr<short>)ldsb;
+    lptr<short> hbt = table + K::CAP1 * K::W;
     for (int i = threadIdx.x; i < (K::CAP1) * K::W; i += blockDim.x) {
         const int s = i / K::W, j = i % K::W;
-        const int c = K::reach.cidx[s][j];
-        table[i] = (short)c;
+        table[i] = (short)K::reach.cidx[s][j];
+        hbt[i] = K::hist_byte.b[i];
     }
     __syncthreads();
     lptr<uint32_t> wbase = (lptr<uint32_t>)(ldsb + K::TABLE_BYTES + wave * K::WAVE_BYTES) + lane;
@@ -549,9 +583,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if (s < 0 || s > CAP || k < -K::KM || k > K::KM) return -1;
                 return table[s * K::W + k + K::KM];
             };
-            auto hm = [&](int c) -> int {
-                const uint32_t w = ln.H[(c >> 2) * 64];
-                const int b = (int)((w >> (8 * (c & 3))) & 0xFFu);
+            // the offset of a reachable cell (s, k): byte hbt of the history
+            auto hm = [&](int s, int k) -> int {
+                const int hb = hbt[s * K::W + k + K::KM];
+                const uint32_t w = ln.H[(hb >> 2) * 64];
+                const int b = (int)((w >> (8 * (hb & 3))) & 0xFFu);
                 return b & 0x80 ? -1 : b;
             };
             auto hr = [&](int c) -> int {
@@ -577,7 +613,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             bad = true;
                             break;
                         }
-                        hn = hm(cs);
+                        hn = hm(s - X, k);
                         h0 = hn + 1;
                         s2 = s - X;
                     } else {
@@ -597,7 +633,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             bad = true;  // a gap with no opening: inconsistent
                             break;
                         }
-                        hn = hm(co);
+                        hn = hm(sc - OE, kc + dj);
                         h0 = ms == 1 ? hn + L : hn;  // insertions consume text
                         s2 = sc - OE;
                         dk = dj * L;
