@@ -103,6 +103,14 @@ __device__ __forceinline__ uint32_t lds_u32(P base, int dw) {
     return base[dw];
 }
 
+// 16 bases from base `pos` of a lane's sequence column (dword q at q * 64).
+template <class P>
+__device__ __forceinline__ uint32_t col_window16(P col, int pos) {
+    const int q = pos >> 4;
+    const uint32_t b = (uint32_t)(pos & 15) << 1;
+    return __builtin_amdgcn_alignbit(col[q * 64 + 64], col[q * 64], b);
+}
+
 // 32 bases from base `pos` of a lane's sequence column (dword q at q * 64).
 template <class P>
 __device__ __forceinline__ uint64_t col_window32(P col, int pos) {
@@ -384,10 +392,18 @@ struct LaneKernel {
                 int hp = Mv;
                 int vp = Mv - k;
                 int rem = go ? L - Mv : 0;
-                // at least one compare per cell: some lane of the wave almost
-                // always extends, and testing for none costs more than it saves
-                bool more;
-                do {
+                // a 16-base compare first, for every cell (some lane of the
+                // wave almost always extends, and testing for none costs more
+                // than it saves); most cells stop within it, and the wave
+                // runs on to 32-base compares only while a lane still matches
+                uint32_t z16;
+                asm("v_ffbl_b32 %0, %1" : "=v"(z16) : "v"(col_window16(ln.P, vp) ^ col_window16(ln.T, hp)));
+                const int r16 = min((int)(min(z16, 32u) >> 1), rem);
+                hp += r16;
+                vp += r16;
+                rem -= r16;
+                bool more = __ballot(r16 == 16 && rem > 0) != 0;
+                while (more) {
                     const uint64_t a = col_window32(ln.P, vp), bb = col_window32(ln.T, hp);
                     const uint64_t dx = a ^ bb;
                     // matching bases before the first mismatch: trailing zero
@@ -405,7 +421,7 @@ struct LaneKernel {
                     // a lane that stopped short (a mismatch, or the end) compares
                     // at the same place again and adds 0 while others go on
                     more = __ballot(r == 32 && rem > 0) != 0;
-                } while (more);
+                }
                 if (go) *bp = (uint8_t)hp;
             }
             const int jt = ln.kt + KM;
